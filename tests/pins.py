@@ -1,0 +1,205 @@
+"""Pins for the CPU oracle: checks against what the paper and the mathematics
+fix, independent of the oracle's own code path.
+
+Each pin takes an ``oracle.Oracle`` instance and raises AssertionError on a
+mismatch, so the same pins can be run against deliberately broken oracle
+builds (mutants) to show that they catch plausible mistakes.
+"""
+
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+import rtgen
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _f32(tok: str) -> np.float32:
+    return np.float32(float(tok))
+
+
+def load_handworked():
+    rects, queries, expect = {}, [], []
+    join_a = join_b = None
+    pairs = None
+    with open(os.path.join(GOLDEN, "select_handworked.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            head, _, tail = line.partition(":")
+            tok = head.split()
+            if tok[0] == "rect":
+                rects[int(tok[1])] = [_f32(t) for t in tok[2:6]]
+            elif tok[0] == "query":
+                queries.append([_f32(t) for t in tok[2:6]])
+                expect.append([int(t) for t in tail.split()])
+            elif tok[0] == "joinA":
+                join_a = [int(t) for t in tok[1:]]
+            elif tok[0] == "joinB":
+                join_b = [int(t) for t in tok[1:]]
+            elif tok[0] == "pairs":
+                pairs = [tuple(int(v) for v in p.split(",")) for p in tail.split()]
+    R = np.array([rects[i] for i in sorted(rects)], dtype=np.float32)
+    Q = np.array(queries, dtype=np.float32)
+    return R, Q, expect, R[join_a], R[join_b], pairs
+
+
+def segments(off, ids):
+    return [ids[int(off[k]):int(off[k + 1])].tolist() for k in range(len(off) - 1)]
+
+
+# ---------------------------------------------------------------------------
+def pin_handworked(o, fanouts=(2, 3, 4)):
+    """Hand-worked golden values (closed predicate, section 3 / 4.1)."""
+    R, Q, expect, A, B, pairs = load_handworked()
+    for F in fanouts:
+        t = o.build_str(R, F)
+        off, ids = o.select(t, Q)
+        got = segments(off, ids)
+        assert got == expect, f"F={F}: {got} != {expect}"
+        ta, tb = o.build_str(A, F), o.build_str(B, F)
+        p = [tuple(x) for x in o.join(ta, tb).tolist()]
+        assert p == pairs, f"join F={F}: {p} != {pairs}"
+    # brute force too: it is the definition written as nested loops
+    off, ids = o.brute_select(R, Q)
+    assert segments(off, ids) == expect
+    assert [tuple(x) for x in o.brute_join(A, B).tolist()] == pairs
+
+
+def pin_select_vs_brute(o, seeds=range(20), sizes=(0, 1, 2, 5, 16, 17, 64, 65, 300, 1500),
+                        fanouts=(2, 3, 4, 8, 16, 32, 64)):
+    """Tree search equals the nested-loop scan on adversarial inputs (touching
+    edges, points, segments, duplicates, infinite windows)."""
+    for s in seeds:
+        for n in sizes:
+            F = fanouts[(s + n) % len(fanouts)]
+            r = rtgen.adversarial_rects(n, 100 + s) if n else np.zeros((0, 4), np.float32)
+            q = rtgen.adversarial_windows(40, 500 + s)
+            t = o.build_str(r, F)
+            a = o.select(t, q)
+            b = o.brute_select(r, q)
+            assert np.array_equal(a[0], b[0]), f"seed {s} n {n} F {F}: counts differ"
+            assert np.array_equal(a[1], b[1]), f"seed {s} n {n} F {F}: ids differ"
+
+
+def pin_join_vs_brute(o, seeds=range(12)):
+    """Synchronized traversal equals the nested-loop join, including trees of
+    different heights and empty relations."""
+    for s in seeds:
+        na = [0, 1, 7, 40, 200, 900][s % 6]
+        nb = [3, 0, 50, 700, 64, 65][(s * 5) % 6]
+        Fa = [2, 4, 8, 16, 3, 32][s % 6]
+        Fb = [5, 16, 2, 8, 64, 4][(s + 1) % 6]
+        A = rtgen.adversarial_rects(na, 900 + s) if na else np.zeros((0, 4), np.float32)
+        B = rtgen.adversarial_rects(nb, 950 + s) if nb else np.zeros((0, 4), np.float32)
+        p = o.join(o.build_str(A, Fa), o.build_str(B, Fb))
+        q = o.brute_join(A, B)
+        assert np.array_equal(p, q), f"seed {s}: join != brute ({p.shape} vs {q.shape})"
+
+
+def pin_join_is_union_of_selects(o, seed=3):
+    """J(A,B) = union over a of {(a,b) : b in select_B(A[a])}, and
+    J(A,B) = swap(J(B,A)): two routes independent of the join recursion."""
+    A = rtgen.uniform_rects(3000, 0.01, seed)
+    B = rtgen.clustered_rects(2500, 5, 0.05, 0.01, seed + 1)
+    ta, tb = o.build_str(A, 8), o.build_str(B, 16)
+    J = o.join(ta, tb)
+    off, ids = o.select(tb, A)
+    cnt = np.diff(off.astype(np.int64))
+    U = np.stack([np.repeat(np.arange(A.shape[0], dtype=np.uint32), cnt), ids], axis=1)
+    assert np.array_equal(J, U)
+    Js = o.join(tb, ta)[:, ::-1]
+    order = np.lexsort((Js[:, 1], Js[:, 0]))
+    assert np.array_equal(J, Js[order])
+
+
+def pin_closed_form_uniform(o):
+    """Uniform rectangles with sides U[0,s] and square windows of side w inside
+    the unit square: E[#hits] = N * (w + s/2)^2 (the window grows by the mean
+    side on the low sides).  The same mean also checks the
+    C1-sized tree: ~11.0 hits per query."""
+    N, s, w = 100_000, 1e-3, 0.01
+    r = rtgen.uniform_rects(N, s, 7)
+    g = rtgen.rng(8)
+    c = g.uniform(0.02, 0.98, size=(2, 4000))
+    q = np.stack([c[0] - w / 2, c[1] - w / 2, c[0] + w / 2, c[1] + w / 2], 1).astype(np.float32)
+    t = o.build_str(r, 16)
+    off, ids = o.select(t, q)
+    cnt = np.diff(off.astype(np.int64))
+    expect = N * (w + s / 2) ** 2
+    se = math.sqrt(expect / len(cnt))          # Poisson standard error of the mean
+    assert abs(cnt.mean() - expect) < 5 * se, (cnt.mean(), expect)
+
+
+def pin_closed_form_join(o):
+    """Two uniform relations with sides U[0,s]: E[#pairs] = NA*NB*(E[wA]+E[wB])^2
+    for objects away from the border; here (s/2 + s/2)^2 = s^2."""
+    N, s = 20_000, 2e-3
+    A = rtgen.uniform_rects(N, s, 11)
+    B = rtgen.uniform_rects(N, s, 12)
+    p = o.join(o.build_str(A, 16), o.build_str(B, 32))
+    expect = N * N * s * s
+    assert abs(p.shape[0] - expect) < 5 * math.sqrt(expect) + 0.01 * expect, (p.shape[0], expect)
+
+
+def pin_tree_shape(o):
+    """STR packs every level completely except possibly its last node:
+    nodes per level = ceil(count / F) repeated until one node is left; every
+    invariant of the checker holds."""
+    for n, F in [(1, 4), (4, 4), (5, 4), (100, 2), (1000, 16), (4097, 64), (33, 32), (99_991, 16)]:
+        r = rtgen.uniform_rects(n, 1e-3, n + F)
+        t = o.build_str(r, F)
+        rc, msg = o.check(t, r)
+        assert rc == 0, (n, F, msg)
+        A = t.arrays()
+        levels = np.bincount(A["level"].astype(np.int64)).tolist()
+        exp, c = [], n
+        while c > F:
+            c = -(-c // F)
+            exp.append(c)
+        exp.append(1)                   # the root
+        assert levels == exp, (n, F, levels, exp)
+        assert t.height == len(exp)
+
+
+def pin_special_cases(o):
+    """Empty relation, select-all window, identical rectangles, n = F and F+1."""
+    q = np.array([[-np.inf, -np.inf, np.inf, np.inf], [0.5, 0.5, 0.5, 0.5]], np.float32)
+    t = o.build_str(np.zeros((0, 4), np.float32), 8)
+    off, ids = o.select(t, q)
+    assert off.tolist() == [0, 0, 0] and ids.size == 0
+    same = np.tile(np.array([[0.25, 0.25, 0.75, 0.75]], np.float32), (37, 1))
+    for F in (2, 4, 36, 37, 38):
+        t = o.build_str(same, F)
+        off, ids = o.select(t, q)
+        assert ids.tolist() == list(range(37)) * 2
+    # degenerate windows on a coarse grid
+    r = rtgen.adversarial_rects(500, 77)
+    t = o.build_str(r, 4)
+    off, ids = o.select(t, q[:1])
+    assert ids.tolist() == list(range(500))
+
+
+def pin_results_canonical(o):
+    """Results are strictly ascending per query (sorted, duplicate-free) and every
+    reported id intersects its window (soundness, checked per element)."""
+    r = rtgen.clustered_rects(20_000, 8, 0.05, 5e-3, 21)
+    q = rtgen.windows_loguniform(300, 1e-5, 1e-2, 22)
+    t = o.build_str(r, 16)
+    off, ids = o.select(t, q)
+    for k in range(q.shape[0]):
+        s = ids[int(off[k]):int(off[k + 1])]
+        assert np.all(np.diff(s.astype(np.int64)) > 0)
+        e = r[s]
+        w = q[k]
+        assert np.all((e[:, 0] <= w[2]) & (w[0] <= e[:, 2]) & (e[:, 1] <= w[3]) & (w[1] <= e[:, 3]))
+
+
+ALL_PINS = [pin_handworked, pin_select_vs_brute, pin_join_vs_brute, pin_join_is_union_of_selects,
+            pin_closed_form_uniform, pin_closed_form_join, pin_tree_shape, pin_special_cases,
+            pin_results_canonical]
