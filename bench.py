@@ -1,0 +1,291 @@
+#!/usr/bin/env python3
+"""Benchmark: batched R-tree range select (and join / batched / served legs)
+on one MI355X.
+
+Default workload (the "step"): one complete range select -- count pass,
+scan, fill pass, segmented sort -- of 1,000,000 query windows (selectivity
+log-uniform in [1e-6, 1e-3]) against a 10,000,000-rectangle tree (half
+uniform, half in 64 Gaussian clusters, sides U[0, 1e-4]), fanout 32, SoA
+node layout, with queries, tree and output buffers resident in device memory
+before timing starts.  Prints one JSON line.
+
+Extra legs (same JSON line, under "legs"): spatial join of two 2M-rectangle
+relations, the 256-instance batched select (persistent + graph vs plain
+per-tree launches), and the scalar CPU oracle timed on a bounded sample of the
+same select workload ("cpu_baseline").
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "range queries/s and join pairs/s on 1 GPU (bit-exact), % HBM peak; p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class HipEvents:
+    """hipEvent_t handles through the HIP runtime already loaded in-process."""
+
+    def __init__(self):
+        self.h = C.CDLL("libamdhip64.so.7")
+        self.h.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.h.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.h.hipEventDestroy.argtypes = [C.c_void_p]
+        self.h.hipEventSynchronize.argtypes = [C.c_void_p]
+
+    def create(self, n):
+        out = []
+        for _ in range(n):
+            e = C.c_void_p()
+            assert self.h.hipEventCreate(C.byref(e)) == 0
+            out.append(e.value)
+        return out
+
+    def ms(self, a, b):
+        f = C.c_float()
+        assert self.h.hipEventSynchronize(C.c_void_p(b)) == 0
+        assert self.h.hipEventElapsedTime(C.byref(f), C.c_void_p(a), C.c_void_p(b)) == 0
+        return float(f.value)
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2309_16913_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(kernel_tag, src_hash):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
+    if not os.path.exists(p):
+        return None
+    vals = {}
+    for line in open(p):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != src_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def select_leg(rt, torch, ev, args, rects, queries):
+    t0 = time.time()
+    tree = rt.build_str(rects, args.fanout, args.layout)
+    build_s = time.time() - t0
+    info = tree.info()
+    nq = queries.shape[0]
+    dq = torch.from_numpy(queries).cuda()
+    off = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    # size the output with the count-only entry point
+    counts = torch.empty(nq, dtype=torch.int32, device="cuda")
+    wb0 = rt.select_workspace_bytes(nq, 0)
+    work0 = torch.empty(wb0, dtype=torch.uint8, device="cuda")
+    rt.range_count_device(tree, dq.data_ptr(), nq, counts.data_ptr(), work0.data_ptr(), wb0, stream.cuda_stream)
+    torch.cuda.synchronize()
+    cap = int(counts.to(torch.int64).sum().item())
+    del work0
+    ids = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    wb = rt.select_workspace_bytes(nq, cap)
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    status = torch.zeros(2, dtype=torch.int64, device="cuda")
+    events = [ev.create(5) for _ in range(args.steps)]
+
+    def step(e=None):
+        rt.range_select_device_timed(tree, dq.data_ptr(), nq, off.data_ptr(), ids.data_ptr(), cap, work.data_ptr(),
+                                     wb, status.data_ptr(), stream.cuda_stream, e)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = status.cpu().numpy()
+    assert st[1] == 0 and st[0] == cap, f"select status {st} (cap {cap})"
+    phases = {"count": [], "scan": [], "fill": [], "sort": []}
+    for e in events:
+        phases["count"].append(ev.ms(e[0], e[1]))
+        phases["scan"].append(ev.ms(e[1], e[2]))
+        phases["fill"].append(ev.ms(e[2], e[3]))
+        phases["sort"].append(ev.ms(e[3], e[4]))
+    avg = {k: float(np.mean(v)) for k, v in phases.items()}
+    vn, ve = rt.visit_stats(tree, queries)
+    node_bytes = 20 * ve + 8 * vn
+    bytes_count = 16 * nq + node_bytes
+    bytes_fill = bytes_count + 4 * cap + 8 * (nq + 1)
+    return dict(tree=tree, info=info, build_s=build_s, cap=cap, wall=wall, avg=avg, vn=vn, ve=ve,
+                bytes_count=bytes_count, bytes_fill=bytes_fill, off=off, ids=ids)
+
+
+def cpu_baseline(args, rects, queries, gpu_off, gpu_ids):
+    import oracle
+    o = oracle.get()
+    t0 = time.time()
+    ot = o.build_str(rects, args.fanout)
+    build_s = time.time() - t0
+    done, spent, chunk = 0, 0.0, 2000
+    mismatches = 0
+    while spent < args.cpu_seconds and done < queries.shape[0]:
+        q = queries[done:done + chunk]
+        t0 = time.perf_counter()
+        woff, wids = o.select(ot, q)
+        spent += time.perf_counter() - t0
+        # bit-exact check of the GPU result on this sample
+        g0, g1 = int(gpu_off[done]), int(gpu_off[done + q.shape[0]])
+        goff = gpu_off[done:done + q.shape[0] + 1] - g0
+        if not (np.array_equal(goff, woff.astype(np.int64)) and
+                np.array_equal(gpu_ids[g0:g1].view(np.uint32), wids)):
+            mismatches += 1
+        done += q.shape[0]
+    return dict(value=done / spent, unit="queries/s", cores=1, kind="oracle",
+                sample=f"first {done} of the {queries.shape[0]} windows against the "
+                       f"{rects.shape[0]}-rectangle tree (fanout {args.fanout}), query phase only, "
+                       f"single thread; oracle STR build {build_s:.1f} s not included",
+                checked_queries=done, mismatching_chunks=mismatches)
+
+
+def join_leg(rt, args):
+    import rtgen
+    a, b = rtgen.c3_join(args.join_n)
+    ta, tb = rt.build_str(a, 32, "soa"), rt.build_str(b, 32, "soa")
+    p = rt.spatial_join(ta, tb)   # warm
+    times = []
+    for _ in range(args.join_reps):
+        t0 = time.perf_counter()
+        p = rt.spatial_join(ta, tb)
+        times.append(time.perf_counter() - t0)
+    ms = float(np.median(times)) * 1e3
+    return dict(workload=f"join_uniform{args.join_n}_x_clustered{args.join_n}_f32_soa", pairs=int(p.shape[0]),
+                ms=ms, pairs_per_s=p.shape[0] / (ms / 1e3),
+                note="synchronous call, includes per-level size reads and the copy of the sorted pairs to host")
+
+
+def batch_leg(rt, torch, args):
+    import rtgen
+    t0 = time.time()
+    inst = rtgen.c4_batch(ntrees=args.batch_trees, scale=args.batch_scale)
+    trees = []
+    for k, x in enumerate(inst):
+        trees.append(rt.build_str(x.rects, 32, "soa"))
+    build_s = time.time() - t0
+    b = rt.Batch(trees, [x.queries for x in inst])
+    nq = sum(x.queries.shape[0] for x in inst)
+    out = {}
+    for name, fn in (("batched_graph", b.run), ("plain_per_tree", b.run_plain)):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.batch_reps):
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        tot, flags = b.status()
+        assert flags == 0
+        out[name] = dict(ms=float(np.median(ts)) * 1e3, queries_per_s=nq / float(np.median(ts)), ids=tot)
+    out["speedup"] = out["plain_per_tree"]["ms"] / out["batched_graph"]["ms"]
+    out.update(workload=f"batch_{len(inst)}_trees_{sum(x.rects.shape[0] for x in inst)}_rects_{nq}_windows_f32_soa",
+               build_s=build_s)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=10_000_000)
+    ap.add_argument("--nq", type=int, default=1_000_000)
+    ap.add_argument("--fanout", type=int, default=32)
+    ap.add_argument("--layout", default="soa")
+    ap.add_argument("--legs", default="join,batch,cpu")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--join-n", type=int, default=2_000_000)
+    ap.add_argument("--join-reps", type=int, default=5)
+    ap.add_argument("--batch-trees", type=int, default=256)
+    ap.add_argument("--batch-scale", type=float, default=1.0)
+    ap.add_argument("--batch-reps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    import paper_2309_16913_amd as rt
+    import rtgen
+    ev = HipEvents()
+    legs = set(x for x in args.legs.split(",") if x)
+
+    log(f"[bench] generating {args.n} rectangles and {args.nq} windows")
+    rects = rtgen.c2_rects(args.n)
+    queries = rtgen.c2_queries(args.nq)
+    log("[bench] select leg")
+    s = select_leg(rt, torch, ev, args, rects, queries)
+    ms_step = s["wall"] / args.steps * 1e3
+    qps = args.nq / (s["wall"] / args.steps)
+    dom = "fill" if s["avg"]["fill"] >= s["avg"]["count"] else "count"
+    dom_bytes = s["bytes_fill"] if dom == "fill" else s["bytes_count"]
+    achieved = dom_bytes / (s["avg"][dom] / 1e3) / 1e9
+    src = source_hash("select.hip")
+    traffic = read_traffic(f"select_{dom}_c2_f{args.fanout}_{args.layout}", src)
+    result = {
+        "metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"select_mixed{args.n}_windows{args.nq}_f{args.fanout}_{args.layout}",
+                   "n_rects": args.n, "n_queries": args.nq, "fanout": args.fanout, "layout": args.layout,
+                   "selectivity": "loguniform[1e-6,1e-3]", "ids_out": s["cap"]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"select_kernel ({dom} pass)", "algorithmic_bytes_per_launch": dom_bytes},
+        "phases_ms": s["avg"],
+        "tree": {"height": s["info"].height, "nodes": s["info"].n_nodes,
+                 "device_bytes": s["info"].device_bytes, "build_s": s["build_s"]},
+        "visited": {"nodes": s["vn"], "entries": s["ve"]},
+        "legs": {},
+    }
+    if "cpu" in legs:
+        log("[bench] cpu baseline (oracle)")
+        goff = s["off"].cpu().numpy()
+        gids = s["ids"].cpu().numpy()
+        result["cpu_baseline"] = cpu_baseline(args, rects, queries, goff, gids)
+    del s
+    torch.cuda.empty_cache()
+    if "join" in legs:
+        log("[bench] join leg")
+        result["legs"]["join"] = join_leg(rt, args)
+    if "batch" in legs:
+        log("[bench] batch leg")
+        result["legs"]["batch"] = batch_leg(rt, torch, args)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,227 @@
+/*
+ * rt.h -- C ABI of the MI355X (gfx950) R-tree range-select and spatial-join
+ * library.
+ *
+ * The operations follow the problem statement of "SIMD-ified R-tree Query
+ * Processing and Optimization" (Rayhan and Aref): an in-memory 2D R-tree whose
+ * node holds up to F entries (MBR, ptr) with MBR = (low_x, low_y, high_x,
+ * high_y) (section 2.3); a range select that returns the objects whose MBR
+ * intersects a query rectangle (section 3); and an R-tree join that returns
+ * the intersecting pairs of two indexed relations by traversing both trees
+ * from their roots and following intersecting child pairs (section 4).
+ *
+ * Predicate.  An object r and a window (or an object of the other relation)
+ * s intersect iff
+ *     r.lx <= s.hx && s.lx <= r.hx && r.ly <= s.hy && s.ly <= r.hy
+ * with IEEE fp32 comparisons (exact; no arithmetic touches a coordinate on
+ * the result path).  Boundaries are closed: touching rectangles intersect.
+ *
+ * Conventions for every call:
+ *   - Rectangles are float32 rows of 4: (low_x, low_y, high_x, high_y).
+ *     Object id = row index (uint32), query id = row index.
+ *   - Sizes are element counts.  "host" pointers are ordinary CPU memory;
+ *     "device" pointers are HIP device memory of the tree's device.
+ *   - Return value: RT_OK (0) or a negative RT_E* code; on failure every
+ *     *out is set to NULL, nothing partial is returned, and rt_last_error()
+ *     holds a message.  No C++ exception crosses this interface.
+ *   - Inputs are borrowed for the duration of the call and never retained.
+ *   - Every object returned through **out is owned by the library and is
+ *     released with rt_free().
+ *   - A built tree is immutable; concurrent selects and joins on it are safe.
+ *     Calls without a stream argument are synchronous.
+ */
+#ifndef RT_MI355X_H
+#define RT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    RT_OK = 0,
+    RT_EINVAL = -1,   /* bad argument: NULL with n > 0, NaN, lx > hx or ly > hy,
+                         fanout not in 2..64, unknown layout, n >= 2^32,
+                         trees on different devices, buffer too small */
+    RT_ENOMEM = -2,   /* a host or device allocation failed, or an output
+                         buffer given by the caller is too small */
+    RT_EDEVICE = -3   /* a HIP runtime error, or an internal check in a kernel */
+};
+
+/* Node storage layouts (section 2.3).  AOS is layout D0: each entry's five
+ * fields contiguous.  SOA is layout D1: per node, arrays lx[F], ly[F], hx[F],
+ * hy[F], ptr[F].  D2 is layout D2: lo[2F] (x,y pairs), hi[2F], ptr[F].
+ * AUTO lets rt_build_str pick (SOA). */
+enum { RT_LAYOUT_AOS = 0, RT_LAYOUT_SOA = 1, RT_LAYOUT_AUTO = 2, RT_LAYOUT_D2 = 3 };
+
+typedef struct rt_tree rt_tree;   /* opaque; device-resident; immutable */
+
+/* Range-select result in CSR form: ids[offsets[q] .. offsets[q+1]) are the
+ * ids of every object intersecting query q, ascending, no duplicates. */
+typedef struct rt_ids {
+    uint64_t nq;
+    uint64_t *offsets;   /* nq + 1 entries, offsets[0] = 0 */
+    uint32_t *ids;       /* offsets[nq] entries */
+} rt_ids;
+
+/* Join result: every (a, b) with A[a] and B[b] intersecting, in
+ * lexicographic order, as pairs[2k] = a, pairs[2k+1] = b. */
+typedef struct rt_pairs {
+    uint64_t n;
+    uint32_t *pairs;     /* 2n entries */
+} rt_pairs;
+
+/* Tree facts (read by the byte model and the tests). */
+typedef struct rt_tree_info {
+    uint64_t n_objects;
+    uint64_t n_entries;      /* sum of node entry counts */
+    uint64_t device_bytes;   /* node storage on the device */
+    uint32_t n_nodes;
+    uint32_t height;         /* levels including the leaf level */
+    uint32_t fanout;
+    uint32_t layout;
+    uint32_t node_bytes;     /* stride of one node = 20 * fanout */
+    uint32_t first_leaf;     /* nodes are numbered root first; leaves last */
+    int32_t device;
+    uint32_t reserved;
+} rt_tree_info;
+
+/*
+ * Build a packed R-tree over n rectangles with Sort-Tile-Recursive bulk
+ * loading (the paper does not say how its trees are built) and upload it to
+ * the current HIP device.
+ *   rects   host, n*4 floats; NaN or lx > hx or ly > hy -> RT_EINVAL;
+ *           +-Inf allowed.  n = 0 gives an empty tree (one empty leaf).
+ *   fanout  maximum entries per node F, 2..64 (0 = 32).
+ *   layout  RT_LAYOUT_*.
+ *   out     receives the tree; free with rt_free.
+ */
+int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uint32_t layout,
+                 rt_tree **out);
+
+/* Same as rt_build_str with the rectangles already on the device (d_rects,
+ * n*4 floats on the current device); the whole build runs in HIP kernels on
+ * `stream` (hipStream_t, NULL = default stream) and the call returns after it
+ * has finished.  Validation of the rectangles is done on the device. */
+int rt_build_str_device(const float *d_rects, uint64_t n, uint32_t fanout, uint32_t layout,
+                        void *stream, rt_tree **out);
+
+/*
+ * Range select (section 3): for each of the nq host query windows, the ids of
+ * the intersecting objects.  queries: host, nq*4 floats (NaN, lx > hx or
+ * ly > hy -> RT_EINVAL; +-Inf allowed).  nq = 0 gives offsets = {0}.
+ */
+int rt_range_select(const rt_tree *t, const float *queries, uint64_t nq, rt_ids **out);
+
+/*
+ * R-tree spatial join (section 4): all intersecting (a, b), a from tree a's
+ * relation and b from tree b's.  Both trees must live on the same device.
+ */
+int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **out);
+
+/* Release an rt_tree, rt_ids or rt_pairs (and a tree's device memory).
+ * NULL is a no-op. */
+void rt_free(void *obj);
+
+/* ------------------------------------------------------------------------ */
+/* Device-pointer, stream-ordered range select (used for batching, serving   */
+/* and timing with inputs already resident in device memory).                */
+/* ------------------------------------------------------------------------ */
+
+/* Workspace bytes that rt_range_select_device needs for nq queries and an
+ * output capacity of ids_capacity ids. */
+uint64_t rt_select_workspace_bytes(uint64_t nq, uint64_t ids_capacity);
+
+/*
+ * Enqueue a complete range select on `stream` and return without waiting.
+ *   d_queries   device, nq*4 floats (not validated: the caller guarantees
+ *               no NaN and lx <= hx, ly <= hy)
+ *   d_offsets   device, nq+1 uint64 (written)
+ *   d_ids       device, ids_capacity uint32 (written only if the result fits)
+ *   d_work      device workspace of at least rt_select_workspace_bytes bytes
+ *   d_status    device, 2 uint64 written at the end: [0] = total ids,
+ *               [1] = flags (1: total > ids_capacity, d_ids left untouched
+ *               and the CSR is not valid; 2: internal error)
+ * Returns RT_EINVAL for bad sizes; kernel-side outcomes are in d_status.
+ */
+int rt_range_select_device(const rt_tree *t, const float *d_queries, uint64_t nq,
+                           uint64_t *d_offsets, uint32_t *d_ids, uint64_t ids_capacity,
+                           void *d_work, uint64_t work_bytes, uint64_t *d_status, void *stream);
+
+/* rt_range_select_device plus phase timing: events (hipEvent_t[5], created by
+ * the caller) are recorded on `stream` before the count pass, after it, after
+ * the scan, after the fill pass and after the segmented sort, so the caller can
+ * read each phase's duration with hipEventElapsedTime.  events may be NULL. */
+int rt_range_select_device_timed(const rt_tree *t, const float *d_queries, uint64_t nq,
+                                 uint64_t *d_offsets, uint32_t *d_ids, uint64_t ids_capacity,
+                                 void *d_work, uint64_t work_bytes, uint64_t *d_status,
+                                 void *stream, void *const *events);
+
+/* Count pass only: d_counts[q] = number of objects intersecting query q
+ * (device, nq uint32).  Used to size outputs before admitting work. */
+int rt_range_count_device(const rt_tree *t, const float *d_queries, uint64_t nq,
+                          uint32_t *d_counts, void *d_work, uint64_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Batched select over many independent trees in one persistent launch.      */
+/* ------------------------------------------------------------------------ */
+
+/* Host-side batch: trees[i] with queries[i] (host, nq[i]*4 floats) for
+ * i < ntrees; out[i] receives tree i's CSR (free each with rt_free).  All
+ * trees must be on the current device; they may differ in fanout and layout.
+ * The traversal of all trees runs as one persistent kernel per pass fed by a
+ * device work queue of (tree, query-chunk) items, replayed from a captured
+ * HIP graph. */
+int rt_range_select_batch(const rt_tree *const *trees, uint32_t ntrees,
+                          const float *const *queries, const uint64_t *nq, rt_ids **out);
+
+typedef struct rt_batch rt_batch;   /* opaque prepared batch (device-resident) */
+
+/* Prepare a device-resident batch: copies the queries to the device, builds
+ * the work queue and captures the count -> scan -> fill -> sort launches
+ * into a HIP graph whose output pool holds ids_capacity ids.
+ * ids_capacity = 0 sizes the pool by running the count pass once. */
+int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees,
+                    const float *const *queries, const uint64_t *nq,
+                    uint64_t ids_capacity, rt_batch **out);
+/* Replay the captured graph on `stream` (asynchronous). */
+int rt_batch_run(rt_batch *b, void *stream);
+/* Same work as rt_batch_run without the graph or the persistent kernel: one
+ * plain launch sequence per tree, in order (the baseline it must beat). */
+int rt_batch_run_plain(rt_batch *b, void *stream);
+/* After a run has finished: total ids and the flags word (see d_status). */
+int rt_batch_status(rt_batch *b, uint64_t *total, uint64_t *flags);
+/* Copy tree i's CSR to the host. */
+int rt_batch_result(rt_batch *b, uint32_t i, rt_ids **out);
+
+/* ------------------------------------------------------------------------ */
+/* Introspection                                                             */
+/* ------------------------------------------------------------------------ */
+
+int rt_tree_stats(const rt_tree *t, rt_tree_info *info);
+
+/* Copy the tree to host arrays in a neutral node/entry form: per node
+ * (root = node 0) level (0 = leaf), entry count and index of its first entry;
+ * per entry the MBR and ptr (object id at a leaf, child node otherwise).
+ * Array lengths: n_nodes for level/count/first, n_entries for the rest. */
+int rt_tree_export(const rt_tree *t, uint32_t *level, uint32_t *count, uint64_t *first,
+                   float *lx, float *ly, float *hx, float *hy, uint32_t *ptr);
+
+/* Per-query traversal statistics for the byte model: visited nodes and
+ * visited entries summed over the nq host queries (same traversal as the
+ * select kernels). */
+int rt_select_visit_stats(const rt_tree *t, const float *queries, uint64_t nq,
+                          uint64_t *visited_nodes, uint64_t *visited_entries);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char *rt_last_error(void);
+
+/* Library version string. */
+const char *rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RT_MI355X_H */

@@ -1,0 +1,324 @@
+// Batched range select over many independent trees.
+//
+// rt_batch_create copies every instance's queries to the device, builds a
+// work queue of (tree, query-chunk) items ordered by estimated cost (largest
+// first, so the long items start early and the tail stays short), runs one
+// count pass to size the output pool, and captures the whole select -- zero
+// the counters, persistent count pass, scan, persistent fill pass, segmented
+// sort, status -- into one HIP graph.  rt_batch_run replays that graph.
+// rt_batch_run_plain does the same work as one launch sequence per tree, in
+// order, with no persistence and no graph: the baseline the batched form is
+// measured against.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "rt_api_internal.h"
+
+using namespace rtk;
+
+struct rt_batch {
+    int device = 0;
+    uint32_t ntrees = 0, nitems = 0, wave_words = 0;
+    uint64_t total_q = 0, cap = 0;
+    bool last_plain = false;
+    std::vector<const rt_tree *> trees;
+    std::vector<uint64_t> q_begin, nq, id_base, id_count, plain_begin;
+    void *d_trees = nullptr, *d_items = nullptr, *d_q = nullptr, *d_counts = nullptr, *d_off = nullptr;
+    void *d_ids = nullptr, *d_scratch = nullptr, *d_ctrl = nullptr, *d_scan = nullptr, *d_status = nullptr;
+    void *d_plain_off = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+void rtk::batch_release(rt_batch *b) {
+    if (!b) return;
+    DevSet ds(b->device);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    void *bufs[] = {b->d_trees, b->d_items, b->d_q,    b->d_counts, b->d_off,       b->d_ids,
+                    b->d_scratch, b->d_ctrl, b->d_scan, b->d_status, b->d_plain_off};
+    for (void *p : bufs)
+        if (p) (void)hipFree(p);
+    b->~rt_batch();
+}
+
+static hipError_t dmalloc(void **p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 16); }
+
+// Persistent count pass + scan over all instances' queries.
+static hipError_t enqueue_count_scan(rt_batch *b, hipStream_t s) {
+    Ctrl *ctrl = static_cast<Ctrl *>(b->d_ctrl);
+    hipError_t e = launch_zero(ctrl, sizeof(Ctrl), s);
+    if (e == hipSuccess)
+        e = launch_batch_pass(static_cast<BatchTree *>(b->d_trees), static_cast<BatchItem *>(b->d_items), b->nitems,
+                              static_cast<float4 *>(b->d_q), SEL_COUNT, static_cast<uint32_t *>(b->d_counts), nullptr,
+                              nullptr, 0, b->total_q, ctrl, 0, b->wave_words, s);
+    if (e == hipSuccess)
+        e = launch_scan_u32(static_cast<uint32_t *>(b->d_counts), b->total_q, static_cast<uint64_t *>(b->d_off),
+                            static_cast<uint64_t *>(b->d_scan), s);
+    return e;
+}
+
+static hipError_t enqueue_all(rt_batch *b, hipStream_t s) {
+    hipError_t e = enqueue_count_scan(b, s);
+    Ctrl *ctrl = static_cast<Ctrl *>(b->d_ctrl);
+    if (e == hipSuccess)
+        e = launch_batch_pass(static_cast<BatchTree *>(b->d_trees), static_cast<BatchItem *>(b->d_items), b->nitems,
+                              static_cast<float4 *>(b->d_q), SEL_FILL, static_cast<uint32_t *>(b->d_counts),
+                              static_cast<uint64_t *>(b->d_off), static_cast<uint32_t *>(b->d_ids), b->cap, b->total_q,
+                              ctrl, 1, b->wave_words, s);
+    if (e == hipSuccess)
+        e = launch_segsort(static_cast<uint64_t *>(b->d_off), b->total_q, static_cast<uint32_t *>(b->d_ids),
+                           static_cast<uint32_t *>(b->d_scratch), b->cap, ctrl, s);
+    if (e == hipSuccess)
+        e = launch_finalize(static_cast<uint64_t *>(b->d_off), b->total_q, b->cap, ctrl,
+                            static_cast<uint64_t *>(b->d_status), s);
+    return e;
+}
+
+extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, const float *const *queries,
+                               const uint64_t *nq, uint64_t ids_capacity, rt_batch **out) {
+    if (!out) return fail(RT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (ntrees && (!trees || !queries || !nq)) return fail(RT_EINVAL, "NULL argument");
+    try {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        uint64_t total = 0;
+        for (uint32_t i = 0; i < ntrees; ++i) {
+            if (!trees[i]) return fail(RT_EINVAL, "tree %u is NULL", i);
+            if (trees[i]->device != dev) return fail(RT_EINVAL, "tree %u is not on the current device", i);
+            if (int rc = check_rects(queries[i], nq[i], "queries")) return rc;
+            total += nq[i];
+        }
+        if (total > 0xFFF00000ull) return fail(RT_EINVAL, "too many queries");
+        void *mem = obj_alloc(KIND_BATCH, sizeof(rt_batch));
+        if (!mem) return fail(RT_ENOMEM, "host allocation failed");
+        rt_batch *b = new (mem) rt_batch();
+        auto bail = [&](int rc) {
+            rt_free(b);
+            return rc;
+        };
+        b->device = dev;
+        b->ntrees = ntrees;
+        b->total_q = total;
+        b->trees.assign(trees, trees + ntrees);
+        b->q_begin.resize(ntrees);
+        b->nq.assign(nq, nq + ntrees);
+        // descriptors and work items
+        std::vector<BatchTree> bt(ntrees);
+        struct Cand {
+            BatchItem it;
+            double cost;
+        };
+        std::vector<Cand> cand;
+        std::vector<float> hq((size_t)total * 4);
+        uint64_t qb = 0;
+        for (uint32_t i = 0; i < ntrees; ++i) {
+            const rt_tree *t = trees[i];
+            bt[i].t = view_of(t);
+            bt[i].q_begin = qb;
+            bt[i].nq = (uint32_t)nq[i];
+            bt[i].stack_cap = stack_bound(t->height, t->fanout);
+            b->q_begin[i] = qb;
+            const uint32_t G = group_width(t->fanout);
+            b->wave_words = std::max(b->wave_words, (64 / G) * bt[i].stack_cap);
+            if (nq[i]) std::memcpy(hq.data() + 4 * qb, queries[i], nq[i] * 16);
+            // chunks of 8 queries per group; cost ~ expected hits + per-query path length
+            const uint32_t chunk = 8 * (64 / G);
+            const double area_scale = (double)t->n_objects;
+            for (uint64_t q0 = 0; q0 < nq[i]; q0 += chunk) {
+                const uint64_t q1 = std::min<uint64_t>(nq[i], q0 + chunk);
+                double c = 0;
+                for (uint64_t k = q0; k < q1; ++k) {
+                    const float *w = queries[i] + 4 * k;
+                    double a = (double)(w[2] - w[0]) * (double)(w[3] - w[1]);
+                    if (!(a < 1.0)) a = 1.0;
+                    c += a * area_scale / t->fanout + t->height;
+                }
+                cand.push_back({BatchItem{i, (uint32_t)q0, (uint32_t)q1, 0u}, c});
+            }
+            qb += nq[i];
+        }
+        std::stable_sort(cand.begin(), cand.end(), [](const Cand &x, const Cand &y) { return x.cost > y.cost; });
+        std::vector<BatchItem> items(cand.size());
+        for (size_t k = 0; k < cand.size(); ++k) items[k] = cand[k].it;
+        b->nitems = (uint32_t)items.size();
+
+        hipError_t e = dmalloc(&b->d_trees, bt.size() * sizeof(BatchTree));
+        if (e == hipSuccess) e = dmalloc(&b->d_items, items.size() * sizeof(BatchItem));
+        if (e == hipSuccess) e = dmalloc(&b->d_q, total * 16);
+        if (e == hipSuccess) e = dmalloc(&b->d_counts, total * 4);
+        if (e == hipSuccess) e = dmalloc(&b->d_off, (total + 1) * 8);
+        if (e == hipSuccess) e = dmalloc(&b->d_ctrl, sizeof(Ctrl));
+        if (e == hipSuccess) e = dmalloc(&b->d_scan, scan_tmp_elems(std::max<uint64_t>(total, 1)) * 8);
+        if (e == hipSuccess) e = dmalloc(&b->d_status, 16);
+        uint64_t plain_total = 0;
+        b->plain_begin.resize(ntrees);
+        for (uint32_t i = 0; i < ntrees; ++i) {
+            b->plain_begin[i] = plain_total;
+            plain_total += nq[i] + 1;
+        }
+        if (e == hipSuccess) e = dmalloc(&b->d_plain_off, plain_total * 8);
+        if (e == hipSuccess) e = hipMemcpy(b->d_trees, bt.data(), bt.size() * sizeof(BatchTree), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !items.empty())
+            e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
+        if (e == hipSuccess && total) e = hipMemcpy(b->d_q, hq.data(), total * 16, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bail(hip_fail(e, "batch setup"));
+
+        // one eager count pass: output size and the per-instance bases
+        e = enqueue_count_scan(b, nullptr);
+        std::vector<uint64_t> off(total + 1);
+        if (e == hipSuccess) e = hipMemcpy(off.data(), b->d_off, (total + 1) * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return bail(hip_fail(e, "batch sizing"));
+        b->id_base.resize(ntrees);
+        b->id_count.resize(ntrees);
+        for (uint32_t i = 0; i < ntrees; ++i) {
+            b->id_base[i] = off[b->q_begin[i]];
+            b->id_count[i] = off[b->q_begin[i] + nq[i]] - off[b->q_begin[i]];
+        }
+        b->cap = ids_capacity ? ids_capacity : off[total];
+        e = dmalloc(&b->d_ids, b->cap * 4);
+        if (e == hipSuccess) e = dmalloc(&b->d_scratch, b->cap * 4);
+        if (e != hipSuccess) return bail(hip_fail(e, "batch output pool"));
+
+        // capture the whole select into a graph
+        hipStream_t cs = nullptr;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = enqueue_all(b, cs);
+            e = hipStreamEndCapture(cs, &b->graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (cs) (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) return bail(hip_fail(e, "batch graph capture"));
+        *out = b;
+        return RT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RT_EDEVICE, "unexpected failure");
+    }
+}
+
+extern "C" int rt_batch_run(rt_batch *b, void *stream) {
+    if (!b) return fail(RT_EINVAL, "batch is NULL");
+    DevSet ds(b->device);
+    b->last_plain = false;
+    hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? RT_OK : hip_fail(e, "graph launch");
+}
+
+extern "C" int rt_batch_run_plain(rt_batch *b, void *stream) {
+    if (!b) return fail(RT_EINVAL, "batch is NULL");
+    DevSet ds(b->device);
+    b->last_plain = true;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Ctrl *ctrl = static_cast<Ctrl *>(b->d_ctrl);
+    uint32_t *ids = static_cast<uint32_t *>(b->d_ids);
+    uint32_t *scratch = static_cast<uint32_t *>(b->d_scratch);
+    hipError_t e = launch_zero(ctrl, sizeof(Ctrl), s);
+    for (uint32_t i = 0; i < b->ntrees && e == hipSuccess; ++i) {
+        const uint64_t n = b->nq[i];
+        if (!n) continue;
+        const TreeView v = view_of(b->trees[i]);
+        const float4 *q = static_cast<float4 *>(b->d_q) + b->q_begin[i];
+        uint32_t *counts = static_cast<uint32_t *>(b->d_counts) + b->q_begin[i];
+        uint64_t *off = static_cast<uint64_t *>(b->d_plain_off) + b->plain_begin[i];
+        const uint64_t base = b->id_base[i], cnt = b->id_count[i];
+        const uint64_t cap = base < b->cap ? std::min<uint64_t>(cnt, b->cap - base) : 0;
+        e = launch_zero(ctrl->work, sizeof(ctrl->work), s);
+        if (e == hipSuccess) e = launch_select_pass(v, q, (uint32_t)n, SEL_COUNT, counts, nullptr, nullptr, 0, ctrl, 0, s);
+        if (e == hipSuccess) e = launch_scan_u32(counts, n, off, static_cast<uint64_t *>(b->d_scan), s);
+        if (e == hipSuccess)
+            e = launch_select_pass(v, q, (uint32_t)n, SEL_FILL, counts, off, ids + base, cap, ctrl, 1, s);
+        if (e == hipSuccess) e = launch_segsort(off, n, ids + base, scratch + base, cap, ctrl, s);
+    }
+    return e == hipSuccess ? RT_OK : hip_fail(e, "plain batch launches");
+}
+
+extern "C" int rt_batch_status(rt_batch *b, uint64_t *total, uint64_t *flags) {
+    if (!b || !total || !flags) return fail(RT_EINVAL, "NULL argument");
+    DevSet ds(b->device);
+    hipError_t e = hipDeviceSynchronize();
+    if (b->last_plain) {
+        Ctrl hc;
+        if (e == hipSuccess) e = hipMemcpy(&hc, b->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "batch status");
+        uint64_t t = 0;
+        for (uint32_t i = 0; i < b->ntrees; ++i) t += b->id_count[i];
+        *total = t;
+        *flags = (hc.err ? 2u : 0u) | (t > b->cap ? 1u : 0u);
+        return RT_OK;
+    }
+    uint64_t st[2] = {0, 0};
+    if (e == hipSuccess) e = hipMemcpy(st, b->d_status, 16, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "batch status");
+    *total = st[0];
+    *flags = st[1];
+    return RT_OK;
+}
+
+extern "C" int rt_batch_result(rt_batch *b, uint32_t i, rt_ids **out) {
+    if (!out) return fail(RT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!b || i >= b->ntrees) return fail(RT_EINVAL, "bad batch or index");
+    try {
+        DevSet ds(b->device);
+        hipError_t e = hipDeviceSynchronize();
+        const uint64_t n = b->nq[i];
+        std::vector<uint64_t> off(n + 1);
+        if (e == hipSuccess) {
+            if (b->last_plain)
+                e = hipMemcpy(off.data(), static_cast<uint64_t *>(b->d_plain_off) + b->plain_begin[i], (n + 1) * 8,
+                              hipMemcpyDeviceToHost);
+            else
+                e = hipMemcpy(off.data(), static_cast<uint64_t *>(b->d_off) + b->q_begin[i], (n + 1) * 8,
+                              hipMemcpyDeviceToHost);
+        }
+        if (e != hipSuccess) return hip_fail(e, "batch result");
+        const uint64_t base = b->last_plain ? 0 : off[0];
+        const uint64_t cnt = off[n] - off[0];
+        const uint64_t at = b->last_plain ? b->id_base[i] : off[0];
+        if (at + cnt > b->cap) return fail(RT_ENOMEM, "result exceeded the output pool");
+        rt_ids *r = nullptr;
+        if (int rc = make_ids(n, cnt, &r)) return rc;
+        for (uint64_t k = 0; k <= n; ++k) r->offsets[k] = off[k] - base;
+        if (cnt) e = hipMemcpy(r->ids, static_cast<uint32_t *>(b->d_ids) + at, cnt * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            rt_free(r);
+            return hip_fail(e, "batch result");
+        }
+        *out = r;
+        return RT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ENOMEM, "host allocation failed");
+    }
+}
+
+extern "C" int rt_range_select_batch(const rt_tree *const *trees, uint32_t ntrees, const float *const *queries,
+                                     const uint64_t *nq, rt_ids **out) {
+    if (!out) return fail(RT_EINVAL, "out is NULL");
+    for (uint32_t i = 0; i < ntrees; ++i) out[i] = nullptr;
+    rt_batch *b = nullptr;
+    if (int rc = rt_batch_create(trees, ntrees, queries, nq, 0, &b)) return rc;
+    int rc = rt_batch_run(b, nullptr);
+    uint64_t total = 0, flags = 0;
+    if (!rc) rc = rt_batch_status(b, &total, &flags);
+    if (!rc && flags) rc = fail(flags & 1 ? RT_ENOMEM : RT_EDEVICE, "batch kernels reported flags %llu",
+                                (unsigned long long)flags);
+    for (uint32_t i = 0; i < ntrees && !rc; ++i) rc = rt_batch_result(b, i, &out[i]);
+    if (rc)
+        for (uint32_t i = 0; i < ntrees; ++i) {
+            rt_free(out[i]);
+            out[i] = nullptr;
+        }
+    rt_free(b);
+    return rc;
+}

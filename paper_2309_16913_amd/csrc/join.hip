@@ -1,0 +1,184 @@
+// R-tree join kernels for gfx950: synchronized traversal of two trees.
+//
+// The paper's join (section 4) starts at both roots and follows every pair of
+// intersecting children.  Its vectorized "one to many" form broadcasts one
+// outer child MBR and compares it with all inner children at once (section
+// 4.1, steps 1-3), then compress-stores the qualifying inner addresses and
+// duplicates the outer address beside them (step 4).
+//
+// On the GPU the pairs of one tree level form a frontier that is processed
+// level by level, one wave per node pair.  The wave covers the Fa x Fb tile of
+// child pairs 64 at a time: lane l of round r tests outer child i and inner
+// child j with r*64 + l = i*Fb + j, so each round compares (64/Fb) outer
+// children against all inner children -- the one-to-many comparison, widened
+// from one broadcast outer MBR to several.  Qualifying pairs are compacted
+// with __ballot + popcount ranks into the next frontier (count pass, scan,
+// fill pass) or, at the leaf level, written out as 64-bit (idA << 32 | idB)
+// keys.
+//
+// Trees of unequal height: only the deeper side descends, with each of its
+// children tested against the MBR of the whole shallower tree, until both
+// sides are at the same level (this can only happen at the roots).
+#include "rt_internal.h"
+
+namespace rtk {
+
+__device__ __forceinline__ void load_any(const TreeView &t, uint32_t node, uint32_t e, float &lx, float &ly,
+                                         float &hx, float &hy) {
+    const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
+    const uint32_t F = t.fanout;
+    if (t.layout == LAYOUT_SOA) {
+        const float *f = reinterpret_cast<const float *>(nb);
+        lx = f[e];
+        ly = f[F + e];
+        hx = f[2 * F + e];
+        hy = f[3 * F + e];
+    } else if (t.layout == LAYOUT_AOS) {
+        const float *f = reinterpret_cast<const float *>(nb) + 5 * e;
+        lx = f[0];
+        ly = f[1];
+        hx = f[2];
+        hy = f[3];
+    } else {
+        const float2 *lo = reinterpret_cast<const float2 *>(nb);
+        const float2 a = lo[e], b = lo[F + e];
+        lx = a.x;
+        ly = a.y;
+        hx = b.x;
+        hy = b.y;
+    }
+}
+
+__device__ __forceinline__ uint32_t ptr_any(const TreeView &t, uint32_t node, uint32_t e) {
+    const uint32_t *u = reinterpret_cast<const uint32_t *>(t.nodes + (size_t)node * t.node_bytes);
+    return t.layout == LAYOUT_AOS ? u[5 * e + 4] : u[4 * t.fanout + e];
+}
+
+// One wave per frontier pair; 4 pairs per block.
+template <int MODE, bool FILL>
+__global__ void __launch_bounds__(256)
+join_level_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t nfr,
+                  uint32_t *__restrict__ counts, const uint64_t *__restrict__ offsets,
+                  uint2 *__restrict__ next, uint64_t *__restrict__ keys, Ctrl *__restrict__ ctrl) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= nfr) return;   // whole wave leaves together
+    const uint2 pr = fr[p];
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t pos = 0, end = 0;
+    if (FILL) {
+        pos = offsets[p];
+        end = offsets[p + 1];
+    }
+    uint32_t total = 0;
+
+    if constexpr (MODE == JOIN_DESC_A || MODE == JOIN_DESC_B) {
+        // Deeper side descends; each child is tested against the shallower
+        // tree's MBR.  One round covers a node (F <= 64).
+        const TreeView &D = (MODE == JOIN_DESC_A) ? A : B;
+        const TreeView &S = (MODE == JOIN_DESC_A) ? B : A;
+        const uint32_t node = (MODE == JOIN_DESC_A) ? pr.x : pr.y;
+        bool hit = false;
+        if (lane < D.fanout) {
+            float lx, ly, hx, hy;
+            load_any(D, node, lane, lx, ly, hx, hy);
+            hit = (lx <= S.mbr[2]) && (S.mbr[0] <= hx) && (ly <= S.mbr[3]) && (S.mbr[1] <= hy);
+        }
+        const uint64_t m = __ballot(hit);
+        total = (uint32_t)__popcll(m);
+        if (FILL && hit) {
+            const uint64_t o = pos + (uint64_t)__popcll(m & below);
+            const uint32_t c = ptr_any(D, node, lane);
+            if (o < end)
+                next[o] = (MODE == JOIN_DESC_A) ? make_uint2(c, pr.y) : make_uint2(pr.x, c);
+            else
+                atomicOr(&ctrl->err, kErrBounds);
+        }
+    } else {
+        const uint32_t Fa = A.fanout, Fb = B.fanout;
+        const uint32_t tile = Fa * Fb;
+        // lane's (i, j) for round 0 and the per-round advance
+        uint32_t i = lane / Fb, j = lane % Fb;
+        const uint32_t di = 64 / Fb, dj = 64 % Fb;
+        for (uint32_t base = 0; base < tile; base += 64) {
+            const bool in = base + lane < tile;
+            bool hit = false;
+            if (in) {
+                float alx, aly, ahx, ahy, blx, bly, bhx, bhy;
+                load_any(A, pr.x, i, alx, aly, ahx, ahy);
+                load_any(B, pr.y, j, blx, bly, bhx, bhy);
+                hit = (alx <= bhx) && (blx <= ahx) && (aly <= bhy) && (bly <= ahy);
+            }
+            const uint64_t m = __ballot(hit);
+            const uint32_t n = (uint32_t)__popcll(m);
+            if (FILL && hit) {
+                const uint64_t o = pos + total + (uint64_t)__popcll(m & below);
+                const uint32_t ca = ptr_any(A, pr.x, i), cb = ptr_any(B, pr.y, j);
+                if (o < end) {
+                    if (MODE == JOIN_EMIT)
+                        keys[o] = ((uint64_t)ca << 32) | cb;
+                    else
+                        next[o] = make_uint2(ca, cb);
+                } else {
+                    atomicOr(&ctrl->err, kErrBounds);
+                }
+            }
+            total += n;
+            i += di;
+            j += dj;
+            if (j >= Fb) {
+                j -= Fb;
+                i += 1;
+            }
+        }
+    }
+    if (!FILL && lane == 0) counts[p] = total;
+}
+
+template <int MODE>
+static hipError_t launch_mode(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr, bool fill,
+                              uint32_t *counts, const uint64_t *offsets, uint2 *next, uint64_t *keys,
+                              Ctrl *ctrl, hipStream_t s) {
+    const uint32_t blocks = (nfr + 3) / 4;
+    if (fill)
+        hipLaunchKernelGGL((join_level_kernel<MODE, true>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr, counts,
+                           offsets, next, keys, ctrl);
+    else
+        hipLaunchKernelGGL((join_level_kernel<MODE, false>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr,
+                           counts, offsets, next, keys, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *frontier, uint32_t nfr,
+                             int mode, bool fill, uint32_t *counts, const uint64_t *offsets, uint2 *next,
+                             uint64_t *keys, Ctrl *ctrl, hipStream_t s) {
+    if (nfr == 0) return hipSuccess;
+    switch (mode) {
+    case JOIN_BOTH:
+        return launch_mode<JOIN_BOTH>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, s);
+    case JOIN_EMIT:
+        return launch_mode<JOIN_EMIT>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, s);
+    case JOIN_DESC_A:
+        return launch_mode<JOIN_DESC_A>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, s);
+    default:
+        return launch_mode<JOIN_DESC_B>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, s);
+    }
+}
+
+__global__ void keys_to_pairs_kernel(const uint64_t *__restrict__ keys, uint64_t n, uint32_t *__restrict__ pairs) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        pairs[2 * i] = (uint32_t)(k >> 32);
+        pairs[2 * i + 1] = (uint32_t)k;
+    }
+}
+
+hipError_t launch_keys_to_pairs(const uint64_t *keys, uint64_t n, uint32_t *pairs, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(keys_to_pairs_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, keys, n, pairs);
+    return hipGetLastError();
+}
+
+}  // namespace rtk

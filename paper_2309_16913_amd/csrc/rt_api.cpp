@@ -1,0 +1,555 @@
+// C-ABI entry points: validation, device memory, the launch sequences of a
+// range select and of a join, result copies, and the tagged rt_free.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rt.h"
+#include "rt_api_internal.h"
+#include "rt_internal.h"
+#include "str_pack.h"
+
+using namespace rtk;
+
+// ---------------------------------------------------------------------------
+// errors and tagged objects
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+int rtk::fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int rtk::hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? RT_ENOMEM : RT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char *rt_last_error(void) { return g_err.c_str(); }
+extern "C" const char *rt_version(void) { return "rt-mi355x 1.0 (gfx950)"; }
+
+void *rtk::obj_alloc(uint32_t kind, size_t bytes) {
+    void *raw = std::malloc(sizeof(ObjHdr) + bytes);
+    if (!raw) return nullptr;
+    ObjHdr *h = static_cast<ObjHdr *>(raw);
+    h->magic = kObjMagic;
+    h->kind = kind;
+    std::memset(h + 1, 0, bytes);
+    return h + 1;
+}
+
+static ObjHdr *hdr_of(void *obj) { return static_cast<ObjHdr *>(obj) - 1; }
+
+void rtk::tree_release(rt_tree *t) {
+    if (!t) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(t->device);
+    if (t->d_nodes) (void)hipFree(t->d_nodes);
+    if (t->d_meta) (void)hipFree(t->d_meta);
+    (void)hipSetDevice(cur);
+    t->~rt_tree();
+}
+
+extern "C" void rt_free(void *obj) {
+    if (!obj) return;
+    ObjHdr *h = hdr_of(obj);
+    if (h->magic != kObjMagic) return;   // not ours: ignore rather than corrupt memory
+    h->magic = 0;
+    switch (h->kind) {
+    case KIND_TREE:
+        tree_release(static_cast<rt_tree *>(obj));
+        break;
+    case KIND_IDS: {
+        rt_ids *r = static_cast<rt_ids *>(obj);
+        std::free(r->offsets);
+        std::free(r->ids);
+        break;
+    }
+    case KIND_PAIRS:
+        std::free(static_cast<rt_pairs *>(obj)->pairs);
+        break;
+    case KIND_BATCH:
+        batch_release(static_cast<rt_batch *>(obj));
+        break;
+    default:
+        break;
+    }
+    std::free(h);
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+int rtk::check_rects(const float *r, uint64_t n, const char *what) {
+    if (n && !r) return fail(RT_EINVAL, "%s is NULL with n = %llu", what, (unsigned long long)n);
+    for (uint64_t i = 0; i < n; ++i) {
+        const float *p = r + 4 * i;
+        if (std::isnan(p[0]) || std::isnan(p[1]) || std::isnan(p[2]) || std::isnan(p[3]))
+            return fail(RT_EINVAL, "%s[%llu] has a NaN coordinate", what, (unsigned long long)i);
+        if (!(p[0] <= p[2]) || !(p[1] <= p[3]))
+            return fail(RT_EINVAL, "%s[%llu] has low > high", what, (unsigned long long)i);
+    }
+    return RT_OK;
+}
+
+TreeView rtk::view_of(const rt_tree *t) {
+    TreeView v;
+    v.nodes = static_cast<const uint8_t *>(t->d_nodes);
+    v.fanout = t->fanout;
+    v.node_bytes = t->node_bytes;
+    v.first_leaf = t->first_leaf;
+    v.height = t->height;
+    v.layout = t->layout;
+    v.pad = 0;
+    for (int i = 0; i < 4; ++i) v.mbr[i] = t->mbr[i];
+    return v;
+}
+
+DevBuf::~DevBuf() {
+    if (p) (void)hipFree(p);
+}
+hipError_t DevBuf::alloc(size_t bytes) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    return hipMalloc(&p, bytes ? bytes : 16);
+}
+
+static uint64_t align256(uint64_t b) { return (b + 255) & ~255ull; }
+
+// Workspace layout of a select: Ctrl | counts[nq] | scan tmp | sort scratch[cap]
+struct SelWs {
+    Ctrl *ctrl;
+    uint32_t *counts;
+    uint64_t *scan_tmp;
+    uint32_t *scratch;
+};
+
+static uint64_t sel_ws_bytes(uint64_t nq, uint64_t cap) {
+    return align256(sizeof(Ctrl)) + align256(4 * nq) + align256(8 * scan_tmp_elems(nq)) + align256(4 * cap);
+}
+
+static SelWs sel_ws(void *w, uint64_t nq) {
+    uint8_t *p = static_cast<uint8_t *>(w);
+    SelWs s;
+    s.ctrl = reinterpret_cast<Ctrl *>(p);
+    p += align256(sizeof(Ctrl));
+    s.counts = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * nq);
+    s.scan_tmp = reinterpret_cast<uint64_t *>(p);
+    p += align256(8 * scan_tmp_elems(nq));
+    s.scratch = reinterpret_cast<uint32_t *>(p);
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// build
+// ---------------------------------------------------------------------------
+int rtk::upload_packed(PackedTree &pt, rt_tree **out) {
+    void *mem = obj_alloc(KIND_TREE, sizeof(rt_tree));
+    if (!mem) return fail(RT_ENOMEM, "host allocation failed");
+    rt_tree *t = new (mem) rt_tree();
+    (void)hipGetDevice(&t->device);
+    t->fanout = pt.fanout;
+    t->layout = pt.layout;
+    t->height = pt.height;
+    t->n_nodes = pt.n_nodes;
+    t->first_leaf = pt.first_leaf;
+    t->node_bytes = pt.node_bytes;
+    t->n_objects = pt.n_objects;
+    t->n_entries = pt.n_entries;
+    for (int i = 0; i < 4; ++i) t->mbr[i] = pt.mbr[i];
+    hipError_t e = hipMalloc(&t->d_nodes, pt.bytes.size());
+    if (e == hipSuccess) e = hipMalloc(&t->d_meta, pt.meta.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(t->d_nodes, pt.bytes.data(), pt.bytes.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t->d_meta, pt.meta.data(), pt.meta.size() * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        tree_release(t);
+        std::free(hdr_of(t));
+        return hip_fail(e, "uploading the tree");
+    }
+    *out = t;
+    return RT_OK;
+}
+
+extern "C" int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uint32_t layout, rt_tree **out) {
+    if (!out) return fail(RT_EINVAL, "out is NULL");
+    *out = nullptr;
+    try {
+        if (fanout == 0) fanout = 32;
+        if (fanout < 2 || fanout > 64) return fail(RT_EINVAL, "fanout %u not in 2..64", fanout);
+        if (layout == RT_LAYOUT_AUTO) layout = RT_LAYOUT_SOA;
+        if (layout != RT_LAYOUT_AOS && layout != RT_LAYOUT_SOA && layout != RT_LAYOUT_D2)
+            return fail(RT_EINVAL, "unknown layout %u", layout);
+        if (n >= 0xFFFFFFFFull) return fail(RT_EINVAL, "n = %llu does not fit 32-bit ids", (unsigned long long)n);
+        int rc = check_rects(rects, n, "rects");
+        if (rc) return rc;
+        PackedTree pt;
+        if (str_pack(rects, n, fanout, layout, pt)) return fail(RT_EINVAL, "too many nodes");
+        return upload_packed(pt, out);
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RT_EDEVICE, "unexpected failure");
+    }
+}
+
+extern "C" int rt_tree_stats(const rt_tree *t, rt_tree_info *info) {
+    if (!t || !info) return fail(RT_EINVAL, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_objects = t->n_objects;
+    info->n_entries = t->n_entries;
+    info->device_bytes = (uint64_t)t->n_nodes * t->node_bytes;
+    info->n_nodes = t->n_nodes;
+    info->height = t->height;
+    info->fanout = t->fanout;
+    info->layout = t->layout;
+    info->node_bytes = t->node_bytes;
+    info->first_leaf = t->first_leaf;
+    info->device = t->device;
+    return RT_OK;
+}
+
+extern "C" int rt_tree_export(const rt_tree *t, uint32_t *level, uint32_t *count, uint64_t *first, float *lx,
+                              float *ly, float *hx, float *hy, uint32_t *ptr) {
+    if (!t || !level || !count || !first || !lx || !ly || !hx || !hy || !ptr) return fail(RT_EINVAL, "NULL argument");
+    try {
+        std::vector<uint8_t> img((size_t)t->n_nodes * t->node_bytes);
+        std::vector<uint32_t> meta(t->n_nodes);
+        DevSet ds(t->device);
+        hipError_t e = hipMemcpy(img.data(), t->d_nodes, img.size(), hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(meta.data(), t->d_meta, meta.size() * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "reading the tree back");
+        const uint32_t F = t->fanout;
+        uint64_t k = 0;
+        for (uint32_t u = 0; u < t->n_nodes; ++u) {
+            const uint32_t cnt = meta[u] & 0xFFu;
+            level[u] = meta[u] >> 8;
+            count[u] = cnt;
+            first[u] = k;
+            const uint8_t *node = img.data() + (size_t)u * t->node_bytes;
+            const float *f = reinterpret_cast<const float *>(node);
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(node);
+            for (uint32_t s = 0; s < cnt; ++s, ++k) {
+                if (t->layout == RT_LAYOUT_SOA) {
+                    lx[k] = f[s]; ly[k] = f[F + s]; hx[k] = f[2 * F + s]; hy[k] = f[3 * F + s]; ptr[k] = w[4 * F + s];
+                } else if (t->layout == RT_LAYOUT_AOS) {
+                    lx[k] = f[5 * s]; ly[k] = f[5 * s + 1]; hx[k] = f[5 * s + 2]; hy[k] = f[5 * s + 3]; ptr[k] = w[5 * s + 4];
+                } else {
+                    lx[k] = f[2 * s]; ly[k] = f[2 * s + 1]; hx[k] = f[2 * F + 2 * s]; hy[k] = f[2 * F + 2 * s + 1];
+                    ptr[k] = w[4 * F + s];
+                }
+            }
+            // unused slots must be NaN padding, or the kernels would see them
+            for (uint32_t s = cnt; s < F; ++s) {
+                float v = t->layout == RT_LAYOUT_SOA ? f[s] : (t->layout == RT_LAYOUT_AOS ? f[5 * s] : f[2 * s]);
+                if (!std::isnan(v)) return fail(RT_EDEVICE, "node %u slot %u is not padding", u, s);
+            }
+        }
+        if (k != t->n_entries) return fail(RT_EDEVICE, "entry count mismatch");
+        return RT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ENOMEM, "host allocation failed");
+    }
+}
+
+// ---------------------------------------------------------------------------
+// range select
+// ---------------------------------------------------------------------------
+extern "C" uint64_t rt_select_workspace_bytes(uint64_t nq, uint64_t cap) { return sel_ws_bytes(nq, cap); }
+
+static int check_nq(uint64_t nq) {
+    if (nq > 0xFFF00000ull) return fail(RT_EINVAL, "nq = %llu too large", (unsigned long long)nq);
+    return RT_OK;
+}
+
+int rtk::enqueue_select(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
+                        uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, bool count_only,
+                        uint32_t *d_counts_out, void *const *events) {
+    SelWs w = sel_ws(work, nq);
+    const TreeView v = view_of(t);
+    uint32_t *counts = d_counts_out ? d_counts_out : w.counts;
+    auto mark = [&](int k) -> hipError_t {
+        return events && events[k] ? hipEventRecord(static_cast<hipEvent_t>(events[k]), s) : hipSuccess;
+    };
+    hipError_t e = launch_zero(w.ctrl, sizeof(Ctrl), s);
+    if (e == hipSuccess) e = mark(0);
+    if (e == hipSuccess)
+        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_COUNT, counts, nullptr, nullptr, 0, w.ctrl, 0, s);
+    if (e == hipSuccess) e = mark(1);
+    if (count_only || e != hipSuccess) return e == hipSuccess ? RT_OK : hip_fail(e, "count pass");
+    e = launch_scan_u32(counts, nq, d_off, w.scan_tmp, s);
+    if (e == hipSuccess) e = mark(2);
+    if (e == hipSuccess)
+        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_FILL, counts, d_off, d_ids, cap, w.ctrl, 1, s);
+    if (e == hipSuccess) e = mark(3);
+    if (e == hipSuccess) e = launch_segsort(d_off, nq, d_ids, w.scratch, cap, w.ctrl, s);
+    if (e == hipSuccess) e = mark(4);
+    if (e == hipSuccess && d_status) e = launch_finalize(d_off, nq, cap, w.ctrl, d_status, s);
+    return e == hipSuccess ? RT_OK : hip_fail(e, "select launch");
+}
+
+extern "C" int rt_range_select_device_timed(const rt_tree *t, const float *d_queries, uint64_t nq,
+                                            uint64_t *d_offsets, uint32_t *d_ids, uint64_t cap, void *d_work,
+                                            uint64_t work_bytes, uint64_t *d_status, void *stream,
+                                            void *const *events) {
+    if (!t || (nq && !d_queries) || !d_offsets || !d_work || !d_status || (cap && !d_ids))
+        return fail(RT_EINVAL, "NULL argument");
+    if (int rc = check_nq(nq)) return rc;
+    if (work_bytes < sel_ws_bytes(nq, cap)) return fail(RT_EINVAL, "workspace too small");
+    if ((reinterpret_cast<uintptr_t>(d_queries) & 15) != 0) return fail(RT_EINVAL, "queries not 16-byte aligned");
+    DevSet ds(t->device);
+    return enqueue_select(t, reinterpret_cast<const float4 *>(d_queries), nq, d_offsets, d_ids, cap, d_work,
+                          d_status, static_cast<hipStream_t>(stream), false, nullptr, events);
+}
+
+extern "C" int rt_range_select_device(const rt_tree *t, const float *d_queries, uint64_t nq, uint64_t *d_offsets,
+                                      uint32_t *d_ids, uint64_t cap, void *d_work, uint64_t work_bytes,
+                                      uint64_t *d_status, void *stream) {
+    return rt_range_select_device_timed(t, d_queries, nq, d_offsets, d_ids, cap, d_work, work_bytes, d_status,
+                                        stream, nullptr);
+}
+
+extern "C" int rt_range_count_device(const rt_tree *t, const float *d_queries, uint64_t nq, uint32_t *d_counts,
+                                     void *d_work, uint64_t work_bytes, void *stream) {
+    if (!t || (nq && !d_queries) || !d_counts || !d_work) return fail(RT_EINVAL, "NULL argument");
+    if (int rc = check_nq(nq)) return rc;
+    if (work_bytes < sel_ws_bytes(nq, 0)) return fail(RT_EINVAL, "workspace too small");
+    if ((reinterpret_cast<uintptr_t>(d_queries) & 15) != 0) return fail(RT_EINVAL, "queries not 16-byte aligned");
+    DevSet ds(t->device);
+    return enqueue_select(t, reinterpret_cast<const float4 *>(d_queries), nq, nullptr, nullptr, 0, d_work, nullptr,
+                          static_cast<hipStream_t>(stream), true, d_counts, nullptr);
+}
+
+int rtk::make_ids(uint64_t nq, uint64_t total, rt_ids **out) {
+    void *mem = obj_alloc(KIND_IDS, sizeof(rt_ids));
+    if (!mem) return fail(RT_ENOMEM, "host allocation failed");
+    rt_ids *r = static_cast<rt_ids *>(mem);
+    r->nq = nq;
+    r->offsets = static_cast<uint64_t *>(std::malloc((nq + 1) * 8));
+    r->ids = static_cast<uint32_t *>(std::malloc(total ? total * 4 : 4));
+    if (!r->offsets || !r->ids) {
+        rt_free(r);
+        return fail(RT_ENOMEM, "host allocation failed");
+    }
+    r->offsets[0] = 0;
+    *out = r;
+    return RT_OK;
+}
+
+extern "C" int rt_range_select(const rt_tree *t, const float *queries, uint64_t nq, rt_ids **out) {
+    if (!out) return fail(RT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!t) return fail(RT_EINVAL, "tree is NULL");
+    try {
+        if (int rc = check_nq(nq)) return rc;
+        if (int rc = check_rects(queries, nq, "queries")) return rc;
+        DevSet ds(t->device);
+        if (nq == 0) return make_ids(0, 0, out);
+        DevBuf dq, doff, work, dids;
+        hipError_t e = dq.alloc(nq * 16);
+        if (e == hipSuccess) e = doff.alloc((nq + 1) * 8);
+        if (e == hipSuccess) e = work.alloc(sel_ws_bytes(nq, 0));
+        if (e == hipSuccess) e = hipMemcpy(dq.p, queries, nq * 16, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "select setup");
+        // count pass + scan, then size the output exactly
+        SelWs w = sel_ws(work.p, nq);
+        const TreeView v = view_of(t);
+        hipStream_t s = nullptr;
+        e = launch_zero(w.ctrl, sizeof(Ctrl), s);
+        if (e == hipSuccess)
+            e = launch_select_pass(v, static_cast<const float4 *>(dq.p), (uint32_t)nq, SEL_COUNT, w.counts, nullptr,
+                                   nullptr, 0, w.ctrl, 0, s);
+        if (e == hipSuccess) e = launch_scan_u32(w.counts, nq, static_cast<uint64_t *>(doff.p), w.scan_tmp, s);
+        uint64_t total = 0;
+        if (e == hipSuccess)
+            e = hipMemcpy(&total, static_cast<uint64_t *>(doff.p) + nq, 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "count pass");
+        DevBuf scratch;
+        e = dids.alloc(total * 4);
+        if (e == hipSuccess) e = scratch.alloc(total * 4);
+        if (e != hipSuccess) return hip_fail(e, "allocating the result");
+        e = launch_select_pass(v, static_cast<const float4 *>(dq.p), (uint32_t)nq, SEL_FILL, w.counts,
+                               static_cast<uint64_t *>(doff.p), static_cast<uint32_t *>(dids.p), total, w.ctrl, 1, s);
+        if (e == hipSuccess)
+            e = launch_segsort(static_cast<uint64_t *>(doff.p), nq, static_cast<uint32_t *>(dids.p),
+                               static_cast<uint32_t *>(scratch.p), total, w.ctrl, s);
+        Ctrl hc;
+        if (e == hipSuccess) e = hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "fill pass");
+        if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
+        rt_ids *r = nullptr;
+        if (int rc = make_ids(nq, total, &r)) return rc;
+        e = hipMemcpy(r->offsets, doff.p, (nq + 1) * 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && total) e = hipMemcpy(r->ids, dids.p, total * 4, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            rt_free(r);
+            return hip_fail(e, "copying the result");
+        }
+        *out = r;
+        return RT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RT_EDEVICE, "unexpected failure");
+    }
+}
+
+extern "C" int rt_select_visit_stats(const rt_tree *t, const float *queries, uint64_t nq, uint64_t *vnodes,
+                                     uint64_t *ventries) {
+    if (!t || !vnodes || !ventries) return fail(RT_EINVAL, "NULL argument");
+    *vnodes = *ventries = 0;
+    if (int rc = check_nq(nq)) return rc;
+    if (int rc = check_rects(queries, nq, "queries")) return rc;
+    if (nq == 0) return RT_OK;
+    DevSet ds(t->device);
+    DevBuf dq, work;
+    hipError_t e = dq.alloc(nq * 16);
+    if (e == hipSuccess) e = work.alloc(sel_ws_bytes(nq, 0));
+    if (e == hipSuccess) e = hipMemcpy(dq.p, queries, nq * 16, hipMemcpyHostToDevice);
+    SelWs w = sel_ws(work.p, nq);
+    if (e == hipSuccess) e = launch_zero(w.ctrl, sizeof(Ctrl), nullptr);
+    if (e == hipSuccess)
+        e = launch_select_pass(view_of(t), static_cast<const float4 *>(dq.p), (uint32_t)nq, SEL_STATS, w.counts,
+                               nullptr, nullptr, 0, w.ctrl, 2, nullptr);
+    Ctrl hc;
+    if (e == hipSuccess) e = hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "visit statistics");
+    if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
+    *vnodes = hc.stats[0];
+    *ventries = hc.stats[1];
+    return RT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// spatial join
+// ---------------------------------------------------------------------------
+static int bits_for(uint64_t maxval) {
+    int b = 0;
+    while (b < 64 && (maxval >> b)) ++b;
+    return b;
+}
+
+extern "C" int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **out) {
+    if (!out) return fail(RT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!a || !b) return fail(RT_EINVAL, "tree is NULL");
+    if (a->device != b->device) return fail(RT_EINVAL, "trees are on different devices");
+    try {
+        DevSet ds(a->device);
+        hipStream_t s = nullptr;
+        const TreeView va = view_of(a), vb = view_of(b);
+        DevBuf ctrl_b, fr, cnt, off, tmp, keys;
+        hipError_t e = ctrl_b.alloc(sizeof(Ctrl));
+        if (e == hipSuccess) e = fr.alloc(8);
+        if (e != hipSuccess) return hip_fail(e, "join setup");
+        Ctrl *ctrl = static_cast<Ctrl *>(ctrl_b.p);
+        e = launch_zero(ctrl, sizeof(Ctrl), s);
+        const uint32_t roots[2] = {0u, 0u};
+        if (e == hipSuccess) e = hipMemcpy(fr.p, roots, 8, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "join setup");
+        uint64_t nfr = (a->n_objects && b->n_objects) ? 1 : 0;
+        int la = (int)a->height - 1, lb = (int)b->height - 1;
+        uint64_t npairs = 0;
+        bool in_tmp = false;
+        DevBuf ktmp, hist, hscan, stmp;
+        while (nfr) {
+            int mode = la > lb ? JOIN_DESC_A : (lb > la ? JOIN_DESC_B : (la == 0 ? JOIN_EMIT : JOIN_BOTH));
+            e = cnt.alloc(nfr * 4);
+            if (e == hipSuccess) e = off.alloc((nfr + 1) * 8);
+            if (e == hipSuccess) e = tmp.alloc(scan_tmp_elems(nfr) * 8);
+            if (e != hipSuccess) return hip_fail(e, "join frontier");
+            e = launch_join_level(va, vb, static_cast<uint2 *>(fr.p), (uint32_t)nfr, mode, false,
+                                  static_cast<uint32_t *>(cnt.p), nullptr, nullptr, nullptr, ctrl, s);
+            if (e == hipSuccess)
+                e = launch_scan_u32(static_cast<uint32_t *>(cnt.p), nfr, static_cast<uint64_t *>(off.p),
+                                    static_cast<uint64_t *>(tmp.p), s);
+            uint64_t total = 0;
+            if (e == hipSuccess) e = hipMemcpy(&total, static_cast<uint64_t *>(off.p) + nfr, 8, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "join count");
+            if (total == 0) {
+                nfr = 0;
+                break;
+            }
+            if (mode == JOIN_EMIT) {
+                e = keys.alloc(total * 8);
+                if (e == hipSuccess)
+                    e = launch_join_level(va, vb, static_cast<uint2 *>(fr.p), (uint32_t)nfr, mode, true, nullptr,
+                                          static_cast<uint64_t *>(off.p), nullptr, static_cast<uint64_t *>(keys.p),
+                                          ctrl, s);
+                if (e != hipSuccess) return hip_fail(e, "join emit");
+                npairs = total;
+                // canonical order: 64-bit (idA << 32 | idB) keys, sorting only the digits that can be nonzero
+                int shifts[16], np = 0;
+                const int bb = bits_for(b->n_objects ? b->n_objects - 1 : 0);
+                const int ba = bits_for(a->n_objects ? a->n_objects - 1 : 0);
+                for (int sft = 0; sft < bb; sft += 8) shifts[np++] = sft;
+                for (int sft = 32; sft < 32 + ba; sft += 8) shifts[np++] = sft;
+                const uint64_t he = radix_hist_elems(total);
+                e = ktmp.alloc(total * 8);
+                if (e == hipSuccess) e = hist.alloc(he * 4);
+                if (e == hipSuccess) e = hscan.alloc((he + 1) * 8);
+                if (e == hipSuccess) e = stmp.alloc(scan_tmp_elems(he) * 8);
+                if (e == hipSuccess)
+                    e = launch_radix_sort_u64(static_cast<uint64_t *>(keys.p), static_cast<uint64_t *>(ktmp.p), total,
+                                              shifts, np, static_cast<uint32_t *>(hist.p),
+                                              static_cast<uint64_t *>(hscan.p), static_cast<uint64_t *>(stmp.p),
+                                              &in_tmp, s);
+                if (e != hipSuccess) return hip_fail(e, "join sort");
+                break;
+            }
+            if (total >= 0xFFFFFFFFull) return fail(RT_ENOMEM, "join frontier too large");
+            DevBuf nxt;
+            e = nxt.alloc(total * 8);
+            if (e == hipSuccess)
+                e = launch_join_level(va, vb, static_cast<uint2 *>(fr.p), (uint32_t)nfr, mode, true, nullptr,
+                                      static_cast<uint64_t *>(off.p), static_cast<uint2 *>(nxt.p), nullptr, ctrl, s);
+            if (e != hipSuccess) return hip_fail(e, "join expand");
+            std::swap(fr.p, nxt.p);
+            nfr = total;
+            if (mode == JOIN_DESC_A) --la;
+            else if (mode == JOIN_DESC_B) --lb;
+            else { --la; --lb; }
+        }
+        Ctrl hc;
+        e = hipMemcpy(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "join status");
+        if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
+        void *mem = obj_alloc(KIND_PAIRS, sizeof(rt_pairs));
+        if (!mem) return fail(RT_ENOMEM, "host allocation failed");
+        rt_pairs *r = static_cast<rt_pairs *>(mem);
+        r->n = npairs;
+        r->pairs = static_cast<uint32_t *>(std::malloc(npairs ? npairs * 8 : 8));
+        if (!r->pairs) {
+            rt_free(r);
+            return fail(RT_ENOMEM, "host allocation failed");
+        }
+        if (npairs) {
+            DevBuf dp;
+            e = dp.alloc(npairs * 8);
+            const uint64_t *sorted = static_cast<const uint64_t *>(in_tmp ? ktmp.p : keys.p);
+            if (e == hipSuccess) e = launch_keys_to_pairs(sorted, npairs, static_cast<uint32_t *>(dp.p), s);
+            if (e == hipSuccess) e = hipMemcpy(r->pairs, dp.p, npairs * 8, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                rt_free(r);
+                return hip_fail(e, "copying the pairs");
+            }
+        }
+        *out = r;
+        return RT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RT_EDEVICE, "unexpected failure");
+    }
+}

@@ -1,0 +1,71 @@
+// Host-side internals shared by the C-ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/rt.h"
+#include "rt_internal.h"
+#include "str_pack.h"
+
+struct rt_tree {
+    int device = 0;
+    uint32_t fanout = 0, layout = 0, height = 0, n_nodes = 0, first_leaf = 0, node_bytes = 0;
+    uint64_t n_objects = 0, n_entries = 0;
+    float mbr[4] = {0, 0, 0, 0};
+    void *d_nodes = nullptr;   // n_nodes * node_bytes
+    void *d_meta = nullptr;    // n_nodes uint32: count | level << 8
+};
+
+namespace rtk {
+
+constexpr uint32_t kObjMagic = 0x52544f42u;   // "RTOB"
+enum : uint32_t { KIND_TREE = 1, KIND_IDS = 2, KIND_PAIRS = 3, KIND_BATCH = 4 };
+
+// Every object handed out through the ABI is preceded by this header so that
+// rt_free can tell what it is.
+struct alignas(16) ObjHdr {
+    uint32_t magic;
+    uint32_t kind;
+    uint64_t pad;
+};
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+void *obj_alloc(uint32_t kind, size_t bytes);
+void tree_release(rt_tree *t);
+void batch_release(rt_batch *b);
+int check_rects(const float *r, uint64_t n, const char *what);
+TreeView view_of(const rt_tree *t);
+int upload_packed(PackedTree &pt, rt_tree **out);
+int make_ids(uint64_t nq, uint64_t total, rt_ids **out);
+int enqueue_select(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
+                   uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, bool count_only,
+                   uint32_t *d_counts_out, void *const *events = nullptr);
+
+// Owning device buffer.
+struct DevBuf {
+    void *p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    hipError_t alloc(size_t bytes);
+};
+
+// Make a device current for a scope.
+struct DevSet {
+    int prev = 0;
+    explicit DevSet(int dev) {
+        (void)hipGetDevice(&prev);
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DevSet() {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace rtk

@@ -1,0 +1,115 @@
+// Internal declarations shared by the library's host code and HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace rtk {
+
+enum : uint32_t { LAYOUT_AOS = 0, LAYOUT_SOA = 1, LAYOUT_D2 = 3 };
+
+// A device tree as the kernels see it.  Nodes are numbered root first (node
+// 0), level by level, so every node with index >= first_leaf is a leaf.  A
+// node is 20*F bytes; unused entry slots of a partly filled node hold NaN
+// rectangles, which fail every comparison and so never qualify.
+struct TreeView {
+    const uint8_t *nodes;
+    uint32_t fanout;
+    uint32_t node_bytes;
+    uint32_t first_leaf;
+    uint32_t height;
+    uint32_t layout;
+    uint32_t pad;
+    float mbr[4];            // MBR of the whole tree (root node)
+};
+
+// Kernel-side status words at the start of every workspace.
+struct Ctrl {
+    uint32_t work[8];        // work-queue counters (one per pass)
+    uint32_t err;            // internal error flags
+    uint32_t pad[7];
+    uint64_t stats[4];       // visit statistics
+};
+
+constexpr uint32_t kErrStack = 1u;     // traversal stack would overflow
+constexpr uint32_t kErrBounds = 2u;    // an output write would fall outside its range
+constexpr uint32_t kErrInput = 4u;     // invalid rectangle found on the device
+
+constexpr uint32_t kSortTile = 4096;   // ids sorted in LDS by one block
+
+// Traversal stack bound for a depth-first walk that pops one node and pushes
+// its qualifying children: (h-1)(F-1)+1 entries.
+inline uint32_t stack_bound(uint32_t height, uint32_t fanout) {
+    return height <= 1 ? 1u : (height - 1) * (fanout - 1) + 1;
+}
+
+inline uint32_t group_width(uint32_t fanout) {
+    return fanout <= 16 ? 16u : (fanout <= 32 ? 32u : 64u);
+}
+
+// ---- select -------------------------------------------------------------
+enum SelectMode : int { SEL_COUNT = 0, SEL_FILL = 1, SEL_STATS = 2 };
+
+// One traversal pass over all queries (persistent grid, dynamic query queue).
+hipError_t launch_select_pass(const TreeView &t, const float4 *q, uint32_t nq, int mode,
+                              uint32_t *counts, const uint64_t *offsets, uint32_t *ids,
+                              uint64_t ids_capacity, Ctrl *ctrl, uint32_t work_slot,
+                              hipStream_t s);
+
+// ---- scan, sort ---------------------------------------------------------
+// Exclusive scan of n uint32 into n+1 uint64 (out[n] = total).  tmp needs
+// scan_tmp_elems(n) uint64.
+uint64_t scan_tmp_elems(uint64_t n);
+hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp,
+                           hipStream_t s);
+
+// Sort every CSR segment ascending.  scratch: ids_capacity uint32 (used for
+// segments longer than kSortTile).  Skips all work if offsets[nq] > capacity.
+hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch,
+                          uint64_t capacity, Ctrl *ctrl, hipStream_t s);
+
+// LSD radix sort of n uint64 keys over the listed 8-bit digit positions.
+// Result ends in keys (if even number of passes) or tmp; returns which via
+// *in_tmp.  hist needs radix_hist_elems(n) uint32, hscan radix_hist_elems+1
+// uint64 plus scan_tmp_elems of it.
+uint64_t radix_hist_elems(uint64_t n);
+hipError_t launch_radix_sort_u64(uint64_t *keys, uint64_t *tmp, uint64_t n, const int *shifts,
+                                 int npasses, uint32_t *hist, uint64_t *hscan, uint64_t *stmp,
+                                 bool *in_tmp, hipStream_t s);
+
+// Status finalizer: status[0] = offsets[nq], status[1] = flags.
+hipError_t launch_finalize(const uint64_t *offsets, uint64_t nq, uint64_t capacity,
+                           const Ctrl *ctrl, uint64_t *status, hipStream_t s);
+
+hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
+
+// ---- join ---------------------------------------------------------------
+enum JoinMode : int { JOIN_BOTH = 0, JOIN_EMIT = 1, JOIN_DESC_A = 2, JOIN_DESC_B = 3 };
+hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *frontier,
+                             uint32_t nfr, int mode, bool fill, uint32_t *counts,
+                             const uint64_t *offsets, uint2 *next, uint64_t *keys, Ctrl *ctrl,
+                             hipStream_t s);
+hipError_t launch_keys_to_pairs(const uint64_t *keys, uint64_t n, uint32_t *pairs, hipStream_t s);
+
+// ---- batch --------------------------------------------------------------
+struct BatchTree {
+    TreeView t;
+    uint64_t q_begin;        // first global query index of this tree
+    uint32_t nq;
+    uint32_t stack_cap;
+};
+struct BatchItem {           // a chunk of one tree's queries
+    uint32_t tree;
+    uint32_t q0, q1;         // local query range [q0, q1)
+    uint32_t pad;
+};
+hipError_t launch_batch_pass(const BatchTree *trees, const BatchItem *items, uint32_t nitems,
+                             const float4 *q, int mode, uint32_t *counts, const uint64_t *offsets,
+                             uint32_t *ids, uint64_t capacity, uint64_t total_q, Ctrl *ctrl,
+                             uint32_t work_slot, uint32_t wave_words, hipStream_t s);
+
+int num_cus();
+
+}  // namespace rtk

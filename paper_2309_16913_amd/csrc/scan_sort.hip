@@ -1,0 +1,365 @@
+// Prefix sums and sorts used to compact and canonicalize results.
+//
+//  * exclusive scan uint32 -> uint64 (counts -> CSR offsets), three kernels:
+//    per-tile sums, a scan of the tile sums, and the per-tile scan with the
+//    tile's base added;
+//  * segmented sort of the CSR id lists: a segment of up to kSortTile ids is
+//    sorted by one block in LDS (bitonic network); a longer segment is sorted
+//    by one block as a merge sort (LDS-sorted tiles, then merge-path merges
+//    between the id buffer and a scratch buffer);
+//  * LSD radix sort of uint64 keys with 8-bit digits (join pairs), stable
+//    per-tile ranking with wave ballots.
+#include "rt_internal.h"
+
+namespace rtk {
+
+// ---------------------------------------------------------------------------
+// wave / block scans
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t lo = __shfl_up((uint32_t)v, d);
+        uint32_t hi = __shfl_up((uint32_t)(v >> 32), d);
+        uint64_t o = ((uint64_t)hi << 32) | lo;
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan over the 256 threads of a block; returns the exclusive
+// prefix and writes the block total to *total.
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *total) {
+    __shared__ uint64_t wsum[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (i < w) base += wsum[i];
+        tot += wsum[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+constexpr uint32_t kScanPer = 8;                 // elements per thread
+constexpr uint32_t kScanTile = 256 * kScanPer;   // elements per block
+
+__global__ void __launch_bounds__(256) scan_tile_sums(const uint32_t *__restrict__ in, uint64_t n,
+                                                      uint64_t *__restrict__ sums) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanPer; ++k)
+        if (base + k < n) s += in[base + k];
+    uint64_t tot;
+    block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the tile sums in place
+__global__ void __launch_bounds__(256) scan_sums(uint64_t *__restrict__ sums, uint64_t nt) {
+    uint64_t carry = 0;
+    for (uint64_t b0 = 0; b0 < nt; b0 += 256) {
+        const uint64_t i = b0 + threadIdx.x;
+        uint64_t v = i < nt ? sums[i] : 0;
+        uint64_t tot;
+        uint64_t ex = block_excl_scan(v, &tot);
+        if (i < nt) sums[i] = carry + ex;
+        carry += tot;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) scan_tiles(const uint32_t *__restrict__ in, uint64_t n,
+                                                  const uint64_t *__restrict__ sums,
+                                                  uint64_t *__restrict__ out) {
+    const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint64_t s = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < kScanPer; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        s += v[k];
+    }
+    uint64_t tot;
+    uint64_t run = block_excl_scan(s, &tot) + sums[blockIdx.x];
+#pragma unroll
+    for (uint32_t k = 0; k < kScanPer; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) out[n] = sums[blockIdx.x] + tot;
+}
+
+__global__ void write_zero_total(uint64_t *out) { out[0] = 0; }
+
+uint64_t scan_tmp_elems(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp, hipStream_t s) {
+    if (n == 0) {
+        hipLaunchKernelGGL(write_zero_total, dim3(1), dim3(1), 0, s, out);
+        return hipGetLastError();
+    }
+    const uint64_t nt = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(scan_tile_sums, dim3((uint32_t)nt), dim3(256), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(256), 0, s, tmp, nt);
+    hipLaunchKernelGGL(scan_tiles, dim3((uint32_t)nt), dim3(256), 0, s, in, n, tmp, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// zero fill (used instead of a memset node so the launches can be captured)
+// ---------------------------------------------------------------------------
+__global__ void zero_kernel(uint32_t *p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s) {
+    const uint64_t n = bytes / 4;
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(zero_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, (uint32_t *)p, n);
+    return hipGetLastError();
+}
+
+__global__ void finalize_kernel(const uint64_t *offsets, uint64_t nq, uint64_t cap, const Ctrl *ctrl,
+                                uint64_t *status) {
+    const uint64_t tot = offsets[nq];
+    uint64_t flags = 0;
+    if (tot > cap) flags |= 1;
+    if (ctrl->err) flags |= 2;
+    status[0] = tot;
+    status[1] = flags;
+}
+
+hipError_t launch_finalize(const uint64_t *offsets, uint64_t nq, uint64_t cap, const Ctrl *ctrl,
+                           uint64_t *status, hipStream_t s) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1), 0, s, offsets, nq, cap, ctrl, status);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// segmented sort
+// ---------------------------------------------------------------------------
+
+// Bitonic sort of P (power of two) keys in LDS by 256 threads.
+__device__ void lds_bitonic(uint32_t *a, uint32_t P) {
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                // t-th compare-exchange: partner pair (i, i ^ j) with i having bit j clear
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const uint32_t l = i | j;
+                const uint32_t x = a[i], y = a[l];
+                const bool up = (i & k) == 0;
+                if ((x > y) == up) {
+                    a[i] = y;
+                    a[l] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t next_pow2(uint32_t v) {
+    uint32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Sort c <= kSortTile keys of src into dst (dst may equal src).
+__device__ void block_sort_tile(const uint32_t *src, uint32_t *dst, uint32_t c, uint32_t *lds) {
+    const uint32_t P = next_pow2(c < 2 ? 2 : c);
+    for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) lds[i] = i < c ? src[i] : 0xFFFFFFFFu;
+    __syncthreads();
+    lds_bitonic(lds, P);
+    for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) dst[i] = lds[i];
+    __syncthreads();
+}
+
+// Number of elements of a[0..la) that precede position d of the merged
+// sequence of a and b (keys are distinct within a segment, ties go to a).
+__device__ __forceinline__ uint64_t merge_path(const uint32_t *a, uint64_t la, const uint32_t *b,
+                                               uint64_t lb, uint64_t d) {
+    uint64_t lo = d > lb ? d - lb : 0;
+    uint64_t hi = d < la ? d : la;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        // take a[mid] before b[d-mid-1]?
+        if (a[mid] <= b[d - mid - 1])
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+constexpr uint32_t kMergePer = 16;   // outputs per thread per merge step
+
+__global__ void __launch_bounds__(256) segsort_kernel(const uint64_t *__restrict__ offsets, uint64_t nq,
+                                                      uint32_t *__restrict__ ids,
+                                                      uint32_t *__restrict__ scratch, uint64_t cap,
+                                                      Ctrl *__restrict__ ctrl) {
+    __shared__ uint32_t lds[kSortTile];
+    if (offsets[nq] > cap) return;
+    for (uint64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+        const uint64_t o = offsets[qi];
+        const uint64_t c = offsets[qi + 1] - o;
+        if (c < 2) continue;
+        uint32_t *seg = ids + o;
+        if (c <= kSortTile) {
+            block_sort_tile(seg, seg, (uint32_t)c, lds);
+            continue;
+        }
+        // long segment: sorted tiles, then pairwise merges
+        for (uint64_t t0 = 0; t0 < c; t0 += kSortTile) {
+            const uint32_t tc = (uint32_t)((c - t0) < kSortTile ? (c - t0) : kSortTile);
+            block_sort_tile(seg + t0, seg + t0, tc, lds);
+        }
+        uint32_t *src = seg, *dst = scratch + o;
+        for (uint64_t w = kSortTile; w < c; w <<= 1) {
+            for (uint64_t r0 = 0; r0 < c; r0 += 2 * w) {
+                const uint64_t la = (c - r0) < w ? (c - r0) : w;
+                const uint64_t rest = c - r0 - la;
+                const uint64_t lb = rest < w ? rest : w;
+                const uint32_t *a = src + r0, *b = src + r0 + la;
+                uint32_t *out = dst + r0;
+                const uint64_t tot = la + lb;
+                for (uint64_t d0 = (uint64_t)threadIdx.x * kMergePer; d0 < tot;
+                     d0 += (uint64_t)blockDim.x * kMergePer) {
+                    uint64_t ia = merge_path(a, la, b, lb, d0);
+                    uint64_t ib = d0 - ia;
+                    const uint64_t d1 = d0 + kMergePer < tot ? d0 + kMergePer : tot;
+                    for (uint64_t d = d0; d < d1; ++d) {
+                        const bool takea = ib >= lb || (ia < la && a[ia] <= b[ib]);
+                        out[d] = takea ? a[ia++] : b[ib++];
+                    }
+                }
+            }
+            __syncthreads();
+            uint32_t *tmp = src;
+            src = dst;
+            dst = tmp;
+        }
+        if (src != seg) {
+            for (uint64_t i = threadIdx.x; i < c; i += blockDim.x) seg[i] = src[i];
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch,
+                          uint64_t cap, Ctrl *ctrl, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    uint64_t blocks = nq < 65536 ? nq : 65536;
+    hipLaunchKernelGGL(segsort_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, offsets, nq, ids, scratch,
+                       cap, ctrl);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort of uint64 keys (8-bit digits)
+// ---------------------------------------------------------------------------
+constexpr uint32_t kRadixPer = 16;                    // keys per lane
+constexpr uint32_t kRadixWaveKeys = 64 * kRadixPer;   // 1024
+constexpr uint32_t kRadixTile = 4 * kRadixWaveKeys;   // 4096 per block
+
+uint64_t radix_hist_elems(uint64_t n) {
+    const uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
+    return nb * 256;
+}
+
+// hist[digit * nblocks + block]
+__global__ void __launch_bounds__(256) radix_hist(const uint64_t *__restrict__ keys, uint64_t n, int shift,
+                                                  uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
+    for (uint32_t k = threadIdx.x; k < kRadixTile; k += 256) {
+        const uint64_t i = base + k;
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) radix_scatter(const uint64_t *__restrict__ in, uint64_t n, int shift,
+                                                     const uint64_t *__restrict__ hscan,
+                                                     uint64_t *__restrict__ out) {
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint64_t dbase[256];
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    for (uint32_t d = threadIdx.x; d < 256; d += 256) {
+        for (int i = 0; i < 4; ++i) wcnt[i][d] = 0;
+        dbase[d] = hscan[(uint64_t)d * gridDim.x + blockIdx.x];
+    }
+    __syncthreads();
+    const uint64_t base = (uint64_t)blockIdx.x * kRadixTile + (uint64_t)w * kRadixWaveKeys;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t key[kRadixPer];
+    uint32_t pos[kRadixPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kRadixPer; ++k) {
+        const uint64_t i = base + (uint64_t)k * 64 + lane;
+        const bool ok = i < n;
+        key[k] = ok ? in[i] : 0ull;
+        const uint32_t dg = (uint32_t)(key[k] >> shift) & 255u;
+        uint64_t peers = __ballot(ok);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bb = __ballot((dg >> b) & 1u);
+            peers &= ((dg >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t r = (uint32_t)__popcll(peers & lt);
+        uint32_t p = 0;
+        if (ok) p = wcnt[w][dg] + r;
+        __builtin_amdgcn_wave_barrier();
+        // highest lane of each digit group advances the wave's counter
+        if (ok && (peers >> lane) == 1ull) wcnt[w][dg] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+        pos[k] = p;
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kRadixPer; ++k) {
+        const uint64_t i = base + (uint64_t)k * 64 + lane;
+        if (i < n) {
+            const uint32_t dg = (uint32_t)(key[k] >> shift) & 255u;
+            uint64_t o = dbase[dg];
+            for (uint32_t ww = 0; ww < w; ++ww) o += wcnt[ww][dg];
+            out[o + pos[k]] = key[k];
+        }
+    }
+}
+
+hipError_t launch_radix_sort_u64(uint64_t *keys, uint64_t *tmp, uint64_t n, const int *shifts, int npasses,
+                                 uint32_t *hist, uint64_t *hscan, uint64_t *stmp, bool *in_tmp,
+                                 hipStream_t s) {
+    *in_tmp = false;
+    if (n < 2 || npasses == 0) return hipSuccess;
+    const uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
+    uint64_t *src = keys, *dst = tmp;
+    for (int p = 0; p < npasses; ++p) {
+        hipLaunchKernelGGL(radix_hist, dim3((uint32_t)nb), dim3(256), 0, s, src, n, shifts[p], hist);
+        hipError_t e = launch_scan_u32(hist, nb * 256, hscan, stmp, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(radix_scatter, dim3((uint32_t)nb), dim3(256), 0, s, src, n, shifts[p], hscan, dst);
+        uint64_t *t = src;
+        src = dst;
+        dst = t;
+    }
+    *in_tmp = (src == tmp);
+    return hipGetLastError();
+}
+
+}  // namespace rtk

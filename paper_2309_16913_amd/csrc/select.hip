@@ -1,0 +1,243 @@
+// Range-select traversal kernels for gfx950.
+//
+// One query is handled by a group of G lanes (G = 16, 32 or 64, the smallest
+// power of two >= F), so a wave64 runs 64/G queries side by side.  Lane e of a
+// group owns entry e of the node being visited.  Per visited node:
+//   1. the query window sits in registers, the same in all lanes of the group
+//      (the paper broadcasts the query into vector registers once per query,
+//      section 3 step 1);
+//   2. each lane loads its entry's MBR -- for the SoA layout D1 the group's
+//      loads of lx[], ly[], hx[], hy[] are four coalesced 4F-byte reads
+//      (section 3 step 2);
+//   3. the four fp32 comparisons give a per-lane hit; __ballot turns the hits
+//      of the wave into a 64-bit mask and the group takes its G bits (the
+//      SIMD compare-to-bitmask of section 3 step 3);
+//   4. at an internal node the qualifying children are pushed onto the group's
+//      stack in LDS at base + rank (rank = popcount of the mask below the
+//      lane), the GPU form of the masked compress-store into the queue
+//      (section 3 step 4, and the recursion-free traversal O1).  At a leaf the
+//      group counts its hits (count pass) or writes the object ids at the
+//      query's output cursor + rank (fill pass).
+// The stack is depth-first (a LIFO of node ids) so its size stays bounded by
+// (h-1)(F-1)+1 entries instead of a whole tree level.
+//
+// Work distribution: the grid is persistent; a group that empties its stack
+// takes the next query index from a device counter.  Both passes walk the same
+// tree with the same predicate, so the fill pass writes exactly the count
+// pass's number of ids for every query.
+#include "rt_internal.h"
+
+namespace rtk {
+
+template <int LAYOUT>
+__device__ __forceinline__ void load_entry(const uint8_t *__restrict__ node, uint32_t F, uint32_t e,
+                                           float &lx, float &ly, float &hx, float &hy) {
+    if constexpr (LAYOUT == LAYOUT_SOA) {
+        const float *f = reinterpret_cast<const float *>(node);
+        lx = f[e];
+        ly = f[F + e];
+        hx = f[2 * F + e];
+        hy = f[3 * F + e];
+    } else if constexpr (LAYOUT == LAYOUT_AOS) {
+        const float *f = reinterpret_cast<const float *>(node) + 5 * e;
+        lx = f[0];
+        ly = f[1];
+        hx = f[2];
+        hy = f[3];
+    } else {
+        const float2 *lo = reinterpret_cast<const float2 *>(node);
+        const float2 a = lo[e];
+        const float2 b = lo[F + e];
+        lx = a.x;
+        ly = a.y;
+        hx = b.x;
+        hy = b.y;
+    }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t load_ptr(const uint8_t *__restrict__ node, uint32_t F, uint32_t e) {
+    const uint32_t *u = reinterpret_cast<const uint32_t *>(node);
+    if constexpr (LAYOUT == LAYOUT_AOS) return u[5 * e + 4];
+    return u[4 * F + e];
+}
+
+template <int G, int LAYOUT, int MODE>
+__global__ void __launch_bounds__(256)
+select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *__restrict__ counts,
+              const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint64_t cap,
+              Ctrl *__restrict__ ctrl, uint32_t slot, uint32_t stack_cap) {
+    extern __shared__ uint32_t smem[];
+    if constexpr (MODE == SEL_FILL) {
+        if (offsets[nq] > cap) return;   // result does not fit: leave ids untouched
+    }
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t e = lane & (G - 1);
+    const uint32_t gbase = lane & ~(uint32_t)(G - 1);
+    uint32_t *stk = smem + (threadIdx.x / G) * stack_cap;
+    const uint32_t F = t.fanout;
+    const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+    const uint64_t below = (e == 0) ? 0ull : (~0ull >> (64 - e));
+
+    uint32_t qi = 0;
+    bool have = false, done = false;
+    uint32_t sp = 0;
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint64_t pos = 0, end = 0;
+    uint64_t vnodes = 0, ventries = 0;
+
+    while (true) {
+        if (!done && sp == 0) {
+            if (have) {
+                if constexpr (MODE == SEL_COUNT) {
+                    if (e == 0) counts[qi] = (uint32_t)pos;
+                }
+            }
+            uint32_t nxt = 0;
+            if (e == 0) nxt = atomicAdd(&ctrl->work[slot], 1u);
+            nxt = __shfl(nxt, (int)gbase);
+            if (nxt < nq) {
+                qi = nxt;
+                have = true;
+                q = qs[qi];
+                stk[0] = 0u;   // root
+                sp = 1;
+                if constexpr (MODE == SEL_FILL) {
+                    pos = offsets[qi];
+                    end = offsets[qi + 1];
+                } else {
+                    pos = 0;
+                }
+            } else {
+                have = false;
+                done = true;
+            }
+        }
+        if (__all(done)) break;
+        __builtin_amdgcn_wave_barrier();
+
+        uint32_t node = 0;
+        if (have) {
+            sp -= 1;
+            node = stk[sp];
+        }
+        const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
+        bool hit = false, valid = false;
+        if (have && e < F) {
+            float lx, ly, hx, hy;
+            load_entry<LAYOUT>(nb, F, e, lx, ly, hx, hy);
+            hit = (lx <= q.z) && (q.x <= hx) && (ly <= q.w) && (q.y <= hy);
+            if constexpr (MODE == SEL_STATS) valid = (lx == lx);
+        }
+        const uint64_t m = (__ballot(hit) >> gbase) & gmask;
+        const uint32_t n = (uint32_t)__popcll(m);
+        const uint32_t rank = (uint32_t)__popcll(m & below);
+        if constexpr (MODE == SEL_STATS) {
+            const uint64_t vm = (__ballot(valid) >> gbase) & gmask;
+            if (have) {
+                vnodes += 1;
+                ventries += (uint64_t)__popcll(vm);
+            }
+        }
+        if (have) {
+            if (node >= t.first_leaf) {
+                if constexpr (MODE == SEL_FILL) {
+                    if (hit) {
+                        const uint64_t o = pos + rank;
+                        if (o < end)
+                            ids[o] = load_ptr<LAYOUT>(nb, F, e);
+                        else
+                            atomicOr(&ctrl->err, kErrBounds);
+                    }
+                }
+                pos += n;
+            } else {
+                if (hit) {
+                    if (sp + rank < stack_cap)
+                        stk[sp + rank] = load_ptr<LAYOUT>(nb, F, e);
+                    else
+                        atomicOr(&ctrl->err, kErrStack);
+                }
+                sp = min(sp + n, stack_cap);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if constexpr (MODE == SEL_STATS) {
+        if (e == 0 && (vnodes | ventries)) {
+            atomicAdd((unsigned long long *)&ctrl->stats[0], (unsigned long long)vnodes);
+            atomicAdd((unsigned long long *)&ctrl->stats[1], (unsigned long long)ventries);
+        }
+    }
+}
+
+int num_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 256;
+        cus = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+    }
+    return cus;
+}
+
+template <int G, int LAYOUT, int MODE>
+static hipError_t launch_g(const TreeView &t, const float4 *q, uint32_t nq, uint32_t *counts,
+                           const uint64_t *offsets, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
+                           uint32_t slot, hipStream_t s) {
+    const uint32_t stack_cap = stack_bound(t.height, t.fanout);
+    const uint32_t groups_per_block = 256 / G;
+    const size_t smem = (size_t)groups_per_block * stack_cap * sizeof(uint32_t);
+    uint64_t want = ((uint64_t)nq + groups_per_block - 1) / groups_per_block;
+    uint64_t persistent = (uint64_t)num_cus() * 8;
+    uint32_t blocks = (uint32_t)(want < persistent ? want : persistent);
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE>), dim3(blocks), dim3(256), smem, s, t, q, nq,
+                       counts, offsets, ids, cap, ctrl, slot, stack_cap);
+    return hipGetLastError();
+}
+
+template <int G, int LAYOUT>
+static hipError_t launch_m(const TreeView &t, const float4 *q, uint32_t nq, int mode, uint32_t *counts,
+                           const uint64_t *offsets, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
+                           uint32_t slot, hipStream_t s) {
+    switch (mode) {
+    case SEL_COUNT:
+        return launch_g<G, LAYOUT, SEL_COUNT>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, s);
+    case SEL_FILL:
+        return launch_g<G, LAYOUT, SEL_FILL>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, s);
+    default:
+        return launch_g<G, LAYOUT, SEL_STATS>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, s);
+    }
+}
+
+template <int G>
+static hipError_t launch_l(const TreeView &t, const float4 *q, uint32_t nq, int mode, uint32_t *counts,
+                           const uint64_t *offsets, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
+                           uint32_t slot, hipStream_t s) {
+    switch (t.layout) {
+    case LAYOUT_AOS:
+        return launch_m<G, LAYOUT_AOS>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+    case LAYOUT_SOA:
+        return launch_m<G, LAYOUT_SOA>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+    default:
+        return launch_m<G, LAYOUT_D2>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+    }
+}
+
+hipError_t launch_select_pass(const TreeView &t, const float4 *q, uint32_t nq, int mode,
+                              uint32_t *counts, const uint64_t *offsets, uint32_t *ids,
+                              uint64_t cap, Ctrl *ctrl, uint32_t slot, hipStream_t s) {
+    switch (group_width(t.fanout)) {
+    case 16:
+        return launch_l<16>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+    case 32:
+        return launch_l<32>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+    default:
+        return launch_l<64>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+    }
+}
+
+}  // namespace rtk

@@ -1,0 +1,191 @@
+"""GPU parity of range select: the HIP path (through the C ABI) against the
+CPU oracle, element by element, on seeded inputs."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import rtgen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    import paper_2309_16913_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ora():
+    return oracle.get()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def assert_csr_equal(got, want, what=""):
+    go, gi = got
+    wo, wi = want
+    assert go.shape == wo.shape, what
+    if not np.array_equal(go, wo):
+        k = int(np.nonzero(go != wo)[0][0])
+        raise AssertionError(f"{what}: offsets differ first at {k}: {go[k]} vs {wo[k]}")
+    if not np.array_equal(gi, wi):
+        k = int(np.nonzero(gi != wi)[0][0])
+        raise AssertionError(f"{what}: ids differ first at {k}: {gi[k]} vs {wi[k]}")
+
+
+def test_select_plain_100k(rt, ora):
+    """100k uniform rectangles, fanout 16 SoA, 1000 windows of side 0.01."""
+    w = rtgen.c1_plain()
+    say("case select_uniform_100k_q1k_f16_soa")
+    t = rt.build_str(w.rects, w.fanout, w.layout)
+    got = rt.range_select(t, w.queries)
+    want = ora.select(ora.build_str(w.rects, 16), w.queries)
+    assert_csr_equal(got, want, "c1")
+    assert 10.0 < want[0][-1] / 1000 < 12.0
+
+
+FANOUTS = [2, 3, 4, 7, 8, 15, 16, 17, 31, 32, 33, 63, 64]
+LAYOUTS = ["aos", "soa", "d2"]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("fanout", FANOUTS)
+def test_select_adversarial(rt, ora, fanout, layout):
+    """Touching edges, points, segments, duplicates, infinite windows; sizes
+    0, 1, F, F+1 and a few larger ones; every fanout width class."""
+    for s, n in enumerate([0, 1, fanout, fanout + 1, 97, 1500, 6000]):
+        say(f"case adversarial F={fanout} {layout} n={n}")
+        r = rtgen.adversarial_rects(n, 1000 * fanout + s) if n else np.zeros((0, 4), np.float32)
+        q = rtgen.adversarial_windows(64, 77 * fanout + s)
+        t = rt.build_str(r, fanout, layout)
+        got = rt.range_select(t, q)
+        want = ora.brute_select(r, q)
+        assert_csr_equal(got, want, f"F={fanout} {layout} n={n}")
+
+
+def test_select_long_segments(rt, ora):
+    """Windows whose results span several LDS sort tiles plus a ragged tail
+    (the merge path of the segmented sort), on clustered data."""
+    r = rtgen.clustered_rects(300_000, 6, 0.03, 1e-3, 31)
+    q = np.concatenate([rtgen.windows_loguniform(200, 1e-3, 5e-2, 32),
+                        np.array([[-np.inf, -np.inf, np.inf, np.inf]], np.float32)])
+    for fanout, layout in [(16, "soa"), (32, "aos"), (64, "soa"), (32, "d2")]:
+        say(f"case long segments F={fanout} {layout}")
+        t = rt.build_str(r, fanout, layout)
+        got = rt.range_select(t, q)
+        want = ora.select(ora.build_str(r, 16), q)
+        assert_csr_equal(got, want, f"long F={fanout} {layout}")
+        assert int(np.diff(want[0].astype(np.int64)).max()) == r.shape[0]
+
+
+def test_select_empty_query_batch(rt):
+    t = rt.build_str(rtgen.uniform_rects(100, 0.01, 1), 16, "soa")
+    off, ids = rt.range_select(t, np.zeros((0, 4), np.float32))
+    assert off.tolist() == [0] and ids.size == 0
+
+
+def test_select_rejects_bad_queries(rt):
+    t = rt.build_str(rtgen.uniform_rects(100, 0.01, 1), 16, "soa")
+    with pytest.raises(rt.RTError):
+        rt.range_select(t, np.array([[0.5, 0.5, 0.4, 0.6]], np.float32))
+    with pytest.raises(rt.RTError):
+        rt.range_select(t, np.array([[np.nan, 0.5, 0.4, 0.6]], np.float32))
+
+
+def test_subnormal_coordinates(rt, ora):
+    """Subnormal fp32 coordinates must compare exactly as on the CPU (the
+    library is built without denormal flushing)."""
+    tiny = np.float32(2.0 ** -140)
+    r = np.array([[0, 0, tiny, tiny], [tiny, tiny, 2 * tiny, 2 * tiny], [-tiny, -tiny, 0, 0],
+                  [3 * tiny, 0, 4 * tiny, tiny], [0, 0, 0, 0]], np.float32)
+    q = np.array([[tiny, tiny, tiny, tiny], [np.float32(1.5) * tiny, 0, 2 * tiny, 0],
+                  [-tiny, -tiny, -tiny, -tiny], [0, 0, 0, 0], [2.5 * tiny, 0, 2.75 * tiny, tiny]], np.float32)
+    for F in (2, 4, 16):
+        t = rt.build_str(r, F, "soa")
+        assert_csr_equal(rt.range_select(t, q), ora.brute_select(r, q), f"subnormal F={F}")
+
+
+def test_tree_invariants(rt, ora):
+    """The library's tree read back from the device satisfies every invariant
+    of the oracle's checker (MBR unions, one leaf entry per object with its own
+    rectangle, levels, counts)."""
+    for n, F, layout in [(0, 8, "soa"), (1, 16, "aos"), (64, 64, "soa"), (65, 64, "d2"),
+                         (10_000, 16, "soa"), (50_000, 32, "aos"), (123_457, 7, "d2")]:
+        r = rtgen.clustered_rects(n, 5, 0.05, 1e-3, n + F) if n else np.zeros((0, 4), np.float32)
+        t = rt.build_str(r, F, layout)
+        ex = t.export()
+        ot = ora.tree_from_arrays(**ex)
+        rc, msg = ora.check(ot, r)
+        assert rc == 0, (n, F, layout, msg)
+        info = t.info()
+        assert info.node_bytes == 20 * F
+
+
+def test_deterministic(rt):
+    r = rtgen.c2_rects(200_000)
+    q = rtgen.c2_queries(5000)
+    t = rt.build_str(r, 32, "soa")
+    a = rt.range_select(t, q)
+    b = rt.range_select(t, q)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_device_api_and_capacity(rt, ora):
+    """Stream-ordered device-pointer select with torch buffers; an output
+    capacity that is too small is reported in the status words and leaves the
+    id buffer untouched."""
+    import torch
+    r = rtgen.c2_rects(200_000)
+    q = rtgen.c2_queries(3000)
+    t = rt.build_str(r, 16, "aos")
+    want = ora.select(ora.build_str(r, 16), q)
+    total = int(want[0][-1])
+    dq = torch.from_numpy(q).cuda()
+    off = torch.empty(q.shape[0] + 1, dtype=torch.int64, device="cuda")
+    for cap, ok in [(total, True), (total + 1000, True), (total - 1, False)]:
+        ids = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
+        wb = rt.select_workspace_bytes(q.shape[0], cap)
+        work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+        st = torch.zeros(2, dtype=torch.int64, device="cuda")
+        s = torch.cuda.current_stream()
+        rt.range_select_device(t, dq.data_ptr(), q.shape[0], off.data_ptr(), ids.data_ptr(), cap,
+                               work.data_ptr(), wb, st.data_ptr(), s.cuda_stream)
+        s.synchronize()
+        stat = st.cpu().numpy()
+        assert stat[0] == total
+        if ok:
+            assert stat[1] == 0
+            got = (off.cpu().numpy().astype(np.uint64), ids.cpu().numpy().view(np.uint32)[:total])
+            assert_csr_equal(got, want, f"device cap={cap}")
+        else:
+            assert stat[1] & 1
+            assert bool((ids == -1).all())
+    # count-only entry point
+    counts = torch.empty(q.shape[0], dtype=torch.int32, device="cuda")
+    wb = rt.select_workspace_bytes(q.shape[0], 0)
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    rt.range_count_device(t, dq.data_ptr(), q.shape[0], counts.data_ptr(), work.data_ptr(), wb,
+                          torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert np.array_equal(counts.cpu().numpy().astype(np.int64), np.diff(want[0].astype(np.int64)))
+
+
+def test_visit_stats(rt):
+    """Visited-node statistics: every query visits at least the root; a
+    select-all window visits every node and every entry."""
+    r = rtgen.uniform_rects(20_000, 1e-3, 5)
+    t = rt.build_str(r, 16, "soa")
+    info = t.info()
+    vn, ve = rt.visit_stats(t, np.array([[-np.inf, -np.inf, np.inf, np.inf]], np.float32))
+    assert vn == info.n_nodes and ve == info.n_entries
+    vn, ve = rt.visit_stats(t, np.array([[5, 5, 6, 6]], np.float32))
+    assert vn == 1
