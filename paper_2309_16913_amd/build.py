@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librt_mi355x.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["select.hip", "scan_sort.hip", "join.hip", "batch_kernels.hip", "str_device.hip",
+SOURCES = ["select.hip", "scan_sort.hip", "segsort.hip", "join.hip", "batch_kernels.hip", "str_device.hip",
            "rt_api.cpp", "str_pack.cpp", "batch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

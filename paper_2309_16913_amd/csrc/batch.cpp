@@ -30,7 +30,8 @@ struct rt_batch {
     std::vector<uint64_t> q_begin, nq, id_base, id_count, plain_begin;
     void *d_trees = nullptr, *d_items = nullptr, *d_q = nullptr, *d_counts = nullptr, *d_off = nullptr;
     void *d_ids = nullptr, *d_scratch = nullptr, *d_ctrl = nullptr, *d_scan = nullptr, *d_status = nullptr;
-    void *d_plain_off = nullptr;
+    void *d_plain_off = nullptr, *d_lists = nullptr;
+    int id_bits = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -41,7 +42,7 @@ void rtk::batch_release(rt_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     void *bufs[] = {b->d_trees, b->d_items, b->d_q,    b->d_counts, b->d_off,       b->d_ids,
-                    b->d_scratch, b->d_ctrl, b->d_scan, b->d_status, b->d_plain_off};
+                    b->d_scratch, b->d_ctrl, b->d_scan, b->d_status, b->d_plain_off, b->d_lists};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     b->~rt_batch();
@@ -73,7 +74,8 @@ static hipError_t enqueue_all(rt_batch *b, hipStream_t s) {
                               ctrl, 1, b->wave_words, s);
     if (e == hipSuccess)
         e = launch_segsort(static_cast<uint64_t *>(b->d_off), b->total_q, static_cast<uint32_t *>(b->d_ids),
-                           static_cast<uint32_t *>(b->d_scratch), b->cap, ctrl, s);
+                           static_cast<uint32_t *>(b->d_scratch), b->cap, static_cast<uint32_t *>(b->d_lists),
+                           b->id_bits, s);
     if (e == hipSuccess)
         e = launch_finalize(static_cast<uint64_t *>(b->d_off), b->total_q, b->cap, ctrl,
                             static_cast<uint64_t *>(b->d_status), s);
@@ -125,6 +127,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
             bt[i].nq = (uint32_t)nq[i];
             bt[i].stack_cap = stack_bound(t->height, t->fanout);
             b->q_begin[i] = qb;
+            b->id_bits = std::max(b->id_bits, id_bits_for(t->n_objects));
             const uint32_t G = group_width(t->fanout);
             b->wave_words = std::max(b->wave_words, (64 / G) * bt[i].stack_cap);
             if (nq[i]) std::memcpy(hq.data() + 4 * qb, queries[i], nq[i] * 16);
@@ -157,6 +160,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         if (e == hipSuccess) e = dmalloc(&b->d_ctrl, sizeof(Ctrl));
         if (e == hipSuccess) e = dmalloc(&b->d_scan, scan_tmp_elems(std::max<uint64_t>(total, 1)) * 8);
         if (e == hipSuccess) e = dmalloc(&b->d_status, 16);
+        if (e == hipSuccess) e = dmalloc(&b->d_lists, segsort_ws_elems(std::max<uint64_t>(total, 1)) * 4);
         uint64_t plain_total = 0;
         b->plain_begin.resize(ntrees);
         for (uint32_t i = 0; i < ntrees; ++i) {
@@ -234,11 +238,14 @@ extern "C" int rt_batch_run_plain(rt_batch *b, void *stream) {
         const uint64_t base = b->id_base[i], cnt = b->id_count[i];
         const uint64_t cap = base < b->cap ? std::min<uint64_t>(cnt, b->cap - base) : 0;
         e = launch_zero(ctrl->work, sizeof(ctrl->work), s);
-        if (e == hipSuccess) e = launch_select_pass(v, q, (uint32_t)n, SEL_COUNT, counts, nullptr, nullptr, 0, ctrl, 0, s);
+        if (e == hipSuccess) e = launch_zero(ctrl->xwork, sizeof(ctrl->xwork), s);
+        if (e == hipSuccess) e = launch_select_pass(v, q, (uint32_t)n, SEL_COUNT, counts, nullptr, nullptr, 0, ctrl, 0, nullptr, s);
         if (e == hipSuccess) e = launch_scan_u32(counts, n, off, static_cast<uint64_t *>(b->d_scan), s);
         if (e == hipSuccess)
-            e = launch_select_pass(v, q, (uint32_t)n, SEL_FILL, counts, off, ids + base, cap, ctrl, 1, s);
-        if (e == hipSuccess) e = launch_segsort(off, n, ids + base, scratch + base, cap, ctrl, s);
+            e = launch_select_pass(v, q, (uint32_t)n, SEL_FILL, counts, off, ids + base, cap, ctrl, 1, nullptr, s);
+        if (e == hipSuccess)
+            e = launch_segsort(off, n, ids + base, scratch + base, cap, static_cast<uint32_t *>(b->d_lists),
+                               id_bits_for(b->trees[i]->n_objects), s);
     }
     return e == hipSuccess ? RT_OK : hip_fail(e, "plain batch launches");
 }

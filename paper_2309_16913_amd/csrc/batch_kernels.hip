@@ -117,8 +117,14 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
                 node = stk[sp];
             }
             const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
+            const bool leaf = node >= t.first_leaf;
             bool hit = false;
+            uint32_t ref = 0;
             if (have && e < F) {
+                if (!leaf)
+                    ref = batch_ptr(t, nb, 0);
+                else if constexpr (MODE == SEL_FILL)
+                    ref = batch_ptr(t, nb, e);
                 float lx, ly, hx, hy;
                 batch_load(t, nb, e, lx, ly, hx, hy);
                 hit = (lx <= q.z) && (q.x <= hx) && (ly <= q.w) && (q.y <= hy);
@@ -127,12 +133,12 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
             const uint32_t n = (uint32_t)__popcll(m);
             const uint32_t rank = (uint32_t)__popcll(m & below);
             if (have) {
-                if (node >= t.first_leaf) {
+                if (leaf) {
                     if constexpr (MODE == SEL_FILL) {
                         if (hit) {
                             const uint64_t o = pos + rank;
                             if (o < end)
-                                ids[o] = batch_ptr(t, nb, e);
+                                ids[o] = ref;
                             else
                                 atomicOr(&ctrl->err, kErrBounds);
                         }
@@ -141,7 +147,7 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
                 } else {
                     if (hit) {
                         if (sp + rank < bt.stack_cap)
-                            stk[sp + rank] = batch_ptr(t, nb, e);
+                            stk[sp + rank] = ref + e;
                         else
                             atomicOr(&ctrl->err, kErrStack);
                     }

@@ -127,16 +127,20 @@ hipError_t DevBuf::alloc(size_t bytes) {
 
 static uint64_t align256(uint64_t b) { return (b + 255) & ~255ull; }
 
-// Workspace layout of a select: Ctrl | counts[nq] | scan tmp | sort scratch[cap]
+// Workspace layout of a select:
+//   Ctrl | counts[nq] | scan tmp | sort lists | query order | sort scratch[cap]
 struct SelWs {
     Ctrl *ctrl;
     uint32_t *counts;
     uint64_t *scan_tmp;
+    uint32_t *lists;
+    void *order;
     uint32_t *scratch;
 };
 
 static uint64_t sel_ws_bytes(uint64_t nq, uint64_t cap) {
-    return align256(sizeof(Ctrl)) + align256(4 * nq) + align256(8 * scan_tmp_elems(nq)) + align256(4 * cap);
+    return align256(sizeof(Ctrl)) + align256(4 * nq) + align256(8 * scan_tmp_elems(nq)) +
+           align256(4 * segsort_ws_elems(nq)) + align256(order_ws_bytes(nq)) + align256(4 * cap);
 }
 
 static SelWs sel_ws(void *w, uint64_t nq) {
@@ -148,6 +152,10 @@ static SelWs sel_ws(void *w, uint64_t nq) {
     p += align256(4 * nq);
     s.scan_tmp = reinterpret_cast<uint64_t *>(p);
     p += align256(8 * scan_tmp_elems(nq));
+    s.lists = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * segsort_ws_elems(nq));
+    s.order = p;
+    p += align256(order_ws_bytes(nq));
     s.scratch = reinterpret_cast<uint32_t *>(p);
     return s;
 }
@@ -284,16 +292,18 @@ int rtk::enqueue_select(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_
     };
     hipError_t e = launch_zero(w.ctrl, sizeof(Ctrl), s);
     if (e == hipSuccess) e = mark(0);
+    const uint64_t *order = nullptr;
+    if (e == hipSuccess && nq >= kOrderMinQueries) e = launch_query_order(dq, (uint32_t)nq, t->mbr, w.order, &order, s);
     if (e == hipSuccess)
-        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_COUNT, counts, nullptr, nullptr, 0, w.ctrl, 0, s);
+        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_COUNT, counts, nullptr, nullptr, 0, w.ctrl, 0, order, s);
     if (e == hipSuccess) e = mark(1);
     if (count_only || e != hipSuccess) return e == hipSuccess ? RT_OK : hip_fail(e, "count pass");
     e = launch_scan_u32(counts, nq, d_off, w.scan_tmp, s);
     if (e == hipSuccess) e = mark(2);
     if (e == hipSuccess)
-        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_FILL, counts, d_off, d_ids, cap, w.ctrl, 1, s);
+        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_FILL, counts, d_off, d_ids, cap, w.ctrl, 1, order, s);
     if (e == hipSuccess) e = mark(3);
-    if (e == hipSuccess) e = launch_segsort(d_off, nq, d_ids, w.scratch, cap, w.ctrl, s);
+    if (e == hipSuccess) e = launch_segsort(d_off, nq, d_ids, w.scratch, cap, w.lists, id_bits_for(t->n_objects), s);
     if (e == hipSuccess) e = mark(4);
     if (e == hipSuccess && d_status) e = launch_finalize(d_off, nq, cap, w.ctrl, d_status, s);
     return e == hipSuccess ? RT_OK : hip_fail(e, "select launch");
@@ -367,9 +377,12 @@ extern "C" int rt_range_select(const rt_tree *t, const float *queries, uint64_t 
         const TreeView v = view_of(t);
         hipStream_t s = nullptr;
         e = launch_zero(w.ctrl, sizeof(Ctrl), s);
+        const uint64_t *order = nullptr;
+        if (e == hipSuccess && nq >= kOrderMinQueries)
+            e = launch_query_order(static_cast<const float4 *>(dq.p), (uint32_t)nq, t->mbr, w.order, &order, s);
         if (e == hipSuccess)
             e = launch_select_pass(v, static_cast<const float4 *>(dq.p), (uint32_t)nq, SEL_COUNT, w.counts, nullptr,
-                                   nullptr, 0, w.ctrl, 0, s);
+                                   nullptr, 0, w.ctrl, 0, order, s);
         if (e == hipSuccess) e = launch_scan_u32(w.counts, nq, static_cast<uint64_t *>(doff.p), w.scan_tmp, s);
         uint64_t total = 0;
         if (e == hipSuccess)
@@ -380,10 +393,11 @@ extern "C" int rt_range_select(const rt_tree *t, const float *queries, uint64_t 
         if (e == hipSuccess) e = scratch.alloc(total * 4);
         if (e != hipSuccess) return hip_fail(e, "allocating the result");
         e = launch_select_pass(v, static_cast<const float4 *>(dq.p), (uint32_t)nq, SEL_FILL, w.counts,
-                               static_cast<uint64_t *>(doff.p), static_cast<uint32_t *>(dids.p), total, w.ctrl, 1, s);
+                               static_cast<uint64_t *>(doff.p), static_cast<uint32_t *>(dids.p), total, w.ctrl, 1,
+                               order, s);
         if (e == hipSuccess)
             e = launch_segsort(static_cast<uint64_t *>(doff.p), nq, static_cast<uint32_t *>(dids.p),
-                               static_cast<uint32_t *>(scratch.p), total, w.ctrl, s);
+                               static_cast<uint32_t *>(scratch.p), total, w.lists, id_bits_for(t->n_objects), s);
         Ctrl hc;
         if (e == hipSuccess) e = hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "fill pass");
@@ -421,7 +435,7 @@ extern "C" int rt_select_visit_stats(const rt_tree *t, const float *queries, uin
     if (e == hipSuccess) e = launch_zero(w.ctrl, sizeof(Ctrl), nullptr);
     if (e == hipSuccess)
         e = launch_select_pass(view_of(t), static_cast<const float4 *>(dq.p), (uint32_t)nq, SEL_STATS, w.counts,
-                               nullptr, nullptr, 0, w.ctrl, 2, nullptr);
+                               nullptr, nullptr, 0, w.ctrl, 2, nullptr, nullptr);
     Ctrl hc;
     if (e == hipSuccess) e = hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "visit statistics");

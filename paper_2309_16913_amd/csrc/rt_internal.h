@@ -10,10 +10,12 @@ namespace rtk {
 
 enum : uint32_t { LAYOUT_AOS = 0, LAYOUT_SOA = 1, LAYOUT_D2 = 3 };
 
-// A device tree as the kernels see it.  Nodes are numbered root first (node
-// 0), level by level, so every node with index >= first_leaf is a leaf.  A
-// node is 20*F bytes; unused entry slots of a partly filled node hold NaN
-// rectangles, which fail every comparison and so never qualify.
+// A device tree as the kernels see it.  Nodes are numbered breadth first from
+// the root (node 0), so every node with index >= first_leaf is a leaf and the
+// children of every internal node are contiguous (entry e points at the
+// node's first child + e).  A node is 20*F bytes; unused entry slots of a
+// partly filled node hold NaN rectangles, which fail every comparison and so
+// never qualify.
 struct TreeView {
     const uint8_t *nodes;
     uint32_t fanout;
@@ -25,19 +27,21 @@ struct TreeView {
     float mbr[4];            // MBR of the whole tree (root node)
 };
 
+constexpr uint32_t kXcds = 8;          // MI355X: 8 XCDs; workgroup i runs on XCD i % 8
+
 // Kernel-side status words at the start of every workspace.
 struct Ctrl {
     uint32_t work[8];        // work-queue counters (one per pass)
     uint32_t err;            // internal error flags
     uint32_t pad[7];
     uint64_t stats[4];       // visit statistics
+    // per-pass, per-XCD query counters, one 128-byte cache line each
+    uint32_t xwork[3][kXcds][32];
 };
 
 constexpr uint32_t kErrStack = 1u;     // traversal stack would overflow
 constexpr uint32_t kErrBounds = 2u;    // an output write would fall outside its range
 constexpr uint32_t kErrInput = 4u;     // invalid rectangle found on the device
-
-constexpr uint32_t kSortTile = 4096;   // ids sorted in LDS by one block
 
 // Traversal stack bound for a depth-first walk that pops one node and pushes
 // its qualifying children: (h-1)(F-1)+1 entries.
@@ -52,11 +56,22 @@ inline uint32_t group_width(uint32_t fanout) {
 // ---- select -------------------------------------------------------------
 enum SelectMode : int { SEL_COUNT = 0, SEL_FILL = 1, SEL_STATS = 2 };
 
-// One traversal pass over all queries (persistent grid, dynamic query queue).
+// One traversal pass over all queries (persistent grid).  order (may be
+// NULL): nq 64-bit keys whose low 32 bits list the queries in the order they
+// should be processed; XCD x takes the x-th eighth of that order first and
+// then helps the others.
 hipError_t launch_select_pass(const TreeView &t, const float4 *q, uint32_t nq, int mode,
                               uint32_t *counts, const uint64_t *offsets, uint32_t *ids,
                               uint64_t ids_capacity, Ctrl *ctrl, uint32_t work_slot,
-                              hipStream_t s);
+                              const uint64_t *order, hipStream_t s);
+
+// Query order for locality: 64-bit keys (Morton code of the window center
+// over the tree's MBR) << 32 | query index, sorted.  tmp: 2*nq uint64 plus
+// radix temporaries (order_ws_bytes).  *sorted receives the sorted keys.
+uint64_t order_ws_bytes(uint64_t nq);
+hipError_t launch_query_order(const float4 *q, uint32_t nq, const float *mbr, void *ws,
+                              const uint64_t **sorted, hipStream_t s);
+constexpr uint32_t kOrderMinQueries = 8192;   // smaller batches keep input order
 
 // ---- scan, sort ---------------------------------------------------------
 // Exclusive scan of n uint32 into n+1 uint64 (out[n] = total).  tmp needs
@@ -65,10 +80,19 @@ uint64_t scan_tmp_elems(uint64_t n);
 hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp,
                            hipStream_t s);
 
-// Sort every CSR segment ascending.  scratch: ids_capacity uint32 (used for
-// segments longer than kSortTile).  Skips all work if offsets[nq] > capacity.
+// Sort every CSR segment ascending.  scratch: capacity uint32 (used for
+// segments longer than one LDS tile); ws: segsort_ws_elems(nq) uint32;
+// id_bits: significant bits of the largest object id.  Skips all work if
+// offsets[nq] > capacity.
+uint64_t segsort_ws_elems(uint64_t nq);
 hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch,
-                          uint64_t capacity, Ctrl *ctrl, hipStream_t s);
+                          uint64_t capacity, uint32_t *ws, int id_bits, hipStream_t s);
+inline int id_bits_for(uint64_t n_objects) {
+    int b = 0;
+    const uint64_t m = n_objects ? n_objects - 1 : 0;
+    while (b < 64 && (m >> b)) ++b;
+    return b;
+}
 
 // LSD radix sort of n uint64 keys over the listed 8-bit digit positions.
 // Result ends in keys (if even number of passes) or tmp; returns which via

@@ -3,10 +3,6 @@
 //  * exclusive scan uint32 -> uint64 (counts -> CSR offsets), three kernels:
 //    per-tile sums, a scan of the tile sums, and the per-tile scan with the
 //    tile's base added;
-//  * segmented sort of the CSR id lists: a segment of up to kSortTile ids is
-//    sorted by one block in LDS (bitonic network); a longer segment is sorted
-//    by one block as a merge sort (LDS-sorted tiles, then merge-path merges
-//    between the id buffer and a scratch buffer);
 //  * LSD radix sort of uint64 keys with 8-bit digits (join pairs), stable
 //    per-tile ranking with wave ballots.
 #include "rt_internal.h"
@@ -143,126 +139,6 @@ __global__ void finalize_kernel(const uint64_t *offsets, uint64_t nq, uint64_t c
 hipError_t launch_finalize(const uint64_t *offsets, uint64_t nq, uint64_t cap, const Ctrl *ctrl,
                            uint64_t *status, hipStream_t s) {
     hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1), 0, s, offsets, nq, cap, ctrl, status);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// segmented sort
-// ---------------------------------------------------------------------------
-
-// Bitonic sort of P (power of two) keys in LDS by 256 threads.
-__device__ void lds_bitonic(uint32_t *a, uint32_t P) {
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
-                // t-th compare-exchange: partner pair (i, i ^ j) with i having bit j clear
-                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                const uint32_t l = i | j;
-                const uint32_t x = a[i], y = a[l];
-                const bool up = (i & k) == 0;
-                if ((x > y) == up) {
-                    a[i] = y;
-                    a[l] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
-}
-
-__device__ __forceinline__ uint32_t next_pow2(uint32_t v) {
-    uint32_t p = 1;
-    while (p < v) p <<= 1;
-    return p;
-}
-
-// Sort c <= kSortTile keys of src into dst (dst may equal src).
-__device__ void block_sort_tile(const uint32_t *src, uint32_t *dst, uint32_t c, uint32_t *lds) {
-    const uint32_t P = next_pow2(c < 2 ? 2 : c);
-    for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) lds[i] = i < c ? src[i] : 0xFFFFFFFFu;
-    __syncthreads();
-    lds_bitonic(lds, P);
-    for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) dst[i] = lds[i];
-    __syncthreads();
-}
-
-// Number of elements of a[0..la) that precede position d of the merged
-// sequence of a and b (keys are distinct within a segment, ties go to a).
-__device__ __forceinline__ uint64_t merge_path(const uint32_t *a, uint64_t la, const uint32_t *b,
-                                               uint64_t lb, uint64_t d) {
-    uint64_t lo = d > lb ? d - lb : 0;
-    uint64_t hi = d < la ? d : la;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        // take a[mid] before b[d-mid-1]?
-        if (a[mid] <= b[d - mid - 1])
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-constexpr uint32_t kMergePer = 16;   // outputs per thread per merge step
-
-__global__ void __launch_bounds__(256) segsort_kernel(const uint64_t *__restrict__ offsets, uint64_t nq,
-                                                      uint32_t *__restrict__ ids,
-                                                      uint32_t *__restrict__ scratch, uint64_t cap,
-                                                      Ctrl *__restrict__ ctrl) {
-    __shared__ uint32_t lds[kSortTile];
-    if (offsets[nq] > cap) return;
-    for (uint64_t qi = blockIdx.x; qi < nq; qi += gridDim.x) {
-        const uint64_t o = offsets[qi];
-        const uint64_t c = offsets[qi + 1] - o;
-        if (c < 2) continue;
-        uint32_t *seg = ids + o;
-        if (c <= kSortTile) {
-            block_sort_tile(seg, seg, (uint32_t)c, lds);
-            continue;
-        }
-        // long segment: sorted tiles, then pairwise merges
-        for (uint64_t t0 = 0; t0 < c; t0 += kSortTile) {
-            const uint32_t tc = (uint32_t)((c - t0) < kSortTile ? (c - t0) : kSortTile);
-            block_sort_tile(seg + t0, seg + t0, tc, lds);
-        }
-        uint32_t *src = seg, *dst = scratch + o;
-        for (uint64_t w = kSortTile; w < c; w <<= 1) {
-            for (uint64_t r0 = 0; r0 < c; r0 += 2 * w) {
-                const uint64_t la = (c - r0) < w ? (c - r0) : w;
-                const uint64_t rest = c - r0 - la;
-                const uint64_t lb = rest < w ? rest : w;
-                const uint32_t *a = src + r0, *b = src + r0 + la;
-                uint32_t *out = dst + r0;
-                const uint64_t tot = la + lb;
-                for (uint64_t d0 = (uint64_t)threadIdx.x * kMergePer; d0 < tot;
-                     d0 += (uint64_t)blockDim.x * kMergePer) {
-                    uint64_t ia = merge_path(a, la, b, lb, d0);
-                    uint64_t ib = d0 - ia;
-                    const uint64_t d1 = d0 + kMergePer < tot ? d0 + kMergePer : tot;
-                    for (uint64_t d = d0; d < d1; ++d) {
-                        const bool takea = ib >= lb || (ia < la && a[ia] <= b[ib]);
-                        out[d] = takea ? a[ia++] : b[ib++];
-                    }
-                }
-            }
-            __syncthreads();
-            uint32_t *tmp = src;
-            src = dst;
-            dst = tmp;
-        }
-        if (src != seg) {
-            for (uint64_t i = threadIdx.x; i < c; i += blockDim.x) seg[i] = src[i];
-        }
-        __syncthreads();
-    }
-}
-
-hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch,
-                          uint64_t cap, Ctrl *ctrl, hipStream_t s) {
-    if (nq == 0) return hipSuccess;
-    uint64_t blocks = nq < 65536 ? nq : 65536;
-    hipLaunchKernelGGL(segsort_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, offsets, nq, ids, scratch,
-                       cap, ctrl);
     return hipGetLastError();
 }
 

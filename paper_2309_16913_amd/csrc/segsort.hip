@@ -1,0 +1,558 @@
+// Segmented sort of the CSR id lists (each query's ids ascending).
+//
+// Object ids are spread over [0, n), so a segment splits evenly when it is
+// bucketed by the top bits of its ids.  The sort is therefore one MSD
+// bucketing pass followed by independent sorts of small buckets:
+//
+//   classify   every segment with >= 2 ids goes to a size-class list
+//              (appends aggregated per block);
+//   class S    (<= 256 ids)     one wave per segment: the ids sit in
+//              registers (up to 4 per lane) and a bitonic network runs over
+//              them with __shfl_xor for cross-lane partners;
+//   class M    (257 .. 16384)   one block per segment: ids to registers, a
+//              counting sort on the top b id bits (2^b ~ length/4 buckets,
+//              LDS counters), scatter into LDS, then each id counts the
+//              smaller ids of its own bucket and is stored at bucket start +
+//              that count;
+//   class L    (> 16384)        the same with global scratch instead of LDS
+//              for the bucketed copy, up to 16384 buckets;
+//   fallback   a segment with a bucket too long for the in-bucket ranking
+//              (ids far from uniform) is sorted by a block bitonic network in
+//              LDS (class M) or, for class L, by sorting 16384-id tiles that
+//              way and merging runs pairwise through LDS-staged merge-path
+//              windows.
+#include "rt_internal.h"
+
+namespace rtk {
+
+constexpr uint32_t kKeyPad = 0xFFFFFFFFu;   // never an object id (ids < 2^32 - 1)
+constexpr uint32_t kMidMax = 16384;         // longest class-M segment
+constexpr uint32_t kListCls = 5;            // S, M-small, M-large, L, fallback-L
+
+__device__ __forceinline__ uint32_t ceil_log2(uint32_t v) {
+    uint32_t b = 0;
+    while (b < 31 && (1u << b) < v) ++b;
+    return b;
+}
+
+// Bitonic sort of the 64*R keys v[r] (element index r*64 + lane) ascending.
+template <int R>
+__device__ __forceinline__ void wave_bitonic(uint32_t (&v)[R]) {
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (uint32_t k = 2; k <= 64u * R; k <<= 1) {
+#pragma unroll
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            if (j >= 64) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int p = r ^ (int)(j / 64);
+                    if (p > r) {
+                        const bool up = (((uint32_t)r * 64 + lane) & k) == 0;
+                        const uint32_t a = v[r], b = v[p];
+                        const bool sw = up ? (a > b) : (a < b);
+                        v[r] = sw ? b : a;
+                        v[p] = sw ? a : b;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t o = __shfl_xor(v[r], (int)j);
+                    const bool up = (((uint32_t)r * 64 + lane) & k) == 0;
+                    const bool lower = (lane & j) == 0;
+                    v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
+                }
+            }
+        }
+    }
+}
+
+// Sort s (<= 64*R) keys at src[0..s) into dst[0..s) with one wave.
+template <int R>
+__device__ __forceinline__ void wave_sort_n(const uint32_t *src, uint32_t *dst, uint32_t s) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = (uint32_t)r * 64 + lane;
+        v[r] = i < s ? src[i] : kKeyPad;
+    }
+    wave_bitonic<R>(v);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = (uint32_t)r * 64 + lane;
+        if (i < s) dst[i] = v[r];
+    }
+}
+
+// Rank sort of s <= 64*R keys by one wave: every lane holds R keys, and the
+// rank of a key is the number of keys that precede it (smaller, or equal and
+// earlier), counted by broadcasting each key with readlane -- plain VALU work
+// without cross-lane latency chains.  Each key is then stored at its rank.
+template <int R>
+__device__ __forceinline__ void wave_rank_sort(const uint32_t *src, uint32_t *dst, uint32_t s) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t v[R], rk[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = (uint32_t)r * 64 + lane;
+        v[r] = i < s ? src[i] : kKeyPad;
+        rk[r] = 0;
+    }
+#pragma unroll
+    for (int rs = 0; rs < R; ++rs) {
+        const uint32_t j1 = s > (uint32_t)rs * 64 ? min(s - (uint32_t)rs * 64, 64u) : 0u;
+        for (uint32_t j = 0; j < j1; ++j) {
+            const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)v[rs], (int)j);
+            const uint32_t xi = (uint32_t)rs * 64 + j;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint32_t i = (uint32_t)r * 64 + lane;
+                rk[r] += (x < v[r] || (x == v[r] && xi < i)) ? 1u : 0u;
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t i = (uint32_t)r * 64 + lane;
+        if (i < s) dst[rk[r]] = v[r];
+    }
+}
+
+// One wave sorts s <= 512 keys (src and dst may alias: all reads precede writes).
+__device__ __forceinline__ void wave_sort_any(const uint32_t *src, uint32_t *dst, uint32_t s) {
+    if (s < 2) {
+        if (s == 1 && src != dst && (threadIdx.x & 63u) == 0) dst[0] = src[0];
+        return;
+    }
+    if (s <= 16)
+        wave_rank_sort<1>(src, dst, s);
+    else if (s <= 64)
+        wave_sort_n<1>(src, dst, s);
+    else if (s <= 128)
+        wave_sort_n<2>(src, dst, s);
+    else if (s <= 256)
+        wave_sort_n<4>(src, dst, s);
+    else
+        wave_sort_n<8>(src, dst, s);
+}
+
+// Block bitonic sort of the first P (power of two) keys of an LDS array.
+__device__ void block_bitonic(uint32_t *a, uint32_t P) {
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const uint32_t l = i | j;
+                const uint32_t x = a[i], y = a[l];
+                const bool up = (i & k) == 0;
+                if ((x > y) == up) {
+                    a[i] = y;
+                    a[l] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// classify
+// ---------------------------------------------------------------------------
+constexpr uint32_t kClsPer = 16;                   // queries per thread
+constexpr uint32_t kClsTile = 256 * kClsPer;       // queries per block
+
+__global__ void __launch_bounds__(256)
+seg_classify(const uint64_t *__restrict__ offsets, uint64_t nq, uint64_t cap, uint32_t *__restrict__ lists,
+             uint32_t *__restrict__ counts) {
+    __shared__ uint32_t bcnt[4], gbase[4];
+    if (offsets[nq] > cap) return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (threadIdx.x < 4) bcnt[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t q0 = (uint64_t)blockIdx.x * kClsTile;
+    int cls[kClsPer];
+    uint32_t pos[kClsPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kClsPer; ++k) {
+        const uint64_t q = q0 + (uint64_t)k * 256 + threadIdx.x;
+        int c = -1;
+        if (q < nq) {
+            const uint64_t len = offsets[q + 1] - offsets[q];
+            if (len >= 2) c = len <= 256 ? 0 : (len <= 2048 ? 1 : (len <= kMidMax ? 2 : 3));
+        }
+        cls[k] = c;
+        pos[k] = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t m = __ballot(c == j);
+            if (m == 0) continue;
+            const uint32_t leader = (uint32_t)__builtin_ctzll(m);
+            uint32_t at = 0;
+            if (lane == leader) at = atomicAdd(&bcnt[j], (uint32_t)__popcll(m));
+            at = __shfl(at, (int)leader);
+            if (c == j) pos[k] = at + (uint32_t)__popcll(m & lt);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 4)
+        gbase[threadIdx.x] = bcnt[threadIdx.x] ? atomicAdd(&counts[threadIdx.x], bcnt[threadIdx.x]) : 0u;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kClsPer; ++k) {
+        const int c = cls[k];
+        if (c >= 0) lists[(uint64_t)c * nq + gbase[c] + pos[k]] = (uint32_t)(q0 + (uint64_t)k * 256 + threadIdx.x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// class S: one wave per segment
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+segsort_small(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
+              const uint32_t *__restrict__ list_count) {
+    const uint32_t m = *list_count;
+    const uint32_t wpb = blockDim.x / 64;
+    for (uint32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < m; i += gridDim.x * wpb) {
+        const uint32_t q = list[i];
+        const uint64_t o = offsets[q];
+        const uint32_t c = (uint32_t)(offsets[q + 1] - o);
+        wave_sort_any(ids + o, ids + o, c);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// classes M and L: counting sort on the top id bits, then in-bucket ranks
+// ---------------------------------------------------------------------------
+// With 2^b ~ length/4 buckets on the top b bits of the ids, a bucket holds a
+// handful of ids.  One LDS counter per bucket first counts, is then turned
+// into the bucket's start by an exclusive scan, and serves as the scatter
+// cursor; after the scatter counter b holds the end of bucket b, so bucket b
+// spans [end(b-1), end(b)).  Every id then counts the ids of its own bucket
+// that are smaller than it (ids of one query are distinct) and is stored at
+// bucket start + that count.  A bucket of more than kRankMax ids (ids far
+// from uniform) sends the segment to a fallback.
+constexpr uint32_t kRankMax = 64;
+
+// Exclusive scan in place of cnt[0 .. nbk) by T threads (nbk <= 4*T or a
+// multiple of 4*T handled in rounds); returns the largest count.
+template <int T>
+__device__ uint32_t block_scan_counters(uint32_t *cnt, uint32_t nbk, uint32_t *wsum, uint32_t *scal) {
+    constexpr uint32_t W = T / 64;
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    uint32_t carry = 0, mxall = 0;
+    for (uint32_t b0 = 0; b0 < nbk; b0 += 4 * T) {
+        uint32_t v[4], sum = 0, mx = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t i = b0 + 4 * t + r;
+            v[r] = i < nbk ? cnt[i] : 0u;
+            sum += v[r];
+            mx = max(mx, v[r]);
+        }
+        uint32_t inc = sum;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t x = __shfl_up(inc, d);
+            if ((int)lane >= d) inc += x;
+            mx = max(mx, __shfl_xor(mx, d));
+        }
+        if (lane == 63) wsum[w] = inc;
+        if (lane == 0) wsum[W + w] = mx;
+        __syncthreads();
+        uint32_t base = carry, tot = 0;
+        for (uint32_t i = 0; i < W; ++i) {
+            if (i < w) base += wsum[i];
+            tot += wsum[i];
+            mxall = max(mxall, wsum[W + i]);
+        }
+        uint32_t ex = base + inc - sum;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t i = b0 + 4 * t + r;
+            if (i < nbk) cnt[i] = ex;
+            ex += v[r];
+        }
+        carry += tot;
+        __syncthreads();
+    }
+    (void)scal;
+    return mxall;
+}
+
+template <int T, int K>
+__global__ void __launch_bounds__(T)
+segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
+            const uint32_t *__restrict__ list_count, int id_bits) {
+    constexpr uint32_t N = T * K;
+    constexpr uint32_t W = T / 64;
+    constexpr uint32_t NB = N / 4;   // most buckets
+    __shared__ uint32_t buf[N];
+    __shared__ uint32_t cnt[NB];
+    __shared__ uint32_t wsum[2 * W];
+    const uint32_t m = *list_count;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
+        const uint32_t q = list[li];
+        const uint64_t o = offsets[q];
+        const uint32_t c = (uint32_t)(offsets[q + 1] - o);
+        uint32_t *seg = ids + o;
+        uint32_t nb = ceil_log2((c + 3) / 4);
+        const uint32_t nbmax = ceil_log2(NB);
+        nb = nb < 1 ? 1 : (nb > nbmax ? nbmax : nb);
+        const int shift = id_bits > (int)nb ? id_bits - (int)nb : 0;
+        const uint32_t nbk = 1u << nb;
+        for (uint32_t b = t; b < nbk; b += T) cnt[b] = 0;
+        __syncthreads();
+        uint32_t key[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t i = (uint32_t)k * T + t;
+            key[k] = i < c ? seg[i] : kKeyPad;
+            if (i < c) atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u);
+        }
+        __syncthreads();
+        const uint32_t big = block_scan_counters<T>(cnt, nbk, wsum, nullptr);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const uint32_t i = (uint32_t)k * T + t;
+            if (i < c) buf[atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u)] = key[k];
+        }
+        __syncthreads();
+        if (big <= kRankMax) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint32_t i = (uint32_t)k * T + t;
+                if (i < c) {
+                    const uint32_t b = (key[k] >> shift) & (nbk - 1);
+                    const uint32_t s0 = b ? cnt[b - 1] : 0u, s1 = cnt[b];
+                    uint32_t r = 0;
+                    for (uint32_t j = s0; j < s1; ++j) r += buf[j] < key[k] ? 1u : 0u;
+                    seg[s0 + r] = key[k];
+                }
+            }
+        } else {   // ids far from uniform: block bitonic over the whole segment
+            uint32_t P = 1;
+            while (P < c) P <<= 1;
+            for (uint32_t i = c + t; i < P; i += T) buf[i] = kKeyPad;
+            __syncthreads();
+            block_bitonic(buf, P);
+            for (uint32_t i = t; i < c; i += T) seg[i] = buf[i];
+        }
+        __syncthreads();
+    }
+}
+
+constexpr uint32_t kLongCounters = 16384;
+
+__global__ void __launch_bounds__(1024)
+segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint32_t *__restrict__ scratch,
+             const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_count,
+             uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, int id_bits) {
+    constexpr uint32_t T = 1024, W = T / 64;
+    __shared__ uint32_t cnt[kLongCounters];
+    __shared__ uint32_t wsum[2 * W];
+    const uint32_t m = *list_count;
+    const uint32_t t = threadIdx.x;
+    for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
+        const uint32_t q = list[li];
+        const uint64_t o = offsets[q];
+        const uint64_t c = offsets[q + 1] - o;
+        uint32_t *seg = ids + o, *tmp = scratch + o;
+        const uint64_t want = (c + 3) / 4;
+        uint32_t nb = ceil_log2(want > 0x80000000ull ? 0x80000000u : (uint32_t)want);
+        const uint32_t nbmax = ceil_log2(kLongCounters);
+        nb = nb < 8 ? 8 : (nb > nbmax ? nbmax : nb);
+        const int shift = id_bits > (int)nb ? id_bits - (int)nb : 0;
+        const uint32_t nbk = 1u << nb;
+        for (uint32_t b = t; b < nbk; b += T) cnt[b] = 0;
+        __syncthreads();
+        for (uint64_t i = t; i < c; i += T) atomicAdd(&cnt[(seg[i] >> shift) & (nbk - 1)], 1u);
+        __syncthreads();
+        const uint32_t big = block_scan_counters<T>(cnt, nbk, wsum, nullptr);
+        // the rank step reads a whole bucket per id: long buckets go to the fallback
+        const uint32_t limit = kRankMax > (uint32_t)((c + nbk - 1) / nbk) * 4 ? kRankMax
+                                                                               : (uint32_t)((c + nbk - 1) / nbk) * 4;
+        if (big > limit) {
+            if (t == 0) fb_list[atomicAdd(fb_count, 1u)] = q;
+            __syncthreads();
+            continue;
+        }
+        for (uint64_t i = t; i < c; i += T) {
+            const uint32_t key = seg[i];
+            tmp[atomicAdd(&cnt[(key >> shift) & (nbk - 1)], 1u)] = key;
+        }
+        __syncthreads();
+        for (uint64_t i = t; i < c; i += T) {
+            const uint32_t key = tmp[i];
+            const uint32_t b = (key >> shift) & (nbk - 1);
+            const uint32_t s0 = b ? cnt[b - 1] : 0u, s1 = cnt[b];
+            uint32_t r = 0;
+            for (uint32_t j = s0; j < s1; ++j) r += tmp[j] < key ? 1u : 0u;
+            seg[s0 + r] = key;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fallback for long segments with skewed ids: sorted tiles + pairwise merges
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024)
+segsort_tiles(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
+              const uint32_t *__restrict__ list_count) {
+    __shared__ uint32_t buf[kMidMax];
+    const uint32_t m = *list_count;
+    for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
+        const uint32_t q = list[li];
+        const uint64_t o = offsets[q];
+        const uint64_t c = offsets[q + 1] - o;
+        for (uint64_t t0 = 0; t0 < c; t0 += kMidMax) {
+            const uint32_t tc = (uint32_t)((c - t0) < kMidMax ? (c - t0) : kMidMax);
+            uint32_t P = 1;
+            while (P < tc) P <<= 1;
+            for (uint32_t i = threadIdx.x; i < P; i += 1024) buf[i] = i < tc ? ids[o + t0 + i] : kKeyPad;
+            __syncthreads();
+            block_bitonic(buf, P);
+            for (uint32_t i = threadIdx.x; i < tc; i += 1024) ids[o + t0 + i] = buf[i];
+            __syncthreads();
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t pidx(uint32_t i) { return i + (i >> 5); }
+
+__device__ __forceinline__ uint32_t lds_merge_path(const uint32_t *lds, uint32_t a0, uint32_t la, uint32_t b0,
+                                                   uint32_t lb, uint32_t d) {
+    uint32_t lo = d > lb ? d - lb : 0;
+    uint32_t hi = d < la ? d : la;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (lds[pidx(a0 + mid)] <= lds[pidx(b0 + d - mid - 1)])
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t glb_merge_path(const uint32_t *a, uint64_t la, const uint32_t *b, uint64_t lb,
+                                                   uint64_t d) {
+    uint64_t lo = d > lb ? d - lb : 0;
+    uint64_t hi = d < la ? d : la;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= b[d - mid - 1])
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Merge the sorted 16384-id runs of each listed segment pairwise until one
+// run is left; every merge proceeds in windows of 16384 outputs whose inputs
+// are staged in LDS.
+__global__ void __launch_bounds__(1024)
+segmerge_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint32_t *__restrict__ scratch,
+              const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_count) {
+    constexpr uint32_t T = 1024, K = 16, N = T * K;
+    __shared__ uint32_t lds[N + N / 32];
+    __shared__ uint64_t split[2];
+    const uint32_t m = *list_count;
+    for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
+        const uint64_t q = list[li];
+        const uint64_t o = offsets[q];
+        const uint64_t c = offsets[q + 1] - o;
+        uint32_t *src = ids + o, *dst = scratch + o;
+        for (uint64_t w = kMidMax; w < c; w <<= 1) {
+            for (uint64_t r0 = 0; r0 < c; r0 += 2 * w) {
+                const uint64_t la = (c - r0) < w ? (c - r0) : w;
+                const uint64_t rest = c - r0 - la;
+                const uint64_t lb = rest < w ? rest : w;
+                const uint32_t *A = src + r0, *B = src + r0 + la;
+                uint32_t *out = dst + r0;
+                for (uint64_t d0 = 0; d0 < la + lb; d0 += N) {
+                    const uint64_t d1 = (d0 + N) < (la + lb) ? (d0 + N) : (la + lb);
+                    if (threadIdx.x == 0) split[0] = glb_merge_path(A, la, B, lb, d0);
+                    if (threadIdx.x == 1) split[1] = glb_merge_path(A, la, B, lb, d1);
+                    __syncthreads();
+                    const uint64_t ia0 = split[0], ia1 = split[1];
+                    const uint32_t na = (uint32_t)(ia1 - ia0);
+                    const uint32_t nb = (uint32_t)((d1 - d0) - na);
+                    const uint64_t ib0 = d0 - ia0;
+                    for (uint32_t i = threadIdx.x; i < na; i += T) lds[pidx(i)] = A[ia0 + i];
+                    for (uint32_t i = threadIdx.x; i < nb; i += T) lds[pidx(na + i)] = B[ib0 + i];
+                    __syncthreads();
+                    uint32_t r[K];
+                    const uint32_t dd = threadIdx.x * K;
+                    const uint32_t tot = na + nb;
+                    if (dd < tot) {
+                        uint32_t ia = lds_merge_path(lds, 0, na, na, nb, dd);
+                        uint32_t ib = dd - ia;
+                        uint32_t a = ia < na ? lds[pidx(ia)] : kKeyPad;
+                        uint32_t b = ib < nb ? lds[pidx(na + ib)] : kKeyPad;
+#pragma unroll
+                        for (uint32_t k = 0; k < K; ++k) {
+                            const bool ta = ib >= nb || (ia < na && a <= b);
+                            r[k] = ta ? a : b;
+                            if (ta) {
+                                ++ia;
+                                a = ia < na ? lds[pidx(ia)] : kKeyPad;
+                            } else {
+                                ++ib;
+                                b = ib < nb ? lds[pidx(na + ib)] : kKeyPad;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                    if (dd < tot) {
+#pragma unroll
+                        for (uint32_t k = 0; k < K; ++k)
+                            if (dd + k < tot) lds[pidx(dd + k)] = r[k];
+                    }
+                    __syncthreads();
+                    for (uint32_t i = threadIdx.x; i < tot; i += T) out[d0 + i] = lds[pidx(i)];
+                    __syncthreads();
+                }
+            }
+            uint32_t *t2 = src;
+            src = dst;
+            dst = t2;
+        }
+        if (src != ids + o) {
+            for (uint64_t i = threadIdx.x; i < c; i += T) ids[o + i] = src[i];
+        }
+        __syncthreads();
+    }
+}
+
+uint64_t segsort_ws_elems(uint64_t nq) { return (uint64_t)kListCls * nq + 64; }
+
+hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch, uint64_t cap,
+                          uint32_t *ws, int id_bits, hipStream_t s) {
+    if (nq == 0) return hipSuccess;
+    uint32_t *counts = ws;            // class counters
+    uint32_t *lists = ws + 64;        // kListCls lists of up to nq query indices
+    const uint32_t cus = (uint32_t)num_cus();
+    hipError_t e = launch_zero(counts, 64 * 4, s);
+    if (e != hipSuccess) return e;
+    const uint64_t cg = (nq + kClsTile - 1) / kClsTile;
+    hipLaunchKernelGGL(seg_classify, dim3((uint32_t)cg), dim3(256), 0, s, offsets, nq, cap, lists, counts);
+    hipLaunchKernelGGL(segsort_small, dim3(cus * 8), dim3(256), 0, s, offsets, ids, lists, counts + 0);
+    hipLaunchKernelGGL((segsort_mid<256, 8>), dim3(cus * 8), dim3(256), 0, s, offsets, ids, lists + nq, counts + 1,
+                       id_bits);
+    hipLaunchKernelGGL((segsort_mid<1024, 16>), dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + 2 * nq,
+                       counts + 2, id_bits);
+    hipLaunchKernelGGL(segsort_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + 3 * nq,
+                       counts + 3, lists + 4 * nq, counts + 4, id_bits);
+    hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + 4 * nq, counts + 4);
+    hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + 4 * nq,
+                       counts + 4);
+    return hipGetLastError();
+}
+
+}  // namespace rtk

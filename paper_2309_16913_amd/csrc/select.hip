@@ -15,7 +15,10 @@
 //   4. at an internal node the qualifying children are pushed onto the group's
 //      stack in LDS at base + rank (rank = popcount of the mask below the
 //      lane), the GPU form of the masked compress-store into the queue
-//      (section 3 step 4, and the recursion-free traversal O1).  At a leaf the
+//      (section 3 step 4, and the recursion-free traversal O1).  Nodes are
+//      numbered breadth first with the children of a node contiguous, so a
+//      child index is the node's first child + the entry slot; only that one
+//      pointer is read per internal node.  At a leaf the
 //      group counts its hits (count pass) or writes the object ids at the
 //      query's output cursor + rank (fill pass).
 // The stack is depth-first (a LIFO of node ids) so its size stays bounded by
@@ -62,11 +65,29 @@ __device__ __forceinline__ uint32_t load_ptr(const uint8_t *__restrict__ node, u
     return u[4 * F + e];
 }
 
+// Next query for a group leader.  The processing order is cut into eight
+// slices; a block on XCD `home` drains slice `home` first (the queries of a
+// slice are close in space, so they share tree nodes in that XCD's L2), then
+// the following slices in turn.  `visited` counts the slices found empty.
+// Returns nq when everything has been handed out.
+__device__ __forceinline__ uint32_t grab_query(Ctrl *ctrl, uint32_t slot, uint32_t nq, const uint64_t *order,
+                                               uint32_t home, uint32_t &visited) {
+    while (visited < kXcds) {
+        const uint32_t x = (home + visited) % kXcds;
+        const uint32_t b0 = (uint32_t)(((uint64_t)x * nq) / kXcds);
+        const uint32_t b1 = (uint32_t)(((uint64_t)(x + 1) * nq) / kXcds);
+        const uint32_t k = atomicAdd(&ctrl->xwork[slot][x][0], 1u);
+        if (k < b1 - b0) return order ? (uint32_t)order[b0 + k] : b0 + k;
+        visited += 1;
+    }
+    return nq;
+}
+
 template <int G, int LAYOUT, int MODE>
 __global__ void __launch_bounds__(256)
 select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *__restrict__ counts,
               const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint64_t cap,
-              Ctrl *__restrict__ ctrl, uint32_t slot, uint32_t stack_cap) {
+              Ctrl *__restrict__ ctrl, uint32_t slot, uint32_t stack_cap, const uint64_t *__restrict__ order) {
     extern __shared__ uint32_t smem[];
     if constexpr (MODE == SEL_FILL) {
         if (offsets[nq] > cap) return;   // result does not fit: leave ids untouched
@@ -79,6 +100,9 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
     const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
     const uint64_t below = (e == 0) ? 0ull : (~0ull >> (64 - e));
 
+    // XCD-relative cursor over the eight slices of the processing order
+    const uint32_t home = blockIdx.x % kXcds;
+    uint32_t visited = 0;
     uint32_t qi = 0;
     bool have = false, done = false;
     uint32_t sp = 0;
@@ -94,7 +118,7 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                 }
             }
             uint32_t nxt = 0;
-            if (e == 0) nxt = atomicAdd(&ctrl->work[slot], 1u);
+            if (e == 0) nxt = grab_query(ctrl, slot, nq, order, home, visited);
             nxt = __shfl(nxt, (int)gbase);
             if (nxt < nq) {
                 qi = nxt;
@@ -122,8 +146,16 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
             node = stk[sp];
         }
         const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
+        const bool leaf = node >= t.first_leaf;
         bool hit = false, valid = false;
+        uint32_t ref = 0;   // first child (internal node) or this entry's object id (leaf, fill pass)
         if (have && e < F) {
+            // the id / first-child load does not depend on the comparison, so it
+            // is in flight together with the coordinate loads
+            if (!leaf)
+                ref = load_ptr<LAYOUT>(nb, F, 0);
+            else if constexpr (MODE == SEL_FILL)
+                ref = load_ptr<LAYOUT>(nb, F, e);
             float lx, ly, hx, hy;
             load_entry<LAYOUT>(nb, F, e, lx, ly, hx, hy);
             hit = (lx <= q.z) && (q.x <= hx) && (ly <= q.w) && (q.y <= hy);
@@ -140,21 +172,22 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
             }
         }
         if (have) {
-            if (node >= t.first_leaf) {
+            if (leaf) {
                 if constexpr (MODE == SEL_FILL) {
                     if (hit) {
                         const uint64_t o = pos + rank;
                         if (o < end)
-                            ids[o] = load_ptr<LAYOUT>(nb, F, e);
+                            ids[o] = ref;
                         else
                             atomicOr(&ctrl->err, kErrBounds);
                     }
                 }
                 pos += n;
             } else {
+                // children of a node are contiguous: entry e points at first + e
                 if (hit) {
                     if (sp + rank < stack_cap)
-                        stk[sp + rank] = load_ptr<LAYOUT>(nb, F, e);
+                        stk[sp + rank] = ref + e;
                     else
                         atomicOr(&ctrl->err, kErrStack);
                 }
@@ -186,58 +219,119 @@ int num_cus() {
 template <int G, int LAYOUT, int MODE>
 static hipError_t launch_g(const TreeView &t, const float4 *q, uint32_t nq, uint32_t *counts,
                            const uint64_t *offsets, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
-                           uint32_t slot, hipStream_t s) {
+                           uint32_t slot, const uint64_t *order, hipStream_t s) {
     const uint32_t stack_cap = stack_bound(t.height, t.fanout);
     const uint32_t groups_per_block = 256 / G;
     const size_t smem = (size_t)groups_per_block * stack_cap * sizeof(uint32_t);
     uint64_t want = ((uint64_t)nq + groups_per_block - 1) / groups_per_block;
     uint64_t persistent = (uint64_t)num_cus() * 8;
     uint32_t blocks = (uint32_t)(want < persistent ? want : persistent);
-    if (blocks == 0) blocks = 1;
+    blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // every XCD gets blocks
     hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE>), dim3(blocks), dim3(256), smem, s, t, q, nq,
-                       counts, offsets, ids, cap, ctrl, slot, stack_cap);
+                       counts, offsets, ids, cap, ctrl, slot, stack_cap, order);
     return hipGetLastError();
 }
 
 template <int G, int LAYOUT>
 static hipError_t launch_m(const TreeView &t, const float4 *q, uint32_t nq, int mode, uint32_t *counts,
                            const uint64_t *offsets, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
-                           uint32_t slot, hipStream_t s) {
+                           uint32_t slot, const uint64_t *order, hipStream_t s) {
     switch (mode) {
     case SEL_COUNT:
-        return launch_g<G, LAYOUT, SEL_COUNT>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, s);
+        return launch_g<G, LAYOUT, SEL_COUNT>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, order, s);
     case SEL_FILL:
-        return launch_g<G, LAYOUT, SEL_FILL>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, s);
+        return launch_g<G, LAYOUT, SEL_FILL>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, order, s);
     default:
-        return launch_g<G, LAYOUT, SEL_STATS>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, s);
+        return launch_g<G, LAYOUT, SEL_STATS>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, order, s);
     }
 }
 
 template <int G>
 static hipError_t launch_l(const TreeView &t, const float4 *q, uint32_t nq, int mode, uint32_t *counts,
                            const uint64_t *offsets, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
-                           uint32_t slot, hipStream_t s) {
+                           uint32_t slot, const uint64_t *order, hipStream_t s) {
     switch (t.layout) {
     case LAYOUT_AOS:
-        return launch_m<G, LAYOUT_AOS>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+        return launch_m<G, LAYOUT_AOS>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
     case LAYOUT_SOA:
-        return launch_m<G, LAYOUT_SOA>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+        return launch_m<G, LAYOUT_SOA>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
     default:
-        return launch_m<G, LAYOUT_D2>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+        return launch_m<G, LAYOUT_D2>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
     }
 }
 
 hipError_t launch_select_pass(const TreeView &t, const float4 *q, uint32_t nq, int mode,
                               uint32_t *counts, const uint64_t *offsets, uint32_t *ids,
-                              uint64_t cap, Ctrl *ctrl, uint32_t slot, hipStream_t s) {
+                              uint64_t cap, Ctrl *ctrl, uint32_t slot, const uint64_t *order, hipStream_t s) {
     switch (group_width(t.fanout)) {
     case 16:
-        return launch_l<16>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+        return launch_l<16>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
     case 32:
-        return launch_l<32>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+        return launch_l<32>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
     default:
-        return launch_l<64>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, s);
+        return launch_l<64>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
     }
+}
+
+// ---------------------------------------------------------------------------
+// query order for locality
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t spread16(uint32_t v) {
+    v &= 0xFFFFu;
+    v = (v | (v << 8)) & 0x00FF00FFu;
+    v = (v | (v << 4)) & 0x0F0F0F0Fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+// Morton (Z-order) code of each window center on a 65536 x 65536 grid over
+// the tree's MBR.  Only the processing order depends on it; no result does.
+__global__ void query_morton(const float4 *__restrict__ q, uint32_t nq, float lx, float ly, float sx, float sy,
+                             uint64_t *__restrict__ keys) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += gridDim.x * blockDim.x) {
+        const float4 w = q[i];
+        float cx = (0.5f * w.x + 0.5f * w.z - lx) * sx;
+        float cy = (0.5f * w.y + 0.5f * w.w - ly) * sy;
+        cx = fminf(fmaxf(cx, 0.f), 65535.f);   // NaN -> 0
+        cy = fminf(fmaxf(cy, 0.f), 65535.f);
+        const uint32_t code = spread16((uint32_t)cx) | (spread16((uint32_t)cy) << 1);
+        keys[i] = ((uint64_t)code << 32) | i;
+    }
+}
+
+static uint64_t al256(uint64_t b) { return (b + 255) & ~255ull; }
+
+uint64_t order_ws_bytes(uint64_t nq) {
+    const uint64_t he = radix_hist_elems(nq);
+    return al256(8 * nq) * 2 + al256(4 * he) + al256(8 * (he + 1)) + al256(8 * scan_tmp_elems(he + 1));
+}
+
+hipError_t launch_query_order(const float4 *q, uint32_t nq, const float *mbr, void *ws, const uint64_t **sorted,
+                              hipStream_t s) {
+    uint8_t *p = static_cast<uint8_t *>(ws);
+    uint64_t *keys = reinterpret_cast<uint64_t *>(p);
+    p += al256(8 * (uint64_t)nq);
+    uint64_t *tmp = reinterpret_cast<uint64_t *>(p);
+    p += al256(8 * (uint64_t)nq);
+    const uint64_t he = radix_hist_elems(nq);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(p);
+    p += al256(4 * he);
+    uint64_t *hscan = reinterpret_cast<uint64_t *>(p);
+    p += al256(8 * (he + 1));
+    uint64_t *stmp = reinterpret_cast<uint64_t *>(p);
+    float lx = mbr[0], ly = mbr[1], w = mbr[2] - mbr[0], h = mbr[3] - mbr[1];
+    const bool ok = (w > 0.f) && (h > 0.f) && (w < 3.0e38f) && (h < 3.0e38f);
+    const float sx = ok ? 65535.f / w : 0.f, sy = ok ? 65535.f / h : 0.f;
+    if (!ok) lx = ly = 0.f;
+    uint32_t blocks = (nq + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(query_morton, dim3(blocks), dim3(256), 0, s, q, nq, lx, ly, sx, sy, keys);
+    const int shifts[4] = {32, 40, 48, 56};
+    bool in_tmp = false;
+    hipError_t e = launch_radix_sort_u64(keys, tmp, nq, shifts, 4, hist, hscan, stmp, &in_tmp, s);
+    *sorted = in_tmp ? tmp : keys;
+    return e == hipSuccess ? hipGetLastError() : e;
 }
 
 }  // namespace rtk

@@ -194,15 +194,34 @@ int str_pack(const float *rects, uint64_t n, uint32_t F, uint32_t layout, Packed
     for (uint32_t l = 0; l < H; ++l) n_entries += items[l];
     pt.n_entries = n_entries;
 
+    // Final numbering: breadth first from the root, each node's children in
+    // its entry order, so the children of every node are contiguous and a
+    // child is found as (first child) + (entry slot).  newidx[l][k] is the
+    // global index of node k of level l (k in creation order).
+    std::vector<std::vector<uint32_t>> newidx(H);
+    for (uint32_t l = 0; l < H; ++l) newidx[l].assign(nodes_at[l], 0);
+    newidx[H - 1][0] = 0;
+    for (uint32_t l = H - 1; l >= 1; --l) {
+        // visit level-l nodes in their final order
+        std::vector<uint32_t> inv(nodes_at[l]);
+        for (uint64_t k = 0; k < nodes_at[l]; ++k) inv[newidx[l][k] - first_at[l]] = (uint32_t)k;
+        uint64_t next = first_at[l - 1];
+        const std::vector<uint32_t> &ord = orders[l];
+        for (uint64_t g = 0; g < nodes_at[l]; ++g) {
+            const uint64_t k = inv[g];
+            const uint64_t r0 = k * F, r1 = std::min<uint64_t>(items[l], r0 + F);
+            for (uint64_t r = r0; r < r1; ++r) newidx[l - 1][ord[r]] = (uint32_t)next++;
+        }
+    }
+
     for (uint32_t l = 0; l < H; ++l) {
         const std::vector<uint32_t> &ord = orders[l];
         const uint64_t c_l = items[l];
         const std::vector<float> &a = L_lx[l], &b = L_ly[l], &cc = L_hx[l], &d = L_hy[l];
-        const uint64_t child_base = l > 0 ? first_at[l - 1] : 0;
         parallel_for((nodes_at[l] + 4095) / 4096, [&](size_t blk) {
             const uint64_t k0 = blk * 4096, k1 = std::min<uint64_t>(nodes_at[l], k0 + 4096);
             for (uint64_t k = k0; k < k1; ++k) {
-                const uint64_t g = first_at[l] + k;
+                const uint64_t g = newidx[l][k];
                 uint8_t *node = pt.bytes.data() + g * pt.node_bytes;
                 float *f = reinterpret_cast<float *>(node);
                 uint32_t *u = reinterpret_cast<uint32_t *>(node);
@@ -218,7 +237,7 @@ int str_pack(const float *rects, uint64_t n, uint32_t F, uint32_t layout, Packed
                         vly = b[i];
                         vhx = cc[i];
                         vhy = d[i];
-                        p = l == 0 ? i : (uint32_t)(child_base + i);
+                        p = l == 0 ? i : newidx[l - 1][i];
                     }
                     if (layout == LAYOUT_SOA) {
                         f[e] = vlx;

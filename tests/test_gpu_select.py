@@ -126,6 +126,12 @@ def test_tree_invariants(rt, ora):
         ot = ora.tree_from_arrays(**ex)
         rc, msg = ora.check(ot, r)
         assert rc == 0, (n, F, layout, msg)
+        # the kernels rely on contiguous children: entry e of an internal node
+        # points at the node's first child + e
+        for u in np.nonzero(ex["level"] > 0)[0]:
+            f0, c = int(ex["first"][u]), int(ex["count"][u])
+            p = ex["ptr"][f0:f0 + c].astype(np.int64)
+            assert np.array_equal(p, p[0] + np.arange(c)), (n, F, layout, u)
         info = t.info()
         assert info.node_bytes == 20 * F
 
@@ -189,3 +195,16 @@ def test_visit_stats(rt):
     assert vn == info.n_nodes and ve == info.n_entries
     vn, ve = rt.visit_stats(t, np.array([[5, 5, 6, 6]], np.float32))
     assert vn == 1
+
+
+@pytest.mark.parametrize("fanout,layout", [(16, "soa"), (32, "aos"), (64, "d2"), (32, "soa")])
+def test_select_ordered_batch(rt, ora, fanout, layout):
+    """Batches of at least 8192 windows are processed in Morton order with
+    per-XCD slices; the CSR must be identical to the oracle's."""
+    r = rtgen.c2_rects(300_000, seed_base=2100)
+    q = rtgen.c2_queries(20_011, seed_base=2100)
+    say(f"case ordered batch F={fanout} {layout}")
+    t = rt.build_str(r, fanout, layout)
+    got = rt.range_select(t, q)
+    want = ora.select(ora.build_str(r, fanout), q)
+    assert_csr_equal(got, want, f"ordered F={fanout} {layout}")
