@@ -9,7 +9,8 @@
 //   class S    (<= 256 ids)     one wave per segment: the ids sit in
 //              registers (up to 4 per lane) and a bitonic network runs over
 //              them with __shfl_xor for cross-lane partners;
-//   class M    (257 .. 16384)   one block per segment: ids to registers, a
+//   class M    (257 .. 16384, in three block sizes: 128, 256 and 1024
+//              threads)             one block per segment: ids to registers, a
 //              counting sort on the top b id bits (2^b ~ length/4 buckets,
 //              LDS counters), scatter into LDS, then each id counts the
 //              smaller ids of its own bucket and is stored at bucket start +
@@ -27,7 +28,8 @@ namespace rtk {
 
 constexpr uint32_t kKeyPad = 0xFFFFFFFFu;   // never an object id (ids < 2^32 - 1)
 constexpr uint32_t kMidMax = 16384;         // longest class-M segment
-constexpr uint32_t kListCls = 5;            // S, M-small, M-large, L, fallback-L
+constexpr uint32_t kListCls = 6;            // S, M1, M2, M3, L, fallback-L
+constexpr uint32_t kFallback = 5;
 
 __device__ __forceinline__ uint32_t ceil_log2(uint32_t v) {
     uint32_t b = 0;
@@ -167,11 +169,11 @@ constexpr uint32_t kClsTile = 256 * kClsPer;       // queries per block
 __global__ void __launch_bounds__(256)
 seg_classify(const uint64_t *__restrict__ offsets, uint64_t nq, uint64_t cap, uint32_t *__restrict__ lists,
              uint32_t *__restrict__ counts) {
-    __shared__ uint32_t bcnt[4], gbase[4];
+    __shared__ uint32_t bcnt[5], gbase[5];
     if (offsets[nq] > cap) return;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    if (threadIdx.x < 4) bcnt[threadIdx.x] = 0;
+    if (threadIdx.x < 5) bcnt[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t q0 = (uint64_t)blockIdx.x * kClsTile;
     int cls[kClsPer];
@@ -182,12 +184,13 @@ seg_classify(const uint64_t *__restrict__ offsets, uint64_t nq, uint64_t cap, ui
         int c = -1;
         if (q < nq) {
             const uint64_t len = offsets[q + 1] - offsets[q];
-            if (len >= 2) c = len <= 256 ? 0 : (len <= 2048 ? 1 : (len <= kMidMax ? 2 : 3));
+            if (len >= 2)
+                c = len <= 256 ? 0 : (len <= 1024 ? 1 : (len <= 4096 ? 2 : (len <= kMidMax ? 3 : 4)));
         }
         cls[k] = c;
         pos[k] = 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 5; ++j) {
             const uint64_t m = __ballot(c == j);
             if (m == 0) continue;
             const uint32_t leader = (uint32_t)__builtin_ctzll(m);
@@ -198,7 +201,7 @@ seg_classify(const uint64_t *__restrict__ offsets, uint64_t nq, uint64_t cap, ui
         }
     }
     __syncthreads();
-    if (threadIdx.x < 4)
+    if (threadIdx.x < 5)
         gbase[threadIdx.x] = bcnt[threadIdx.x] ? atomicAdd(&counts[threadIdx.x], bcnt[threadIdx.x]) : 0u;
     __syncthreads();
 #pragma unroll
@@ -370,7 +373,18 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
         const uint32_t nbk = 1u << nb;
         for (uint32_t b = t; b < nbk; b += T) cnt[b] = 0;
         __syncthreads();
-        for (uint64_t i = t; i < c; i += T) atomicAdd(&cnt[(seg[i] >> shift) & (nbk - 1)], 1u);
+        constexpr uint32_t U = 8;   // ids in flight per thread
+        for (uint64_t i0 = t; i0 < c; i0 += (uint64_t)T * U) {
+            uint32_t kk[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * T;
+                kk[u] = i < c ? seg[i] : 0u;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (i0 + (uint64_t)u * T < c) atomicAdd(&cnt[(kk[u] >> shift) & (nbk - 1)], 1u);
+        }
         __syncthreads();
         const uint32_t big = block_scan_counters<T>(cnt, nbk, wsum, nullptr);
         // the rank step reads a whole bucket per id: long buckets go to the fallback
@@ -381,18 +395,36 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
             __syncthreads();
             continue;
         }
-        for (uint64_t i = t; i < c; i += T) {
-            const uint32_t key = seg[i];
-            tmp[atomicAdd(&cnt[(key >> shift) & (nbk - 1)], 1u)] = key;
+        for (uint64_t i0 = t; i0 < c; i0 += (uint64_t)T * U) {
+            uint32_t kk[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * T;
+                kk[u] = i < c ? seg[i] : 0u;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (i0 + (uint64_t)u * T < c) tmp[atomicAdd(&cnt[(kk[u] >> shift) & (nbk - 1)], 1u)] = kk[u];
         }
         __syncthreads();
-        for (uint64_t i = t; i < c; i += T) {
-            const uint32_t key = tmp[i];
-            const uint32_t b = (key >> shift) & (nbk - 1);
-            const uint32_t s0 = b ? cnt[b - 1] : 0u, s1 = cnt[b];
-            uint32_t r = 0;
-            for (uint32_t j = s0; j < s1; ++j) r += tmp[j] < key ? 1u : 0u;
-            seg[s0 + r] = key;
+        for (uint64_t i0 = t; i0 < c; i0 += (uint64_t)T * U) {
+            uint32_t kk[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint64_t i = i0 + (uint64_t)u * T;
+                kk[u] = i < c ? tmp[i] : 0u;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                if (i0 + (uint64_t)u * T < c) {
+                    const uint32_t key = kk[u];
+                    const uint32_t b = (key >> shift) & (nbk - 1);
+                    const uint32_t s0 = b ? cnt[b - 1] : 0u, s1 = cnt[b];
+                    uint32_t r = 0;
+                    for (uint32_t j = s0; j < s1; ++j) r += tmp[j] < key ? 1u : 0u;
+                    seg[s0 + r] = key;
+                }
+            }
         }
         __syncthreads();
     }
@@ -543,15 +575,18 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     const uint64_t cg = (nq + kClsTile - 1) / kClsTile;
     hipLaunchKernelGGL(seg_classify, dim3((uint32_t)cg), dim3(256), 0, s, offsets, nq, cap, lists, counts);
     hipLaunchKernelGGL(segsort_small, dim3(cus * 8), dim3(256), 0, s, offsets, ids, lists, counts + 0);
-    hipLaunchKernelGGL((segsort_mid<256, 8>), dim3(cus * 8), dim3(256), 0, s, offsets, ids, lists + nq, counts + 1,
+    hipLaunchKernelGGL((segsort_mid<128, 8>), dim3(cus * 16), dim3(128), 0, s, offsets, ids, lists + nq, counts + 1,
                        id_bits);
-    hipLaunchKernelGGL((segsort_mid<1024, 16>), dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + 2 * nq,
+    hipLaunchKernelGGL((segsort_mid<256, 16>), dim3(cus * 8), dim3(256), 0, s, offsets, ids, lists + 2 * nq,
                        counts + 2, id_bits);
-    hipLaunchKernelGGL(segsort_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + 3 * nq,
-                       counts + 3, lists + 4 * nq, counts + 4, id_bits);
-    hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + 4 * nq, counts + 4);
-    hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + 4 * nq,
-                       counts + 4);
+    hipLaunchKernelGGL((segsort_mid<1024, 16>), dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + 3 * nq,
+                       counts + 3, id_bits);
+    hipLaunchKernelGGL(segsort_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + 4 * nq,
+                       counts + 4, lists + kFallback * nq, counts + kFallback, id_bits);
+    hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + kFallback * nq,
+                       counts + kFallback);
+    hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + kFallback * nq,
+                       counts + kFallback);
     return hipGetLastError();
 }
 
