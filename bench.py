@@ -214,6 +214,57 @@ def batch_leg(rt, torch, args):
     return out
 
 
+def serve_leg(rt, torch, args):
+    import rtgen
+    from paper_2309_16913_amd.serve import Server
+    t0 = time.time()
+    big, jt = rtgen.c5_trees(args.serve_n, args.serve_join_n)
+    gen_s = time.time() - t0
+    t0 = time.time()
+    tb = rt.build_str(big, 32, "soa")
+    tj = rt.build_str(jt, 32, "soa")
+    build_s = time.time() - t0
+    del big, jt
+    info = tb.info()
+    out = {"workload": f"serve_clustered{args.serve_n}_f32_soa_plus_uniform{args.serve_join_n}_joins",
+           "gen_s": gen_s, "build_s": build_s, "tree_bytes": info.device_bytes, "tree_height": info.height,
+           "open_loop": [], "note": "latency = result in pinned host memory - scheduled arrival"}
+    srv = Server(tb, tj, nslots=3, max_windows=16384, pool_ids=1 << 27)
+    warm = rtgen.c5_requests(2000, rate=1e6, seed_base=5900, probe_n=10_000)
+    srv.run(warm)
+    for rate in args.serve_rates:
+        reqs = rtgen.c5_requests(args.serve_requests, rate=rate, seed_base=5000, probe_n=10_000)
+        log(f"[bench] serve open loop {rate:g}/s")
+        r = srv.run(reqs)
+        r["offered_rate"] = rate
+        out["open_loop"].append(r)
+    # closed loop: every request is waiting at t = 0 (saturation throughput)
+    reqs = rtgen.c5_requests(args.serve_requests, rate=1e12, seed_base=5000, probe_n=10_000)
+    log("[bench] serve closed loop")
+    r = srv.run(reqs)
+    sel = np.concatenate([q.payload for q in reqs if q.kind == "select"])
+    probes = [q.payload for q in reqs if q.kind == "join"]
+    vn, ve = rt.visit_stats(tb, sel)
+    bytes_ = 16 * sel.shape[0] + 20 * ve + 8 * vn
+    for p_ in probes:
+        a, b_ = rt.visit_stats(tj, p_)
+        bytes_ += 16 * p_.shape[0] + 20 * b_ + 8 * a
+    bytes_ += 4 * r["ids"] + 8 * r["batches"]
+    r["algorithmic_bytes"] = bytes_
+    r["algorithmic_GBps"] = bytes_ / r["wall_s"] / 1e9
+    r["hbm_frac"] = r["algorithmic_GBps"] / HBM_PEAK_GBS
+    out["closed_loop"] = r
+    # unbatched baseline: one request per launch, one stream
+    base = Server(tb, tj, nslots=1, max_windows=16384, pool_ids=1 << 27, one_per_batch=True)
+    reqs = rtgen.c5_requests(min(args.serve_requests, 4000), rate=1e12, seed_base=5000, probe_n=10_000)
+    log("[bench] serve unbatched baseline")
+    rb = base.run(reqs)
+    out["unbatched_closed_loop"] = rb
+    out["speedup_vs_unbatched"] = (r["throughput_req_per_s"] / rb["throughput_req_per_s"]
+                                   if rb["throughput_req_per_s"] else None)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -223,13 +274,17 @@ def main():
     ap.add_argument("--nq", type=int, default=1_000_000)
     ap.add_argument("--fanout", type=int, default=32)
     ap.add_argument("--layout", default="soa")
-    ap.add_argument("--legs", default="join,batch,cpu")
+    ap.add_argument("--legs", default="join,batch,serve,cpu")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--join-n", type=int, default=2_000_000)
     ap.add_argument("--join-reps", type=int, default=5)
     ap.add_argument("--batch-trees", type=int, default=256)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serve-n", type=int, default=50_000_000)
+    ap.add_argument("--serve-join-n", type=int, default=5_000_000)
+    ap.add_argument("--serve-requests", type=int, default=20_000)
+    ap.add_argument("--serve-rates", type=float, nargs="*", default=[1e4, 1e5, 1e6])
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -284,6 +339,14 @@ def main():
     if "batch" in legs:
         log("[bench] batch leg")
         result["legs"]["batch"] = batch_leg(rt, torch, args)
+        torch.cuda.empty_cache()
+    if "serve" in legs:
+        log("[bench] serve leg")
+        sv = serve_leg(rt, torch, args)
+        result["legs"]["serve"] = sv
+        ol = [x for x in sv["open_loop"] if x.get("select_p99_ms") is not None]
+        if ol:
+            result["p99_ms"] = {str(int(x["offered_rate"])): x["select_p99_ms"] for x in ol}
     print(json.dumps(result), flush=True)
 
 

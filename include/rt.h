@@ -202,6 +202,13 @@ int rt_batch_result(rt_batch *b, uint32_t i, rt_ids **out);
 
 int rt_tree_stats(const rt_tree *t, rt_tree_info *info);
 
+/* Work mapping of later selects on this tree (never changes a result).
+ * A query whose walk reaches at least kmin parents-of-leaves nodes is split
+ * into one work item per such subtree, so many lane groups share one large
+ * window instead of one group walking it alone; kmin = 0 keeps one group per
+ * query (the default).  Not to be called while selects on the tree run. */
+int rt_tree_set_split(rt_tree *t, uint32_t kmin);
+
 /* Copy the tree to host arrays in a neutral node/entry form: per node
  * (root = node 0) level (0 = leaf), entry count and index of its first entry;
  * per entry the MBR and ptr (object id at a leaf, child node otherwise).

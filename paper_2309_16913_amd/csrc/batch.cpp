@@ -238,11 +238,13 @@ extern "C" int rt_batch_run_plain(rt_batch *b, void *stream) {
         const uint64_t base = b->id_base[i], cnt = b->id_count[i];
         const uint64_t cap = base < b->cap ? std::min<uint64_t>(cnt, b->cap - base) : 0;
         e = launch_zero(ctrl->work, sizeof(ctrl->work), s);
-        if (e == hipSuccess) e = launch_zero(ctrl->xwork, sizeof(ctrl->xwork), s);
-        if (e == hipSuccess) e = launch_select_pass(v, q, (uint32_t)n, SEL_COUNT, counts, nullptr, nullptr, 0, ctrl, 0, nullptr, s);
+        if (e == hipSuccess) e = launch_zero(ctrl->xwork, sizeof(ctrl->xwork) + sizeof(ctrl->hwork), s);
+        if (e == hipSuccess) e = launch_select_pass(v, q, (uint32_t)n, SEL_COUNT, counts, nullptr, nullptr, 0, ctrl, 0, SelectPlan(),
+                                                    (uint32_t)n, s);
         if (e == hipSuccess) e = launch_scan_u32(counts, n, off, static_cast<uint64_t *>(b->d_scan), s);
         if (e == hipSuccess)
-            e = launch_select_pass(v, q, (uint32_t)n, SEL_FILL, counts, off, ids + base, cap, ctrl, 1, nullptr, s);
+            e = launch_select_pass(v, q, (uint32_t)n, SEL_FILL, counts, off, ids + base, cap, ctrl, 1, SelectPlan(),
+                                   (uint32_t)n, s);
         if (e == hipSuccess)
             e = launch_segsort(off, n, ids + base, scratch + base, cap, static_cast<uint32_t *>(b->d_lists),
                                id_bits_for(b->trees[i]->n_objects), s);

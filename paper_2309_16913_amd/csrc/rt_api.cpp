@@ -127,25 +127,47 @@ hipError_t DevBuf::alloc(size_t bytes) {
 
 static uint64_t align256(uint64_t b) { return (b + 255) & ~255ull; }
 
+// Split work items granted per select: at most 4 per query (and 65536),
+// divided evenly over the kXcds lists.
+static uint64_t split_hcap(uint64_t nq) {
+    const uint64_t b = nq * 4 > 65536 ? nq * 4 : 65536;
+    return (b + kXcds - 1) / kXcds;
+}
+static uint64_t split_budget(uint64_t nq) { return split_hcap(nq) * kXcds; }
+
 // Workspace layout of a select:
-//   Ctrl | counts[nq] | scan tmp | sort lists | query order | sort scratch[cap]
+//   Ctrl | counts[nq] | scan tmp | sort lists | query order | slots per query
+//   | slot offsets per query | slot counts | slot offsets | split items
+//   | slot scan tmp | sort scratch[cap]
 struct SelWs {
     Ctrl *ctrl;
     uint32_t *counts;
     uint64_t *scan_tmp;
     uint32_t *lists;
     void *order;
+    uint32_t *nslots;
+    uint64_t *slot_first;
+    uint32_t *slot_counts;
+    uint64_t *slot_off;
+    uint4 *heavy;
+    uint64_t *slot_scan_tmp;
     uint32_t *scratch;
+    uint64_t nslot_max;
 };
 
 static uint64_t sel_ws_bytes(uint64_t nq, uint64_t cap) {
+    const uint64_t S = nq + split_budget(nq);
     return align256(sizeof(Ctrl)) + align256(4 * nq) + align256(8 * scan_tmp_elems(nq)) +
-           align256(4 * segsort_ws_elems(nq)) + align256(order_ws_bytes(nq)) + align256(4 * cap);
+           align256(4 * segsort_ws_elems(nq)) + align256(order_ws_bytes(nq)) + align256(4 * nq) +
+           align256(8 * (nq + 1)) + align256(4 * S) + align256(8 * (S + 1)) + align256(16 * split_budget(nq)) +
+           align256(8 * scan_tmp_elems(S)) + align256(4 * cap);
 }
 
 static SelWs sel_ws(void *w, uint64_t nq) {
+    const uint64_t S = nq + split_budget(nq);
     uint8_t *p = static_cast<uint8_t *>(w);
     SelWs s;
+    s.nslot_max = S;
     s.ctrl = reinterpret_cast<Ctrl *>(p);
     p += align256(sizeof(Ctrl));
     s.counts = reinterpret_cast<uint32_t *>(p);
@@ -156,6 +178,18 @@ static SelWs sel_ws(void *w, uint64_t nq) {
     p += align256(4 * segsort_ws_elems(nq));
     s.order = p;
     p += align256(order_ws_bytes(nq));
+    s.nslots = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * nq);
+    s.slot_first = reinterpret_cast<uint64_t *>(p);
+    p += align256(8 * (nq + 1));
+    s.slot_counts = reinterpret_cast<uint32_t *>(p);
+    p += align256(4 * S);
+    s.slot_off = reinterpret_cast<uint64_t *>(p);
+    p += align256(8 * (S + 1));
+    s.heavy = reinterpret_cast<uint4 *>(p);
+    p += align256(16 * split_budget(nq));
+    s.slot_scan_tmp = reinterpret_cast<uint64_t *>(p);
+    p += align256(8 * scan_tmp_elems(S));
     s.scratch = reinterpret_cast<uint32_t *>(p);
     return s;
 }
@@ -177,6 +211,7 @@ int rtk::upload_packed(PackedTree &pt, rt_tree **out) {
     t->n_objects = pt.n_objects;
     t->n_entries = pt.n_entries;
     for (int i = 0; i < 4; ++i) t->mbr[i] = pt.mbr[i];
+    for (int i = 0; i < 33; ++i) t->level_start[i] = pt.level_start[i];
     hipError_t e = hipMalloc(&t->d_nodes, pt.bytes.size());
     if (e == hipSuccess) e = hipMalloc(&t->d_meta, pt.meta.size() * 4);
     if (e == hipSuccess) e = hipMemcpy(t->d_nodes, pt.bytes.data(), pt.bytes.size(), hipMemcpyHostToDevice);
@@ -210,6 +245,12 @@ extern "C" int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uin
     } catch (...) {
         return fail(RT_EDEVICE, "unexpected failure");
     }
+}
+
+extern "C" int rt_tree_set_split(rt_tree *t, uint32_t kmin) {
+    if (!t) return fail(RT_EINVAL, "tree is NULL");
+    t->split_kmin = kmin;
+    return RT_OK;
 }
 
 extern "C" int rt_tree_stats(const rt_tree *t, rt_tree_info *info) {
@@ -281,32 +322,101 @@ static int check_nq(uint64_t nq) {
     return RT_OK;
 }
 
-int rtk::enqueue_select(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
-                        uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, bool count_only,
-                        uint32_t *d_counts_out, void *const *events) {
+// Split plan of a select on tree t: queries whose walk reaches at least
+// t->split_kmin parents-of-leaves nodes run as one work item per such node.
+struct SplitCfg {
+    bool on = false;
+    uint32_t split_first = 0, kmin = 0, budget = 0;
+    float min_area = 0.f;
+};
+
+static SplitCfg split_cfg(const rt_tree *t, uint64_t nq) {
+    SplitCfg c;
+    if (t->split_kmin == 0 || t->height < 3 || nq == 0 || t->n_objects == 0) return c;
+    c.on = true;
+    c.split_first = t->level_start[2];   // first grandparent-of-leaves node
+    c.kmin = t->split_kmin;
+    c.budget = (uint32_t)split_hcap(nq);   // per list
+    // prefilter: a window smaller than 1/64 of the area that kmin full
+    // parents-of-leaves cover on average cannot reach kmin of them
+    const double area = (double)(t->mbr[2] - t->mbr[0]) * (double)(t->mbr[3] - t->mbr[1]);
+    const double per = (double)t->fanout * t->fanout / (double)t->n_objects;
+    const double a = area * per * c.kmin / 64.0;
+    c.min_area = (area > 0 && area < 1e300 && a < 3e38) ? (float)a : 0.f;
+    return c;
+}
+
+int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
+                              uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, int stage,
+                              uint32_t *d_counts_out, void *const *events) {
     SelWs w = sel_ws(work, nq);
     const TreeView v = view_of(t);
-    uint32_t *counts = d_counts_out ? d_counts_out : w.counts;
+    const SplitCfg sc = d_counts_out ? SplitCfg() : split_cfg(t, nq);
     auto mark = [&](int k) -> hipError_t {
         return events && events[k] ? hipEventRecord(static_cast<hipEvent_t>(events[k]), s) : hipSuccess;
     };
-    hipError_t e = launch_zero(w.ctrl, sizeof(Ctrl), s);
-    if (e == hipSuccess) e = mark(0);
-    const uint64_t *order = nullptr;
-    if (e == hipSuccess && nq >= kOrderMinQueries) e = launch_query_order(dq, (uint32_t)nq, t->mbr, w.order, &order, s);
-    if (e == hipSuccess)
-        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_COUNT, counts, nullptr, nullptr, 0, w.ctrl, 0, order, s);
-    if (e == hipSuccess) e = mark(1);
-    if (count_only || e != hipSuccess) return e == hipSuccess ? RT_OK : hip_fail(e, "count pass");
-    e = launch_scan_u32(counts, nq, d_off, w.scan_tmp, s);
-    if (e == hipSuccess) e = mark(2);
-    if (e == hipSuccess)
-        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_FILL, counts, d_off, d_ids, cap, w.ctrl, 1, order, s);
-    if (e == hipSuccess) e = mark(3);
-    if (e == hipSuccess) e = launch_segsort(d_off, nq, d_ids, w.scratch, cap, w.lists, id_bits_for(t->n_objects), s);
-    if (e == hipSuccess) e = mark(4);
-    if (e == hipSuccess && d_status) e = launch_finalize(d_off, nq, cap, w.ctrl, d_status, s);
-    return e == hipSuccess ? RT_OK : hip_fail(e, "select launch");
+    hipError_t e = hipSuccess;
+    SelectPlan plan;
+    if (sc.on) {
+        plan.slot_first = w.slot_first;
+        plan.heavy = w.heavy;
+        plan.hcap = sc.budget;
+    }
+    if (stage & 1) {   // count stage: ctrl, order, split, count pass, offsets
+        uint32_t *counts = d_counts_out ? d_counts_out : (sc.on ? w.slot_counts : w.counts);
+        e = launch_zero(w.ctrl, sizeof(Ctrl), s);
+        if (e == hipSuccess) e = mark(0);
+        const uint64_t *order = nullptr;
+        if (e == hipSuccess && nq >= kOrderMinQueries)
+            e = launch_query_order(dq, (uint32_t)nq, t->mbr, w.order, &order, s);
+        plan.order = order;
+        if (sc.on) {
+            if (e == hipSuccess)
+                e = launch_split(v, dq, (uint32_t)nq, 0, sc.split_first, sc.kmin, sc.budget, sc.min_area, w.nslots,
+                                 nullptr, nullptr, order, w.ctrl, s);
+            if (e == hipSuccess) e = launch_scan_u32(w.nslots, nq, w.slot_first, w.scan_tmp, s);
+            // phase 1 walks the XCD slices again: reset their counters
+            if (e == hipSuccess) e = launch_zero(w.ctrl->xwork[2], sizeof(w.ctrl->xwork[2]), s);
+            if (e == hipSuccess)
+                e = launch_split(v, dq, (uint32_t)nq, 1, sc.split_first, sc.kmin, sc.budget, sc.min_area, nullptr,
+                                 w.slot_first, w.heavy, order, w.ctrl, s);
+            if (e == hipSuccess) e = launch_zero(w.slot_counts, 4 * w.nslot_max, s);
+        }
+        if (e == hipSuccess)
+            e = launch_select_pass(v, dq, (uint32_t)nq, SEL_COUNT, counts, nullptr, nullptr, 0, w.ctrl, 0, plan,
+                                   (uint32_t)nq, s);
+        if (e == hipSuccess) e = mark(1);
+        if (d_counts_out || e != hipSuccess) return e == hipSuccess ? RT_OK : hip_fail(e, "count pass");
+        if (sc.on) {
+            e = launch_scan_u32(w.slot_counts, w.nslot_max, w.slot_off, w.slot_scan_tmp, s);
+            if (e == hipSuccess) e = launch_gather_offsets(w.slot_first, w.slot_off, (uint32_t)nq, d_off, s);
+        } else {
+            e = launch_scan_u32(w.counts, nq, d_off, w.scan_tmp, s);
+        }
+        if (e == hipSuccess) e = mark(2);
+        if (e != hipSuccess) return hip_fail(e, "count stage");
+    }
+    if (stage & 2) {   // fill stage: fill pass, sort, status
+        // the processing order written by the count stage is still in the workspace
+        if (nq >= kOrderMinQueries) plan.order = query_order_result(w.order, nq);
+        const uint64_t *fo = sc.on ? w.slot_off : d_off;
+        const uint32_t no = sc.on ? (uint32_t)w.nslot_max : (uint32_t)nq;
+        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_FILL, nullptr, fo, d_ids, cap, w.ctrl, 1, plan, no, s);
+        if (e == hipSuccess) e = mark(3);
+        if (e == hipSuccess)
+            e = launch_segsort(d_off, nq, d_ids, w.scratch, cap, w.lists, id_bits_for(t->n_objects), s);
+        if (e == hipSuccess) e = mark(4);
+        if (e == hipSuccess && d_status) e = launch_finalize(d_off, nq, cap, w.ctrl, d_status, s);
+        if (e != hipSuccess) return hip_fail(e, "fill stage");
+    }
+    return RT_OK;
+}
+
+int rtk::enqueue_select(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
+                        uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, bool count_only,
+                        uint32_t *d_counts_out, void *const *events) {
+    return enqueue_select_stage(t, dq, nq, d_off, d_ids, cap, work, d_status, s, count_only ? 1 : 3,
+                                count_only ? d_counts_out : nullptr, events);
 }
 
 extern "C" int rt_range_select_device_timed(const rt_tree *t, const float *d_queries, uint64_t nq,
@@ -372,34 +482,26 @@ extern "C" int rt_range_select(const rt_tree *t, const float *queries, uint64_t 
         if (e == hipSuccess) e = work.alloc(sel_ws_bytes(nq, 0));
         if (e == hipSuccess) e = hipMemcpy(dq.p, queries, nq * 16, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "select setup");
-        // count pass + scan, then size the output exactly
+        // count stage, then size the output exactly and run the fill stage
         SelWs w = sel_ws(work.p, nq);
-        const TreeView v = view_of(t);
         hipStream_t s = nullptr;
-        e = launch_zero(w.ctrl, sizeof(Ctrl), s);
-        const uint64_t *order = nullptr;
-        if (e == hipSuccess && nq >= kOrderMinQueries)
-            e = launch_query_order(static_cast<const float4 *>(dq.p), (uint32_t)nq, t->mbr, w.order, &order, s);
-        if (e == hipSuccess)
-            e = launch_select_pass(v, static_cast<const float4 *>(dq.p), (uint32_t)nq, SEL_COUNT, w.counts, nullptr,
-                                   nullptr, 0, w.ctrl, 0, order, s);
-        if (e == hipSuccess) e = launch_scan_u32(w.counts, nq, static_cast<uint64_t *>(doff.p), w.scan_tmp, s);
+        int rc = enqueue_select_stage(t, static_cast<const float4 *>(dq.p), nq, static_cast<uint64_t *>(doff.p),
+                                      nullptr, 0, work.p, nullptr, s, 1, nullptr, nullptr);
+        if (rc) return rc;
         uint64_t total = 0;
-        if (e == hipSuccess)
-            e = hipMemcpy(&total, static_cast<uint64_t *>(doff.p) + nq, 8, hipMemcpyDeviceToHost);
+        e = hipMemcpy(&total, static_cast<uint64_t *>(doff.p) + nq, 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "count pass");
-        DevBuf scratch;
+        DevBuf work2;
         e = dids.alloc(total * 4);
-        if (e == hipSuccess) e = scratch.alloc(total * 4);
+        if (e == hipSuccess) e = work2.alloc(sel_ws_bytes(nq, total));
+        if (e == hipSuccess) e = hipMemcpy(work2.p, work.p, sel_ws_bytes(nq, 0), hipMemcpyDeviceToDevice);
         if (e != hipSuccess) return hip_fail(e, "allocating the result");
-        e = launch_select_pass(v, static_cast<const float4 *>(dq.p), (uint32_t)nq, SEL_FILL, w.counts,
-                               static_cast<uint64_t *>(doff.p), static_cast<uint32_t *>(dids.p), total, w.ctrl, 1,
-                               order, s);
-        if (e == hipSuccess)
-            e = launch_segsort(static_cast<uint64_t *>(doff.p), nq, static_cast<uint32_t *>(dids.p),
-                               static_cast<uint32_t *>(scratch.p), total, w.lists, id_bits_for(t->n_objects), s);
+        w = sel_ws(work2.p, nq);
+        rc = enqueue_select_stage(t, static_cast<const float4 *>(dq.p), nq, static_cast<uint64_t *>(doff.p),
+                                  static_cast<uint32_t *>(dids.p), total, work2.p, nullptr, s, 2, nullptr, nullptr);
+        if (rc) return rc;
         Ctrl hc;
-        if (e == hipSuccess) e = hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+        e = hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "fill pass");
         if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
         rt_ids *r = nullptr;
@@ -435,7 +537,7 @@ extern "C" int rt_select_visit_stats(const rt_tree *t, const float *queries, uin
     if (e == hipSuccess) e = launch_zero(w.ctrl, sizeof(Ctrl), nullptr);
     if (e == hipSuccess)
         e = launch_select_pass(view_of(t), static_cast<const float4 *>(dq.p), (uint32_t)nq, SEL_STATS, w.counts,
-                               nullptr, nullptr, 0, w.ctrl, 2, nullptr, nullptr);
+                               nullptr, nullptr, 0, w.ctrl, 2, SelectPlan(), (uint32_t)nq, nullptr);
     Ctrl hc;
     if (e == hipSuccess) e = hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "visit statistics");

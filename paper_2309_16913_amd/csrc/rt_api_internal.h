@@ -14,6 +14,9 @@ struct rt_tree {
     uint32_t fanout = 0, layout = 0, height = 0, n_nodes = 0, first_leaf = 0, node_bytes = 0;
     uint64_t n_objects = 0, n_entries = 0;
     float mbr[4] = {0, 0, 0, 0};
+    uint32_t level_start[33] = {0};   // first node index of each level (0 = leaves)
+    uint32_t split_kmin = 0;          // mapping: split queries reaching >= this many
+                                      // parents-of-leaves (0 = one group per query)
     void *d_nodes = nullptr;   // n_nodes * node_bytes
     void *d_meta = nullptr;    // n_nodes uint32: count | level << 8
 };
@@ -40,6 +43,11 @@ int check_rects(const float *r, uint64_t n, const char *what);
 TreeView view_of(const rt_tree *t);
 int upload_packed(PackedTree &pt, rt_tree **out);
 int make_ids(uint64_t nq, uint64_t total, rt_ids **out);
+// stage bit 1: count stage (order, split, count pass, offsets); bit 2: fill
+// stage (fill pass, sort, status).  d_counts_out: count-only mode.
+int enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
+                         uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, int stage,
+                         uint32_t *d_counts_out, void *const *events);
 int enqueue_select(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
                    uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, bool count_only,
                    uint32_t *d_counts_out, void *const *events = nullptr);

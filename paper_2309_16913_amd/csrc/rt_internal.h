@@ -37,6 +37,10 @@ struct Ctrl {
     uint64_t stats[4];       // visit statistics
     // per-pass, per-XCD query counters, one 128-byte cache line each
     uint32_t xwork[3][kXcds][32];
+    // split work items live in kXcds lists (by the XCD slice of their query)
+    uint32_t hwork[3][kXcds][32];    // per-pass grab counters per list
+    uint32_t hlist[kXcds][32];       // items per list
+    uint32_t budget_used[kXcds][32]; // items granted per list
 };
 
 constexpr uint32_t kErrStack = 1u;     // traversal stack would overflow
@@ -56,19 +60,44 @@ inline uint32_t group_width(uint32_t fanout) {
 // ---- select -------------------------------------------------------------
 enum SelectMode : int { SEL_COUNT = 0, SEL_FILL = 1, SEL_STATS = 2 };
 
-// One traversal pass over all queries (persistent grid).  order (may be
-// NULL): nq 64-bit keys whose low 32 bits list the queries in the order they
-// should be processed; XCD x takes the x-th eighth of that order first and
-// then helps the others.
+// How a traversal pass finds its work.
+//   order       NULL or nq 64-bit keys whose low 32 bits list the queries in
+//               processing order; XCD x takes the x-th eighth first.
+//   slot_first  NULL (query q writes output slot q) or nq+1 offsets: query q
+//               owns slots [slot_first[q], slot_first[q+1]).
+//   heavy       split work items {query, subtree root, slot, 0} in kXcds
+//               lists of hcap entries (list x: queries of order slice x,
+//               length in Ctrl::hlist[x]); handed out before whole queries,
+//               XCD x draining list x first.
+struct SelectPlan {
+    const uint64_t *order = nullptr;
+    const uint64_t *slot_first = nullptr;
+    const uint4 *heavy = nullptr;
+    uint32_t hcap = 0;
+};
+
+// One traversal pass (persistent grid).  counts/offsets are indexed by output
+// slot; noffsets = number of slots (offsets[noffsets] = total).
 hipError_t launch_select_pass(const TreeView &t, const float4 *q, uint32_t nq, int mode,
                               uint32_t *counts, const uint64_t *offsets, uint32_t *ids,
                               uint64_t ids_capacity, Ctrl *ctrl, uint32_t work_slot,
-                              const uint64_t *order, hipStream_t s);
+                              const SelectPlan &plan, uint32_t noffsets, hipStream_t s);
+
+// Split pre-pass (phase 0: slots per query; phase 1: work items).  Queries
+// are taken in the plan's order with the same XCD slices as the passes;
+// hcap: items per list (the budget of each list).
+hipError_t launch_split(const TreeView &t, const float4 *q, uint32_t nq, int phase, uint32_t split_parent,
+                        uint32_t kmin, uint32_t hcap, float min_area, uint32_t *nslots,
+                        const uint64_t *slot_first, uint4 *heavy, const uint64_t *order, Ctrl *ctrl,
+                        hipStream_t s);
+hipError_t launch_gather_offsets(const uint64_t *slot_first, const uint64_t *slot_off, uint32_t nq,
+                                 uint64_t *offsets, hipStream_t s);
 
 // Query order for locality: 64-bit keys (Morton code of the window center
 // over the tree's MBR) << 32 | query index, sorted.  tmp: 2*nq uint64 plus
 // radix temporaries (order_ws_bytes).  *sorted receives the sorted keys.
 uint64_t order_ws_bytes(uint64_t nq);
+const uint64_t *query_order_result(const void *ws, uint64_t nq);   // where the sorted keys end up
 hipError_t launch_query_order(const float4 *q, uint32_t nq, const float *mbr, void *ws,
                               const uint64_t **sorted, hipStream_t s);
 constexpr uint32_t kOrderMinQueries = 8192;   // smaller batches keep input order

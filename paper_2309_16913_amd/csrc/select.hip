@@ -71,26 +71,59 @@ __device__ __forceinline__ uint32_t load_ptr(const uint8_t *__restrict__ node, u
 // the following slices in turn.  `visited` counts the slices found empty.
 // Returns nq when everything has been handed out.
 __device__ __forceinline__ uint32_t grab_query(Ctrl *ctrl, uint32_t slot, uint32_t nq, const uint64_t *order,
-                                               uint32_t home, uint32_t &visited) {
+                                               uint32_t home, uint32_t &visited, uint32_t *slice = nullptr) {
     while (visited < kXcds) {
         const uint32_t x = (home + visited) % kXcds;
         const uint32_t b0 = (uint32_t)(((uint64_t)x * nq) / kXcds);
         const uint32_t b1 = (uint32_t)(((uint64_t)(x + 1) * nq) / kXcds);
         const uint32_t k = atomicAdd(&ctrl->xwork[slot][x][0], 1u);
-        if (k < b1 - b0) return order ? (uint32_t)order[b0 + k] : b0 + k;
+        if (k < b1 - b0) {
+            if (slice) *slice = x;
+            return order ? (uint32_t)order[b0 + k] : b0 + k;
+        }
         visited += 1;
     }
     return nq;
+}
+
+// Work unit of a pass: a query started at the root, or -- for a query split
+// into subtrees -- one (query, subtree root) item.  `oslot` is the output
+// slot (count pass: index into counts; fill pass: index into offsets).
+struct Unit {
+    uint32_t q, node, oslot;
+};
+
+// Next unit for a group leader: split items first (they are the long ones),
+// then whole queries from the XCD slices, skipping queries that were split.
+__device__ __forceinline__ Unit next_unit(Ctrl *ctrl, uint32_t slot, uint32_t nq, const SelectPlan &plan,
+                                          uint32_t home, uint32_t &visited, uint32_t &hvisited) {
+    while (hvisited < kXcds) {
+        const uint32_t x = (home + hvisited) % kXcds;
+        const uint32_t nh = ctrl->hlist[x][0];
+        const uint32_t k = atomicAdd(&ctrl->hwork[slot][x][0], 1u);
+        if (k < nh) {
+            const uint4 it = plan.heavy[(uint64_t)x * plan.hcap + k];
+            return Unit{it.x, it.y, it.z};
+        }
+        hvisited += 1;
+    }
+    while (true) {
+        const uint32_t q = grab_query(ctrl, slot, nq, plan.order, home, visited);
+        if (q >= nq) return Unit{nq, 0u, 0u};
+        if (!plan.slot_first) return Unit{q, 0u, q};
+        const uint64_t s0 = plan.slot_first[q], s1 = plan.slot_first[q + 1];
+        if (s1 - s0 == 1) return Unit{q, 0u, (uint32_t)s0};
+    }
 }
 
 template <int G, int LAYOUT, int MODE>
 __global__ void __launch_bounds__(256)
 select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *__restrict__ counts,
               const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint64_t cap,
-              Ctrl *__restrict__ ctrl, uint32_t slot, uint32_t stack_cap, const uint64_t *__restrict__ order) {
+              Ctrl *__restrict__ ctrl, uint32_t slot, uint32_t stack_cap, SelectPlan plan, uint32_t noffsets) {
     extern __shared__ uint32_t smem[];
     if constexpr (MODE == SEL_FILL) {
-        if (offsets[nq] > cap) return;   // result does not fit: leave ids untouched
+        if (offsets[noffsets] > cap) return;   // result does not fit: leave ids untouched
     }
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t e = lane & (G - 1);
@@ -103,7 +136,8 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
     // XCD-relative cursor over the eight slices of the processing order
     const uint32_t home = blockIdx.x % kXcds;
     uint32_t visited = 0;
-    uint32_t qi = 0;
+    uint32_t hvisited = plan.heavy ? 0u : kXcds;
+    uint32_t oslot = 0;
     bool have = false, done = false;
     uint32_t sp = 0;
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -114,21 +148,23 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
         if (!done && sp == 0) {
             if (have) {
                 if constexpr (MODE == SEL_COUNT) {
-                    if (e == 0) counts[qi] = (uint32_t)pos;
+                    if (e == 0) counts[oslot] = (uint32_t)pos;
                 }
             }
-            uint32_t nxt = 0;
-            if (e == 0) nxt = grab_query(ctrl, slot, nq, order, home, visited);
-            nxt = __shfl(nxt, (int)gbase);
-            if (nxt < nq) {
-                qi = nxt;
+            Unit u{nq, 0u, 0u};
+            if (e == 0) u = next_unit(ctrl, slot, nq, plan, home, visited, hvisited);
+            u.q = __shfl(u.q, (int)gbase);
+            u.node = __shfl(u.node, (int)gbase);
+            u.oslot = __shfl(u.oslot, (int)gbase);
+            if (u.q < nq) {
+                oslot = u.oslot;
                 have = true;
-                q = qs[qi];
-                stk[0] = 0u;   // root
+                q = qs[u.q];
+                stk[0] = u.node;
                 sp = 1;
                 if constexpr (MODE == SEL_FILL) {
-                    pos = offsets[qi];
-                    end = offsets[qi + 1];
+                    pos = offsets[oslot];
+                    end = offsets[oslot + 1];
                 } else {
                     pos = 0;
                 }
@@ -204,6 +240,124 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
     }
 }
 
+// Split pre-pass.  Walks only the internal levels above the parents of leaves
+// (`split_parent` is the first node of the level above them) and finds the
+// parents-of-leaves nodes a query reaches.  PHASE 0 counts them: a query reaching at least
+// kmin of them (while the item budget lasts) gets one output slot per such
+// node, others one slot.  PHASE 1 (after a scan of the slot counts) writes
+// one work item {query, node, slot} per node of every split query.  Both
+// phases walk identically, so the items match the counts.
+template <int G, int LAYOUT, int PHASE>
+__global__ void __launch_bounds__(256)
+split_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t split_parent, uint32_t kmin,
+             uint32_t hcap, float min_area, uint32_t *__restrict__ nslots, const uint64_t *__restrict__ slot_first,
+             uint4 *__restrict__ heavy, const uint64_t *__restrict__ order, Ctrl *__restrict__ ctrl,
+             uint32_t stack_cap) {
+    extern __shared__ uint32_t smem[];
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t e = lane & (G - 1);
+    const uint32_t gbase = lane & ~(uint32_t)(G - 1);
+    uint32_t *stk = smem + (threadIdx.x / G) * stack_cap;
+    const uint32_t F = t.fanout;
+    const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+    const uint64_t below = (e == 0) ? 0ull : (~0ull >> (64 - e));
+    uint32_t qi = 0, sp = 0, k = 0, base = 0, slot0 = 0, list = 0;
+    bool have = false, done = false;
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t home = blockIdx.x % kXcds;
+    uint32_t visited = 0;
+    while (true) {
+        if (!done && sp == 0) {
+            if (have && PHASE == 0 && e == 0) {
+                uint32_t ns = 1;
+                if (k >= kmin) {
+                    const uint32_t old = atomicAdd(&ctrl->budget_used[list][0], k);
+                    if (old + k <= hcap) ns = k;
+                }
+                nslots[qi] = ns;
+            }
+            have = false;
+            uint32_t nxt = 0, b = 0, sl = 0;
+            if (e == 0) {
+                while (true) {
+                    nxt = grab_query(ctrl, 2, nq, order, home, visited, &sl);
+                    if (nxt >= nq) break;
+                    const float4 w = qs[nxt];
+                    if constexpr (PHASE == 0) {
+                        // windows too small to reach kmin subtrees keep one slot
+                        if (!((w.z - w.x) * (w.w - w.y) >= min_area)) {
+                            nslots[nxt] = 1;
+                            continue;
+                        }
+                        break;
+                    } else {
+                        const uint32_t ns = (uint32_t)(slot_first[nxt + 1] - slot_first[nxt]);
+                        if (ns <= 1) continue;
+                        b = (uint32_t)(sl * hcap) + atomicAdd(&ctrl->hlist[sl][0], ns);
+                        break;
+                    }
+                }
+            }
+            nxt = __shfl(nxt, (int)gbase);
+            b = __shfl(b, (int)gbase);
+            sl = __shfl(sl, (int)gbase);
+            if (nxt < nq) {
+                qi = nxt;
+                list = sl;
+                have = true;
+                q = qs[qi];
+                stk[0] = 0u;
+                sp = 1;
+                k = 0;
+                base = b;
+                if constexpr (PHASE == 1) slot0 = (uint32_t)slot_first[qi];
+            } else {
+                done = true;
+            }
+        }
+        if (__all(done)) break;
+        __builtin_amdgcn_wave_barrier();
+        uint32_t node = 0;
+        if (have) {
+            sp -= 1;
+            node = stk[sp];
+        }
+        const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
+        bool hit = false;
+        uint32_t ref = 0;
+        if (have && e < F) {
+            ref = load_ptr<LAYOUT>(nb, F, 0);
+            float lx, ly, hx, hy;
+            load_entry<LAYOUT>(nb, F, e, lx, ly, hx, hy);
+            hit = (lx <= q.z) && (q.x <= hx) && (ly <= q.w) && (q.y <= hy);
+        }
+        const uint64_t m = (__ballot(hit) >> gbase) & gmask;
+        const uint32_t n = (uint32_t)__popcll(m);
+        const uint32_t rank = (uint32_t)__popcll(m & below);
+        if (have) {
+            // group-uniform test: only nodes above the parents-of-leaves level are
+            // ever pushed, so a popped node at or past split_parent (the first
+            // grandparent-of-leaves node) has parents of leaves as children
+            if (node >= split_parent) {
+                // the children are parents of leaves: they are the split nodes
+                if constexpr (PHASE == 1) {
+                    if (hit) heavy[base + k + rank] = make_uint4(qi, ref + e, slot0 + k + rank, 0u);
+                }
+                k += n;
+            } else {
+                if (hit) {
+                    if (sp + rank < stack_cap)
+                        stk[sp + rank] = ref + e;
+                    else
+                        atomicOr(&ctrl->err, kErrStack);
+                }
+                sp = min(sp + n, stack_cap);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 int num_cus() {
     static int cus = 0;
     if (!cus) {
@@ -219,58 +373,117 @@ int num_cus() {
 template <int G, int LAYOUT, int MODE>
 static hipError_t launch_g(const TreeView &t, const float4 *q, uint32_t nq, uint32_t *counts,
                            const uint64_t *offsets, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
-                           uint32_t slot, const uint64_t *order, hipStream_t s) {
+                           uint32_t slot, const SelectPlan &plan, uint32_t noffsets, hipStream_t s) {
     const uint32_t stack_cap = stack_bound(t.height, t.fanout);
     const uint32_t groups_per_block = 256 / G;
     const size_t smem = (size_t)groups_per_block * stack_cap * sizeof(uint32_t);
     uint64_t want = ((uint64_t)nq + groups_per_block - 1) / groups_per_block;
     uint64_t persistent = (uint64_t)num_cus() * 8;
     uint32_t blocks = (uint32_t)(want < persistent ? want : persistent);
+    if (plan.heavy) blocks = (uint32_t)persistent;   // split items add work beyond nq
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // every XCD gets blocks
     hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE>), dim3(blocks), dim3(256), smem, s, t, q, nq,
-                       counts, offsets, ids, cap, ctrl, slot, stack_cap, order);
+                       counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
+    return hipGetLastError();
+}
+
+template <int G, int LAYOUT, int PHASE>
+static hipError_t launch_split_g(const TreeView &t, const float4 *q, uint32_t nq, uint32_t split_first,
+                                 uint32_t kmin, uint32_t budget, float min_area, uint32_t *nslots,
+                                 const uint64_t *slot_first, uint4 *heavy, const uint64_t *order, Ctrl *ctrl,
+                                 hipStream_t s) {
+    const uint32_t stack_cap = stack_bound(t.height, t.fanout);
+    const uint32_t groups_per_block = 256 / G;
+    const size_t smem = (size_t)groups_per_block * stack_cap * sizeof(uint32_t);
+    uint64_t want = ((uint64_t)nq + groups_per_block - 1) / groups_per_block;
+    uint64_t persistent = (uint64_t)num_cus() * 8;
+    uint32_t blocks = (uint32_t)(want < persistent ? want : persistent);
+    blocks = (blocks + kXcds - 1) / kXcds * kXcds;
+    hipLaunchKernelGGL((split_kernel<G, LAYOUT, PHASE>), dim3(blocks), dim3(256), smem, s, t, q, nq, split_first,
+                       kmin, budget, min_area, nslots, slot_first, heavy, order, ctrl, stack_cap);
     return hipGetLastError();
 }
 
 template <int G, int LAYOUT>
 static hipError_t launch_m(const TreeView &t, const float4 *q, uint32_t nq, int mode, uint32_t *counts,
                            const uint64_t *offsets, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
-                           uint32_t slot, const uint64_t *order, hipStream_t s) {
+                           uint32_t slot, const SelectPlan &plan, uint32_t noffsets, hipStream_t s) {
     switch (mode) {
     case SEL_COUNT:
-        return launch_g<G, LAYOUT, SEL_COUNT>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, order, s);
+        return launch_g<G, LAYOUT, SEL_COUNT>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, plan, noffsets, s);
     case SEL_FILL:
-        return launch_g<G, LAYOUT, SEL_FILL>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, order, s);
+        return launch_g<G, LAYOUT, SEL_FILL>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, plan, noffsets, s);
     default:
-        return launch_g<G, LAYOUT, SEL_STATS>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, order, s);
+        return launch_g<G, LAYOUT, SEL_STATS>(t, q, nq, counts, offsets, ids, cap, ctrl, slot, plan, noffsets, s);
     }
 }
 
 template <int G>
 static hipError_t launch_l(const TreeView &t, const float4 *q, uint32_t nq, int mode, uint32_t *counts,
                            const uint64_t *offsets, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
-                           uint32_t slot, const uint64_t *order, hipStream_t s) {
+                           uint32_t slot, const SelectPlan &plan, uint32_t noffsets, hipStream_t s) {
     switch (t.layout) {
     case LAYOUT_AOS:
-        return launch_m<G, LAYOUT_AOS>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
+        return launch_m<G, LAYOUT_AOS>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, plan, noffsets, s);
     case LAYOUT_SOA:
-        return launch_m<G, LAYOUT_SOA>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
+        return launch_m<G, LAYOUT_SOA>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, plan, noffsets, s);
     default:
-        return launch_m<G, LAYOUT_D2>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
+        return launch_m<G, LAYOUT_D2>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, plan, noffsets, s);
     }
 }
 
 hipError_t launch_select_pass(const TreeView &t, const float4 *q, uint32_t nq, int mode,
                               uint32_t *counts, const uint64_t *offsets, uint32_t *ids,
-                              uint64_t cap, Ctrl *ctrl, uint32_t slot, const uint64_t *order, hipStream_t s) {
+                              uint64_t cap, Ctrl *ctrl, uint32_t slot, const SelectPlan &plan,
+                              uint32_t noffsets, hipStream_t s) {
     switch (group_width(t.fanout)) {
     case 16:
-        return launch_l<16>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
+        return launch_l<16>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, plan, noffsets, s);
     case 32:
-        return launch_l<32>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
+        return launch_l<32>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, plan, noffsets, s);
     default:
-        return launch_l<64>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, order, s);
+        return launch_l<64>(t, q, nq, mode, counts, offsets, ids, cap, ctrl, slot, plan, noffsets, s);
     }
+}
+
+template <int PHASE>
+static hipError_t launch_split_phase(const TreeView &t, const float4 *q, uint32_t nq, uint32_t split_first,
+                                     uint32_t kmin, uint32_t budget, float min_area, uint32_t *nslots,
+                                     const uint64_t *slot_first, uint4 *heavy, const uint64_t *order, Ctrl *ctrl,
+                                     hipStream_t s) {
+#define RT_SPLIT(G_, L_) \
+    launch_split_g<G_, L_, PHASE>(t, q, nq, split_first, kmin, budget, min_area, nslots, slot_first, heavy, order, \
+                                  ctrl, s)
+    const uint32_t G = group_width(t.fanout);
+    if (t.layout == LAYOUT_AOS) return G == 16 ? RT_SPLIT(16, LAYOUT_AOS) : G == 32 ? RT_SPLIT(32, LAYOUT_AOS) : RT_SPLIT(64, LAYOUT_AOS);
+    if (t.layout == LAYOUT_SOA) return G == 16 ? RT_SPLIT(16, LAYOUT_SOA) : G == 32 ? RT_SPLIT(32, LAYOUT_SOA) : RT_SPLIT(64, LAYOUT_SOA);
+    return G == 16 ? RT_SPLIT(16, LAYOUT_D2) : G == 32 ? RT_SPLIT(32, LAYOUT_D2) : RT_SPLIT(64, LAYOUT_D2);
+#undef RT_SPLIT
+}
+
+hipError_t launch_split(const TreeView &t, const float4 *q, uint32_t nq, int phase, uint32_t split_parent,
+                        uint32_t kmin, uint32_t hcap, float min_area, uint32_t *nslots, const uint64_t *slot_first,
+                        uint4 *heavy, const uint64_t *order, Ctrl *ctrl, hipStream_t s) {
+    return phase == 0 ? launch_split_phase<0>(t, q, nq, split_parent, kmin, hcap, min_area, nslots, slot_first,
+                                              heavy, order, ctrl, s)
+                      : launch_split_phase<1>(t, q, nq, split_parent, kmin, hcap, min_area, nslots, slot_first,
+                                              heavy, order, ctrl, s);
+}
+
+// offsets[q] = slot_offsets[slot_first[q]] for q <= nq (the CSR of whole
+// queries from the CSR of output slots)
+__global__ void gather_offsets(const uint64_t *__restrict__ slot_first, const uint64_t *__restrict__ slot_off,
+                               uint32_t nq, uint64_t *__restrict__ offsets) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= nq; i += gridDim.x * blockDim.x)
+        offsets[i] = slot_off[slot_first[i]];
+}
+
+hipError_t launch_gather_offsets(const uint64_t *slot_first, const uint64_t *slot_off, uint32_t nq,
+                                 uint64_t *offsets, hipStream_t s) {
+    uint32_t blocks = (nq + 256) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(gather_offsets, dim3(blocks), dim3(256), 0, s, slot_first, slot_off, nq, offsets);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -327,11 +540,18 @@ hipError_t launch_query_order(const float4 *q, uint32_t nq, const float *mbr, vo
     uint32_t blocks = (nq + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(query_morton, dim3(blocks), dim3(256), 0, s, q, nq, lx, ly, sx, sy, keys);
+    // four passes (an even number): the sorted keys end in the first buffer
     const int shifts[4] = {32, 40, 48, 56};
     bool in_tmp = false;
     hipError_t e = launch_radix_sort_u64(keys, tmp, nq, shifts, 4, hist, hscan, stmp, &in_tmp, s);
-    *sorted = in_tmp ? tmp : keys;
+    *sorted = keys;
+    if (e == hipSuccess && in_tmp) e = hipErrorUnknown;
     return e == hipSuccess ? hipGetLastError() : e;
+}
+
+const uint64_t *query_order_result(const void *ws, uint64_t nq) {
+    (void)nq;
+    return static_cast<const uint64_t *>(ws);
 }
 
 }  // namespace rtk

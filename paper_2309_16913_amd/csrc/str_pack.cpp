@@ -186,6 +186,7 @@ int str_pack(const float *rects, uint64_t n, uint32_t F, uint32_t layout, Packed
     pt.height = H;
     pt.n_nodes = (uint32_t)total;
     pt.first_leaf = (uint32_t)first_at[0];
+    for (uint32_t l = 0; l < H && l < 33; ++l) pt.level_start[l] = (uint32_t)first_at[l];
     pt.node_bytes = 20u * F;
     pt.n_objects = n;
     pt.bytes.assign((size_t)total * pt.node_bytes, 0);

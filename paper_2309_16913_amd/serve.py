@@ -64,10 +64,11 @@ class Admission:
       slot share; unknown sizes are admitted optimistically (the device
       reports an overflow without writing past the buffer)."""
 
-    def __init__(self, max_windows: int, slot_ids: int, pool_ids: int):
+    def __init__(self, max_windows: int, slot_ids: int, pool_ids: int, one_per_batch: bool = False):
         self.max_windows = max_windows
         self.slot_ids = slot_ids
         self.pool_ids = pool_ids
+        self.one_per_batch = one_per_batch   # the unbatched baseline: one request per launch
         self.queue: deque = deque()
 
     def push(self, p: Pending):
@@ -92,20 +93,26 @@ class Admission:
         if head.kind == "join":
             self.queue.popleft()
             return Batch("join", [head], head.windows)
+        # pack waiting range windows in arrival order; join requests and solo
+        # requests stay queued in place (they form batches of their own)
         reqs, known, nwin = [], 0, 0
-        while self.queue and nwin < self.max_windows:
-            p = self.queue[0]
-            if p.kind != "select" or p.solo:
-                break
-            if nwin + p.windows.shape[0] > self.max_windows:
-                break
-            if p.known_ids >= 0 and reqs and known + p.known_ids > self.slot_ids:
-                break
-            self.queue.popleft()
-            reqs.append(p)
-            nwin += p.windows.shape[0]
-            if p.known_ids >= 0:
-                known += p.known_ids
+        rest = deque()
+        while self.queue:
+            p = self.queue.popleft()
+            take = (p.kind == "select" and not p.solo and nwin + p.windows.shape[0] <= self.max_windows
+                    and not (p.known_ids >= 0 and reqs and known + p.known_ids > self.slot_ids)
+                    and not (self.one_per_batch and reqs))
+            if take:
+                reqs.append(p)
+                nwin += p.windows.shape[0]
+                if p.known_ids >= 0:
+                    known += p.known_ids
+            else:
+                rest.append(p)
+                if nwin >= self.max_windows or (self.one_per_batch and reqs):
+                    break
+        rest.extend(self.queue)
+        self.queue = rest
         if not reqs:
             return None
         return Batch("select", reqs, np.concatenate([r.windows for r in reqs]))
@@ -174,13 +181,19 @@ class _Slot:
 
 class Server:
     def __init__(self, range_tree, join_tree, *, nslots: int = 3, max_windows: int = 16384,
-                 pool_ids: int = 1 << 27):
+                 pool_ids: int = 1 << 27, one_per_batch: bool = False, split_kmin: int | None = 16):
         import torch
 
         import paper_2309_16913_amd as rt
         self.torch, self.rt = torch, rt
         self.trees = {"select": range_tree, "join": join_tree}
+        if split_kmin is not None:
+            # served windows span up to 1e-2 of the space: large ones are split
+            # over many lane groups so one window does not serialize a batch
+            for t in (range_tree, join_tree):
+                t.set_split(split_kmin)
         self.nslots = nslots
+        self.one_per_batch = one_per_batch
         self.max_windows = max_windows
         self.pool_ids = pool_ids
         self.slot_ids = pool_ids // nslots
@@ -263,7 +276,7 @@ class Server:
         """Serve `requests` (objects with t_arrival, kind, payload, rid) in
         real time.  `sink(req, offsets, ids)` receives every result."""
         reqs = sorted(requests, key=lambda r: r.t_arrival)
-        adm = Admission(self.max_windows, self.slot_ids, self.pool_ids)
+        adm = Admission(self.max_windows, self.slot_ids, self.pool_ids, self.one_per_batch)
         st = Stats()
         n = len(reqs)
         nxt, finished = 0, 0

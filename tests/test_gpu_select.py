@@ -208,3 +208,22 @@ def test_select_ordered_batch(rt, ora, fanout, layout):
     got = rt.range_select(t, q)
     want = ora.select(ora.build_str(r, fanout), q)
     assert_csr_equal(got, want, f"ordered F={fanout} {layout}")
+
+
+@pytest.mark.parametrize("kmin", [0, 1, 2, 16])
+@pytest.mark.parametrize("fanout,layout", [(16, "aos"), (32, "soa"), (8, "d2")])
+def test_select_split_mapping(rt, ora, kmin, fanout, layout):
+    """Queries split into (query, subtree) work items -- kmin = 1 splits every
+    query that reaches a parents-of-leaves node -- give the same CSR as one
+    lane group per query (kmin = 0) and as the oracle, for small and large
+    batches (with and without the Morton order)."""
+    r = rtgen.clustered_rects(250_000, 16, 0.02, 2e-3, 77)
+    for nq, lo, hi in [(300, 1e-4, 0.3), (9000, 1e-6, 1e-2)]:
+        q = rtgen.windows_loguniform(nq, lo, hi, 78 + nq)
+        q = np.concatenate([q, np.array([[-np.inf, -np.inf, np.inf, np.inf]], np.float32)])
+        say(f"case split kmin={kmin} F={fanout} {layout} nq={nq}")
+        t = rt.build_str(r, fanout, layout)
+        t.set_split(kmin)
+        got = rt.range_select(t, q)
+        want = ora.select(ora.build_str(r, fanout), q)
+        assert_csr_equal(got, want, f"split kmin={kmin} F={fanout} {layout} nq={nq}")

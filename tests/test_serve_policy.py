@@ -20,17 +20,17 @@ def test_packs_windows_up_to_limit():
     assert len(a) == 6
 
 
-def test_join_runs_alone_and_stops_packing():
+def test_join_runs_alone_and_does_not_block_windows():
     a = Admission(max_windows=8, slot_ids=100, pool_ids=300)
     a.push(Pending(0, "select", win(), 0.0))
     a.push(Pending(1, "join", win(5), 0.0))
     a.push(Pending(2, "select", win(), 0.0))
     b1 = a.next_batch(True)
-    assert b1.kind == "select" and [r.rid for r in b1.reqs] == [0]
+    # windows behind a waiting join are packed with the ones before it
+    assert b1.kind == "select" and [r.rid for r in b1.reqs] == [0, 2]
     b2 = a.next_batch(True)
     assert b2.kind == "join" and [r.rid for r in b2.reqs] == [1] and b2.windows.shape[0] == 5
-    b3 = a.next_batch(True)
-    assert [r.rid for r in b3.reqs] == [2]
+    assert a.next_batch(True) is None
 
 
 def test_overflow_defers_and_splits_never_drops():
