@@ -90,9 +90,10 @@ def read_traffic(kernel_tag, src_hash):
         return None
 
 
-def select_leg(rt, torch, ev, args, rects, queries):
+def select_leg(rt, torch, ev, args, rects, queries, kmin=0):
     t0 = time.time()
     tree = rt.build_str(rects, args.fanout, args.layout)
+    tree.set_split(kmin)
     build_s = time.time() - t0
     info = tree.info()
     nq = queries.shape[0]
@@ -189,28 +190,48 @@ def batch_leg(rt, torch, args):
     import rtgen
     t0 = time.time()
     inst = rtgen.c4_batch(ntrees=args.batch_trees, scale=args.batch_scale)
-    trees = []
-    for k, x in enumerate(inst):
-        trees.append(rt.build_str(x.rects, 32, "soa"))
-    build_s = time.time() - t0
-    b = rt.Batch(trees, [x.queries for x in inst])
+    gen_s = time.time() - t0
     nq = sum(x.queries.shape[0] for x in inst)
-    out = {}
-    for name, fn in (("batched_graph", b.run), ("plain_per_tree", b.run_plain)):
+
+    def timed(b, fn, reps):
         fn()
         torch.cuda.synchronize()
         ts = []
-        for _ in range(args.batch_reps):
-            t0 = time.perf_counter()
+        for _ in range(reps):
+            t1 = time.perf_counter()
             fn()
             torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
+            ts.append(time.perf_counter() - t1)
         tot, flags = b.status()
         assert flags == 0
-        out[name] = dict(ms=float(np.median(ts)) * 1e3, queries_per_s=nq / float(np.median(ts)), ids=tot)
+        return float(np.median(ts)), tot
+
+    # autotune fanout x layout in batch context on a subset of the instances
+    # (the persistent kernel serves every tree with its own configuration,
+    # but one configuration for the whole batch keeps its waves uniform)
+    sub = inst[:: max(1, len(inst) // args.batch_tune_subset)]
+    tune = {}
+    for F in (16, 32, 64):
+        for lay in ("aos", "soa"):
+            ts = [rt.build_str(x.rects, F, lay) for x in sub]
+            b = rt.Batch(ts, [x.queries for x in sub])
+            tune[f"{F}/{lay}"] = timed(b, b.run, 2)[0] * 1e3
+            b.free()
+            for t in ts:
+                t.free()
+    best = min(tune, key=tune.get)
+    F, lay = best.split("/")
+    t0 = time.time()
+    trees = [rt.build_str(x.rects, int(F), lay) for x in inst]
+    build_s = time.time() - t0
+    b = rt.Batch(trees, [x.queries for x in inst])
+    out = {}
+    for name, fn in (("batched_graph", b.run), ("plain_per_tree", b.run_plain)):
+        ms, tot = timed(b, fn, args.batch_reps)
+        out[name] = dict(ms=ms * 1e3, queries_per_s=nq / ms, ids=tot)
     out["speedup"] = out["plain_per_tree"]["ms"] / out["batched_graph"]["ms"]
-    out.update(workload=f"batch_{len(inst)}_trees_{sum(x.rects.shape[0] for x in inst)}_rects_{nq}_windows_f32_soa",
-               build_s=build_s)
+    out.update(workload=f"batch_{len(inst)}_trees_{sum(x.rects.shape[0] for x in inst)}_rects_{nq}_windows",
+               fanout=int(F), layout=lay, tune_subset_ms=tune, gen_s=gen_s, build_s=build_s)
     return out
 
 
@@ -275,12 +296,18 @@ def main():
     ap.add_argument("--fanout", type=int, default=32)
     ap.add_argument("--layout", default="soa")
     ap.add_argument("--legs", default="join,batch,serve,cpu")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before the select leg, copy this many MiB device-to-device three times (a plain copy "
+                         "kernel of known size, used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="time --fanout/--layout directly instead of the autotuner's choice")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--join-n", type=int, default=2_000_000)
     ap.add_argument("--join-reps", type=int, default=5)
     ap.add_argument("--batch-trees", type=int, default=256)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--batch-tune-subset", type=int, default=64)
     ap.add_argument("--serve-n", type=int, default=50_000_000)
     ap.add_argument("--serve-join-n", type=int, default=5_000_000)
     ap.add_argument("--serve-requests", type=int, default=20_000)
@@ -298,11 +325,29 @@ def main():
     ev = HipEvents()
     legs = set(x for x in args.legs.split(",") if x)
 
+    if args.calib_copy_mib:
+        nb = args.calib_copy_mib << 20
+        a = torch.ones(nb // 4, dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: 3 x {nb} bytes")
+        del a, b
     log(f"[bench] generating {args.n} rectangles and {args.nq} windows")
     rects = rtgen.c2_rects(args.n)
     queries = rtgen.c2_queries(args.nq)
-    log("[bench] select leg")
-    s = select_leg(rt, torch, ev, args, rects, queries)
+    tune = None
+    kmin = 0
+    if args.autotune:
+        from paper_2309_16913_amd.autotune import Autotuner
+        log("[bench] autotuning fanout x layout x mapping on the full workload")
+        tuner = Autotuner(cache_path=None, fanouts=(16, 32, 64), layouts=("aos", "soa"), kmins=(0, 16),
+                          sample=args.nq, reps=2)
+        tune = tuner.tune(rects, queries, "mixed")
+        args.fanout, args.layout, kmin = tune["fanout"], tune["layout"], tune["kmin"]
+    log(f"[bench] select leg (fanout {args.fanout}, {args.layout}, split kmin {kmin})")
+    s = select_leg(rt, torch, ev, args, rects, queries, kmin)
     ms_step = s["wall"] / args.steps * 1e3
     qps = args.nq / (s["wall"] / args.steps)
     dom = "fill" if s["avg"]["fill"] >= s["avg"]["count"] else "count"
@@ -316,7 +361,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"select_mixed{args.n}_windows{args.nq}_f{args.fanout}_{args.layout}",
                    "n_rects": args.n, "n_queries": args.nq, "fanout": args.fanout, "layout": args.layout,
-                   "selectivity": "loguniform[1e-6,1e-3]", "ids_out": s["cap"]},
+                   "split_kmin": kmin, "selectivity": "loguniform[1e-6,1e-3]", "ids_out": s["cap"]},
+        "variants_ms": tune["timings_ms"] if tune else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"select_kernel ({dom} pass)", "algorithmic_bytes_per_launch": dom_bytes},

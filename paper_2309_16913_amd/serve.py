@@ -256,7 +256,9 @@ class Server:
         m = b.windows.shape[0]
         off = sl.hoff[:m + 1].numpy().copy()
         _, hids, _ = sl.cur
-        ids = hids[:sl.total].numpy().view(np.uint32).copy() if sl.total else np.zeros(0, np.uint32)
+        # views into the slot's pinned buffer: valid until the slot is reused,
+        # so a sink that keeps results must copy them
+        ids = hids[:sl.total].numpy().view(np.uint32) if sl.total else np.zeros(0, np.uint32)
         at = 0
         for r in b.reqs:
             k = r.windows.shape[0]
@@ -274,7 +276,9 @@ class Server:
     # -- the loop ------------------------------------------------------------
     def run(self, requests, sink=None, time_scale: float = 1.0) -> dict:
         """Serve `requests` (objects with t_arrival, kind, payload, rid) in
-        real time.  `sink(req, offsets, ids)` receives every result."""
+        real time.  `sink(req, offsets, ids)` receives every result as views
+        into pinned staging memory that is reused by later batches (copy what
+        must be kept)."""
         reqs = sorted(requests, key=lambda r: r.t_arrival)
         adm = Admission(self.max_windows, self.slot_ids, self.pool_ids, self.one_per_batch)
         st = Stats()

@@ -118,3 +118,23 @@ def test_batch_small_pool_flags_overflow(rt):
     small.run()
     t2, flags = small.status()
     assert t2 == tot and (flags & 1)
+
+
+def test_autotuner_choice_is_valid_and_exact(rt, ora, tmp_path):
+    """The autotuner times every candidate, caches its choice, and the tree it
+    builds returns the oracle's CSR."""
+    from paper_2309_16913_amd.autotune import Autotuner
+    r = rtgen.c2_rects(120_000, seed_base=2300)
+    q = rtgen.c2_queries(3000, seed_base=2300)
+    cache = str(tmp_path / "tune.json")
+    tu = Autotuner(cache_path=cache, fanouts=(16, 32), layouts=("aos", "soa"), kmins=(0, 4), sample=2000, reps=1)
+    t, c = tu.build(r, q, "mixed")
+    assert c["cached"] is False and len(c["timings_ms"]) == 8
+    assert (c["fanout"], c["layout"], c["kmin"]) in {(F, L, K) for F in (16, 32) for L in ("aos", "soa")
+                                                     for K in (0, 4)}
+    got = rt.range_select(t, q)
+    want = ora.select(ora.build_str(r, 16), q)
+    assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1])
+    tu2 = Autotuner(cache_path=cache, fanouts=(16, 32), layouts=("aos", "soa"), kmins=(0, 4), sample=2000, reps=1)
+    c2 = tu2.tune(r, q, "mixed")
+    assert c2["cached"] is True and c2["fanout"] == c["fanout"] and c2["layout"] == c["layout"]
