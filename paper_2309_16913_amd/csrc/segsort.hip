@@ -240,6 +240,20 @@ segsort_small(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, 
 // from uniform) sends the segment to a fallback.
 constexpr uint32_t kRankMax = 64;
 
+// Number of ids in bucket [s0, s1) of a that are smaller than key.  The first
+// eight reads do not depend on each other (predicated), so they are in flight
+// together; buckets hold about four ids, and only longer ones loop.
+__device__ __forceinline__ uint32_t bucket_rank(const uint32_t *a, uint32_t s0, uint32_t s1, uint32_t key) {
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 8; ++j) {
+        const uint32_t v = (s0 + j < s1) ? a[s0 + j] : kKeyPad;
+        r += v < key ? 1u : 0u;
+    }
+    for (uint32_t j = s0 + 8; j < s1; ++j) r += a[j] < key ? 1u : 0u;
+    return r;
+}
+
 // Exclusive scan in place of cnt[0 .. nbk) by T threads (nbk <= 4*T or a
 // multiple of 4*T handled in rounds); returns the largest count.
 template <int T>
@@ -332,9 +346,7 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
                 if (i < c) {
                     const uint32_t b = (key[k] >> shift) & (nbk - 1);
                     const uint32_t s0 = b ? cnt[b - 1] : 0u, s1 = cnt[b];
-                    uint32_t r = 0;
-                    for (uint32_t j = s0; j < s1; ++j) r += buf[j] < key[k] ? 1u : 0u;
-                    seg[s0 + r] = key[k];
+                    seg[s0 + bucket_rank(buf, s0, s1, key[k])] = key[k];
                 }
             }
         } else {   // ids far from uniform: block bitonic over the whole segment
@@ -420,9 +432,7 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
                     const uint32_t key = kk[u];
                     const uint32_t b = (key >> shift) & (nbk - 1);
                     const uint32_t s0 = b ? cnt[b - 1] : 0u, s1 = cnt[b];
-                    uint32_t r = 0;
-                    for (uint32_t j = s0; j < s1; ++j) r += tmp[j] < key ? 1u : 0u;
-                    seg[s0 + r] = key;
+                    seg[s0 + bucket_rank(tmp, s0, s1, key)] = key;
                 }
             }
         }

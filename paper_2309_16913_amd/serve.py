@@ -147,6 +147,8 @@ class Stats:
     overflows: int = 0
     windows: int = 0
     ids: int = 0
+    gpu_select_ms: float = 0.0    # device time of the selects (incl. overflowed attempts)
+    gpu_copy_ms: float = 0.0      # device time of the result copies to pinned memory
 
     def summary(self, wall: float, nreq: int) -> dict:
         def pct(v, q):
@@ -157,6 +159,7 @@ class Stats:
             "select_p50_ms": pct(self.lat_select, 50), "select_p99_ms": pct(self.lat_select, 99),
             "join_p50_ms": pct(self.lat_join, 50), "join_p99_ms": pct(self.lat_join, 99),
             "batches": self.batches, "overflow_retries": self.overflows, "ids": self.ids,
+            "gpu_select_ms": self.gpu_select_ms, "gpu_copy_ms": self.gpu_copy_ms,
         }
 
 
@@ -221,11 +224,13 @@ class Server:
         sl.hq[:m].copy_(torch.from_numpy(b.windows))
         with torch.cuda.stream(sl.stream):
             sl.dq[:m].copy_(sl.hq[:m], non_blocking=True)
+            sl.ev0 = torch.cuda.Event(enable_timing=True)
+            sl.ev0.record(sl.stream)
             rt.range_select_device(self.trees[b.kind], sl.dq.data_ptr(), m, sl.off.data_ptr(), ids.data_ptr(),
                                    cap, work.data_ptr(), wb, sl.status.data_ptr(), sl.stream.cuda_stream)
             sl.hstat.copy_(sl.status, non_blocking=True)
             sl.hoff[:m + 1].copy_(sl.off[:m + 1], non_blocking=True)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(sl.stream)
         sl.batch, sl.done_ev, sl.stage = b, ev, 1
 
@@ -233,6 +238,8 @@ class Server:
         """Select done: on overflow re-queue, else start the copy of the ids."""
         torch = self.torch
         b = sl.batch
+        st.gpu_select_ms += sl.ev0.elapsed_time(sl.done_ev)
+        sl.ev1 = sl.done_ev
         tot, flags = int(sl.hstat[0]), int(sl.hstat[1])
         m = b.windows.shape[0]
         if flags & 2:
@@ -247,12 +254,13 @@ class Server:
         with torch.cuda.stream(sl.stream):
             if tot:
                 hids[:tot].copy_(ids[:tot], non_blocking=True)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(sl.stream)
         sl.total, sl.done_ev, sl.stage = tot, ev, 2
 
     def _finish_stage2(self, sl: _Slot, now: float, st: Stats, sink):
         b = sl.batch
+        st.gpu_copy_ms += sl.ev1.elapsed_time(sl.done_ev)
         m = b.windows.shape[0]
         off = sl.hoff[:m + 1].numpy().copy()
         _, hids, _ = sl.cur
