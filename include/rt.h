@@ -90,8 +90,14 @@ typedef struct rt_tree_info {
 
 /*
  * Build a packed R-tree over n rectangles with Sort-Tile-Recursive bulk
- * loading (the paper does not say how its trees are built) and upload it to
- * the current HIP device.
+ * loading (the paper does not say how its trees are built; section 2.3 gives
+ * what a node holds) on the current HIP device.  The rectangles are checked
+ * on the host, copied to the device and packed there by the same kernels as
+ * rt_build_str_device.  Shape: a level of c > F items gets ceil(c/F) nodes in
+ * S = ceil(sqrt(ceil(c/F))) vertical slices of S*F items by x-center, each
+ * slice ordered by y-center (f32 0.5*lo + 0.5*hi, ties by item index), runs
+ * of F items per node; nodes are numbered breadth first from the root with
+ * the children of every node contiguous in entry order.
  *   rects   host, n*4 floats; NaN or lx > hx or ly > hy -> RT_EINVAL;
  *           +-Inf allowed.  n = 0 gives an empty tree (one empty leaf).
  *   fanout  maximum entries per node F, 2..64 (0 = 32).
@@ -102,9 +108,11 @@ int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uint32_t layou
                  rt_tree **out);
 
 /* Same as rt_build_str with the rectangles already on the device (d_rects,
- * n*4 floats on the current device); the whole build runs in HIP kernels on
- * `stream` (hipStream_t, NULL = default stream) and the call returns after it
- * has finished.  Validation of the rectangles is done on the device. */
+ * n*4 floats on the current device, 16-byte aligned, read only); the whole
+ * build runs in HIP kernels on `stream` (hipStream_t, NULL = default stream)
+ * and the call returns after it has finished.  The rectangles are validated
+ * on the device (RT_EINVAL without the index of the bad one).  Temporary
+ * device memory: about 30 bytes per rectangle. */
 int rt_build_str_device(const float *d_rects, uint64_t n, uint32_t fanout, uint32_t layout,
                         void *stream, rt_tree **out);
 

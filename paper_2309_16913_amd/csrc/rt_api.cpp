@@ -12,7 +12,6 @@
 #include "../../include/rt.h"
 #include "rt_api_internal.h"
 #include "rt_internal.h"
-#include "str_pack.h"
 
 using namespace rtk;
 
@@ -197,34 +196,6 @@ static SelWs sel_ws(void *w, uint64_t nq) {
 // ---------------------------------------------------------------------------
 // build
 // ---------------------------------------------------------------------------
-int rtk::upload_packed(PackedTree &pt, rt_tree **out) {
-    void *mem = obj_alloc(KIND_TREE, sizeof(rt_tree));
-    if (!mem) return fail(RT_ENOMEM, "host allocation failed");
-    rt_tree *t = new (mem) rt_tree();
-    (void)hipGetDevice(&t->device);
-    t->fanout = pt.fanout;
-    t->layout = pt.layout;
-    t->height = pt.height;
-    t->n_nodes = pt.n_nodes;
-    t->first_leaf = pt.first_leaf;
-    t->node_bytes = pt.node_bytes;
-    t->n_objects = pt.n_objects;
-    t->n_entries = pt.n_entries;
-    for (int i = 0; i < 4; ++i) t->mbr[i] = pt.mbr[i];
-    for (int i = 0; i < 33; ++i) t->level_start[i] = pt.level_start[i];
-    hipError_t e = hipMalloc(&t->d_nodes, pt.bytes.size());
-    if (e == hipSuccess) e = hipMalloc(&t->d_meta, pt.meta.size() * 4);
-    if (e == hipSuccess) e = hipMemcpy(t->d_nodes, pt.bytes.data(), pt.bytes.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(t->d_meta, pt.meta.data(), pt.meta.size() * 4, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        tree_release(t);
-        std::free(hdr_of(t));
-        return hip_fail(e, "uploading the tree");
-    }
-    *out = t;
-    return RT_OK;
-}
-
 extern "C" int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uint32_t layout, rt_tree **out) {
     if (!out) return fail(RT_EINVAL, "out is NULL");
     *out = nullptr;
@@ -237,9 +208,12 @@ extern "C" int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uin
         if (n >= 0xFFFFFFFFull) return fail(RT_EINVAL, "n = %llu does not fit 32-bit ids", (unsigned long long)n);
         int rc = check_rects(rects, n, "rects");
         if (rc) return rc;
-        PackedTree pt;
-        if (str_pack(rects, n, fanout, layout, pt)) return fail(RT_EINVAL, "too many nodes");
-        return upload_packed(pt, out);
+        // the build itself runs on the device
+        DevBuf d;
+        hipError_t e = d.alloc(n ? n * 16 : 16);
+        if (e == hipSuccess && n) e = hipMemcpy(d.p, rects, n * 16, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "uploading the rectangles");
+        return build_str_on_device(static_cast<const float4 *>(d.p), n, fanout, layout, nullptr, out);
     } catch (const std::bad_alloc &) {
         return fail(RT_ENOMEM, "host allocation failed");
     } catch (...) {

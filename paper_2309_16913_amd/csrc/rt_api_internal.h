@@ -7,7 +7,6 @@
 
 #include "../../include/rt.h"
 #include "rt_internal.h"
-#include "str_pack.h"
 
 struct rt_tree {
     int device = 0;
@@ -41,7 +40,10 @@ void tree_release(rt_tree *t);
 void batch_release(rt_batch *b);
 int check_rects(const float *r, uint64_t n, const char *what);
 TreeView view_of(const rt_tree *t);
-int upload_packed(PackedTree &pt, rt_tree **out);
+// STR bulk load of n device rectangles (validated again on the device) on
+// stream s; returns after the build has finished.
+int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t fanout, uint32_t layout, hipStream_t s,
+                        rt_tree **out);
 int make_ids(uint64_t nq, uint64_t total, rt_ids **out);
 // stage bit 1: count stage (order, split, count pass, offsets); bit 2: fill
 // stage (fill pass, sort, status).  d_counts_out: count-only mode.
