@@ -83,6 +83,15 @@ class Oracle:
         L.ora_brute_join.argtypes = [C.POINTER(C.c_float), C.c_uint64, C.POINTER(C.c_float),
                                      C.c_uint64, C.POINTER(C.POINTER(C.c_uint32)),
                                      C.POINTER(C.c_uint64)]
+        L.ora_join_opt.argtypes = [T, T, C.c_int, C.POINTER(C.POINTER(C.c_uint32)), C.POINTER(C.c_uint64),
+                                   C.POINTER(C.c_uint64)]
+        L.ora_sort_entries_lx.argtypes = [T]
+        L.ora_m2m_update.argtypes = [C.c_uint32, C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32),
+                                     C.POINTER(C.c_uint32)]
+        L.ora_m2m_update.restype = None
+        L.ora_m2m_flip.argtypes = [C.c_uint32, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_uint32,
+                                   C.POINTER(C.c_uint32)]
+        L.ora_m2m_flip.restype = None
         L.ora_check_tree.argtypes = [T, C.POINTER(C.c_float), C.c_char_p, C.c_int]
         L.ora_free_buf.argtypes = [C.c_void_p]
         self.L = L
@@ -148,6 +157,48 @@ class Oracle:
         if self.L.ora_brute_join(_fptr(a), a.shape[0], _fptr(b), b.shape[0], C.byref(pp), C.byref(n)):
             raise MemoryError("oracle brute join failed")
         return self._take_pairs(pp, n)
+
+    # -- join over nodes sorted by low x (section 4 pruning) ---------------
+    O3, O4, O5 = 1, 2, 4
+
+    def sort_entries_lx(self, tree: "OraTree") -> None:
+        """Reorder every node's entries by ascending low x (in place)."""
+        if self.L.ora_sort_entries_lx(C.byref(tree.t)):
+            raise ValueError("oracle could not sort the tree's nodes")
+
+    def join_opt(self, a: "OraTree", b: "OraTree", flags: int):
+        """(pairs, tests): the join with O3 / O4 / O5 pruning (flags 1 / 2 / 4)
+        and the number of pair predicates it evaluated."""
+        pp = C.POINTER(C.c_uint32)()
+        n = C.c_uint64()
+        tests = C.c_uint64()
+        rc = self.L.ora_join_opt(C.byref(a.t), C.byref(b.t), int(flags), C.byref(pp), C.byref(n), C.byref(tests))
+        if rc == -1:
+            raise ValueError("pruned join needs nodes sorted by low x and fanout <= 64")
+        if rc:
+            raise MemoryError("oracle join failed")
+        return self._take_pairs(pp, n), int(tests.value)
+
+    def m2m_update(self, mask: int, step: int, n_pow: int, gidx, flip):
+        """One many-to-many index update; returns the new (gidx, flip)."""
+        g = np.ascontiguousarray(gidx, np.uint32).copy()
+        f = np.ascontiguousarray(flip, np.uint32).copy()
+        assert g.shape == f.shape and g.size <= 64
+        u32p = C.POINTER(C.c_uint32)
+        self.L.ora_m2m_update(g.size, int(mask), int(step), int(n_pow), g.ctypes.data_as(u32p),
+                              f.ctypes.data_as(u32p))
+        return g, f
+
+    def m2m_flip(self, out_hx, in_lx):
+        """Flip index of each outer high x (at most 64) against the sorted
+        inner low x values."""
+        o = np.ascontiguousarray(out_hx, np.float32)
+        i = np.ascontiguousarray(in_lx, np.float32)
+        assert o.size <= 64 and i.size <= 64
+        f = np.zeros(o.size, np.uint32)
+        self.L.ora_m2m_flip(o.size, _fptr(o), _fptr(i) if i.size else None, i.size,
+                            f.ctypes.data_as(C.POINTER(C.c_uint32)))
+        return f
 
     # -- invariants -------------------------------------------------------
     def check(self, tree: "OraTree", rects=None):

@@ -40,6 +40,13 @@
  *     and follow every intersecting child pair.  When one side reaches its
  *     leaves first, that leaf entry stays fixed and only the other side
  *     descends.  Pairs are sorted at the end.
+ *   - Join with sorted nodes (section 4.1 pruning rules and the many-to-many
+ *     approach of section 4.2): every node's entries in ascending low-x
+ *     order; O3 stops the outer scan at the first outer child whose low x
+ *     exceeds every inner high x; O4 stops the inner scan of one outer child
+ *     at the first inner child whose low x exceeds the outer high x; O5 finds
+ *     the same stop for a batch of 16 outer children by the gather / compare /
+ *     update rounds of the many-to-many approach.  Same pairs as the join.
  *   - Brute force: nested loops over the plain definitions above.
  *   - Tree invariants: every parent entry MBR equals the exact union of its
  *     child's entries, every object appears in exactly one leaf entry with its
@@ -412,6 +419,203 @@ int ora_join(const ora_tree *A, const ora_tree *B, uint32_t **pairs_out, uint64_
     free(acc.v);
     *pairs_out = p;
     *n_out = acc.n;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* join over nodes sorted by low x: outer slicing (O3) and inner shrinking   */
+/* (O4 one outer child at a time, O5 a batch of outer children at once)      */
+/* ------------------------------------------------------------------------ */
+
+/* Entries of every node in ascending low-x order, ties kept in their order
+ * (section 4.1 assumes nodes sorted on one MBR key; low x is the paper's
+ * example).  Children are moved with their entries. */
+typedef struct { float lx, ly, hx, hy; uint32_t ptr; uint32_t pos; } sent;
+
+static int cmp_sent(const void *a, const void *b)
+{
+    const sent *x = (const sent *)a, *y = (const sent *)b;
+    if (x->lx < y->lx) return -1;
+    if (x->lx > y->lx) return 1;
+    return (x->pos > y->pos) - (x->pos < y->pos);
+}
+
+int ora_sort_entries_lx(ora_tree *t)
+{
+    sent *buf = (sent *)malloc((size_t)(t->fanout ? t->fanout : 1) * sizeof(sent));
+    if (!buf) return -2;
+    for (uint32_t u = 0; u < t->n_nodes; u++) {
+        uint64_t e0 = t->first[u];
+        uint32_t c = t->count[u];
+        if (c > t->fanout) { free(buf); return -1; }
+        for (uint32_t k = 0; k < c; k++) {
+            buf[k].lx = t->lx[e0 + k]; buf[k].ly = t->ly[e0 + k];
+            buf[k].hx = t->hx[e0 + k]; buf[k].hy = t->hy[e0 + k];
+            buf[k].ptr = t->ptr[e0 + k]; buf[k].pos = k;
+        }
+        qsort(buf, c, sizeof(sent), cmp_sent);
+        for (uint32_t k = 0; k < c; k++) {
+            t->lx[e0 + k] = buf[k].lx; t->ly[e0 + k] = buf[k].ly;
+            t->hx[e0 + k] = buf[k].hx; t->hy[e0 + k] = buf[k].hy;
+            t->ptr[e0 + k] = buf[k].ptr;
+        }
+    }
+    free(buf);
+    return 0;
+}
+
+static int node_sorted_lx(const ora_tree *t, uint32_t u)
+{
+    for (uint64_t e = t->first[u] + 1; e < t->first[u] + t->count[u]; e++)
+        if (t->lx[e] < t->lx[e - 1]) return 0;
+    return 1;
+}
+
+/* Many-to-many inner shrinking (section 4.2, steps 2-4; figure 6 works one
+ * update through).  Each outer lane k holds a gather index gidx[k] into the
+ * low-x-sorted inner children and a flip index flip[k]: the inner position
+ * from which on no child can qualify for that outer child.  One update takes
+ * the compare mask of out.hx >= in.lx[gidx] (bit k for lane k):
+ *   bit set   -> that inner child (and all before it) may qualify: move up,
+ *                gidx += step
+ *   bit clear -> it and all after it cannot: flip = gidx, move down,
+ *                gidx -= step
+ * Lanes whose index has left the search range [0, n_pow) are not updated. */
+void ora_m2m_update(uint32_t w, uint64_t mask, uint32_t step, uint32_t n_pow, uint32_t *gidx, uint32_t *flip)
+{
+    for (uint32_t k = 0; k < w; k++) {
+        if (gidx[k] >= n_pow) continue;
+        if ((mask >> k) & 1u) {
+            gidx[k] += step;
+        } else {
+            flip[k] = gidx[k];
+#if ORA_MUTANT == 8          /* clear bit moves the wrong way */
+            gidx[k] += step;
+#else
+            gidx[k] -= step;
+#endif
+        }
+    }
+}
+
+/* Flip indices of w outer children against n_in inner children sorted by low
+ * x: flip[k] = the first j with in_lx[j] > out_hx[k], or n_in if none.  The
+ * search runs over n_pow = the smallest power of two >= n_in positions
+ * (positions >= n_in never qualify); it starts every lane at n_pow/2 with
+ * flip = n_pow ("all qualify") and takes log2(n_pow) + 1 gather/compare/update
+ * rounds, the step halving from n_pow/4 down to 1 and staying at 1 for the
+ * last round.  With n_in = n_pow = F this is the paper's schedule. */
+void ora_m2m_flip(uint32_t w, const float *out_hx, const float *in_lx, uint32_t n_in, uint32_t *flip)
+{
+    if (w > 64) w = 64;   /* at most 64 lanes */
+    uint32_t n_pow = 1, lg = 0;
+    while (n_pow < n_in) { n_pow <<= 1; lg++; }
+    uint32_t gidx[64];
+    for (uint32_t k = 0; k < w; k++) { gidx[k] = n_pow / 2; flip[k] = n_pow; }
+    for (uint32_t it = 0; it <= lg; it++) {
+        uint64_t mask = 0;
+        for (uint32_t k = 0; k < w; k++) {
+            uint32_t g = gidx[k];
+            if (g < n_in && out_hx[k] >= in_lx[g]) mask |= 1ull << k;
+        }
+        uint32_t step = (it + 2 <= lg) ? (n_pow >> (it + 2)) : 1;
+        ora_m2m_update(w, mask, step, n_pow, gidx, flip);
+    }
+}
+
+#define ORA_O3 1
+#define ORA_O4 2
+#define ORA_O5 4
+#define ORA_W 16   /* outer children per many-to-many batch: one 512-bit vector of fp32 */
+
+static int join_nodes_opt(const ora_tree *A, uint32_t u, const ora_tree *B, uint32_t v, int flags, vec64 *out,
+                          uint64_t *tests)
+{
+    uint64_t e0 = A->first[u], f0 = B->first[v];
+    uint32_t na = A->count[u], nb = B->count[v];
+    /* O3: the first outer child whose low x exceeds every inner high x ends
+     * the outer scan; later outer children have a larger low x still */
+    uint32_t cut = na;
+    if (flags & ORA_O3) {
+        for (uint32_t i = 0; i < na; i++) {
+            int any = 0;
+            for (uint32_t j = 0; j < nb && !any; j++)
+#if ORA_MUTANT == 9          /* touching children treated as disjoint */
+                any = A->lx[e0 + i] < B->hx[f0 + j];
+#else
+                any = A->lx[e0 + i] <= B->hx[f0 + j];
+#endif
+            if (!any) { cut = i; break; }
+        }
+    }
+    /* inner limit per outer child */
+    uint32_t lim[64];
+    for (uint32_t i = 0; i < cut; i++) lim[i] = nb;
+    if (flags & ORA_O5) {
+        float ohx[ORA_W], ilx[64];
+        for (uint32_t j = 0; j < nb; j++) ilx[j] = B->lx[f0 + j];
+        for (uint32_t i0 = 0; i0 < cut; i0 += ORA_W) {
+            uint32_t w = cut - i0 < ORA_W ? cut - i0 : ORA_W;
+            for (uint32_t k = 0; k < w; k++) ohx[k] = A->hx[e0 + i0 + k];
+            ora_m2m_flip(w, ohx, ilx, nb, lim + i0);
+        }
+    } else if (flags & ORA_O4) {
+        /* O4: scan the inner children of one outer child in low-x order and
+         * stop at the first one that starts right of the outer child's high x */
+        for (uint32_t i = 0; i < cut; i++) {
+            uint32_t j = 0;
+            while (j < nb && B->lx[f0 + j] <= A->hx[e0 + i]) j++;
+            lim[i] = j;
+        }
+    }
+    for (uint32_t i = 0; i < cut; i++) {
+        uint64_t e = e0 + i;
+        for (uint32_t j = 0; j < lim[i]; j++) {
+            uint64_t f = f0 + j;
+            (*tests)++;
+            if (!overlap4(A->lx[e], A->ly[e], A->hx[e], A->hy[e], B->lx[f], B->ly[f], B->hx[f], B->hy[f]))
+                continue;
+            int la = A->level[u] == 0, lb = B->level[v] == 0;
+            int rc;
+            if (la && lb) rc = emit(out, A->ptr[e], B->ptr[f]);
+            else if (!la && !lb) rc = join_nodes_opt(A, A->ptr[e], B, B->ptr[f], flags, out, tests);
+            else if (la) rc = join_fixed_a(A, e, B, B->ptr[f], out);
+            else rc = join_fixed_b(A, A->ptr[e], B, f, out);
+            if (rc) return rc;
+        }
+    }
+    return 0;
+}
+
+/* Join with the pruning options of section 4 (flags: 1 = O3, 2 = O4, 4 = O5;
+ * O5 takes precedence over O4).  Pruning needs every node sorted by low x
+ * (returns -1 otherwise).  *tests_out: pair predicates evaluated in node-pair
+ * expansions (the leaf-entry-fixed descent of trees of unequal height is not
+ * pruned and not counted).  Same output format as ora_join. */
+int ora_join_opt(const ora_tree *A, const ora_tree *B, int flags, uint32_t **pairs_out, uint64_t *n_out,
+                 uint64_t *tests_out)
+{
+    if (A->fanout > 64 || B->fanout > 64) return -1;
+    if (flags & (ORA_O3 | ORA_O4 | ORA_O5)) {
+        for (uint32_t u = 0; u < A->n_nodes; u++) if (!node_sorted_lx(A, u)) return -1;
+        for (uint32_t v = 0; v < B->n_nodes; v++) if (!node_sorted_lx(B, v)) return -1;
+    }
+    vec64 acc = {0, 0, 0};
+    uint64_t tests = 0;
+    if (A->n_nodes > 0 && B->n_nodes > 0 && A->n_objects > 0 && B->n_objects > 0) {
+        if (join_nodes_opt(A, A->root, B, B->root, flags, &acc, &tests)) { free(acc.v); return -2; }
+    }
+    qsort(acc.v, acc.n, sizeof(uint64_t), cmp_u64);
+    uint32_t *p = (uint32_t *)malloc((acc.n ? acc.n : 1) * 2 * sizeof(uint32_t));
+    if (!p) { free(acc.v); return -2; }
+    for (size_t i = 0; i < acc.n; i++) {
+        p[2 * i] = (uint32_t)(acc.v[i] >> 32);
+        p[2 * i + 1] = (uint32_t)(acc.v[i] & 0xFFFFFFFFu);
+    }
+    free(acc.v);
+    *pairs_out = p;
+    *n_out = acc.n;
+    *tests_out = tests;
     return 0;
 }
 

@@ -200,6 +200,94 @@ def pin_results_canonical(o):
         assert np.all((e[:, 0] <= w[2]) & (w[0] <= e[:, 2]) & (e[:, 1] <= w[3]) & (w[1] <= e[:, 3]))
 
 
+# ---------------------------------------------------------------------------
+# join over nodes sorted by low x (section 4.1 pruning, section 4.2 many-to-many)
+
+def load_m2m_example():
+    v = {}
+    with open(os.path.join(GOLDEN, "m2m_worked_example.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            tok = line.split()
+            v[tok[0]] = tok[1:]
+    return v
+
+
+def pin_m2m_worked_example(o):
+    """The index update printed in section 4.2: gather [2,2,2,2] with mask
+    0b1001 gives flip [x,2,2,x] and next gather [3,1,1,3]; and the finished
+    search on values that produce that mask ends at the hand-worked stops."""
+    v = load_m2m_example()
+    g, f = o.m2m_update(int(v["mask"][0], 0), int(v["step"][0]), int(v["n_pow"][0]),
+                        [int(x) for x in v["gidx"]], [int(x) for x in v["flip"]])
+    assert g.tolist() == [int(x) for x in v["gidx_next"]], g
+    assert f.tolist() == [int(x) for x in v["flip_next"]], f
+    lx = np.array([_f32(x) for x in v["in_lx"]], np.float32)
+    hx = np.array([_f32(x) for x in v["out_hx"]], np.float32)
+    mask = sum(1 << k for k in range(4) if hx[k] >= lx[2])
+    assert mask == int(v["mask"][0], 0)
+    assert o.m2m_flip(hx, lx).tolist() == [int(x) for x in v["flip_final"]]
+
+
+def pin_m2m_flip_is_lower_bound(o, seed=11):
+    """The finished many-to-many search equals the plain definition: the
+    first inner position whose low x exceeds the outer high x (a binary
+    search over the sorted low x values), for every inner size 0..64,
+    with ties, touching values and infinities."""
+    g = np.random.default_rng(seed)
+    for n_in in range(0, 65):
+        for rep in range(3):
+            lx = np.sort(g.integers(0, 12, n_in).astype(np.float32) / 8)
+            if n_in and rep == 2:
+                lx[0] = -np.inf
+            w = int(g.integers(1, 65))
+            hx = g.integers(-2, 14, w).astype(np.float32) / 8
+            hx[g.random(w) < 0.1] = np.inf
+            hx[g.random(w) < 0.1] = -np.inf
+            want = np.searchsorted(lx, hx, side="right")
+            got = o.m2m_flip(hx, lx)
+            assert np.array_equal(got, want), (n_in, rep, lx, hx, got, want)
+
+
+def pin_join_pruned_vs_brute(o, seeds=range(10)):
+    """Pruning never changes the pair set: every combination of O3, O4 and
+    O5 over low-x-sorted nodes equals the nested-loop join; O4 and O5 stop the
+    inner scan at the same place, and pruning only ever removes predicate
+    evaluations."""
+    for s in seeds:
+        na = [1, 7, 40, 200, 900, 1500][s % 6]
+        nb = [3, 50, 700, 64, 65, 1200][(s * 5) % 6]
+        Fa = [2, 4, 8, 16, 3, 32][s % 6]
+        Fb = [5, 16, 2, 8, 64, 4][(s + 1) % 6]
+        A = rtgen.adversarial_rects(na, 1900 + s)
+        B = rtgen.adversarial_rects(nb, 1950 + s)
+        ta, tb = o.build_str(A, Fa), o.build_str(B, Fb)
+        o.sort_entries_lx(ta)
+        o.sort_entries_lx(tb)
+        assert o.check(ta, A)[0] == 0 and o.check(tb, B)[0] == 0
+        want = o.brute_join(A, B)
+        tests = {}
+        for flags in (0, o.O3, o.O4, o.O5, o.O3 | o.O4, o.O3 | o.O5):
+            p, t = o.join_opt(ta, tb, flags)
+            assert np.array_equal(p, want), f"seed {s} flags {flags}: {p.shape} vs {want.shape}"
+            tests[flags] = t
+        assert tests[o.O4] == tests[o.O5] and tests[o.O3 | o.O4] == tests[o.O3 | o.O5], tests
+        assert tests[o.O3 | o.O5] <= tests[o.O3] <= tests[0], tests
+        assert tests[o.O5] <= tests[0], tests
+    # pruning needs sorted nodes: STR orders a node's entries by y-center, so
+    # this unsorted tree is refused
+    t = o.build_str(rtgen.uniform_rects(500, 0.05, 5), 8)
+    try:
+        o.join_opt(t, t, o.O3)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("pruned join accepted nodes not sorted by low x")
+
+
 ALL_PINS = [pin_handworked, pin_select_vs_brute, pin_join_vs_brute, pin_join_is_union_of_selects,
             pin_closed_form_uniform, pin_closed_form_join, pin_tree_shape, pin_special_cases,
-            pin_results_canonical]
+            pin_results_canonical, pin_m2m_worked_example, pin_m2m_flip_is_lower_bound,
+            pin_join_pruned_vs_brute]
