@@ -56,6 +56,30 @@ enum {
  * AUTO lets rt_build_str pick (SOA). */
 enum { RT_LAYOUT_AOS = 0, RT_LAYOUT_SOA = 1, RT_LAYOUT_AUTO = 2, RT_LAYOUT_D2 = 3 };
 
+/* Build option, OR-ed into the layout argument of the builders: store the
+ * entries of every node in ascending low-x order (ties keep the STR order),
+ * children moving with their entries, so that their subtrees stay
+ * contiguous.  Section 4.1 assumes nodes sorted on one MBR key for its join
+ * pruning; the order never changes a select or join result. */
+#define RT_BUILD_SORT_LX 0x100u
+
+/* Join expansion variants for rt_spatial_join_ex (section 4):
+ *   RT_JOIN_O3    outer slicing: outer children whose low x exceeds every
+ *                 inner high x are skipped (with sorted nodes, the rest of the
+ *                 outer node after the first such child)
+ *   RT_JOIN_O4    inner shrinking, one outer child at a time (one-to-many):
+ *                 the inner scan stops at the first inner child whose low x
+ *                 exceeds the outer high x
+ *   RT_JOIN_O5    the same stop found for all outer children at once by the
+ *                 many-to-many search of section 4.2 (takes precedence over
+ *                 O4)
+ *   RT_JOIN_TILE  no candidate lists: every one of the Fa x Fb child pairs
+ *                 is tested (cannot be combined with the others)
+ * O3, O4 and O5 need both trees built with RT_BUILD_SORT_LX.  No flag gives
+ * candidate lists without pruning.  RT_JOIN_DEFAULT picks O3|O5 when both
+ * trees are sorted, else RT_JOIN_TILE. */
+enum { RT_JOIN_O3 = 1, RT_JOIN_O4 = 2, RT_JOIN_O5 = 4, RT_JOIN_TILE = 8, RT_JOIN_DEFAULT = -1 };
+
 typedef struct rt_tree rt_tree;   /* opaque; device-resident; immutable */
 
 /* Range-select result in CSR form: ids[offsets[q] .. offsets[q+1]) are the
@@ -85,7 +109,7 @@ typedef struct rt_tree_info {
     uint32_t node_bytes;     /* stride of one node = 20 * fanout */
     uint32_t first_leaf;     /* nodes are numbered root first; leaves last */
     int32_t device;
-    uint32_t reserved;
+    uint32_t flags;          /* RT_BUILD_SORT_LX if the nodes are sorted by low x */
 } rt_tree_info;
 
 /*
@@ -101,7 +125,7 @@ typedef struct rt_tree_info {
  *   rects   host, n*4 floats; NaN or lx > hx or ly > hy -> RT_EINVAL;
  *           +-Inf allowed.  n = 0 gives an empty tree (one empty leaf).
  *   fanout  maximum entries per node F, 2..64 (0 = 32).
- *   layout  RT_LAYOUT_*.
+ *   layout  RT_LAYOUT_*, optionally OR-ed with RT_BUILD_SORT_LX.
  *   out     receives the tree; free with rt_free.
  */
 int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uint32_t layout,
@@ -126,8 +150,17 @@ int rt_range_select(const rt_tree *t, const float *queries, uint64_t nq, rt_ids 
 /*
  * R-tree spatial join (section 4): all intersecting (a, b), a from tree a's
  * relation and b from tree b's.  Both trees must live on the same device.
+ * Same as rt_spatial_join_ex(a, b, RT_JOIN_DEFAULT, out, NULL).
  */
 int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **out);
+
+/* Join with an explicit expansion variant (RT_JOIN_* flags above; results
+ * never depend on it).  tests, if not NULL, receives the number of child-pair
+ * predicates evaluated in expansions where both nodes are at the same level
+ * (0 for RT_JOIN_TILE, which does not count).  Pruning flags on a tree built
+ * without RT_BUILD_SORT_LX, unknown bits, or TILE combined with pruning ->
+ * RT_EINVAL. */
+int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t flags, rt_pairs **out, uint64_t *tests);
 
 /* Release an rt_tree, rt_ids or rt_pairs (and a tree's device memory).
  * NULL is a no-op. */

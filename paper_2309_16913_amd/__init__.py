@@ -24,6 +24,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librt_mi355x.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE = 0, -1, -2, -3
+BUILD_SORT_LX = 0x100
+JOIN_O3, JOIN_O4, JOIN_O5, JOIN_TILE, JOIN_DEFAULT = 1, 2, 4, 8, -1
 LAYOUT_AOS, LAYOUT_SOA, LAYOUT_AUTO, LAYOUT_D2 = 0, 1, 2, 3
 _LAYOUTS = {"aos": LAYOUT_AOS, "soa": LAYOUT_SOA, "auto": LAYOUT_AUTO, "d2": LAYOUT_D2,
             LAYOUT_AOS: LAYOUT_AOS, LAYOUT_SOA: LAYOUT_SOA, LAYOUT_AUTO: LAYOUT_AUTO, LAYOUT_D2: LAYOUT_D2}
@@ -51,7 +53,7 @@ class TreeInfo(C.Structure):
     _fields_ = [("n_objects", C.c_uint64), ("n_entries", C.c_uint64), ("device_bytes", C.c_uint64),
                 ("n_nodes", C.c_uint32), ("height", C.c_uint32), ("fanout", C.c_uint32),
                 ("layout", C.c_uint32), ("node_bytes", C.c_uint32), ("first_leaf", C.c_uint32),
-                ("device", C.c_int32), ("reserved", C.c_uint32)]
+                ("device", C.c_int32), ("flags", C.c_uint32)]
 
 
 class _Ids(C.Structure):
@@ -68,6 +70,7 @@ _sig = {
     "rt_build_str_device": ([_vp, _u64, _u32, _u32, _vp, C.POINTER(_vp)], C.c_int),
     "rt_range_select": ([_vp, _fp, _u64, C.POINTER(C.POINTER(_Ids))], C.c_int),
     "rt_spatial_join": ([_vp, _vp, C.POINTER(C.POINTER(_Pairs))], C.c_int),
+    "rt_spatial_join_ex": ([_vp, _vp, C.c_int32, C.POINTER(C.POINTER(_Pairs)), C.POINTER(_u64)], C.c_int),
     "rt_free": ([_vp], None),
     "rt_select_workspace_bytes": ([_u64, _u64], _u64),
     "rt_range_select_device": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _u64, _vp, _vp], C.c_int),
@@ -155,16 +158,24 @@ class Tree:
             pass
 
 
-def build_str(rects, fanout: int = 32, layout="soa") -> Tree:
+def _layout_arg(layout, sort_lx: bool) -> int:
+    return _LAYOUTS[layout] | (BUILD_SORT_LX if sort_lx else 0)
+
+
+def build_str(rects, fanout: int = 32, layout="soa", sort_lx: bool = False) -> Tree:
+    """STR tree over host rectangles (built on the device).  sort_lx: entries
+    of every node in ascending low x (needed by the join pruning)."""
     r = _rects(rects)
     h = _vp()
-    _check(_L.rt_build_str(_f(r), r.shape[0], int(fanout), _LAYOUTS[layout], C.byref(h)))
+    _check(_L.rt_build_str(_f(r), r.shape[0], int(fanout), _layout_arg(layout, sort_lx), C.byref(h)))
     return Tree(h.value)
 
 
-def build_str_device(d_rects: int, n: int, fanout: int = 32, layout="soa", stream: int = 0) -> Tree:
+def build_str_device(d_rects: int, n: int, fanout: int = 32, layout="soa", stream: int = 0,
+                     sort_lx: bool = False) -> Tree:
     h = _vp()
-    _check(_L.rt_build_str_device(_vp(d_rects), int(n), int(fanout), _LAYOUTS[layout], _vp(stream), C.byref(h)))
+    _check(_L.rt_build_str_device(_vp(d_rects), int(n), int(fanout), _layout_arg(layout, sort_lx), _vp(stream),
+                                  C.byref(h)))
     return Tree(h.value)
 
 
@@ -185,14 +196,23 @@ def range_select(tree: Tree, queries):
     return _take_ids(p)
 
 
-def spatial_join(a: Tree, b: Tree) -> np.ndarray:
+def spatial_join(a: Tree, b: Tree, flags: int | None = None, with_tests: bool = False):
+    """All intersecting (a, b) as an (n, 2) uint32 array in lexicographic
+    order.  flags: JOIN_O3 | JOIN_O4 | JOIN_O5, JOIN_TILE, 0, or None for the
+    library default.  with_tests: also return the number of child-pair
+    predicates evaluated."""
     p = C.POINTER(_Pairs)()
-    _check(_L.rt_spatial_join(a.h, b.h, C.byref(p)))
+    tests = _u64(0)
+    if flags is None and not with_tests:
+        _check(_L.rt_spatial_join(a.h, b.h, C.byref(p)))
+    else:
+        _check(_L.rt_spatial_join_ex(a.h, b.h, JOIN_DEFAULT if flags is None else int(flags), C.byref(p),
+                                     C.byref(tests) if with_tests else None))
     n = int(p.contents.n)
     out = np.ctypeslib.as_array(p.contents.pairs, shape=(2 * n,)).copy().reshape(n, 2) if n else \
         np.zeros((0, 2), np.uint32)
     _L.rt_free(C.cast(p, _vp))
-    return out
+    return (out, int(tests.value)) if with_tests else out
 
 
 def visit_stats(tree: Tree, queries):

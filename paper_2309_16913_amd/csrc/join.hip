@@ -135,6 +135,175 @@ join_level_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t
     if (!FILL && lane == 0) counts[p] = total;
 }
 
+// ---------------------------------------------------------------------------
+// Node-pair expansion over candidate lists (section 4.1 pruning, section 4.2
+// many-to-many).  One wave per frontier pair; lane i holds outer child i of
+// node u (tree A) and lane j inner child j of node v (tree B) in registers,
+// loaded once.  Each outer lane i gets a count f_i of inner candidates, the
+// inner children 0..f_i-1:
+//   no pruning          f_i = number of inner children
+//   O3 (outer slicing)  f_i = 0 unless outer low x <= max inner high x; with
+//                       children sorted by low x this keeps a prefix of the
+//                       outer node (the first child that fails ends the scan)
+//   O4 (one to many)    for each kept outer child, its high x is broadcast and
+//                       compared with every inner low x in one ballot; f_i is
+//                       the length of the leading run of qualifying children
+//   O5 (many to many)   every outer lane searches the sorted inner low x on
+//                       its own: gather at n/2, compare, and on a clear bit
+//                       record the flip index and step down, else step up,
+//                       log2(n)+1 rounds -- the same f_i as O4
+// The candidates (i, j < f_i) are then enumerated 64 per round through an
+// exclusive scan of f: lane t finds its i by a binary search over the scan
+// and j = t - scan[i], fetches both MBRs from their lanes and applies the
+// full overlap predicate.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float wave_max(float v) {
+    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d));
+    return v;
+}
+
+// exclusive prefix sum over the wave; *total receives the sum
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane, uint32_t *total) {
+    uint32_t inc = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t x = __shfl_up(inc, d);
+        if (lane >= (uint32_t)d) inc += x;
+    }
+    *total = __shfl(inc, 63);
+    return inc - v;
+}
+
+template <int MODE, bool FILL, bool O3, int SHRINK>
+__global__ void __launch_bounds__(256)
+join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t nfr, uint32_t *__restrict__ counts,
+                 const uint64_t *__restrict__ offsets, uint2 *__restrict__ next, uint64_t *__restrict__ keys,
+                 Ctrl *__restrict__ ctrl, unsigned long long *__restrict__ tests_acc) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (p >= nfr) return;   // whole wave leaves together
+    const uint2 pr = fr[p];
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    float alx = NAN, aly = NAN, ahx = NAN, ahy = NAN, blx = NAN, bly = NAN, bhx = NAN, bhy = NAN;
+    if (lane < A.fanout) load_any(A, pr.x, lane, alx, aly, ahx, ahy);
+    if (lane < B.fanout) load_any(B, pr.y, lane, blx, bly, bhx, bhy);
+    // unused slots hold NaN and sit after the used ones
+    const bool av = alx == alx, bv = blx == blx;
+    const uint32_t nb = (uint32_t)__popcll(__ballot(bv));
+    bool act = av;
+    if (O3) {
+        const float m = wave_max(bv ? bhx : -INFINITY);
+        act = av && alx <= m;
+    }
+    uint32_t f = nb;
+    if (SHRINK == 4) {
+        f = 0;
+        uint64_t todo = __ballot(act);
+        while (todo) {
+            const uint32_t i = (uint32_t)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const float h = __shfl(ahx, (int)i);
+            const uint64_t q = __ballot(bv && blx <= h);
+            const uint32_t stop = ~q ? (uint32_t)__builtin_ctzll(~q) : 64u;
+            if (lane == i) f = stop;
+        }
+    } else if (SHRINK == 5) {
+        uint32_t npow = 1, lg = 0;
+        while (npow < nb) {
+            npow <<= 1;
+            ++lg;
+        }
+        int g = (int)(npow >> 1);
+        uint32_t flip = npow;
+        for (uint32_t it = 0; it <= lg; ++it) {
+            const float v = __shfl(blx, g & 63);
+            const bool in = g >= 0 && (uint32_t)g < npow;
+            const bool bit = (uint32_t)g < nb && v <= ahx;
+            const int step = (it + 2 <= lg) ? (int)(npow >> (it + 2)) : 1;
+            if (in) {
+                if (bit) {
+                    g += step;
+                } else {
+                    flip = (uint32_t)g;
+                    g -= step;
+                }
+            }
+        }
+        f = flip;
+    }
+    if (!act) f = 0;
+    uint32_t T = 0;
+    const uint32_t pre = wave_excl_scan(f, lane, &T);
+    uint64_t pos = 0, end = 0;
+    if (FILL) {
+        pos = offsets[p];
+        end = offsets[p + 1];
+    }
+    uint32_t total = 0;
+    for (uint32_t base = 0; base < T; base += 64) {
+        const uint32_t t = base + lane;
+        uint32_t i = 0;
+        for (uint32_t sft = 32; sft >= 1; sft >>= 1) {
+            const uint32_t c = __shfl(pre, (int)(i + sft));
+            if (c <= t) i += sft;
+        }
+        const uint32_t j = min(t - __shfl(pre, (int)i), 63u);
+        const float olx = __shfl(alx, (int)i), oly = __shfl(aly, (int)i);
+        const float ohx = __shfl(ahx, (int)i), ohy = __shfl(ahy, (int)i);
+        const float ilx = __shfl(blx, (int)j), ily = __shfl(bly, (int)j);
+        const float ihx = __shfl(bhx, (int)j), ihy = __shfl(bhy, (int)j);
+        const bool hit = t < T && (olx <= ihx) && (ilx <= ohx) && (oly <= ihy) && (ily <= ohy);
+        const uint64_t m = __ballot(hit);
+        if (FILL && hit) {
+            const uint64_t o = pos + total + (uint64_t)__popcll(m & below);
+            const uint32_t ca = ptr_any(A, pr.x, i), cb = ptr_any(B, pr.y, j);
+            if (o < end) {
+                if (MODE == JOIN_EMIT)
+                    keys[o] = ((uint64_t)ca << 32) | cb;
+                else
+                    next[o] = make_uint2(ca, cb);
+            } else {
+                atomicOr(&ctrl->err, kErrBounds);
+            }
+        }
+        total += (uint32_t)__popcll(m);
+    }
+    if (!FILL && lane == 0) {
+        counts[p] = total;
+        // spread over kTestSlots counters, one 128-byte line each
+        if (tests_acc) atomicAdd(&tests_acc[(p % kTestSlots) * 16], (unsigned long long)T);
+    }
+}
+
+template <int MODE, bool O3, int SHRINK>
+static hipError_t launch_cand(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr, bool fill,
+                              uint32_t *counts, const uint64_t *offsets, uint2 *next, uint64_t *keys, Ctrl *ctrl,
+                              unsigned long long *tests_acc, hipStream_t s) {
+    const uint32_t blocks = (nfr + 3) / 4;
+    if (fill)
+        hipLaunchKernelGGL((join_cand_kernel<MODE, true, O3, SHRINK>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr,
+                           counts, offsets, next, keys, ctrl, (unsigned long long *)nullptr);
+    else
+        hipLaunchKernelGGL((join_cand_kernel<MODE, false, O3, SHRINK>), dim3(blocks), dim3(256), 0, s, a, b, fr,
+                           nfr, counts, offsets, next, keys, ctrl, tests_acc);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_cand_flags(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr, bool fill,
+                                    uint32_t *counts, const uint64_t *offsets, uint2 *next, uint64_t *keys,
+                                    Ctrl *ctrl, int flags, unsigned long long *ta, hipStream_t s) {
+    const bool o3 = flags & JOIN_O3;
+    const int sh = (flags & JOIN_O5) ? 5 : ((flags & JOIN_O4) ? 4 : 0);
+    if (o3) {
+        if (sh == 5) return launch_cand<MODE, true, 5>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
+        if (sh == 4) return launch_cand<MODE, true, 4>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
+        return launch_cand<MODE, true, 0>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
+    }
+    if (sh == 5) return launch_cand<MODE, false, 5>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
+    if (sh == 4) return launch_cand<MODE, false, 4>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
+    return launch_cand<MODE, false, 0>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
+}
+
 template <int MODE>
 static hipError_t launch_mode(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr, bool fill,
                               uint32_t *counts, const uint64_t *offsets, uint2 *next, uint64_t *keys,
@@ -151,8 +320,16 @@ static hipError_t launch_mode(const TreeView &a, const TreeView &b, const uint2 
 
 hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *frontier, uint32_t nfr,
                              int mode, bool fill, uint32_t *counts, const uint64_t *offsets, uint2 *next,
-                             uint64_t *keys, Ctrl *ctrl, hipStream_t s) {
+                             uint64_t *keys, Ctrl *ctrl, int flags, unsigned long long *tests_acc,
+                             hipStream_t s) {
     if (nfr == 0) return hipSuccess;
+    if (!(flags & JOIN_TILE) && (mode == JOIN_BOTH || mode == JOIN_EMIT)) {
+        if (mode == JOIN_BOTH)
+            return launch_cand_flags<JOIN_BOTH>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, flags,
+                                                tests_acc, s);
+        return launch_cand_flags<JOIN_EMIT>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, flags,
+                                            tests_acc, s);
+    }
     switch (mode) {
     case JOIN_BOTH:
         return launch_mode<JOIN_BOTH>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, s);

@@ -202,6 +202,8 @@ extern "C" int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uin
     try {
         if (fanout == 0) fanout = 32;
         if (fanout < 2 || fanout > 64) return fail(RT_EINVAL, "fanout %u not in 2..64", fanout);
+        const bool sort_lx = (layout & RT_BUILD_SORT_LX) != 0;
+        layout &= ~RT_BUILD_SORT_LX;
         if (layout == RT_LAYOUT_AUTO) layout = RT_LAYOUT_SOA;
         if (layout != RT_LAYOUT_AOS && layout != RT_LAYOUT_SOA && layout != RT_LAYOUT_D2)
             return fail(RT_EINVAL, "unknown layout %u", layout);
@@ -213,7 +215,7 @@ extern "C" int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uin
         hipError_t e = d.alloc(n ? n * 16 : 16);
         if (e == hipSuccess && n) e = hipMemcpy(d.p, rects, n * 16, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "uploading the rectangles");
-        return build_str_on_device(static_cast<const float4 *>(d.p), n, fanout, layout, nullptr, out);
+        return build_str_on_device(static_cast<const float4 *>(d.p), n, fanout, layout, sort_lx, nullptr, out);
     } catch (const std::bad_alloc &) {
         return fail(RT_ENOMEM, "host allocation failed");
     } catch (...) {
@@ -240,6 +242,7 @@ extern "C" int rt_tree_stats(const rt_tree *t, rt_tree_info *info) {
     info->node_bytes = t->node_bytes;
     info->first_leaf = t->first_leaf;
     info->device = t->device;
+    info->flags = t->sorted_lx ? RT_BUILD_SORT_LX : 0u;
     return RT_OK;
 }
 
@@ -531,17 +534,36 @@ static int bits_for(uint64_t maxval) {
 }
 
 extern "C" int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **out) {
+    return rt_spatial_join_ex(a, b, RT_JOIN_DEFAULT, out, nullptr);
+}
+
+extern "C" int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t flags, rt_pairs **out,
+                                  uint64_t *tests) {
     if (!out) return fail(RT_EINVAL, "out is NULL");
     *out = nullptr;
+    if (tests) *tests = 0;
     if (!a || !b) return fail(RT_EINVAL, "tree is NULL");
     if (a->device != b->device) return fail(RT_EINVAL, "trees are on different devices");
+    const bool both_sorted = a->sorted_lx && b->sorted_lx;
+    // measured fastest: candidate lists with O3 + O5 on sorted trees, else the
+    // full tile (candidate lists without pruning cost more than they save)
+    if (flags == RT_JOIN_DEFAULT) flags = both_sorted ? (RT_JOIN_O3 | RT_JOIN_O5) : RT_JOIN_TILE;
+    if (flags & ~(RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5 | RT_JOIN_TILE))
+        return fail(RT_EINVAL, "unknown join flags 0x%x", (unsigned)flags);
+    if ((flags & RT_JOIN_TILE) && (flags & ~RT_JOIN_TILE))
+        return fail(RT_EINVAL, "RT_JOIN_TILE cannot be combined with pruning");
+    if ((flags & (RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5)) && !both_sorted)
+        return fail(RT_EINVAL, "join pruning needs both trees built with RT_BUILD_SORT_LX");
     try {
         DevSet ds(a->device);
         hipStream_t s = nullptr;
         const TreeView va = view_of(a), vb = view_of(b);
-        DevBuf ctrl_b, fr, cnt, off, tmp, keys;
+        DevBuf ctrl_b, fr, cnt, off, tmp, keys, tacc;
         hipError_t e = ctrl_b.alloc(sizeof(Ctrl));
         if (e == hipSuccess) e = fr.alloc(8);
+        if (e == hipSuccess && tests) e = tacc.alloc(kTestSlots * 16 * 8);
+        if (e == hipSuccess && tests) e = launch_zero(tacc.p, kTestSlots * 16 * 8, s);
+        unsigned long long *tests_acc = static_cast<unsigned long long *>(tacc.p);
         if (e != hipSuccess) return hip_fail(e, "join setup");
         Ctrl *ctrl = static_cast<Ctrl *>(ctrl_b.p);
         e = launch_zero(ctrl, sizeof(Ctrl), s);
@@ -560,7 +582,7 @@ extern "C" int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **ou
             if (e == hipSuccess) e = tmp.alloc(scan_tmp_elems(nfr) * 8);
             if (e != hipSuccess) return hip_fail(e, "join frontier");
             e = launch_join_level(va, vb, static_cast<uint2 *>(fr.p), (uint32_t)nfr, mode, false,
-                                  static_cast<uint32_t *>(cnt.p), nullptr, nullptr, nullptr, ctrl, s);
+                                  static_cast<uint32_t *>(cnt.p), nullptr, nullptr, nullptr, ctrl, flags, tests_acc, s);
             if (e == hipSuccess)
                 e = launch_scan_u32(static_cast<uint32_t *>(cnt.p), nfr, static_cast<uint64_t *>(off.p),
                                     static_cast<uint64_t *>(tmp.p), s);
@@ -576,7 +598,7 @@ extern "C" int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **ou
                 if (e == hipSuccess)
                     e = launch_join_level(va, vb, static_cast<uint2 *>(fr.p), (uint32_t)nfr, mode, true, nullptr,
                                           static_cast<uint64_t *>(off.p), nullptr, static_cast<uint64_t *>(keys.p),
-                                          ctrl, s);
+                                          ctrl, flags, nullptr, s);
                 if (e != hipSuccess) return hip_fail(e, "join emit");
                 npairs = total;
                 // canonical order: 64-bit (idA << 32 | idB) keys, sorting only the digits that can be nonzero
@@ -603,7 +625,8 @@ extern "C" int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **ou
             e = nxt.alloc(total * 8);
             if (e == hipSuccess)
                 e = launch_join_level(va, vb, static_cast<uint2 *>(fr.p), (uint32_t)nfr, mode, true, nullptr,
-                                      static_cast<uint64_t *>(off.p), static_cast<uint2 *>(nxt.p), nullptr, ctrl, s);
+                                      static_cast<uint64_t *>(off.p), static_cast<uint2 *>(nxt.p), nullptr, ctrl,
+                                      flags, nullptr, s);
             if (e != hipSuccess) return hip_fail(e, "join expand");
             std::swap(fr.p, nxt.p);
             nfr = total;
@@ -615,6 +638,14 @@ extern "C" int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **ou
         e = hipMemcpy(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "join status");
         if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
+        if (tests) {
+            std::vector<unsigned long long> h(kTestSlots * 16);
+            e = hipMemcpy(h.data(), tacc.p, h.size() * 8, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return hip_fail(e, "join statistics");
+            uint64_t sum = 0;
+            for (uint32_t k = 0; k < kTestSlots; ++k) sum += h[k * 16];
+            *tests = sum;
+        }
         void *mem = obj_alloc(KIND_PAIRS, sizeof(rt_pairs));
         if (!mem) return fail(RT_ENOMEM, "host allocation failed");
         rt_pairs *r = static_cast<rt_pairs *>(mem);

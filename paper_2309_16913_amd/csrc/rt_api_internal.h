@@ -14,6 +14,7 @@ struct rt_tree {
     uint64_t n_objects = 0, n_entries = 0;
     float mbr[4] = {0, 0, 0, 0};
     uint32_t level_start[33] = {0};   // first node index of each level (0 = leaves)
+    uint32_t sorted_lx = 0;           // 1: every node's entries ascend in low x
     uint32_t split_kmin = 0;          // mapping: split queries reaching >= this many
                                       // parents-of-leaves (0 = one group per query)
     void *d_nodes = nullptr;   // n_nodes * node_bytes
@@ -42,8 +43,8 @@ int check_rects(const float *r, uint64_t n, const char *what);
 TreeView view_of(const rt_tree *t);
 // STR bulk load of n device rectangles (validated again on the device) on
 // stream s; returns after the build has finished.
-int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t fanout, uint32_t layout, hipStream_t s,
-                        rt_tree **out);
+int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t fanout, uint32_t layout, bool sort_lx,
+                        hipStream_t s, rt_tree **out);
 int make_ids(uint64_t nq, uint64_t total, rt_ids **out);
 // stage bit 1: count stage (order, split, count pass, offsets); bit 2: fill
 // stage (fill pass, sort, status).  d_counts_out: count-only mode.

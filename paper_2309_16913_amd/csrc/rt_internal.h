@@ -140,10 +140,18 @@ hipError_t launch_zero(void *p, uint64_t bytes, hipStream_t s);
 
 // ---- join ---------------------------------------------------------------
 enum JoinMode : int { JOIN_BOTH = 0, JOIN_EMIT = 1, JOIN_DESC_A = 2, JOIN_DESC_B = 3 };
+// expansion variants (same values as the public RT_JOIN_* flags): outer
+// slicing, one-to-many / many-to-many inner shrinking (need nodes sorted by
+// low x), or the full Fa x Fb tile without candidate lists
+enum JoinFlags : int { JOIN_O3 = 1, JOIN_O4 = 2, JOIN_O5 = 4, JOIN_TILE = 8 };
+// tests_acc (NULL: not counted): the count pass (fill = false) of the
+// candidate kernels adds the number of pair predicates it evaluates to
+// tests_acc[(pair % kTestSlots) * 16]; the sum over the slots is the total.
+constexpr uint32_t kTestSlots = 256;
 hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *frontier,
                              uint32_t nfr, int mode, bool fill, uint32_t *counts,
                              const uint64_t *offsets, uint2 *next, uint64_t *keys, Ctrl *ctrl,
-                             hipStream_t s);
+                             int flags, unsigned long long *tests_acc, hipStream_t s);
 hipError_t launch_keys_to_pairs(const uint64_t *keys, uint64_t n, uint32_t *pairs, hipStream_t s);
 
 // ---- batch --------------------------------------------------------------

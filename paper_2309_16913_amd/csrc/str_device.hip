@@ -20,6 +20,9 @@
 // is the place of node k of level l (creation order) inside its level; it is
 // computed from the root down: the children of the node stored at place g
 // start at the sum of the entry counts of the nodes stored before g.
+//
+// Optionally (RT_BUILD_SORT_LX) the entries of every node are reordered by
+// low x before the placement, which moves the children with their entries.
 #include <cmath>
 #include <new>
 #include <vector>
@@ -74,6 +77,29 @@ __global__ void str_slice_keys(const uint64_t *__restrict__ ys, const uint32_t *
         const uint32_t i = (uint32_t)ys[q];
         keys[q] = ((uint64_t)(xrank[i] / slice) << 32) | i;
     }
+}
+
+// Optional low-x order inside every node (one wave per node): each entry's
+// rank among its node's entries by (low x, position in the packing order).
+// order_in NULL: identity.  order_in may equal order_out.
+__global__ void str_sort_runs(const uint64_t *order_in, uint64_t *order_out, const float4 *__restrict__ items,
+                              uint32_t c, uint32_t F, uint32_t P) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (k >= P) return;   // whole wave leaves together
+    const uint32_t r0 = k * F;
+    const uint32_t cnt = c > r0 ? min(c - r0, F) : 0u;
+    uint32_t item = 0, key = 0xFFFFFFFFu;
+    if (lane < cnt) {
+        item = order_in ? (uint32_t)order_in[r0 + lane] : r0 + lane;
+        key = order_key(items[item].x);
+    }
+    uint32_t rank = 0;
+    for (uint32_t e = 0; e < cnt; ++e) {
+        const uint32_t ke = __shfl(key, (int)e);
+        rank += (ke < key || (ke == key && e < lane)) ? 1u : 0u;
+    }
+    if (lane < cnt) order_out[r0 + rank] = item;
 }
 
 // Node MBRs of a level: node k covers packing positions [kF, min(kF+F, c)).
@@ -160,8 +186,8 @@ static uint32_t grid_for(uint64_t n) {
 
 static uint64_t al(uint64_t b) { return (b + 255) & ~255ull; }
 
-int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t layout, hipStream_t s,
-                        rt_tree **out) {
+int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t layout, bool sort_lx,
+                        hipStream_t s, rt_tree **out) {
     // level sizes, leaves first
     std::vector<uint64_t> items, nodes;
     for (uint64_t c = n;;) {
@@ -186,7 +212,7 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
     uint64_t ws = 0;
     for (uint32_t l = 0; l < H; ++l) {
         ord_off[l] = ws;
-        ws += items[l] > F ? al(8 * items[l]) : 0;
+        ws += (items[l] > F || sort_lx) ? al(8 * items[l] + 8) : 0;
         mbr_off[l] = ws;
         ws += al(16 * nodes[l]);
         pos_off[l] = ws;
@@ -215,6 +241,7 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
     (void)hipGetDevice(&t->device);
     t->fanout = F;
     t->layout = layout;
+    t->sorted_lx = sort_lx ? 1u : 0u;
     t->height = H;
     t->n_nodes = (uint32_t)total;
     t->first_leaf = (uint32_t)first[0];
@@ -235,7 +262,7 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
     if (e != hipSuccess) return bail(hip_fail(e, "device build allocation"));
     uint8_t *wb = static_cast<uint8_t *>(work.p);
     auto ord = [&](uint32_t l) {
-        return items[l] > F ? reinterpret_cast<uint64_t *>(wb + ord_off[l]) : (uint64_t *)nullptr;
+        return (items[l] > F || sort_lx) ? reinterpret_cast<uint64_t *>(wb + ord_off[l]) : (uint64_t *)nullptr;
     };
     auto mbr = [&](uint32_t l) { return reinterpret_cast<float4 *>(wb + mbr_off[l]); };
     auto pos = [&](uint32_t l) { return reinterpret_cast<uint32_t *>(wb + pos_off[l]); };
@@ -258,7 +285,7 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
         const uint32_t cl = (uint32_t)items[l];
         const float4 *it = l == 0 ? d_rects : mbr(l - 1);
         uint64_t *order = ord(l);
-        if (order) {
+        if (cl > F) {
             const uint64_t P = nodes[l];
             uint64_t S = (uint64_t)std::sqrt((double)P);
             while (S * S < P) ++S;
@@ -291,6 +318,10 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
                 e = hipErrorUnknown;
                 break;
             }
+        }
+        if (sort_lx) {   // the top level's packing order is the identity
+            hipLaunchKernelGGL(str_sort_runs, dim3((uint32_t)((nodes[l] + 3) / 4)), dim3(256), 0, s,
+                               cl > F ? order : (const uint64_t *)nullptr, order, it, cl, F, (uint32_t)nodes[l]);
         }
         hipLaunchKernelGGL(str_mbrs, dim3(grid_for(nodes[l])), dim3(256), 0, s, it, order, cl, F,
                            (uint32_t)nodes[l], mbr(l));
@@ -337,13 +368,15 @@ extern "C" int rt_build_str_device(const float *d_rects, uint64_t n, uint32_t fa
     try {
         if (fanout == 0) fanout = 32;
         if (fanout < 2 || fanout > 64) return fail(RT_EINVAL, "fanout %u not in 2..64", fanout);
+        const bool sort_lx = (layout & RT_BUILD_SORT_LX) != 0;
+        layout &= ~RT_BUILD_SORT_LX;
         if (layout == RT_LAYOUT_AUTO) layout = RT_LAYOUT_SOA;
         if (layout != RT_LAYOUT_AOS && layout != RT_LAYOUT_SOA && layout != RT_LAYOUT_D2)
             return fail(RT_EINVAL, "unknown layout %u", layout);
         if (n >= 0xFFFFFFFFull) return fail(RT_EINVAL, "n = %llu does not fit 32-bit ids", (unsigned long long)n);
         if (n && !d_rects) return fail(RT_EINVAL, "rects is NULL with n = %llu", (unsigned long long)n);
         if ((reinterpret_cast<uintptr_t>(d_rects) & 15) != 0) return fail(RT_EINVAL, "rects not 16-byte aligned");
-        return build_str_on_device(reinterpret_cast<const float4 *>(d_rects), n, fanout, layout,
+        return build_str_on_device(reinterpret_cast<const float4 *>(d_rects), n, fanout, layout, sort_lx,
                                    static_cast<hipStream_t>(stream), out);
     } catch (const std::bad_alloc &) {
         return fail(RT_ENOMEM, "host allocation failed");

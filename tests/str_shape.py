@@ -14,7 +14,9 @@ from these rules, restated here independently of the library's code:
   * a level of c <= F items is the root, holding them in index order;
   * node MBRs (exact min/max of their items) are the next level's items;
   * numbering is breadth first from the root; the children of each node are
-    stored contiguously in its entry order.
+    stored contiguously in its entry order;
+  * with the low-x option, the entries of every node are reordered by
+    ascending low x (ties keep their order) before the numbering.
 
 `expected_export` gives the same arrays as `Tree.export()`.
 """
@@ -54,12 +56,24 @@ def packing_order(items: np.ndarray, F: int) -> np.ndarray:
     return np.lexsort((idx, cy, xrank // slice_len))
 
 
-def expected_export(rects, F: int) -> dict:
+def sort_runs_lx(items: np.ndarray, order: np.ndarray, F: int) -> np.ndarray:
+    """Reorder each run of F packing positions (one node) by ascending low x,
+    ties keeping their packing order."""
+    out = order.copy()
+    for k0 in range(0, order.shape[0], F):
+        run = order[k0:k0 + F]
+        out[k0:k0 + F] = run[np.argsort(items[run, 0], kind="stable")]
+    return out
+
+
+def expected_export(rects, F: int, sort_lx: bool = False) -> dict:
     items = np.ascontiguousarray(rects, np.float32).reshape(-1, 4)
     levels = []   # (items, packing order, node count), leaves first
     while True:
         c = items.shape[0]
         order = packing_order(items, F)
+        if sort_lx:
+            order = sort_runs_lx(items, order, F)
         P = -(-c // F) if c > F else 1
         mbr = np.full((P, 4), np.nan, np.float32)
         for k in range(P):

@@ -72,6 +72,7 @@ def test_null_arguments_rejected():
     assert lib.rt_range_select(None, None, 0, C.byref(p)) == rt.RT_EINVAL
     q = C.POINTER(rt._Pairs)()
     assert lib.rt_spatial_join(None, None, C.byref(q)) == rt.RT_EINVAL
+    assert lib.rt_spatial_join_ex(None, None, rt.JOIN_O3 | rt.JOIN_O5, C.byref(q), None) == rt.RT_EINVAL
     lib.rt_free(None)   # no-op
     assert lib.rt_tree_stats(None, None) == rt.RT_EINVAL
     assert lib.rt_select_workspace_bytes(1000, 0) > 1000 * 4

@@ -1,0 +1,126 @@
+"""GPU join over nodes sorted by low x with the pruning of section 4: outer
+slicing (O3), one-to-many (O4) and many-to-many (O5) inner shrinking.  Every
+variant returns exactly the oracle's pair set, and evaluates exactly as many
+child-pair predicates as the oracle's pruned join does on the same trees
+(which pins the GPU's slicing and flip indices, not only its results)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import rtgen
+from str_shape import assert_export_equal, expected_export
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    assert torch.cuda.is_available(), "GPU test needs a GPU"
+    import paper_2309_16913_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ora():
+    return oracle.get()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _flag_sets(rt):
+    return [0, rt.JOIN_O3, rt.JOIN_O4, rt.JOIN_O5, rt.JOIN_O3 | rt.JOIN_O4, rt.JOIN_O3 | rt.JOIN_O5]
+
+
+@pytest.mark.parametrize("n,F,layout", [(0, 8, "soa"), (1, 4, "aos"), (64, 64, "d2"), (5000, 7, "soa"),
+                                        (60_000, 32, "aos"), (123_457, 16, "d2")])
+def test_sorted_build_shape(rt, ora, n, F, layout):
+    r = rtgen.adversarial_rects(n, 40 + n) if n else np.zeros((0, 4), np.float32)
+    t = rt.build_str(r, F, layout, sort_lx=True)
+    assert t.info().flags == rt.BUILD_SORT_LX
+    ex = t.export()
+    assert_export_equal(ex, expected_export(r, F, sort_lx=True), f"n={n} F={F} {layout}")
+    for u in range(ex["level"].shape[0]):
+        f0, c = int(ex["first"][u]), int(ex["count"][u])
+        assert np.all(np.diff(ex["lx"][f0:f0 + c]) >= 0)
+    assert ora.check(ora.tree_from_arrays(**ex), r)[0] == 0
+
+
+JOIN_CASES = [
+    # (name, A, Fa, layout a, B, Fb, layout b)
+    ("adv-small", lambda: rtgen.adversarial_rects(700, 1), 4, "soa", lambda: rtgen.adversarial_rects(900, 2), 4, "aos"),
+    ("uniform-clustered", lambda: rtgen.uniform_rects(40_000, 0.004, 3), 32, "soa",
+     lambda: rtgen.clustered_rects(40_000, 8, 0.05, 0.004, 4), 32, "soa"),
+    ("f64-f16", lambda: rtgen.uniform_rects(30_000, 0.005, 5), 64, "d2",
+     lambda: rtgen.uniform_rects(2_000, 0.01, 6), 16, "aos"),
+    ("unequal-height", lambda: rtgen.uniform_rects(50_000, 0.003, 7), 8, "soa",
+     lambda: rtgen.uniform_rects(300, 0.02, 8), 32, "soa"),
+    ("ragged", lambda: rtgen.clustered_rects(12_345, 5, 0.1, 0.01, 9), 7, "aos",
+     lambda: rtgen.adversarial_rects(30_000, 10), 13, "d2"),
+]
+
+
+@pytest.mark.parametrize("case", JOIN_CASES, ids=lambda c: c[0])
+def test_pruned_join_parity(rt, ora, case):
+    name, fa, Fa, la, fb, Fb, lb = case
+    A, B = fa(), fb()
+    say("join", name, A.shape[0], B.shape[0])
+    want = ora.join(ora.build_str(A, Fa), ora.build_str(B, Fb))
+    ta, tb = rt.build_str(A, Fa, la, sort_lx=True), rt.build_str(B, Fb, lb, sort_lx=True)
+    equal_h = ta.info().height == tb.info().height
+    assert equal_h == (name != "unequal-height"), (name, ta.info().height, tb.info().height)
+    oa = ora.tree_from_arrays(**ta.export())
+    ob = ora.tree_from_arrays(**tb.export())
+    for flags in _flag_sets(rt):
+        got, tests = rt.spatial_join(ta, tb, flags, with_tests=True)
+        assert np.array_equal(got, want), f"{name} flags {flags}: {got.shape} vs {want.shape}"
+        if equal_h:
+            p, otests = ora.join_opt(oa, ob, flags)
+            assert np.array_equal(p, want)
+            assert tests == otests, f"{name} flags {flags}: GPU evaluated {tests}, oracle {otests}"
+    got = rt.spatial_join(ta, tb, rt.JOIN_TILE)
+    assert np.array_equal(got, want)
+    assert np.array_equal(rt.spatial_join(ta, tb), want)   # default: O3|O5 on sorted trees
+
+
+def test_pruned_join_c3_sample(rt, ora):
+    """C3-shaped relations (2M x 2M at full size; a 200k x 200k cut here):
+    pruning removes most predicate evaluations and no pair."""
+    A = rtgen.uniform_rects(200_000, 5e-4, 3001)
+    B = rtgen.clustered_rects(200_000, 64, 0.01, 5e-4, 3002)
+    ta, tb = rt.build_str(A, 32, "soa", sort_lx=True), rt.build_str(B, 32, "soa", sort_lx=True)
+    want = ora.join(ora.build_str(A, 32), ora.build_str(B, 32))
+    oa, ob = ora.tree_from_arrays(**ta.export()), ora.tree_from_arrays(**tb.export())
+    assert ta.info().height == tb.info().height
+    res = {}
+    for flags in _flag_sets(rt):
+        got, tests = rt.spatial_join(ta, tb, flags, with_tests=True)
+        assert np.array_equal(got, want), flags
+        assert tests == ora.join_opt(oa, ob, flags)[1], flags
+        res[flags] = tests
+    say("tests per variant", res)
+    assert res[rt.JOIN_O3 | rt.JOIN_O5] == res[rt.JOIN_O3 | rt.JOIN_O4] < res[rt.JOIN_O3] <= res[0]
+
+
+def test_pruning_needs_sorted_trees(rt):
+    A = rtgen.uniform_rects(2000, 0.01, 11)
+    ts, tu = rt.build_str(A, 16, "soa", sort_lx=True), rt.build_str(A, 16, "soa")
+    assert tu.info().flags == 0
+    for flags in (rt.JOIN_O3, rt.JOIN_O4, rt.JOIN_O5):
+        with pytest.raises(rt.RTError):
+            rt.spatial_join(ts, tu, flags)
+    with pytest.raises(rt.RTError):
+        rt.spatial_join(ts, ts, rt.JOIN_TILE | rt.JOIN_O3)
+    with pytest.raises(rt.RTError):
+        rt.spatial_join(ts, ts, 64)
+    # unsorted trees still join without pruning, in both kernels
+    want = rt.spatial_join(ts, ts, rt.JOIN_O3 | rt.JOIN_O5)
+    assert np.array_equal(rt.spatial_join(tu, tu, 0), want)
+    assert np.array_equal(rt.spatial_join(tu, tu, rt.JOIN_TILE), want)
+    assert np.array_equal(rt.spatial_join(tu, tu), want)
