@@ -170,20 +170,74 @@ def cpu_baseline(args, rects, queries, gpu_off, gpu_ids):
                 checked_queries=done, mismatching_chunks=mismatches)
 
 
-def join_leg(rt, args):
+def join_leg(rt, torch, args):
+    """C3 join (2M uniform x 2M clustered at full size).  Trees are built on
+    the device with every node sorted by low x; the headline variant is the
+    library default on such trees (O3 outer slicing + O5 many-to-many inner
+    shrinking).  Times are for the device-output call (pairs left in HBM);
+    the host-output call (pairs copied over PCIe) is reported beside it, and
+    every variant of section 4 is timed on the same trees."""
     import rtgen
     a, b = rtgen.c3_join(args.join_n)
-    ta, tb = rt.build_str(a, 32, "soa"), rt.build_str(b, 32, "soa")
-    p = rt.spatial_join(ta, tb)   # warm
-    times = []
+    F = args.join_fanout
+    ta = rt.build_str(a, F, "soa", sort_lx=True)
+    tb = rt.build_str(b, F, "soa", sort_lx=True)
+    n = rt.spatial_join_device(ta, tb, 0, 0)
+    buf = torch.empty(2 * max(n, 1), dtype=torch.int32, device="cuda")
+
+    def time_dev(flags):
+        rt.spatial_join_device(ta, tb, buf.data_ptr(), n, flags)   # warm
+        ts = []
+        for _ in range(args.join_reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            got = rt.spatial_join_device(ta, tb, buf.data_ptr(), n, flags)
+            ts.append(time.perf_counter() - t0)
+            assert got == n
+        return float(np.median(ts)) * 1e3
+
+    ms = time_dev(None)
+    hts = []
     for _ in range(args.join_reps):
         t0 = time.perf_counter()
         p = rt.spatial_join(ta, tb)
-        times.append(time.perf_counter() - t0)
-    ms = float(np.median(times)) * 1e3
-    return dict(workload=f"join_uniform{args.join_n}_x_clustered{args.join_n}_f32_soa", pairs=int(p.shape[0]),
-                ms=ms, pairs_per_s=p.shape[0] / (ms / 1e3),
-                note="synchronous call, includes per-level size reads and the copy of the sorted pairs to host")
+        hts.append(time.perf_counter() - t0)
+    assert p.shape[0] == n
+    variants = {}
+    for name, fl in [("tile", rt.JOIN_TILE), ("cand", 0), ("O3", rt.JOIN_O3), ("O3+O4", rt.JOIN_O3 | rt.JOIN_O4),
+                     ("O3+O5", rt.JOIN_O3 | rt.JOIN_O5), ("O5", rt.JOIN_O5)]:
+        _, tests = rt.spatial_join(ta, tb, fl, with_tests=True)
+        variants[name] = dict(ms=round(time_dev(fl), 4), predicate_tests=tests)
+    return dict(workload=f"join_uniform{args.join_n}_x_clustered{args.join_n}_f{F}_soa_sorted_lx", pairs=int(n),
+                ms=ms, pairs_per_s=n / (ms / 1e3), host_output_ms=float(np.median(hts)) * 1e3,
+                variants_ms=variants,
+                note="device-output call, synchronous; includes per-level size reads on the host and the sort")
+
+
+def build_leg(rt, torch, args, rects):
+    """Device STR bulk load of the resident rectangles (not part of the
+    query step): rectangles already in HBM, and from host memory."""
+    d = torch.from_numpy(rects).cuda()
+    s = torch.cuda.current_stream()
+    out = {}
+    for sort_lx in (False, True):
+        ts = []
+        for _ in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            t = rt.build_str_device(d.data_ptr(), rects.shape[0], args.fanout, args.layout, s.cuda_stream,
+                                    sort_lx=sort_lx)
+            ts.append(time.perf_counter() - t0)
+            t.free()
+        out["device_ms" + ("_sorted_lx" if sort_lx else "")] = float(np.median(ts[1:])) * 1e3
+    t0 = time.perf_counter()
+    t = rt.build_str(rects, args.fanout, args.layout)
+    out["host_input_ms"] = (time.perf_counter() - t0) * 1e3
+    t.free()
+    del d
+    out["rects"] = int(rects.shape[0])
+    out["fanout"] = args.fanout
+    return out
 
 
 def batch_leg(rt, torch, args):
@@ -295,7 +349,7 @@ def main():
     ap.add_argument("--nq", type=int, default=1_000_000)
     ap.add_argument("--fanout", type=int, default=32)
     ap.add_argument("--layout", default="soa")
-    ap.add_argument("--legs", default="join,batch,serve,cpu")
+    ap.add_argument("--legs", default="build,join,batch,serve,cpu")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before the select leg, copy this many MiB device-to-device three times (a plain copy "
                          "kernel of known size, used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -304,6 +358,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--join-n", type=int, default=2_000_000)
     ap.add_argument("--join-reps", type=int, default=5)
+    ap.add_argument("--join-fanout", type=int, default=32)
     ap.add_argument("--batch-trees", type=int, default=256)
     ap.add_argument("--batch-scale", type=float, default=1.0)
     ap.add_argument("--batch-reps", type=int, default=3)
@@ -379,9 +434,14 @@ def main():
         result["cpu_baseline"] = cpu_baseline(args, rects, queries, goff, gids)
     del s
     torch.cuda.empty_cache()
+    if "build" in legs:
+        log("[bench] build leg")
+        result["legs"]["build"] = build_leg(rt, torch, args, rects)
+        torch.cuda.empty_cache()
     if "join" in legs:
         log("[bench] join leg")
-        result["legs"]["join"] = join_leg(rt, args)
+        result["legs"]["join"] = join_leg(rt, torch, args)
+        torch.cuda.empty_cache()
     if "batch" in legs:
         log("[bench] batch leg")
         result["legs"]["batch"] = batch_leg(rt, torch, args)

@@ -162,6 +162,16 @@ int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **out);
  * RT_EINVAL. */
 int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t flags, rt_pairs **out, uint64_t *tests);
 
+/* Join with the result left in device memory: d_pairs (2 * capacity uint32
+ * on the trees' device, caller-owned) receives pairs[2k] = a,
+ * pairs[2k+1] = b in lexicographic order and *n_pairs (host) their number.
+ * More pairs than capacity -> RT_ENOMEM with *n_pairs set and d_pairs
+ * untouched (call again with a buffer that large).  flags as for
+ * rt_spatial_join_ex.  Runs on `stream` (hipStream_t, NULL = default) and
+ * returns after that work has finished. */
+int rt_spatial_join_device(const rt_tree *a, const rt_tree *b, int32_t flags, uint32_t *d_pairs,
+                           uint64_t capacity, uint64_t *n_pairs, void *stream);
+
 /* Release an rt_tree, rt_ids or rt_pairs (and a tree's device memory).
  * NULL is a no-op. */
 void rt_free(void *obj);

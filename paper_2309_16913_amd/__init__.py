@@ -71,6 +71,7 @@ _sig = {
     "rt_range_select": ([_vp, _fp, _u64, C.POINTER(C.POINTER(_Ids))], C.c_int),
     "rt_spatial_join": ([_vp, _vp, C.POINTER(C.POINTER(_Pairs))], C.c_int),
     "rt_spatial_join_ex": ([_vp, _vp, C.c_int32, C.POINTER(C.POINTER(_Pairs)), C.POINTER(_u64)], C.c_int),
+    "rt_spatial_join_device": ([_vp, _vp, C.c_int32, _vp, _u64, C.POINTER(_u64), _vp], C.c_int),
     "rt_free": ([_vp], None),
     "rt_select_workspace_bytes": ([_u64, _u64], _u64),
     "rt_range_select_device": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _u64, _vp, _vp], C.c_int),
@@ -213,6 +214,20 @@ def spatial_join(a: Tree, b: Tree, flags: int | None = None, with_tests: bool = 
         np.zeros((0, 2), np.uint32)
     _L.rt_free(C.cast(p, _vp))
     return (out, int(tests.value)) if with_tests else out
+
+
+def spatial_join_device(a: Tree, b: Tree, d_pairs: int, capacity: int, flags: int | None = None,
+                        stream: int = 0) -> int:
+    """Join into caller device memory (2 * capacity uint32 at d_pairs).
+    Returns the number of pairs; if it exceeds capacity nothing was written
+    and the call can be repeated with a larger buffer."""
+    n = _u64(0)
+    rc = _L.rt_spatial_join_device(a.h, b.h, JOIN_DEFAULT if flags is None else int(flags), _vp(d_pairs),
+                                   int(capacity), C.byref(n), _vp(stream))
+    if rc == RT_ENOMEM and n.value > capacity:
+        return int(n.value)
+    _check(rc)
+    return int(n.value)
 
 
 def visit_stats(tree: Tree, queries):

@@ -1,0 +1,228 @@
+// Spatial join entry points: level-synchronous traversal of both trees
+// (section 4) driven from the host, one frontier of node pairs per level.
+//
+// Per level: a count pass gives each frontier pair its number of qualifying
+// child pairs, a scan turns the counts into output offsets, the host reads
+// the total, and a fill pass writes the next frontier (or, at the leaves,
+// the (idA << 32 | idB) keys).  The keys are radix sorted into the canonical
+// lexicographic order.  Device buffers are kept across levels and grown
+// geometrically, so a join allocates only a handful of times.
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "rt_api_internal.h"
+
+using namespace rtk;
+
+namespace {
+
+int bits_for(uint64_t maxval) {
+    int b = 0;
+    while (b < 64 && (maxval >> b)) ++b;
+    return b;
+}
+
+// Device buffer that only reallocates when it has to grow.
+struct Grow {
+    DevBuf b;
+    uint64_t cap = 0;   // bytes
+    hipError_t need(uint64_t bytes) {
+        if (bytes <= cap && b.p) return hipSuccess;
+        uint64_t c = cap * 2 > bytes ? cap * 2 : bytes;
+        if (c < 4096) c = 4096;
+        hipError_t e = b.alloc(c);
+        cap = e == hipSuccess ? c : 0;
+        return e;
+    }
+    template <class T> T *as() const { return static_cast<T *>(b.p); }
+};
+
+struct JoinRun {
+    Grow ctrl, fr[2], cnt, off, stmp, keys, ktmp, hist, hscan, rtmp, tacc;
+    uint64_t npairs = 0;
+    const uint64_t *sorted = nullptr;   // device, npairs keys
+    uint64_t tests = 0;
+};
+
+// Runs the join up to the sorted keys on the device.
+int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, hipStream_t s, JoinRun &w) {
+    const TreeView va = view_of(a), vb = view_of(b);
+    hipError_t e = w.ctrl.need(sizeof(Ctrl));
+    if (e == hipSuccess) e = w.fr[0].need(8);
+    if (e == hipSuccess && count_tests) e = w.tacc.need(kTestSlots * 16 * 8);
+    if (e != hipSuccess) return hip_fail(e, "join setup");
+    Ctrl *ctrl = w.ctrl.as<Ctrl>();
+    unsigned long long *tacc = count_tests ? w.tacc.as<unsigned long long>() : nullptr;
+    e = launch_zero(ctrl, sizeof(Ctrl), s);
+    if (e == hipSuccess && tacc) e = launch_zero(tacc, kTestSlots * 16 * 8, s);
+    if (e == hipSuccess) e = launch_zero(w.fr[0].b.p, 8, s);   // (root A, root B) = (0, 0)
+    if (e != hipSuccess) return hip_fail(e, "join setup");
+    uint64_t nfr = (a->n_objects && b->n_objects) ? 1 : 0;
+    int cur = 0;
+    int la = (int)a->height - 1, lb = (int)b->height - 1;
+    w.npairs = 0;
+    w.sorted = nullptr;
+    while (nfr) {
+        const int mode = la > lb ? JOIN_DESC_A : (lb > la ? JOIN_DESC_B : (la == 0 ? JOIN_EMIT : JOIN_BOTH));
+        e = w.cnt.need(nfr * 4);
+        if (e == hipSuccess) e = w.off.need((nfr + 1) * 8);
+        if (e == hipSuccess) e = w.stmp.need(scan_tmp_elems(nfr) * 8);
+        if (e != hipSuccess) return hip_fail(e, "join frontier");
+        const uint2 *fr = w.fr[cur].as<uint2>();
+        uint64_t *off = w.off.as<uint64_t>();
+        e = launch_join_level(va, vb, fr, (uint32_t)nfr, mode, false, w.cnt.as<uint32_t>(), nullptr, nullptr,
+                              nullptr, ctrl, flags, tacc, s);
+        if (e == hipSuccess) e = launch_scan_u32(w.cnt.as<uint32_t>(), nfr, off, w.stmp.as<uint64_t>(), s);
+        uint64_t total = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&total, off + nfr, 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "join count");
+        if (total == 0) break;
+        if (mode == JOIN_EMIT) {
+            e = w.keys.need(total * 8);
+            if (e == hipSuccess)
+                e = launch_join_level(va, vb, fr, (uint32_t)nfr, mode, true, nullptr, off, nullptr,
+                                      w.keys.as<uint64_t>(), ctrl, flags, nullptr, s);
+            if (e != hipSuccess) return hip_fail(e, "join emit");
+            // canonical order: sort only the digits that can be nonzero
+            int shifts[16], np = 0;
+            const int bb = bits_for(b->n_objects ? b->n_objects - 1 : 0);
+            const int ba = bits_for(a->n_objects ? a->n_objects - 1 : 0);
+            for (int sft = 0; sft < bb; sft += 8) shifts[np++] = sft;
+            for (int sft = 32; sft < 32 + ba; sft += 8) shifts[np++] = sft;
+            const uint64_t he = radix_hist_elems(total);
+            e = w.ktmp.need(total * 8);
+            if (e == hipSuccess) e = w.hist.need(he * 4);
+            if (e == hipSuccess) e = w.hscan.need((he + 1) * 8);
+            if (e == hipSuccess) e = w.rtmp.need(scan_tmp_elems(he) * 8);
+            bool in_tmp = false;
+            if (e == hipSuccess)
+                e = launch_radix_sort_u64(w.keys.as<uint64_t>(), w.ktmp.as<uint64_t>(), total, shifts, np,
+                                          w.hist.as<uint32_t>(), w.hscan.as<uint64_t>(), w.rtmp.as<uint64_t>(),
+                                          &in_tmp, s);
+            if (e != hipSuccess) return hip_fail(e, "join sort");
+            w.npairs = total;
+            w.sorted = in_tmp ? w.ktmp.as<uint64_t>() : w.keys.as<uint64_t>();
+            break;
+        }
+        if (total >= 0xFFFFFFFFull) return fail(RT_ENOMEM, "join frontier too large");
+        e = w.fr[1 - cur].need(total * 8);
+        if (e == hipSuccess)
+            e = launch_join_level(va, vb, fr, (uint32_t)nfr, mode, true, nullptr, off, w.fr[1 - cur].as<uint2>(),
+                                  nullptr, ctrl, flags, nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "join expand");
+        cur = 1 - cur;
+        nfr = total;
+        if (mode == JOIN_DESC_A) --la;
+        else if (mode == JOIN_DESC_B) --lb;
+        else { --la; --lb; }
+    }
+    Ctrl hc;
+    e = hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "join status");
+    if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
+    w.tests = 0;
+    if (tacc) {
+        std::vector<unsigned long long> h(kTestSlots * 16);
+        e = hipMemcpy(h.data(), tacc, h.size() * 8, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "join statistics");
+        for (uint32_t k = 0; k < kTestSlots; ++k) w.tests += h[k * 16];
+    }
+    return RT_OK;
+}
+
+int check_join_args(const rt_tree *a, const rt_tree *b, int32_t *flags) {
+    if (!a || !b) return fail(RT_EINVAL, "tree is NULL");
+    if (a->device != b->device) return fail(RT_EINVAL, "trees are on different devices");
+    const bool both_sorted = a->sorted_lx && b->sorted_lx;
+    // measured fastest: candidate lists with O3 + O5 on sorted trees, else the
+    // full tile (candidate lists without pruning cost more than they save)
+    if (*flags == RT_JOIN_DEFAULT) *flags = both_sorted ? (RT_JOIN_O3 | RT_JOIN_O5) : RT_JOIN_TILE;
+    if (*flags & ~(RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5 | RT_JOIN_TILE))
+        return fail(RT_EINVAL, "unknown join flags 0x%x", (unsigned)*flags);
+    if ((*flags & RT_JOIN_TILE) && (*flags & ~RT_JOIN_TILE))
+        return fail(RT_EINVAL, "RT_JOIN_TILE cannot be combined with pruning");
+    if ((*flags & (RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5)) && !both_sorted)
+        return fail(RT_EINVAL, "join pruning needs both trees built with RT_BUILD_SORT_LX");
+    return RT_OK;
+}
+
+}  // namespace
+
+extern "C" int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **out) {
+    return rt_spatial_join_ex(a, b, RT_JOIN_DEFAULT, out, nullptr);
+}
+
+extern "C" int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t flags, rt_pairs **out,
+                                  uint64_t *tests) {
+    if (!out) return fail(RT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (tests) *tests = 0;
+    int rc = check_join_args(a, b, &flags);
+    if (rc) return rc;
+    try {
+        DevSet ds(a->device);
+        hipStream_t s = nullptr;
+        JoinRun w;
+        rc = join_keys(a, b, flags, tests != nullptr, s, w);
+        if (rc) return rc;
+        if (tests) *tests = w.tests;
+        void *mem = obj_alloc(KIND_PAIRS, sizeof(rt_pairs));
+        if (!mem) return fail(RT_ENOMEM, "host allocation failed");
+        rt_pairs *r = static_cast<rt_pairs *>(mem);
+        r->n = w.npairs;
+        r->pairs = static_cast<uint32_t *>(std::malloc(w.npairs ? w.npairs * 8 : 8));
+        if (!r->pairs) {
+            rt_free(r);
+            return fail(RT_ENOMEM, "host allocation failed");
+        }
+        if (w.npairs) {
+            // reuse the sort's other buffer for the (a, b) words
+            uint32_t *dp = const_cast<uint32_t *>(reinterpret_cast<const uint32_t *>(
+                w.sorted == w.keys.as<uint64_t>() ? w.ktmp.as<uint64_t>() : w.keys.as<uint64_t>()));
+            hipError_t e = launch_keys_to_pairs(w.sorted, w.npairs, dp, s);
+            if (e == hipSuccess) e = hipMemcpy(r->pairs, dp, w.npairs * 8, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                rt_free(r);
+                return hip_fail(e, "copying the pairs");
+            }
+        }
+        *out = r;
+        return RT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RT_EDEVICE, "unexpected failure");
+    }
+}
+
+extern "C" int rt_spatial_join_device(const rt_tree *a, const rt_tree *b, int32_t flags, uint32_t *d_pairs,
+                                      uint64_t capacity, uint64_t *n_pairs, void *stream) {
+    if (!n_pairs) return fail(RT_EINVAL, "n_pairs is NULL");
+    *n_pairs = 0;
+    int rc = check_join_args(a, b, &flags);
+    if (rc) return rc;
+    if (capacity && !d_pairs) return fail(RT_EINVAL, "d_pairs is NULL with capacity > 0");
+    try {
+        DevSet ds(a->device);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        JoinRun w;
+        rc = join_keys(a, b, flags, false, s, w);
+        if (rc) return rc;
+        *n_pairs = w.npairs;
+        if (w.npairs > capacity)
+            return fail(RT_ENOMEM, "join has %llu pairs, capacity %llu", (unsigned long long)w.npairs,
+                        (unsigned long long)capacity);
+        hipError_t e = launch_keys_to_pairs(w.sorted, w.npairs, d_pairs, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "writing the pairs");
+        return RT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RT_EDEVICE, "unexpected failure");
+    }
+}

@@ -523,154 +523,3 @@ extern "C" int rt_select_visit_stats(const rt_tree *t, const float *queries, uin
     *ventries = hc.stats[1];
     return RT_OK;
 }
-
-// ---------------------------------------------------------------------------
-// spatial join
-// ---------------------------------------------------------------------------
-static int bits_for(uint64_t maxval) {
-    int b = 0;
-    while (b < 64 && (maxval >> b)) ++b;
-    return b;
-}
-
-extern "C" int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **out) {
-    return rt_spatial_join_ex(a, b, RT_JOIN_DEFAULT, out, nullptr);
-}
-
-extern "C" int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t flags, rt_pairs **out,
-                                  uint64_t *tests) {
-    if (!out) return fail(RT_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (tests) *tests = 0;
-    if (!a || !b) return fail(RT_EINVAL, "tree is NULL");
-    if (a->device != b->device) return fail(RT_EINVAL, "trees are on different devices");
-    const bool both_sorted = a->sorted_lx && b->sorted_lx;
-    // measured fastest: candidate lists with O3 + O5 on sorted trees, else the
-    // full tile (candidate lists without pruning cost more than they save)
-    if (flags == RT_JOIN_DEFAULT) flags = both_sorted ? (RT_JOIN_O3 | RT_JOIN_O5) : RT_JOIN_TILE;
-    if (flags & ~(RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5 | RT_JOIN_TILE))
-        return fail(RT_EINVAL, "unknown join flags 0x%x", (unsigned)flags);
-    if ((flags & RT_JOIN_TILE) && (flags & ~RT_JOIN_TILE))
-        return fail(RT_EINVAL, "RT_JOIN_TILE cannot be combined with pruning");
-    if ((flags & (RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5)) && !both_sorted)
-        return fail(RT_EINVAL, "join pruning needs both trees built with RT_BUILD_SORT_LX");
-    try {
-        DevSet ds(a->device);
-        hipStream_t s = nullptr;
-        const TreeView va = view_of(a), vb = view_of(b);
-        DevBuf ctrl_b, fr, cnt, off, tmp, keys, tacc;
-        hipError_t e = ctrl_b.alloc(sizeof(Ctrl));
-        if (e == hipSuccess) e = fr.alloc(8);
-        if (e == hipSuccess && tests) e = tacc.alloc(kTestSlots * 16 * 8);
-        if (e == hipSuccess && tests) e = launch_zero(tacc.p, kTestSlots * 16 * 8, s);
-        unsigned long long *tests_acc = static_cast<unsigned long long *>(tacc.p);
-        if (e != hipSuccess) return hip_fail(e, "join setup");
-        Ctrl *ctrl = static_cast<Ctrl *>(ctrl_b.p);
-        e = launch_zero(ctrl, sizeof(Ctrl), s);
-        const uint32_t roots[2] = {0u, 0u};
-        if (e == hipSuccess) e = hipMemcpy(fr.p, roots, 8, hipMemcpyHostToDevice);
-        if (e != hipSuccess) return hip_fail(e, "join setup");
-        uint64_t nfr = (a->n_objects && b->n_objects) ? 1 : 0;
-        int la = (int)a->height - 1, lb = (int)b->height - 1;
-        uint64_t npairs = 0;
-        bool in_tmp = false;
-        DevBuf ktmp, hist, hscan, stmp;
-        while (nfr) {
-            int mode = la > lb ? JOIN_DESC_A : (lb > la ? JOIN_DESC_B : (la == 0 ? JOIN_EMIT : JOIN_BOTH));
-            e = cnt.alloc(nfr * 4);
-            if (e == hipSuccess) e = off.alloc((nfr + 1) * 8);
-            if (e == hipSuccess) e = tmp.alloc(scan_tmp_elems(nfr) * 8);
-            if (e != hipSuccess) return hip_fail(e, "join frontier");
-            e = launch_join_level(va, vb, static_cast<uint2 *>(fr.p), (uint32_t)nfr, mode, false,
-                                  static_cast<uint32_t *>(cnt.p), nullptr, nullptr, nullptr, ctrl, flags, tests_acc, s);
-            if (e == hipSuccess)
-                e = launch_scan_u32(static_cast<uint32_t *>(cnt.p), nfr, static_cast<uint64_t *>(off.p),
-                                    static_cast<uint64_t *>(tmp.p), s);
-            uint64_t total = 0;
-            if (e == hipSuccess) e = hipMemcpy(&total, static_cast<uint64_t *>(off.p) + nfr, 8, hipMemcpyDeviceToHost);
-            if (e != hipSuccess) return hip_fail(e, "join count");
-            if (total == 0) {
-                nfr = 0;
-                break;
-            }
-            if (mode == JOIN_EMIT) {
-                e = keys.alloc(total * 8);
-                if (e == hipSuccess)
-                    e = launch_join_level(va, vb, static_cast<uint2 *>(fr.p), (uint32_t)nfr, mode, true, nullptr,
-                                          static_cast<uint64_t *>(off.p), nullptr, static_cast<uint64_t *>(keys.p),
-                                          ctrl, flags, nullptr, s);
-                if (e != hipSuccess) return hip_fail(e, "join emit");
-                npairs = total;
-                // canonical order: 64-bit (idA << 32 | idB) keys, sorting only the digits that can be nonzero
-                int shifts[16], np = 0;
-                const int bb = bits_for(b->n_objects ? b->n_objects - 1 : 0);
-                const int ba = bits_for(a->n_objects ? a->n_objects - 1 : 0);
-                for (int sft = 0; sft < bb; sft += 8) shifts[np++] = sft;
-                for (int sft = 32; sft < 32 + ba; sft += 8) shifts[np++] = sft;
-                const uint64_t he = radix_hist_elems(total);
-                e = ktmp.alloc(total * 8);
-                if (e == hipSuccess) e = hist.alloc(he * 4);
-                if (e == hipSuccess) e = hscan.alloc((he + 1) * 8);
-                if (e == hipSuccess) e = stmp.alloc(scan_tmp_elems(he) * 8);
-                if (e == hipSuccess)
-                    e = launch_radix_sort_u64(static_cast<uint64_t *>(keys.p), static_cast<uint64_t *>(ktmp.p), total,
-                                              shifts, np, static_cast<uint32_t *>(hist.p),
-                                              static_cast<uint64_t *>(hscan.p), static_cast<uint64_t *>(stmp.p),
-                                              &in_tmp, s);
-                if (e != hipSuccess) return hip_fail(e, "join sort");
-                break;
-            }
-            if (total >= 0xFFFFFFFFull) return fail(RT_ENOMEM, "join frontier too large");
-            DevBuf nxt;
-            e = nxt.alloc(total * 8);
-            if (e == hipSuccess)
-                e = launch_join_level(va, vb, static_cast<uint2 *>(fr.p), (uint32_t)nfr, mode, true, nullptr,
-                                      static_cast<uint64_t *>(off.p), static_cast<uint2 *>(nxt.p), nullptr, ctrl,
-                                      flags, nullptr, s);
-            if (e != hipSuccess) return hip_fail(e, "join expand");
-            std::swap(fr.p, nxt.p);
-            nfr = total;
-            if (mode == JOIN_DESC_A) --la;
-            else if (mode == JOIN_DESC_B) --lb;
-            else { --la; --lb; }
-        }
-        Ctrl hc;
-        e = hipMemcpy(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
-        if (e != hipSuccess) return hip_fail(e, "join status");
-        if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
-        if (tests) {
-            std::vector<unsigned long long> h(kTestSlots * 16);
-            e = hipMemcpy(h.data(), tacc.p, h.size() * 8, hipMemcpyDeviceToHost);
-            if (e != hipSuccess) return hip_fail(e, "join statistics");
-            uint64_t sum = 0;
-            for (uint32_t k = 0; k < kTestSlots; ++k) sum += h[k * 16];
-            *tests = sum;
-        }
-        void *mem = obj_alloc(KIND_PAIRS, sizeof(rt_pairs));
-        if (!mem) return fail(RT_ENOMEM, "host allocation failed");
-        rt_pairs *r = static_cast<rt_pairs *>(mem);
-        r->n = npairs;
-        r->pairs = static_cast<uint32_t *>(std::malloc(npairs ? npairs * 8 : 8));
-        if (!r->pairs) {
-            rt_free(r);
-            return fail(RT_ENOMEM, "host allocation failed");
-        }
-        if (npairs) {
-            DevBuf dp;
-            e = dp.alloc(npairs * 8);
-            const uint64_t *sorted = static_cast<const uint64_t *>(in_tmp ? ktmp.p : keys.p);
-            if (e == hipSuccess) e = launch_keys_to_pairs(sorted, npairs, static_cast<uint32_t *>(dp.p), s);
-            if (e == hipSuccess) e = hipMemcpy(r->pairs, dp.p, npairs * 8, hipMemcpyDeviceToHost);
-            if (e != hipSuccess) {
-                rt_free(r);
-                return hip_fail(e, "copying the pairs");
-            }
-        }
-        *out = r;
-        return RT_OK;
-    } catch (const std::bad_alloc &) {
-        return fail(RT_ENOMEM, "host allocation failed");
-    } catch (...) {
-        return fail(RT_EDEVICE, "unexpected failure");
-    }
-}

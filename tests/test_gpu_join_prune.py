@@ -124,3 +124,26 @@ def test_pruning_needs_sorted_trees(rt):
     assert np.array_equal(rt.spatial_join(tu, tu, 0), want)
     assert np.array_equal(rt.spatial_join(tu, tu, rt.JOIN_TILE), want)
     assert np.array_equal(rt.spatial_join(tu, tu), want)
+
+
+def test_join_device_output(rt, ora):
+    """Device-output join: same pairs as the host API; too small a buffer is
+    reported with the needed size and left untouched."""
+    import torch
+    A = rtgen.uniform_rects(30_000, 0.004, 21)
+    B = rtgen.clustered_rects(30_000, 6, 0.05, 0.004, 22)
+    want = ora.join(ora.build_str(A, 16), ora.build_str(B, 16))
+    for sort_lx, flags in [(False, None), (True, None), (True, rt.JOIN_O3 | rt.JOIN_O4), (False, 0)]:
+        ta, tb = rt.build_str(A, 16, "soa", sort_lx=sort_lx), rt.build_str(B, 32, "aos", sort_lx=sort_lx)
+        small = torch.full((2 * 10,), 7, dtype=torch.int32, device="cuda")
+        n = rt.spatial_join_device(ta, tb, small.data_ptr(), 10, flags)
+        assert n == want.shape[0] and n > 10
+        assert bool((small == 7).all())
+        buf = torch.full((2 * n,), 7, dtype=torch.int32, device="cuda")
+        s = torch.cuda.current_stream()
+        assert rt.spatial_join_device(ta, tb, buf.data_ptr(), n, flags, s.cuda_stream) == n
+        got = buf.cpu().numpy().view(np.uint32).reshape(-1, 2)
+        assert np.array_equal(got, want), (sort_lx, flags)
+    # empty relation
+    te = rt.build_str(np.zeros((0, 4), np.float32), 16)
+    assert rt.spatial_join_device(te, ta, 0, 0) == 0
