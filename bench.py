@@ -128,6 +128,16 @@ def select_leg(rt, torch, ev, args, rects, queries, kmin=0):
     wall = time.perf_counter() - t0
     st = status.cpu().numpy()
     assert st[1] == 0 and st[0] == cap, f"select status {st} (cap {cap})"
+    # the lookahead variant (loads one node ahead after each leaf), timed the
+    # same way on the same buffers, then switched off again
+    tree.set_lookahead(True)
+    la_ev = ev.create(5)
+    step()
+    step(la_ev)
+    torch.cuda.synchronize()
+    tree.set_lookahead(False)
+    lookahead = {"count": ev.ms(la_ev[0], la_ev[1]), "fill": ev.ms(la_ev[2], la_ev[3]),
+                 "step": ev.ms(la_ev[0], la_ev[4])}
     phases = {"count": [], "scan": [], "fill": [], "sort": []}
     for e in events:
         phases["count"].append(ev.ms(e[0], e[1]))
@@ -140,7 +150,7 @@ def select_leg(rt, torch, ev, args, rects, queries, kmin=0):
     bytes_count = 16 * nq + node_bytes
     bytes_fill = bytes_count + 4 * cap + 8 * (nq + 1)
     return dict(tree=tree, info=info, build_s=build_s, cap=cap, wall=wall, avg=avg, vn=vn, ve=ve,
-                bytes_count=bytes_count, bytes_fill=bytes_fill, off=off, ids=ids)
+                bytes_count=bytes_count, bytes_fill=bytes_fill, off=off, ids=ids, lookahead=lookahead)
 
 
 def cpu_baseline(args, rects, queries, gpu_off, gpu_ids):
@@ -422,6 +432,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"select_kernel ({dom} pass)", "algorithmic_bytes_per_launch": dom_bytes},
         "phases_ms": s["avg"],
+        "lookahead_ms": s["lookahead"],
         "tree": {"height": s["info"].height, "nodes": s["info"].n_nodes,
                  "device_bytes": s["info"].device_bytes, "build_s": s["build_s"]},
         "visited": {"nodes": s["vn"], "entries": s["ve"]},

@@ -260,6 +260,14 @@ int rt_tree_stats(const rt_tree *t, rt_tree_info *info);
  * query (the default).  Not to be called while selects on the tree run. */
 int rt_tree_set_split(rt_tree *t, uint32_t kmin);
 
+/* Lookahead loads in later selects on this tree (section 3, optimization O2;
+ * never changes a result): on = 1 makes the traversal load the next node's
+ * entries as soon as it pops a leaf (the next node is then already known),
+ * so that load overlaps the leaf's comparison and output; on = 0 (default)
+ * loads each node when it is popped.  Other values -> RT_EINVAL.  Not to be
+ * called while selects on the tree run. */
+int rt_tree_set_lookahead(rt_tree *t, uint32_t on);
+
 /* Copy the tree to host arrays in a neutral node/entry form: per node
  * (root = node 0) level (0 = leaf), entry count and index of its first entry;
  * per entry the MBR and ptr (object id at a leaf, child node otherwise).

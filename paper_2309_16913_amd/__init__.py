@@ -87,6 +87,7 @@ _sig = {
     "rt_batch_result": ([_vp, _u32, C.POINTER(C.POINTER(_Ids))], C.c_int),
     "rt_tree_stats": ([_vp, C.POINTER(TreeInfo)], C.c_int),
     "rt_tree_set_split": ([_vp, _u32], C.c_int),
+    "rt_tree_set_lookahead": ([_vp, _u32], C.c_int),
     "rt_tree_export": ([_vp] + [_vp] * 8, C.c_int),
     "rt_select_visit_stats": ([_vp, _fp, _u64, C.POINTER(_u64), C.POINTER(_u64)], C.c_int),
     "rt_last_error": ([], C.c_char_p),
@@ -146,6 +147,11 @@ class Tree:
         """Work mapping knob (never changes results): split queries that reach
         at least kmin parents-of-leaves nodes; 0 = one lane group per query."""
         _check(_L.rt_tree_set_split(self.h, int(kmin)))
+
+    def set_lookahead(self, on: bool):
+        """Load the next node ahead after a leaf in later selects (never
+        changes results)."""
+        _check(_L.rt_tree_set_lookahead(self.h, 1 if on else 0))
 
     def free(self):
         if self.h is not None and self.h.value:

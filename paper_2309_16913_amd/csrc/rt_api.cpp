@@ -110,7 +110,7 @@ TreeView rtk::view_of(const rt_tree *t) {
     v.first_leaf = t->first_leaf;
     v.height = t->height;
     v.layout = t->layout;
-    v.pad = 0;
+    v.lookahead = t->lookahead;
     for (int i = 0; i < 4; ++i) v.mbr[i] = t->mbr[i];
     return v;
 }
@@ -221,6 +221,13 @@ extern "C" int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uin
     } catch (...) {
         return fail(RT_EDEVICE, "unexpected failure");
     }
+}
+
+extern "C" int rt_tree_set_lookahead(rt_tree *t, uint32_t on) {
+    if (!t) return fail(RT_EINVAL, "tree is NULL");
+    if (on > 1) return fail(RT_EINVAL, "lookahead %u is not 0 or 1", on);
+    t->lookahead = on;
+    return RT_OK;
 }
 
 extern "C" int rt_tree_set_split(rt_tree *t, uint32_t kmin) {

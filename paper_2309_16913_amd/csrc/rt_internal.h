@@ -23,9 +23,10 @@ struct TreeView {
     uint32_t first_leaf;
     uint32_t height;
     uint32_t layout;
-    uint32_t pad;
+    uint32_t lookahead;      // 1: select loads the next node ahead after a leaf
     float mbr[4];            // MBR of the whole tree (root node)
 };
+constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
 constexpr uint32_t kXcds = 8;          // MI355X: 8 XCDs; workgroup i runs on XCD i % 8
 

@@ -324,29 +324,41 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
         const uint32_t nbk = 1u << nb;
         for (uint32_t b = t; b < nbk; b += T) cnt[b] = 0;
         __syncthreads();
+        // rows k with k*T >= c hold nothing: the (block-uniform) row loops
+        // stop there, so the work follows c rather than the tile size
         uint32_t key[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
+            key[k] = kKeyPad;
+            if ((uint32_t)k * T >= c) break;
             const uint32_t i = (uint32_t)k * T + t;
-            key[k] = i < c ? seg[i] : kKeyPad;
-            if (i < c) atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u);
+            if (i < c) {
+                key[k] = seg[i];
+                atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u);
+            }
         }
         __syncthreads();
         const uint32_t big = block_scan_counters<T>(cnt, nbk, wsum, nullptr);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
+            if ((uint32_t)k * T >= c) break;
             const uint32_t i = (uint32_t)k * T + t;
             if (i < c) buf[atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u)] = key[k];
         }
         __syncthreads();
         if (big <= kRankMax) {
+            // walk the ids in bucket order: each lands inside its own bucket's
+            // range, a few places from where it is read, so a wave's stores
+            // stay within a few cache lines
 #pragma unroll
             for (int k = 0; k < K; ++k) {
+                if ((uint32_t)k * T >= c) break;
                 const uint32_t i = (uint32_t)k * T + t;
                 if (i < c) {
-                    const uint32_t b = (key[k] >> shift) & (nbk - 1);
+                    const uint32_t kk = buf[i];
+                    const uint32_t b = (kk >> shift) & (nbk - 1);
                     const uint32_t s0 = b ? cnt[b - 1] : 0u, s1 = cnt[b];
-                    seg[s0 + bucket_rank(buf, s0, s1, key[k])] = key[k];
+                    seg[s0 + bucket_rank(buf, s0, s1, kk)] = kk;
                 }
             }
         } else {   // ids far from uniform: block bitonic over the whole segment

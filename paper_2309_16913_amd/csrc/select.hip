@@ -116,7 +116,14 @@ __device__ __forceinline__ Unit next_unit(Ctrl *ctrl, uint32_t slot, uint32_t nq
     }
 }
 
-template <int G, int LAYOUT, int MODE>
+// LA = 1: lookahead (section 3, optimization O2, as a load issued one node
+// ahead).  A leaf pushes nothing, so after popping a leaf the next node to be
+// visited is already on top of the stack; its entries are loaded right away,
+// while the leaf is compared and written out, and the next iteration uses
+// them without waiting for a fresh load.  After an internal node the next
+// node is one of its children, decided only by the comparison, so nothing is
+// loaded ahead there.
+template <int G, int LAYOUT, int MODE, int LA>
 __global__ void __launch_bounds__(256)
 select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *__restrict__ counts,
               const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint64_t cap,
@@ -143,6 +150,9 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
     uint64_t pos = 0, end = 0;
     uint64_t vnodes = 0, ventries = 0;
+    // lookahead registers: the node loaded ahead and this lane's entry of it
+    uint32_t pf_node = kNoNode, pf_ref = 0;
+    float pf_lx = 0.f, pf_ly = 0.f, pf_hx = 0.f, pf_hy = 0.f;
 
     while (true) {
         if (!done && sp == 0) {
@@ -185,15 +195,44 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
         const bool leaf = node >= t.first_leaf;
         bool hit = false, valid = false;
         uint32_t ref = 0;   // first child (internal node) or this entry's object id (leaf, fill pass)
-        if (have && e < F) {
+        float lx = 0.f, ly = 0.f, hx = 0.f, hy = 0.f;
+        bool got = false;
+        if constexpr (LA != 0) {
+            got = have && pf_node == node;
+            if (got) {
+                lx = pf_lx;
+                ly = pf_ly;
+                hx = pf_hx;
+                hy = pf_hy;
+                ref = pf_ref;
+            }
+        }
+        if (have && e < F && !got) {
             // the id / first-child load does not depend on the comparison, so it
             // is in flight together with the coordinate loads
             if (!leaf)
                 ref = load_ptr<LAYOUT>(nb, F, 0);
             else if constexpr (MODE == SEL_FILL)
                 ref = load_ptr<LAYOUT>(nb, F, e);
-            float lx, ly, hx, hy;
             load_entry<LAYOUT>(nb, F, e, lx, ly, hx, hy);
+        }
+        if constexpr (LA != 0) {
+            pf_node = kNoNode;
+            if (have && leaf && sp > 0) {
+                const uint32_t nx = stk[sp - 1];
+                pf_node = nx;
+                if (e < F) {
+                    const uint8_t *nb2 = t.nodes + (size_t)nx * t.node_bytes;
+                    pf_ref = 0;
+                    if (nx < t.first_leaf)
+                        pf_ref = load_ptr<LAYOUT>(nb2, F, 0);
+                    else if constexpr (MODE == SEL_FILL)
+                        pf_ref = load_ptr<LAYOUT>(nb2, F, e);
+                    load_entry<LAYOUT>(nb2, F, e, pf_lx, pf_ly, pf_hx, pf_hy);
+                }
+            }
+        }
+        if (have && e < F) {
             hit = (lx <= q.z) && (q.x <= hx) && (ly <= q.w) && (q.y <= hy);
             if constexpr (MODE == SEL_STATS) valid = (lx == lx);
         }
@@ -382,8 +421,12 @@ static hipError_t launch_g(const TreeView &t, const float4 *q, uint32_t nq, uint
     uint32_t blocks = (uint32_t)(want < persistent ? want : persistent);
     if (plan.heavy) blocks = (uint32_t)persistent;   // split items add work beyond nq
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // every XCD gets blocks
-    hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE>), dim3(blocks), dim3(256), smem, s, t, q, nq,
-                       counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
+    if (MODE != SEL_STATS && t.lookahead)
+        hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 1>), dim3(blocks), dim3(256), smem, s, t, q, nq,
+                           counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
+    else
+        hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 0>), dim3(blocks), dim3(256), smem, s, t, q, nq,
+                           counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
     return hipGetLastError();
 }
 

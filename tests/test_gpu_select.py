@@ -70,6 +70,8 @@ def test_select_adversarial(rt, ora, fanout, layout):
         got = rt.range_select(t, q)
         want = ora.brute_select(r, q)
         assert_csr_equal(got, want, f"F={fanout} {layout} n={n}")
+        t.set_lookahead(True)
+        assert_csr_equal(rt.range_select(t, q), want, f"lookahead F={fanout} {layout} n={n}")
 
 
 def test_select_long_segments(rt, ora):
@@ -85,6 +87,22 @@ def test_select_long_segments(rt, ora):
         want = ora.select(ora.build_str(r, 16), q)
         assert_csr_equal(got, want, f"long F={fanout} {layout}")
         assert int(np.diff(want[0].astype(np.int64)).max()) == r.shape[0]
+
+
+def test_lookahead_parity(rt, ora):
+    """Lookahead loads (on after every leaf) with Morton-ordered batches, the
+    split mapping and every layout: results equal the oracle's."""
+    r = rtgen.c2_rects(200_000)
+    q = rtgen.c2_queries(20_000)
+    want = ora.select(ora.build_str(r, 32), q)
+    for fanout, layout, kmin in [(16, "soa", 0), (32, "aos", 2), (64, "d2", 0), (64, "soa", 16), (7, "aos", 0)]:
+        say(f"case lookahead F={fanout} {layout} kmin={kmin}")
+        t = rt.build_str(r, fanout, layout)
+        t.set_split(kmin)
+        t.set_lookahead(True)
+        assert_csr_equal(rt.range_select(t, q), want, f"lookahead F={fanout} {layout} kmin={kmin}")
+    with pytest.raises(rt.RTError):
+        rt._check(rt._L.rt_tree_set_lookahead(t.h, 2))
 
 
 def test_select_empty_query_batch(rt):
