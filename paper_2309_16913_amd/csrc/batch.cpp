@@ -187,7 +187,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         }
         b->cap = ids_capacity ? ids_capacity : off[total];
         e = dmalloc(&b->d_ids, b->cap * 4);
-        if (e == hipSuccess) e = dmalloc(&b->d_scratch, b->cap * 4);
+        if (e == hipSuccess) e = dmalloc(&b->d_scratch, segsort_scratch_elems(b->cap) * 4);
         if (e != hipSuccess) return bail(hip_fail(e, "batch output pool"));
 
         // capture the whole select into a graph

@@ -137,7 +137,7 @@ static uint64_t split_budget(uint64_t nq) { return split_hcap(nq) * kXcds; }
 // Workspace layout of a select:
 //   Ctrl | counts[nq] | scan tmp | sort lists | query order | slots per query
 //   | slot offsets per query | slot counts | slot offsets | split items
-//   | slot scan tmp | sort scratch[cap]
+//   | slot scan tmp | sort scratch (cap ids, then class-L descriptors)
 struct SelWs {
     Ctrl *ctrl;
     uint32_t *counts;
@@ -159,7 +159,7 @@ static uint64_t sel_ws_bytes(uint64_t nq, uint64_t cap) {
     return align256(sizeof(Ctrl)) + align256(4 * nq) + align256(8 * scan_tmp_elems(nq)) +
            align256(4 * segsort_ws_elems(nq)) + align256(order_ws_bytes(nq)) + align256(4 * nq) +
            align256(8 * (nq + 1)) + align256(4 * S) + align256(8 * (S + 1)) + align256(16 * split_budget(nq)) +
-           align256(8 * scan_tmp_elems(S)) + align256(4 * cap);
+           align256(8 * scan_tmp_elems(S)) + align256(4 * segsort_scratch_elems(cap));
 }
 
 static SelWs sel_ws(void *w, uint64_t nq) {

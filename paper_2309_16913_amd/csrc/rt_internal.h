@@ -110,11 +110,13 @@ uint64_t scan_tmp_elems(uint64_t n);
 hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp,
                            hipStream_t s);
 
-// Sort every CSR segment ascending.  scratch: capacity uint32 (used for
-// segments longer than one LDS tile); ws: segsort_ws_elems(nq) uint32;
+// Sort every CSR segment ascending.  scratch: segsort_scratch_elems(capacity)
+// uint32 (segments longer than one LDS tile are bucketed through it); ws:
+// segsort_ws_elems(nq) uint32;
 // id_bits: significant bits of the largest object id.  Skips all work if
 // offsets[nq] > capacity.
 uint64_t segsort_ws_elems(uint64_t nq);
+uint64_t segsort_scratch_elems(uint64_t capacity);
 hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch,
                           uint64_t capacity, uint32_t *ws, int id_bits, hipStream_t s);
 inline int id_bits_for(uint64_t n_objects) {

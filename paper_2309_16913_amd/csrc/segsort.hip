@@ -15,13 +15,15 @@
 //              LDS counters), scatter into LDS, then each id counts the
 //              smaller ids of its own bucket and is stored at bucket start +
 //              that count;
-//   class L    (> 16384)        the same with global scratch instead of LDS
-//              for the bucketed copy, up to 16384 buckets;
+//   class L    (> 16384)        one block per segment: an MSD pass on the top
+//              8 id bits into global scratch (chunks digit-sorted in LDS and
+//              written as runs), then each of the 256 sub-buckets sorted
+//              back by one wave (<= 256 ids) or the block (<= 4096);
 //   fallback   a segment with a bucket too long for the in-bucket ranking
 //              (ids far from uniform) is sorted by a block bitonic network in
-//              LDS (class M) or, for class L, by sorting 16384-id tiles that
-//              way and merging runs pairwise through LDS-staged merge-path
-//              windows.
+//              LDS (class M) or, for class L with a sub-bucket over 4096 ids,
+//              by sorting 16384-id tiles that way and merging runs pairwise
+//              through LDS-staged merge-path windows.
 #include "rt_internal.h"
 
 namespace rtk {
@@ -228,31 +230,16 @@ segsort_small(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, 
 }
 
 // ---------------------------------------------------------------------------
-// classes M and L: counting sort on the top id bits, then in-bucket ranks
+// classes M and L: counting sort on the top id bits, then in-bucket sorts
 // ---------------------------------------------------------------------------
 // With 2^b ~ length/4 buckets on the top b bits of the ids, a bucket holds a
 // handful of ids.  One LDS counter per bucket first counts, is then turned
 // into the bucket's start by an exclusive scan, and serves as the scatter
 // cursor; after the scatter counter b holds the end of bucket b, so bucket b
-// spans [end(b-1), end(b)).  Every id then counts the ids of its own bucket
-// that are smaller than it (ids of one query are distinct) and is stored at
-// bucket start + that count.  A bucket of more than kRankMax ids (ids far
-// from uniform) sends the segment to a fallback.
+// spans [end(b-1), end(b)).  Every bucket is then sorted in place (one lane
+// per bucket, a register network).  A bucket of more than kRankMax ids (ids
+// far from uniform) sends the segment to a fallback.
 constexpr uint32_t kRankMax = 64;
-
-// Number of ids in bucket [s0, s1) of a that are smaller than key.  The first
-// eight reads do not depend on each other (predicated), so they are in flight
-// together; buckets hold about four ids, and only longer ones loop.
-__device__ __forceinline__ uint32_t bucket_rank(const uint32_t *a, uint32_t s0, uint32_t s1, uint32_t key) {
-    uint32_t r = 0;
-#pragma unroll
-    for (uint32_t j = 0; j < 8; ++j) {
-        const uint32_t v = (s0 + j < s1) ? a[s0 + j] : kKeyPad;
-        r += v < key ? 1u : 0u;
-    }
-    for (uint32_t j = s0 + 8; j < s1; ++j) r += a[j] < key ? 1u : 0u;
-    return r;
-}
 
 // Exclusive scan in place of cnt[0 .. nbk) by T threads (nbk <= 4*T or a
 // multiple of 4*T handled in rounds); returns the largest count.
@@ -300,155 +287,379 @@ __device__ uint32_t block_scan_counters(uint32_t *cnt, uint32_t nbk, uint32_t *w
     return mxall;
 }
 
+// Bitonic network over N registers (all indices fixed at compile time).
+template <int N>
+__device__ __forceinline__ void reg_bitonic(uint32_t (&v)[N]) {
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint32_t a = v[i], b = v[l];
+                    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
+                    const bool up = (i & k) == 0;
+                    v[i] = up ? lo : hi;
+                    v[l] = up ? hi : lo;
+                }
+            }
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void sort_run_regs(uint32_t *a, uint32_t s0, uint32_t k) {
+    uint32_t v[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) v[j] = (uint32_t)j < k ? a[s0 + j] : kKeyPad;
+    reg_bitonic<N>(v);
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        if ((uint32_t)j < k) a[s0 + j] = v[j];
+}
+
+// Sort every bucket [end(b-1), end(b)) of a in place, one lane per bucket:
+// the ids of a bucket go through a register network sized by the longest
+// bucket in the wave (8 or 16), longer buckets (rare) are insertion-sorted.
+template <int T>
+__device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, uint32_t nbk) {
+    for (uint32_t b0 = 0; b0 < nbk; b0 += T) {
+        const uint32_t b = b0 + threadIdx.x;
+        uint32_t s0 = 0, k = 0;
+        if (b < nbk) {
+            s0 = b ? end[b - 1] : 0u;
+            k = end[b] - s0;
+        }
+        uint32_t kmax = k;
+        for (int d = 32; d >= 1; d >>= 1) kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d));
+        if (kmax <= 8) {
+            sort_run_regs<8>(a, s0, k);
+        } else if (kmax <= 16) {
+            sort_run_regs<16>(a, s0, k);
+        } else {
+            for (uint32_t i = 1; i < k; ++i) {
+                const uint32_t x = a[s0 + i];
+                uint32_t j = i;
+                while (j > 0 && a[s0 + j - 1] > x) {
+                    a[s0 + j] = a[s0 + j - 1];
+                    --j;
+                }
+                a[s0 + j] = x;
+            }
+        }
+    }
+}
+
+// Sort c <= T*K ids, given in registers (key[k] holds id k*T + thread, pad
+// beyond c), into dst with one block: counting sort on the top b of the
+// id_bits significant bits (2^b ~ c/4 buckets, LDS counters), scatter into
+// LDS, sort every bucket in place, copy out.  Bits above id_bits are ignored
+// (the caller guarantees they are equal across the ids).  A bucket longer
+// than kRankMax (ids far from uniform) switches the segment to a block
+// bitonic network.  buf: T*K words, cnt: T*K/4 words, wsum: 2*T/64 words of
+// LDS.
+template <int T, int K>
+__device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *dst, uint32_t c, int id_bits,
+                                                uint32_t *buf, uint32_t *cnt, uint32_t *wsum) {
+    constexpr uint32_t N = T * K;
+    constexpr uint32_t NB = N / 4;   // most buckets
+    const uint32_t t = threadIdx.x;
+    uint32_t nb = ceil_log2((c + 3) / 4);
+    const uint32_t nbmax = ceil_log2(NB);
+    nb = nb < 1 ? 1 : (nb > nbmax ? nbmax : nb);
+    const int shift = id_bits > (int)nb ? id_bits - (int)nb : 0;
+    const uint32_t nbk = 1u << nb;
+    for (uint32_t b = t; b < nbk; b += T) cnt[b] = 0;
+    __syncthreads();
+    // rows k with k*T >= c hold nothing: the (block-uniform) row loops stop
+    // there, so the work follows c rather than the tile size
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if ((uint32_t)k * T >= c) break;
+        if ((uint32_t)k * T + t < c) atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u);
+    }
+    __syncthreads();
+    const uint32_t big = block_scan_counters<T>(cnt, nbk, wsum, nullptr);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if ((uint32_t)k * T >= c) break;
+        if ((uint32_t)k * T + t < c) buf[atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u)] = key[k];
+    }
+    __syncthreads();
+    if (big <= kRankMax) {
+        // buckets are contiguous in buf: sort each in place, then one
+        // coalesced copy out
+        sort_buckets<T>(buf, cnt, nbk);
+        __syncthreads();
+        for (uint32_t i = t; i < c; i += T) dst[i] = buf[i];
+    } else {   // ids far from uniform: block bitonic over the whole segment
+        uint32_t P = 1;
+        while (P < c) P <<= 1;
+        for (uint32_t i = c + t; i < P; i += T) buf[i] = kKeyPad;
+        __syncthreads();
+        block_bitonic(buf, P);
+        for (uint32_t i = t; i < c; i += T) dst[i] = buf[i];
+    }
+    __syncthreads();
+}
+
+template <int T, int K>
+__device__ __forceinline__ void load_keys(const uint32_t *src, uint32_t c, uint32_t (&key)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t i = (uint32_t)k * T + threadIdx.x;
+        key[k] = i < c ? src[i] : kKeyPad;
+    }
+}
+
+// The same from src (src may equal dst).
+template <int T, int K>
+__device__ __forceinline__ void block_sort(const uint32_t *src, uint32_t *dst, uint32_t c, int id_bits, uint32_t *buf,
+                                           uint32_t *cnt, uint32_t *wsum) {
+    uint32_t key[K];
+    load_keys<T, K>(src, c, key);
+    block_sort_keys<T, K>(key, dst, c, id_bits, buf, cnt, wsum);
+}
+
+// One block per segment of the class list.  The next segment's ids are
+// loaded into registers before the current one is sorted, so their load
+// overlaps the sort.
 template <int T, int K>
 __global__ void __launch_bounds__(T)
 segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
             const uint32_t *__restrict__ list_count, int id_bits) {
     constexpr uint32_t N = T * K;
-    constexpr uint32_t W = T / 64;
-    constexpr uint32_t NB = N / 4;   // most buckets
     __shared__ uint32_t buf[N];
-    __shared__ uint32_t cnt[NB];
-    __shared__ uint32_t wsum[2 * W];
+    __shared__ uint32_t cnt[N / 4];
+    __shared__ uint32_t wsum[2 * (T / 64)];
     const uint32_t m = *list_count;
-    const uint32_t t = threadIdx.x;
+    uint32_t nkey[K];
+    uint64_t no = 0;
+    uint32_t nc = 0;
+    if (blockIdx.x < m) {
+        const uint32_t q = list[blockIdx.x];
+        no = offsets[q];
+        nc = (uint32_t)(offsets[q + 1] - no);
+        load_keys<T, K>(ids + no, nc, nkey);
+    }
+    for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
+        uint32_t key[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) key[k] = nkey[k];
+        const uint64_t o = no;
+        const uint32_t c = nc;
+        const uint32_t ln = li + gridDim.x;
+        if (ln < m) {   // segments are disjoint: this read never meets the writes below
+            const uint32_t q = list[ln];
+            no = offsets[q];
+            nc = (uint32_t)(offsets[q + 1] - no);
+            load_keys<T, K>(ids + no, nc, nkey);
+        }
+        block_sort_keys<T, K>(key, ids + o, c, id_bits, buf, cnt, wsum);
+    }
+}
+
+// Class L: two levels.  First (segsort_long, one block per segment) the
+// segment is split by its top 8 id bits into 256 sub-buckets in global
+// scratch: a histogram (per-wave LDS counters, eight loads in flight per
+// thread), a scan, then chunks of 4096
+// ids are counting-sorted by that digit in LDS and written out as contiguous
+// runs, one run per digit and chunk; the 257 sub-bucket starts go to the
+// segment's descriptor.  Then every sub-bucket (about c/256 ids sharing their
+// top bits) is sorted from scratch back into place by the whole grid: one
+// wave per sub-bucket of <= 256 ids (segsort_sub_small), one block per larger
+// one (segsort_sub_mid).  A segment with a sub-bucket over 4096 ids (ids far
+// from uniform, or more than about a million ids) is left as it is, flagged
+// in its descriptor, and goes to the fallback list.
+constexpr uint32_t kLongDigits = 256;
+constexpr uint32_t kLongChunk = 4096;   // ids per chunk: 1024 threads x 4
+constexpr uint32_t kSubMax = 4096;      // longest sub-bucket sorted by one block
+constexpr uint32_t kDesc = kLongDigits + 1;
+constexpr uint32_t kSubCounts = 8;      // counters of the two sub-bucket lists (in the class counter block)
+
+template <int T>
+__global__ void __launch_bounds__(T)
+segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint32_t *__restrict__ scratch,
+             uint32_t *__restrict__ desc, uint32_t *__restrict__ sub_lists, uint32_t *__restrict__ sub_counts,
+             uint64_t sub_cap, const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_count,
+             uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, int id_bits) {
+    constexpr uint32_t W = T / 64, R = kLongChunk / T;
+    static_assert(T >= kLongDigits, "one thread per digit");
+    __shared__ uint32_t whist[W * kLongDigits];   // per-wave digit counts
+    __shared__ uint32_t stage[kLongChunk];        // digit-sorted chunk
+    __shared__ uint32_t start[kLongDigits + 1];   // sub-bucket starts (start[256] = c)
+    __shared__ uint32_t cur[kLongDigits];         // write cursor per digit
+    __shared__ uint32_t lh[kLongDigits], loff[kLongDigits], lcur[kLongDigits];
+    __shared__ uint32_t big, nsub[2], subbase[2];
+    const uint32_t m = *list_count;
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const int db = id_bits < 8 ? id_bits : 8;
+    const int sh = id_bits - db;
+    const uint32_t dmask = (1u << db) - 1u;
     for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
         const uint32_t q = list[li];
         const uint64_t o = offsets[q];
         const uint32_t c = (uint32_t)(offsets[q + 1] - o);
-        uint32_t *seg = ids + o;
-        uint32_t nb = ceil_log2((c + 3) / 4);
-        const uint32_t nbmax = ceil_log2(NB);
-        nb = nb < 1 ? 1 : (nb > nbmax ? nbmax : nb);
-        const int shift = id_bits > (int)nb ? id_bits - (int)nb : 0;
-        const uint32_t nbk = 1u << nb;
-        for (uint32_t b = t; b < nbk; b += T) cnt[b] = 0;
+        const uint32_t *seg = ids + o;
+        uint32_t *tmp = scratch + o;
+        uint32_t *dsc = desc + (uint64_t)li * kDesc;
+        // digit histogram
+        for (uint32_t i = t; i < W * kLongDigits; i += T) whist[i] = 0;
+        if (t == 0) big = 0;
         __syncthreads();
-        // rows k with k*T >= c hold nothing: the (block-uniform) row loops
-        // stop there, so the work follows c rather than the tile size
-        uint32_t key[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            key[k] = kKeyPad;
-            if ((uint32_t)k * T >= c) break;
-            const uint32_t i = (uint32_t)k * T + t;
-            if (i < c) {
-                key[k] = seg[i];
-                atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u);
-            }
-        }
-        __syncthreads();
-        const uint32_t big = block_scan_counters<T>(cnt, nbk, wsum, nullptr);
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if ((uint32_t)k * T >= c) break;
-            const uint32_t i = (uint32_t)k * T + t;
-            if (i < c) buf[atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u)] = key[k];
-        }
-        __syncthreads();
-        if (big <= kRankMax) {
-            // walk the ids in bucket order: each lands inside its own bucket's
-            // range, a few places from where it is read, so a wave's stores
-            // stay within a few cache lines
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                if ((uint32_t)k * T >= c) break;
-                const uint32_t i = (uint32_t)k * T + t;
-                if (i < c) {
-                    const uint32_t kk = buf[i];
-                    const uint32_t b = (kk >> shift) & (nbk - 1);
-                    const uint32_t s0 = b ? cnt[b - 1] : 0u, s1 = cnt[b];
-                    seg[s0 + bucket_rank(buf, s0, s1, kk)] = kk;
-                }
-            }
-        } else {   // ids far from uniform: block bitonic over the whole segment
-            uint32_t P = 1;
-            while (P < c) P <<= 1;
-            for (uint32_t i = c + t; i < P; i += T) buf[i] = kKeyPad;
-            __syncthreads();
-            block_bitonic(buf, P);
-            for (uint32_t i = t; i < c; i += T) seg[i] = buf[i];
-        }
-        __syncthreads();
-    }
-}
-
-constexpr uint32_t kLongCounters = 16384;
-
-__global__ void __launch_bounds__(1024)
-segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint32_t *__restrict__ scratch,
-             const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_count,
-             uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, int id_bits) {
-    constexpr uint32_t T = 1024, W = T / 64;
-    __shared__ uint32_t cnt[kLongCounters];
-    __shared__ uint32_t wsum[2 * W];
-    const uint32_t m = *list_count;
-    const uint32_t t = threadIdx.x;
-    for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
-        const uint32_t q = list[li];
-        const uint64_t o = offsets[q];
-        const uint64_t c = offsets[q + 1] - o;
-        uint32_t *seg = ids + o, *tmp = scratch + o;
-        const uint64_t want = (c + 3) / 4;
-        uint32_t nb = ceil_log2(want > 0x80000000ull ? 0x80000000u : (uint32_t)want);
-        const uint32_t nbmax = ceil_log2(kLongCounters);
-        nb = nb < 8 ? 8 : (nb > nbmax ? nbmax : nb);
-        const int shift = id_bits > (int)nb ? id_bits - (int)nb : 0;
-        const uint32_t nbk = 1u << nb;
-        for (uint32_t b = t; b < nbk; b += T) cnt[b] = 0;
-        __syncthreads();
-        constexpr uint32_t U = 8;   // ids in flight per thread
-        for (uint64_t i0 = t; i0 < c; i0 += (uint64_t)T * U) {
+        constexpr uint32_t U = 8;   // loads in flight per thread
+        for (uint32_t i0 = t; i0 < c; i0 += T * U) {
             uint32_t kk[U];
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
-                const uint64_t i = i0 + (uint64_t)u * T;
+                const uint32_t i = i0 + u * T;
                 kk[u] = i < c ? seg[i] : 0u;
             }
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u)
-                if (i0 + (uint64_t)u * T < c) atomicAdd(&cnt[(kk[u] >> shift) & (nbk - 1)], 1u);
+                if (i0 + u * T < c) atomicAdd(&whist[w * kLongDigits + ((kk[u] >> sh) & dmask)], 1u);
         }
         __syncthreads();
-        const uint32_t big = block_scan_counters<T>(cnt, nbk, wsum, nullptr);
-        // the rank step reads a whole bucket per id: long buckets go to the fallback
-        const uint32_t limit = kRankMax > (uint32_t)((c + nbk - 1) / nbk) * 4 ? kRankMax
-                                                                               : (uint32_t)((c + nbk - 1) / nbk) * 4;
-        if (big > limit) {
-            if (t == 0) fb_list[atomicAdd(fb_count, 1u)] = q;
+        if (w == 0) {   // one wave: totals and exclusive scan over the 256 digits
+            uint32_t v[4], sum = 0, mx = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint32_t d = lane * 4 + r;
+                uint32_t x = 0;
+                for (uint32_t ww = 0; ww < W; ++ww) x += whist[ww * kLongDigits + d];
+                v[r] = x;
+                sum += x;
+                mx = max(mx, x);
+            }
+            uint32_t inc = sum;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t x = __shfl_up(inc, d);
+                if ((int)lane >= d) inc += x;
+                mx = max(mx, (uint32_t)__shfl_xor((int)mx, d));
+            }
+            uint32_t ex = inc - sum;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                start[lane * 4 + r] = ex;
+                cur[lane * 4 + r] = ex;
+                ex += v[r];
+            }
+            if (lane == 63) start[kLongDigits] = inc;
+            if (lane == 0) big = mx;
+        }
+        __syncthreads();
+        if (big > kSubMax) {   // leave the segment to the fallback
+            if (t == 0) {
+                dsc[kLongDigits] = kKeyPad;
+                fb_list[atomicAdd(fb_count, 1u)] = q;
+            }
             __syncthreads();
             continue;
         }
-        for (uint64_t i0 = t; i0 < c; i0 += (uint64_t)T * U) {
-            uint32_t kk[U];
-#pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                const uint64_t i = i0 + (uint64_t)u * T;
-                kk[u] = i < c ? seg[i] : 0u;
-            }
-#pragma unroll
-            for (uint32_t u = 0; u < U; ++u)
-                if (i0 + (uint64_t)u * T < c) tmp[atomicAdd(&cnt[(kk[u] >> shift) & (nbk - 1)], 1u)] = kk[u];
+        for (uint32_t d = t; d <= kLongDigits; d += T) dsc[d] = start[d];
+        // work items (li << 8 | digit) for the sub-bucket sorts, in two
+        // lists: 1 .. 256 ids (one wave each) and more (one block each)
+        if (t < 2) nsub[t] = 0;
+        __syncthreads();
+        uint32_t cls = 2, slot = 0;
+        if (t < kLongDigits) {
+            const uint32_t n = start[t + 1] - start[t];
+            cls = n == 0 ? 2u : (n <= 256 ? 0u : 1u);
+            if (cls < 2) slot = atomicAdd(&nsub[cls], 1u);
         }
         __syncthreads();
-        for (uint64_t i0 = t; i0 < c; i0 += (uint64_t)T * U) {
-            uint32_t kk[U];
+        if (t < 2) subbase[t] = nsub[t] ? atomicAdd(&sub_counts[t], nsub[t]) : 0u;
+        __syncthreads();
+        if (cls < 2) sub_lists[cls * sub_cap + subbase[cls] + slot] = (li << 8) | t;
+        // chunks, digit-sorted in LDS, written out as runs
+        for (uint32_t base = 0; base < c; base += kLongChunk) {
+            const uint32_t len = (c - base) < kLongChunk ? (c - base) : kLongChunk;
+            if (t < kLongDigits) lh[t] = 0;
+            __syncthreads();
+            uint32_t key[R];
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                const uint64_t i = i0 + (uint64_t)u * T;
-                kk[u] = i < c ? tmp[i] : 0u;
+            for (uint32_t r = 0; r < R; ++r) {
+                const uint32_t i = r * T + t;
+                key[r] = i < len ? seg[base + i] : 0u;
+                if (i < len) atomicAdd(&lh[(key[r] >> sh) & dmask], 1u);
             }
+            __syncthreads();
+            if (w == 0) {
+                uint32_t v[4], sum = 0;
 #pragma unroll
-            for (uint32_t u = 0; u < U; ++u) {
-                if (i0 + (uint64_t)u * T < c) {
-                    const uint32_t key = kk[u];
-                    const uint32_t b = (key >> shift) & (nbk - 1);
-                    const uint32_t s0 = b ? cnt[b - 1] : 0u, s1 = cnt[b];
-                    seg[s0 + bucket_rank(tmp, s0, s1, key)] = key;
+                for (int r = 0; r < 4; ++r) {
+                    v[r] = lh[lane * 4 + r];
+                    sum += v[r];
+                }
+                uint32_t inc = sum;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const uint32_t x = __shfl_up(inc, d);
+                    if ((int)lane >= d) inc += x;
+                }
+                uint32_t ex = inc - sum;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    loff[lane * 4 + r] = ex;
+                    lcur[lane * 4 + r] = ex;
+                    ex += v[r];
                 }
             }
+            __syncthreads();
+#pragma unroll
+            for (uint32_t r = 0; r < R; ++r) {
+                const uint32_t i = r * T + t;
+                if (i < len) stage[atomicAdd(&lcur[(key[r] >> sh) & dmask], 1u)] = key[r];
+            }
+            __syncthreads();
+            for (uint32_t j = t; j < len; j += T) {
+                const uint32_t x = stage[j];
+                const uint32_t d = (x >> sh) & dmask;
+                tmp[cur[d] + (j - loff[d])] = x;
+            }
+            __syncthreads();
+            if (t < kLongDigits) cur[t] += lh[t];
+            __syncthreads();
         }
-        __syncthreads();
+    }
+}
+
+// Sub-buckets of <= 256 ids: one wave each, from scratch into place.
+__global__ void __launch_bounds__(256)
+segsort_sub_small(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ scratch,
+                  const uint32_t *__restrict__ desc, const uint32_t *__restrict__ items,
+                  const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list) {
+    const uint32_t m = *item_count;
+    const uint32_t wpb = blockDim.x / 64;
+    for (uint32_t k = blockIdx.x * wpb + (threadIdx.x >> 6); k < m; k += gridDim.x * wpb) {
+        const uint32_t it = items[k], li = it >> 8, d = it & 255u;
+        const uint32_t *dsc = desc + (uint64_t)li * kDesc;
+        const uint32_t s0 = dsc[d], n = dsc[d + 1] - s0;
+        const uint64_t o = offsets[list[li]] + s0;
+        wave_sort_any(scratch + o, ids + o, n);
+    }
+}
+
+// Sub-buckets of 257 .. 4096 ids: one block each, from scratch into place.
+__global__ void __launch_bounds__(256)
+segsort_sub_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ scratch,
+                const uint32_t *__restrict__ desc, const uint32_t *__restrict__ items,
+                const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list, int id_bits) {
+    constexpr uint32_t T = 256, K = 16;
+    __shared__ uint32_t buf[T * K];
+    __shared__ uint32_t cnt[T * K / 4];
+    __shared__ uint32_t wsum[2 * (T / 64)];
+    const uint32_t m = *item_count;
+    const int db = id_bits < 8 ? id_bits : 8;
+    for (uint32_t k = blockIdx.x; k < m; k += gridDim.x) {
+        const uint32_t it = items[k], li = it >> 8, d = it & 255u;
+        const uint32_t *dsc = desc + (uint64_t)li * kDesc;
+        const uint32_t s0 = dsc[d], n = dsc[d + 1] - s0;
+        const uint64_t o = offsets[list[li]] + s0;
+        block_sort<T, K>(scratch + o, ids + o, n, id_bits - db, buf, cnt, wsum);
     }
 }
 
@@ -586,6 +797,12 @@ segmerge_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, 
 
 uint64_t segsort_ws_elems(uint64_t nq) { return (uint64_t)kListCls * nq + 64; }
 
+// cap ids, then for each possible class-L segment (> kMidMax ids) kDesc
+// sub-bucket starts and two work-list slots per digit
+uint64_t segsort_scratch_elems(uint64_t cap) {
+    return cap + (cap / (kMidMax + 1) + 1) * (kDesc + 2 * kLongDigits);
+}
+
 hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch, uint64_t cap,
                           uint32_t *ws, int id_bits, hipStream_t s) {
     if (nq == 0) return hipSuccess;
@@ -603,8 +820,19 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
                        counts + 2, id_bits);
     hipLaunchKernelGGL((segsort_mid<1024, 16>), dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + 3 * nq,
                        counts + 3, id_bits);
-    hipLaunchKernelGGL(segsort_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + 4 * nq,
-                       counts + 4, lists + kFallback * nq, counts + kFallback, id_bits);
+    // after the cap ids of scratch: 257 sub-bucket starts per class-L
+    // segment, then two work lists of up to 256 items per class-L segment
+    const uint64_t nlong = cap / (kMidMax + 1) + 1;
+    uint32_t *desc = scratch + cap;
+    uint32_t *sub_lists = desc + nlong * kDesc;
+    const uint64_t sub_cap = nlong * kLongDigits;
+    hipLaunchKernelGGL(segsort_long<512>, dim3(cus * 4), dim3(512), 0, s, offsets, ids, scratch, desc, sub_lists,
+                       counts + kSubCounts, sub_cap, lists + 4 * nq, counts + 4, lists + kFallback * nq,
+                       counts + kFallback, id_bits);
+    hipLaunchKernelGGL(segsort_sub_small, dim3(cus * 8), dim3(256), 0, s, offsets, ids, scratch, desc, sub_lists,
+                       counts + kSubCounts, lists + 4 * nq);
+    hipLaunchKernelGGL(segsort_sub_mid, dim3(cus * 8), dim3(256), 0, s, offsets, ids, scratch, desc,
+                       sub_lists + sub_cap, counts + kSubCounts + 1, lists + 4 * nq, id_bits);
     hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + kFallback * nq,
                        counts + kFallback);
     hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + kFallback * nq,
