@@ -354,15 +354,15 @@ __device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, u
 
 // Sort c <= T*K ids, given in registers (key[k] holds id k*T + thread, pad
 // beyond c), into dst with one block: counting sort on the top b of the
-// id_bits significant bits (2^b ~ c/4 buckets, LDS counters), scatter into
-// LDS, sort every bucket in place, copy out.  Bits above id_bits are ignored
-// (the caller guarantees they are equal across the ids).  A bucket longer
+// id_bits significant bits of (id - base) (2^b ~ c/4 buckets, LDS counters),
+// scatter into LDS, sort every bucket in place, copy out.  The caller
+// guarantees base <= id < base + 2^id_bits for every id.  A bucket longer
 // than kRankMax (ids far from uniform) switches the segment to a block
 // bitonic network.  buf: T*K words, cnt: T*K/4 words, wsum: 2*T/64 words of
 // LDS.
 template <int T, int K>
 __device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *dst, uint32_t c, int id_bits,
-                                                uint32_t *buf, uint32_t *cnt, uint32_t *wsum) {
+                                                uint32_t *buf, uint32_t *cnt, uint32_t *wsum, uint32_t base = 0) {
     constexpr uint32_t N = T * K;
     constexpr uint32_t NB = N / 4;   // most buckets
     const uint32_t t = threadIdx.x;
@@ -378,14 +378,14 @@ __device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *ds
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if ((uint32_t)k * T >= c) break;
-        if ((uint32_t)k * T + t < c) atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u);
+        if ((uint32_t)k * T + t < c) atomicAdd(&cnt[((key[k] - base) >> shift) & (nbk - 1)], 1u);
     }
     __syncthreads();
     const uint32_t big = block_scan_counters<T>(cnt, nbk, wsum, nullptr);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if ((uint32_t)k * T >= c) break;
-        if ((uint32_t)k * T + t < c) buf[atomicAdd(&cnt[(key[k] >> shift) & (nbk - 1)], 1u)] = key[k];
+        if ((uint32_t)k * T + t < c) buf[atomicAdd(&cnt[((key[k] - base) >> shift) & (nbk - 1)], 1u)] = key[k];
     }
     __syncthreads();
     if (big <= kRankMax) {
@@ -467,23 +467,22 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
 // thread), a scan, then chunks of 4096
 // ids are counting-sorted by that digit in LDS and written out as contiguous
 // runs, one run per digit and chunk; the 257 sub-bucket starts go to the
-// segment's descriptor.  Then every sub-bucket (about c/256 ids sharing their
-// top bits) is sorted from scratch back into place by the whole grid: one
-// wave per sub-bucket of <= 256 ids (segsort_sub_small), one block per larger
-// one (segsort_sub_mid).  A segment with a sub-bucket over 4096 ids (ids far
-// from uniform, or more than about a million ids) is left as it is, flagged
-// in its descriptor, and goes to the fallback list.
+// segment's descriptor.  Then groups of G consecutive sub-buckets (G chosen
+// so that a group holds at most 4096 ids) are sorted from scratch back into
+// place by the whole grid, one block per group (segsort_sub).  A segment with
+// a sub-bucket over 4096 ids (ids far from uniform, or more than about a
+// million ids) is left as it is and goes to the fallback list.
 constexpr uint32_t kLongDigits = 256;
 constexpr uint32_t kLongChunk = 4096;   // ids per chunk: 1024 threads x 4
 constexpr uint32_t kSubMax = 4096;      // longest sub-bucket sorted by one block
-constexpr uint32_t kDesc = kLongDigits + 1;
-constexpr uint32_t kSubCounts = 8;      // counters of the two sub-bucket lists (in the class counter block)
+constexpr uint32_t kDesc = kLongDigits + 2;   // 257 sub-bucket starts, group width
+constexpr uint32_t kSubCounts = 8;      // counter of the group work list (in the class counter block)
 
 template <int T>
 __global__ void __launch_bounds__(T)
 segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint32_t *__restrict__ scratch,
              uint32_t *__restrict__ desc, uint32_t *__restrict__ sub_lists, uint32_t *__restrict__ sub_counts,
-             uint64_t sub_cap, const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_count,
+             const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_count,
              uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, int id_bits) {
     constexpr uint32_t W = T / 64, R = kLongChunk / T;
     static_assert(T >= kLongDigits, "one thread per digit");
@@ -492,7 +491,7 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
     __shared__ uint32_t start[kLongDigits + 1];   // sub-bucket starts (start[256] = c)
     __shared__ uint32_t cur[kLongDigits];         // write cursor per digit
     __shared__ uint32_t lh[kLongDigits], loff[kLongDigits], lcur[kLongDigits];
-    __shared__ uint32_t big, nsub[2], subbase[2];
+    __shared__ uint32_t big, subbase[1];
     const uint32_t m = *list_count;
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
     const int db = id_bits < 8 ? id_bits : 8;
@@ -552,28 +551,22 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
         }
         __syncthreads();
         if (big > kSubMax) {   // leave the segment to the fallback
-            if (t == 0) {
-                dsc[kLongDigits] = kKeyPad;
-                fb_list[atomicAdd(fb_count, 1u)] = q;
-            }
+            if (t == 0) fb_list[atomicAdd(fb_count, 1u)] = q;
             __syncthreads();
             continue;
         }
+        // sub-bucket groups for the block sorts: G consecutive digits each,
+        // G = kSubMax / (largest digit count), so a group never exceeds
+        // kSubMax ids; work items are li << 8 | group
+        const uint32_t G = kSubMax / (big ? big : 1u);
+        const uint32_t ngroups = (kLongDigits + G - 1) / G;
         for (uint32_t d = t; d <= kLongDigits; d += T) dsc[d] = start[d];
-        // work items (li << 8 | digit) for the sub-bucket sorts, in two
-        // lists: 1 .. 256 ids (one wave each) and more (one block each)
-        if (t < 2) nsub[t] = 0;
-        __syncthreads();
-        uint32_t cls = 2, slot = 0;
-        if (t < kLongDigits) {
-            const uint32_t n = start[t + 1] - start[t];
-            cls = n == 0 ? 2u : (n <= 256 ? 0u : 1u);
-            if (cls < 2) slot = atomicAdd(&nsub[cls], 1u);
+        if (t == 0) {
+            dsc[kLongDigits + 1] = G;
+            subbase[0] = atomicAdd(&sub_counts[0], ngroups);
         }
         __syncthreads();
-        if (t < 2) subbase[t] = nsub[t] ? atomicAdd(&sub_counts[t], nsub[t]) : 0u;
-        __syncthreads();
-        if (cls < 2) sub_lists[cls * sub_cap + subbase[cls] + slot] = (li << 8) | t;
+        if (t < ngroups) sub_lists[subbase[0] + t] = (li << 8) | t;
         // chunks, digit-sorted in LDS, written out as runs
         for (uint32_t base = 0; base < c; base += kLongChunk) {
             const uint32_t len = (c - base) < kLongChunk ? (c - base) : kLongChunk;
@@ -627,39 +620,55 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
     }
 }
 
-// Sub-buckets of <= 256 ids: one wave each, from scratch into place.
+// Groups of sub-buckets (<= kSubMax ids, digits [gG, gG + G)): one block
+// each, sorted from scratch into place; the ids of a group lie in
+// [gG << sh, (gG + G) << sh).  The next group's ids are loaded before the
+// current one is sorted.
 __global__ void __launch_bounds__(256)
-segsort_sub_small(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ scratch,
-                  const uint32_t *__restrict__ desc, const uint32_t *__restrict__ items,
-                  const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list) {
-    const uint32_t m = *item_count;
-    const uint32_t wpb = blockDim.x / 64;
-    for (uint32_t k = blockIdx.x * wpb + (threadIdx.x >> 6); k < m; k += gridDim.x * wpb) {
-        const uint32_t it = items[k], li = it >> 8, d = it & 255u;
-        const uint32_t *dsc = desc + (uint64_t)li * kDesc;
-        const uint32_t s0 = dsc[d], n = dsc[d + 1] - s0;
-        const uint64_t o = offsets[list[li]] + s0;
-        wave_sort_any(scratch + o, ids + o, n);
-    }
-}
-
-// Sub-buckets of 257 .. 4096 ids: one block each, from scratch into place.
-__global__ void __launch_bounds__(256)
-segsort_sub_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ scratch,
-                const uint32_t *__restrict__ desc, const uint32_t *__restrict__ items,
-                const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list, int id_bits) {
-    constexpr uint32_t T = 256, K = 16;
+segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ scratch,
+            const uint32_t *__restrict__ desc, const uint32_t *__restrict__ items,
+            const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list, int id_bits) {
+    constexpr uint32_t T = 256, K = kSubMax / T;
     __shared__ uint32_t buf[T * K];
     __shared__ uint32_t cnt[T * K / 4];
     __shared__ uint32_t wsum[2 * (T / 64)];
     const uint32_t m = *item_count;
     const int db = id_bits < 8 ? id_bits : 8;
-    for (uint32_t k = blockIdx.x; k < m; k += gridDim.x) {
-        const uint32_t it = items[k], li = it >> 8, d = it & 255u;
+    const int sh = id_bits - db;
+    struct Grp {
+        uint64_t o;
+        uint32_t n, base;
+        int bits;
+    };
+    auto group = [&](uint32_t k) {
+        const uint32_t it = items[k], li = it >> 8, g = it & 255u;
         const uint32_t *dsc = desc + (uint64_t)li * kDesc;
-        const uint32_t s0 = dsc[d], n = dsc[d + 1] - s0;
-        const uint64_t o = offsets[list[li]] + s0;
-        block_sort<T, K>(scratch + o, ids + o, n, id_bits - db, buf, cnt, wsum);
+        const uint32_t G = dsc[kLongDigits + 1];
+        const uint32_t d0 = g * G, d1 = (d0 + G) < kLongDigits ? (d0 + G) : kLongDigits;
+        const uint32_t s0 = dsc[d0];
+        Grp r;
+        r.o = offsets[list[li]] + s0;
+        r.n = dsc[d1] - s0;
+        r.base = d0 << sh;
+        r.bits = sh + (int)ceil_log2(d1 - d0);
+        return r;
+    };
+    uint32_t nkey[K];
+    Grp nx{0, 0, 0, 0};
+    if (blockIdx.x < m) {
+        nx = group(blockIdx.x);
+        load_keys<T, K>(scratch + nx.o, nx.n, nkey);
+    }
+    for (uint32_t k = blockIdx.x; k < m; k += gridDim.x) {
+        uint32_t key[K];
+#pragma unroll
+        for (int r = 0; r < (int)K; ++r) key[r] = nkey[r];
+        const Grp cu = nx;
+        if (k + gridDim.x < m) {
+            nx = group(k + gridDim.x);
+            load_keys<T, K>(scratch + nx.o, nx.n, nkey);
+        }
+        block_sort_keys<T, K>(key, ids + cu.o, cu.n, cu.bits, buf, cnt, wsum, cu.base);
     }
 }
 
@@ -797,10 +806,10 @@ segmerge_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, 
 
 uint64_t segsort_ws_elems(uint64_t nq) { return (uint64_t)kListCls * nq + 64; }
 
-// cap ids, then for each possible class-L segment (> kMidMax ids) kDesc
-// sub-bucket starts and two work-list slots per digit
+// cap ids, then for each possible class-L segment (> kMidMax ids) its
+// descriptor and up to 256 work items
 uint64_t segsort_scratch_elems(uint64_t cap) {
-    return cap + (cap / (kMidMax + 1) + 1) * (kDesc + 2 * kLongDigits);
+    return cap + (cap / (kMidMax + 1) + 1) * (kDesc + kLongDigits);
 }
 
 hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch, uint64_t cap,
@@ -820,19 +829,17 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
                        counts + 2, id_bits);
     hipLaunchKernelGGL((segsort_mid<1024, 16>), dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + 3 * nq,
                        counts + 3, id_bits);
-    // after the cap ids of scratch: 257 sub-bucket starts per class-L
-    // segment, then two work lists of up to 256 items per class-L segment
+    // after the cap ids of scratch: kDesc words per class-L segment (257
+    // sub-bucket starts and the group width), then its work items (at most
+    // 256 groups per segment)
     const uint64_t nlong = cap / (kMidMax + 1) + 1;
     uint32_t *desc = scratch + cap;
-    uint32_t *sub_lists = desc + nlong * kDesc;
-    const uint64_t sub_cap = nlong * kLongDigits;
-    hipLaunchKernelGGL(segsort_long<512>, dim3(cus * 4), dim3(512), 0, s, offsets, ids, scratch, desc, sub_lists,
-                       counts + kSubCounts, sub_cap, lists + 4 * nq, counts + 4, lists + kFallback * nq,
-                       counts + kFallback, id_bits);
-    hipLaunchKernelGGL(segsort_sub_small, dim3(cus * 8), dim3(256), 0, s, offsets, ids, scratch, desc, sub_lists,
-                       counts + kSubCounts, lists + 4 * nq);
-    hipLaunchKernelGGL(segsort_sub_mid, dim3(cus * 8), dim3(256), 0, s, offsets, ids, scratch, desc,
-                       sub_lists + sub_cap, counts + kSubCounts + 1, lists + 4 * nq, id_bits);
+    uint32_t *sub_list = desc + nlong * kDesc;
+    hipLaunchKernelGGL(segsort_long<512>, dim3(cus * 4), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
+                       counts + kSubCounts, lists + 4 * nq, counts + 4, lists + kFallback * nq, counts + kFallback,
+                       id_bits);
+    hipLaunchKernelGGL(segsort_sub, dim3(cus * 8), dim3(256), 0, s, offsets, ids, scratch, desc, sub_list,
+                       counts + kSubCounts, lists + 4 * nq, id_bits);
     hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + kFallback * nq,
                        counts + kFallback);
     hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + kFallback * nq,
