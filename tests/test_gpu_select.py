@@ -105,6 +105,21 @@ def test_lookahead_parity(rt, ora):
         rt._check(rt._L.rt_tree_set_lookahead(t.h, 2))
 
 
+def test_select_all_windows(rt):
+    """64 windows covering all 2M rectangles: 2M-id segments, whose
+    sub-buckets exceed one block tile, take the sort's tile-and-merge
+    fallback; every window gets every id, ascending."""
+    n = 2_000_000
+    r = rtgen.uniform_rects(n, 1e-4, 55)
+    t = rt.build_str(r, 16, "soa")
+    q = np.tile(np.array([[-np.inf, -np.inf, np.inf, np.inf]], np.float32), (64, 1))
+    off, ids = rt.range_select(t, q)
+    assert np.array_equal(off, np.arange(65, dtype=np.uint64) * n)
+    want = np.arange(n, dtype=np.uint32)
+    for k in range(64):
+        assert np.array_equal(ids[k * n:(k + 1) * n], want), k
+
+
 def test_select_empty_query_batch(rt):
     t = rt.build_str(rtgen.uniform_rects(100, 0.01, 1), 16, "soa")
     off, ids = rt.range_select(t, np.zeros((0, 4), np.float32))
