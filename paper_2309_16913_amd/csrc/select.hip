@@ -71,11 +71,23 @@ __device__ __forceinline__ uint32_t load_ptr(const uint8_t *__restrict__ node, u
 // the following slices in turn.  `visited` counts the slices found empty.
 // Returns nq when everything has been handed out.
 __device__ __forceinline__ uint32_t grab_query(Ctrl *ctrl, uint32_t slot, uint32_t nq, const uint64_t *order,
-                                               uint32_t home, uint32_t &visited, uint32_t *slice = nullptr) {
+                                               uint32_t home, uint32_t &visited, uint32_t *slice = nullptr,
+                                               bool look_first = false) {
     while (visited < kXcds) {
         const uint32_t x = (home + visited) % kXcds;
         const uint32_t b0 = (uint32_t)(((uint64_t)x * nq) / kXcds);
         const uint32_t b1 = (uint32_t)(((uint64_t)(x + 1) * nq) / kXcds);
+        // look_first (grids sized independently of the work, where most
+        // groups of a small batch are idle): read another XCD's counter
+        // before taking from it.  A drained slice's counter only grows, so a
+        // read that shows it drained is final and the atomic, which thousands
+        // of idle groups would otherwise queue on, is skipped.  Otherwise the
+        // read would only add a round trip per steal.
+        if (look_first && visited > 0 &&
+            __hip_atomic_load(&ctrl->xwork[slot][x][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b1 - b0) {
+            visited += 1;
+            continue;
+        }
         const uint32_t k = atomicAdd(&ctrl->xwork[slot][x][0], 1u);
         if (k < b1 - b0) {
             if (slice) *slice = x;
@@ -100,6 +112,11 @@ __device__ __forceinline__ Unit next_unit(Ctrl *ctrl, uint32_t slot, uint32_t nq
     while (hvisited < kXcds) {
         const uint32_t x = (home + hvisited) % kXcds;
         const uint32_t nh = ctrl->hlist[x][0];
+        if (hvisited > 0 &&
+            __hip_atomic_load(&ctrl->hwork[slot][x][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= nh) {
+            hvisited += 1;
+            continue;
+        }
         const uint32_t k = atomicAdd(&ctrl->hwork[slot][x][0], 1u);
         if (k < nh) {
             const uint4 it = plan.heavy[(uint64_t)x * plan.hcap + k];
@@ -108,7 +125,7 @@ __device__ __forceinline__ Unit next_unit(Ctrl *ctrl, uint32_t slot, uint32_t nq
         hvisited += 1;
     }
     while (true) {
-        const uint32_t q = grab_query(ctrl, slot, nq, plan.order, home, visited);
+        const uint32_t q = grab_query(ctrl, slot, nq, plan.order, home, visited, nullptr, plan.heavy != nullptr);
         if (q >= nq) return Unit{nq, 0u, 0u};
         if (!plan.slot_first) return Unit{q, 0u, q};
         const uint64_t s0 = plan.slot_first[q], s1 = plan.slot_first[q + 1];
