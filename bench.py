@@ -145,11 +145,13 @@ def select_leg(rt, torch, ev, args, rects, queries, kmin=0):
         phases["fill"].append(ev.ms(e[2], e[3]))
         phases["sort"].append(ev.ms(e[3], e[4]))
     avg = {k: float(np.mean(v)) for k, v in phases.items()}
-    vn, ve = rt.visit_stats(tree, queries)
+    vn, ve, vc = rt.visit_stats(tree, queries)
     node_bytes = 20 * ve + 8 * vn
     bytes_count = 16 * nq + node_bytes
-    bytes_fill = bytes_count + 4 * cap + 8 * (nq + 1)
-    return dict(tree=tree, info=info, build_s=build_s, cap=cap, wall=wall, avg=avg, vn=vn, ve=ve,
+    # fill: the same walk, the ids written, and the id arrays of the leaves of
+    # subtrees that lie inside their window (copied without comparisons)
+    bytes_fill = bytes_count + 4 * cap + 4 * vc + 8 * (nq + 1)
+    return dict(tree=tree, info=info, build_s=build_s, cap=cap, wall=wall, avg=avg, vn=vn, ve=ve, vc=vc,
                 bytes_count=bytes_count, bytes_fill=bytes_fill, off=off, ids=ids, lookahead=lookahead)
 
 
@@ -329,11 +331,11 @@ def serve_leg(rt, torch, args):
     r = srv.run(reqs)
     sel = np.concatenate([q.payload for q in reqs if q.kind == "select"])
     probes = [q.payload for q in reqs if q.kind == "join"]
-    vn, ve = rt.visit_stats(tb, sel)
-    bytes_ = 16 * sel.shape[0] + 20 * ve + 8 * vn
+    vn, ve, vc = rt.visit_stats(tb, sel)
+    bytes_ = 16 * sel.shape[0] + 20 * ve + 8 * vn + 4 * vc
     for p_ in probes:
-        a, b_ = rt.visit_stats(tj, p_)
-        bytes_ += 16 * p_.shape[0] + 20 * b_ + 8 * a
+        a, b_, c_ = rt.visit_stats(tj, p_)
+        bytes_ += 16 * p_.shape[0] + 20 * b_ + 8 * a + 4 * c_
     bytes_ += 4 * r["ids"] + 8 * r["batches"]
     r["algorithmic_bytes"] = bytes_
     r["algorithmic_GBps"] = bytes_ / r["wall_s"] / 1e9
@@ -435,7 +437,7 @@ def main():
         "lookahead_ms": s["lookahead"],
         "tree": {"height": s["info"].height, "nodes": s["info"].n_nodes,
                  "device_bytes": s["info"].device_bytes, "build_s": s["build_s"]},
-        "visited": {"nodes": s["vn"], "entries": s["ve"]},
+        "visited": {"nodes": s["vn"], "entries": s["ve"], "ids_from_contained_subtrees": s["vc"]},
         "legs": {},
     }
     if "cpu" in legs:

@@ -275,11 +275,12 @@ int rt_tree_set_lookahead(rt_tree *t, uint32_t on);
 int rt_tree_export(const rt_tree *t, uint32_t *level, uint32_t *count, uint64_t *first,
                    float *lx, float *ly, float *hx, float *hy, uint32_t *ptr);
 
-/* Per-query traversal statistics for the byte model: visited nodes and
- * visited entries summed over the nq host queries (same traversal as the
- * select kernels). */
+/* Per-query traversal statistics for the byte model, summed over the nq host
+ * queries (same traversal as the select kernels): visited nodes, their
+ * entries, and (vcontained, may be NULL) the ids emitted wholesale from
+ * subtrees whose MBR lies inside the window. */
 int rt_select_visit_stats(const rt_tree *t, const float *queries, uint64_t nq,
-                          uint64_t *visited_nodes, uint64_t *visited_entries);
+                          uint64_t *vnodes, uint64_t *ventries, uint64_t *vcontained);
 
 /* Message for the last failure on the calling thread ("" if none). */
 const char *rt_last_error(void);

@@ -89,7 +89,7 @@ _sig = {
     "rt_tree_set_split": ([_vp, _u32], C.c_int),
     "rt_tree_set_lookahead": ([_vp, _u32], C.c_int),
     "rt_tree_export": ([_vp] + [_vp] * 8, C.c_int),
-    "rt_select_visit_stats": ([_vp, _fp, _u64, C.POINTER(_u64), C.POINTER(_u64)], C.c_int),
+    "rt_select_visit_stats": ([_vp, _fp, _u64, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)], C.c_int),
     "rt_last_error": ([], C.c_char_p),
     "rt_version": ([], C.c_char_p),
 }
@@ -237,10 +237,12 @@ def spatial_join_device(a: Tree, b: Tree, d_pairs: int, capacity: int, flags: in
 
 
 def visit_stats(tree: Tree, queries):
+    """(visited nodes, visited entries, ids taken wholesale from subtrees that
+    lie inside their window) summed over the queries."""
     q = _rects(queries)
-    vn, ve = _u64(), _u64()
-    _check(_L.rt_select_visit_stats(tree.h, _f(q), q.shape[0], C.byref(vn), C.byref(ve)))
-    return int(vn.value), int(ve.value)
+    vn, ve, vc = _u64(), _u64(), _u64()
+    _check(_L.rt_select_visit_stats(tree.h, _f(q), q.shape[0], C.byref(vn), C.byref(ve), C.byref(vc)))
+    return int(vn.value), int(ve.value), int(vc.value)
 
 
 def select_workspace_bytes(nq: int, ids_capacity: int) -> int:

@@ -56,6 +56,7 @@ void rtk::tree_release(rt_tree *t) {
     (void)hipSetDevice(t->device);
     if (t->d_nodes) (void)hipFree(t->d_nodes);
     if (t->d_meta) (void)hipFree(t->d_meta);
+    if (t->d_range) (void)hipFree(t->d_range);
     (void)hipSetDevice(cur);
     t->~rt_tree();
 }
@@ -112,6 +113,9 @@ TreeView rtk::view_of(const rt_tree *t) {
     v.layout = t->layout;
     v.lookahead = t->lookahead;
     for (int i = 0; i < 4; ++i) v.mbr[i] = t->mbr[i];
+    v.range = static_cast<const uint2 *>(t->d_range);
+    v.partial_leaf = t->partial_leaf;
+    v.partial_cnt = t->partial_cnt;
     return v;
 }
 
@@ -506,9 +510,10 @@ extern "C" int rt_range_select(const rt_tree *t, const float *queries, uint64_t 
 }
 
 extern "C" int rt_select_visit_stats(const rt_tree *t, const float *queries, uint64_t nq, uint64_t *vnodes,
-                                     uint64_t *ventries) {
+                                     uint64_t *ventries, uint64_t *vcontained) {
     if (!t || !vnodes || !ventries) return fail(RT_EINVAL, "NULL argument");
     *vnodes = *ventries = 0;
+    if (vcontained) *vcontained = 0;
     if (int rc = check_nq(nq)) return rc;
     if (int rc = check_rects(queries, nq, "queries")) return rc;
     if (nq == 0) return RT_OK;
@@ -528,5 +533,6 @@ extern "C" int rt_select_visit_stats(const rt_tree *t, const float *queries, uin
     if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
     *vnodes = hc.stats[0];
     *ventries = hc.stats[1];
+    if (vcontained) *vcontained = hc.stats[2];
     return RT_OK;
 }

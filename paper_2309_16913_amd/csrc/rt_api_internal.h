@@ -20,6 +20,8 @@ struct rt_tree {
                                       // parents-of-leaves (0 = one group per query)
     void *d_nodes = nullptr;   // n_nodes * node_bytes
     void *d_meta = nullptr;    // n_nodes uint32: count | level << 8
+    void *d_range = nullptr;   // n_nodes uint2: leaves [x, y) under the node
+    uint32_t partial_leaf = 0xFFFFFFFFu, partial_cnt = 0;   // the leaf with < F entries, if any
 };
 
 namespace rtk {

@@ -25,6 +25,11 @@ struct TreeView {
     uint32_t layout;
     uint32_t lookahead;      // 1: select loads the next node ahead after a leaf
     float mbr[4];            // MBR of the whole tree (root node)
+    // per node the range [x, y) of leaves under it (leaves under a node are
+    // contiguous); the one leaf with fewer than F entries (kNoNode if none)
+    // and its entry count
+    const uint2 *range;
+    uint32_t partial_leaf, partial_cnt;
 };
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
@@ -76,6 +81,7 @@ struct SelectPlan {
     const uint4 *heavy = nullptr;
     uint32_t hcap = 0;
 };
+
 
 // One traversal pass (persistent grid).  counts/offsets are indexed by output
 // slot; noffsets = number of slots (offsets[noffsets] = total).

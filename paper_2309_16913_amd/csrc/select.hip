@@ -133,6 +133,14 @@ __device__ __forceinline__ Unit next_unit(Ctrl *ctrl, uint32_t slot, uint32_t nq
     }
 }
 
+// Objects under a node whose leaves are [r.x, r.y): F per leaf, less the
+// missing entries of the one leaf that is not full.
+__device__ __forceinline__ uint32_t subtree_objects(const TreeView &t, uint2 r) {
+    uint32_t c = (r.y - r.x) * t.fanout;
+    if (t.partial_leaf >= r.x && t.partial_leaf < r.y) c -= t.fanout - t.partial_cnt;
+    return c;
+}
+
 // LA = 1: lookahead (section 3, optimization O2, as a load issued one node
 // ahead).  A leaf pushes nothing, so after popping a leaf the next node to be
 // visited is already on top of the stack; its entries are loaded right away,
@@ -166,7 +174,7 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
     uint32_t sp = 0;
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
     uint64_t pos = 0, end = 0;
-    uint64_t vnodes = 0, ventries = 0;
+    uint64_t vnodes = 0, ventries = 0, vcont = 0;
     // lookahead registers: the node loaded ahead and this lane's entry of it
     uint32_t pf_node = kNoNode, pf_ref = 0;
     float pf_lx = 0.f, pf_ly = 0.f, pf_hx = 0.f, pf_hy = 0.f;
@@ -249,11 +257,17 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                 }
             }
         }
+        bool cont = false;
         if (have && e < F) {
             hit = (lx <= q.z) && (q.x <= hx) && (ly <= q.w) && (q.y <= hy);
             if constexpr (MODE == SEL_STATS) valid = (lx == lx);
+            // an internal entry whose MBR lies inside the window: every object
+            // below it qualifies, so its subtree is taken whole
+            cont = hit && !leaf && (q.x <= lx) && (hx <= q.z) && (q.y <= ly) && (hy <= q.w);
         }
         const uint64_t m = (__ballot(hit) >> gbase) & gmask;
+        const uint64_t cm = (__ballot(cont) >> gbase) & gmask;
+        const uint64_t pm = m & ~cm;   // children to descend into
         const uint32_t n = (uint32_t)__popcll(m);
         const uint32_t rank = (uint32_t)__popcll(m & below);
         if constexpr (MODE == SEL_STATS) {
@@ -277,13 +291,63 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                 pos += n;
             } else {
                 // children of a node are contiguous: entry e points at first + e
-                if (hit) {
-                    if (sp + rank < stack_cap)
-                        stk[sp + rank] = ref + e;
+                const uint32_t first = __shfl(ref, (int)gbase);
+                if (cm) {   // group-uniform: contained subtrees
+                    if constexpr (MODE == SEL_FILL) {
+                        // copy the ids of the contained subtrees' leaves.
+                        // Consecutive contained children have consecutive
+                        // leaves, so each run of them is one leaf range; lane
+                        // e copies entry e of U leaves at a time.
+                        uint64_t todo = cm;
+                        while (todo) {
+                            const uint32_t j0 = (uint32_t)__builtin_ctzll(todo);
+                            const uint64_t sh = todo >> j0;
+                            const uint32_t len = ~sh ? (uint32_t)__builtin_ctzll(~sh) : 64u - j0;
+                            todo = (j0 + len >= 64) ? 0ull : (todo & (~0ull << (j0 + len)));
+                            const uint32_t l0 = t.range[first + j0].x, l1 = t.range[first + j0 + len - 1].y;
+                            const bool hasp = t.partial_leaf >= l0 && t.partial_leaf < l1;
+                            constexpr uint32_t U = 8;
+                            for (uint32_t lb = l0; lb < l1; lb += U) {
+                                uint32_t v[U];
+                                uint64_t o[U];
+#pragma unroll
+                                for (uint32_t u = 0; u < U; ++u) {
+                                    const uint32_t lf = lb + u;
+                                    o[u] = ~0ull;
+                                    v[u] = 0;
+                                    if (lf < l1 && e < F && !(hasp && lf == t.partial_leaf && e >= t.partial_cnt)) {
+                                        o[u] = pos + (uint64_t)(lf - l0) * F + e -
+                                               ((hasp && lf > t.partial_leaf) ? F - t.partial_cnt : 0u);
+                                        v[u] = load_ptr<LAYOUT>(t.nodes + (size_t)lf * t.node_bytes, F, e);
+                                    }
+                                }
+#pragma unroll
+                                for (uint32_t u = 0; u < U; ++u) {
+                                    if (o[u] != ~0ull) {
+                                        if (o[u] < end)
+                                            ids[o[u]] = v[u];
+                                        else
+                                            atomicOr(&ctrl->err, kErrBounds);
+                                    }
+                                }
+                            }
+                            pos += subtree_objects(t, make_uint2(l0, l1));
+                        }
+                    } else {
+                        uint32_t sc = cont ? subtree_objects(t, t.range[first + e]) : 0u;
+                        for (uint32_t d = 1; d < G; d <<= 1) sc += (uint32_t)__shfl_xor((int)sc, (int)d);
+                        pos += sc;
+                        if constexpr (MODE == SEL_STATS) vcont += sc;
+                    }
+                }
+                const uint32_t prank = (uint32_t)__popcll(pm & below);
+                if (hit && !cont) {
+                    if (sp + prank < stack_cap)
+                        stk[sp + prank] = first + e;
                     else
                         atomicOr(&ctrl->err, kErrStack);
                 }
-                sp = min(sp + n, stack_cap);
+                sp = min(sp + (uint32_t)__popcll(pm), stack_cap);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -292,6 +356,7 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
         if (e == 0 && (vnodes | ventries)) {
             atomicAdd((unsigned long long *)&ctrl->stats[0], (unsigned long long)vnodes);
             atomicAdd((unsigned long long *)&ctrl->stats[1], (unsigned long long)ventries);
+            atomicAdd((unsigned long long *)&ctrl->stats[2], (unsigned long long)vcont);
         }
     }
 }

@@ -178,6 +178,35 @@ __global__ void str_write_level(const uint64_t *__restrict__ order, const float4
     }
 }
 
+// Leaf ranges: a leaf covers [g, g + 1); the one leaf with fewer than F
+// entries is reported in partial[0..1] = {leaf, count}.
+__global__ void str_range_leaves(uint32_t first, uint32_t n, uint32_t F, const uint32_t *__restrict__ meta,
+                                 uint2 *__restrict__ range, uint32_t *__restrict__ partial) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t g = first + i;
+        range[g] = make_uint2(g, g + 1);
+        const uint32_t cnt = meta[g] & 0xFFu;
+        if (cnt < F) {
+            partial[0] = g;
+            partial[1] = cnt;
+        }
+    }
+}
+
+// Internal node: its children are contiguous from its first pointer, so its
+// leaves run from the first child's first leaf to the last child's end.
+__global__ void str_range_up(uint32_t first, uint32_t n, uint32_t F, uint32_t layout,
+                             const uint8_t *__restrict__ nodes, const uint32_t *__restrict__ meta,
+                             uint2 *__restrict__ range) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t g = first + i;
+        const uint32_t cnt = meta[g] & 0xFFu;
+        const uint32_t *u = reinterpret_cast<const uint32_t *>(nodes + (uint64_t)g * (20u * F));
+        const uint32_t c0 = layout == LAYOUT_AOS ? u[4] : u[4 * F];
+        range[g] = make_uint2(range[c0].x, range[c0 + cnt - 1].y);
+    }
+}
+
 static uint32_t grid_for(uint64_t n) {
     uint64_t b = (n + 255) / 256;
     if (b == 0) b = 1;
@@ -234,6 +263,8 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
     ws += al(8 * scan_tmp_elems(he + 1));
     const uint64_t flag_off = ws;
     ws += 256;
+    const uint64_t partial_off = ws;
+    ws += 256;
 
     void *mem = obj_alloc(KIND_TREE, sizeof(rt_tree));
     if (!mem) return fail(RT_ENOMEM, "host allocation failed");
@@ -259,6 +290,7 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
     hipError_t e = work.alloc(ws);
     if (e == hipSuccess) e = hipMalloc(&t->d_nodes, total * t->node_bytes);
     if (e == hipSuccess) e = hipMalloc(&t->d_meta, total * 4);
+    if (e == hipSuccess) e = hipMalloc(&t->d_range, total * 8);
     if (e != hipSuccess) return bail(hip_fail(e, "device build allocation"));
     uint8_t *wb = static_cast<uint8_t *>(work.p);
     auto ord = [&](uint32_t l) {
@@ -273,6 +305,7 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
     uint64_t *hscan = reinterpret_cast<uint64_t *>(wb + hscan_off);
     uint64_t *stmp = reinterpret_cast<uint64_t *>(wb + stmp_off);
     uint32_t *flag = reinterpret_cast<uint32_t *>(wb + flag_off);
+    uint32_t *partial = reinterpret_cast<uint32_t *>(wb + partial_off);
 
     e = launch_zero(flag, 4, s);
     if (e == hipSuccess && n) {
@@ -342,6 +375,23 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
                            static_cast<uint8_t *>(t->d_nodes), static_cast<uint32_t *>(t->d_meta));
         e = hipGetLastError();
     }
+    // leaf ranges, bottom up, and the leaf that is not full
+    const uint32_t no_partial[2] = {0xFFFFFFFFu, F};
+    if (e == hipSuccess) e = hipMemcpyAsync(partial, no_partial, 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(str_range_leaves, dim3(grid_for(nodes[0])), dim3(256), 0, s, (uint32_t)first[0],
+                           (uint32_t)nodes[0], F, static_cast<const uint32_t *>(t->d_meta),
+                           static_cast<uint2 *>(t->d_range), partial);
+        e = hipGetLastError();
+    }
+    for (uint32_t l = 1; l < H && e == hipSuccess; ++l) {
+        hipLaunchKernelGGL(str_range_up, dim3(grid_for(nodes[l])), dim3(256), 0, s, (uint32_t)first[l],
+                           (uint32_t)nodes[l], F, layout, static_cast<const uint8_t *>(t->d_nodes),
+                           static_cast<const uint32_t *>(t->d_meta), static_cast<uint2 *>(t->d_range));
+        e = hipGetLastError();
+    }
+    uint32_t hpartial[2] = {0xFFFFFFFFu, F};
+    if (e == hipSuccess) e = hipMemcpyAsync(hpartial, partial, 8, hipMemcpyDeviceToHost, s);
     float4 root = make_float4(NAN, NAN, NAN, NAN);
     uint32_t hflag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&root, mbr(H - 1), 16, hipMemcpyDeviceToHost, s);
@@ -349,6 +399,8 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(hip_fail(e, "device build"));
     if (hflag) return bail(fail(RT_EINVAL, "rects contain a NaN coordinate or low > high"));
+    t->partial_leaf = hpartial[0];
+    t->partial_cnt = hpartial[1];
     t->mbr[0] = root.x;
     t->mbr[1] = root.y;
     t->mbr[2] = root.z;

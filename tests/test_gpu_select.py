@@ -220,14 +220,16 @@ def test_device_api_and_capacity(rt, ora):
 
 def test_visit_stats(rt):
     """Visited-node statistics: every query visits at least the root; a
-    select-all window visits every node and every entry."""
+    select-all window contains every child of the root, so it visits only
+    the root and takes all ids wholesale; a window away from the data visits
+    only the root."""
     r = rtgen.uniform_rects(20_000, 1e-3, 5)
     t = rt.build_str(r, 16, "soa")
-    info = t.info()
-    vn, ve = rt.visit_stats(t, np.array([[-np.inf, -np.inf, np.inf, np.inf]], np.float32))
-    assert vn == info.n_nodes and ve == info.n_entries
-    vn, ve = rt.visit_stats(t, np.array([[5, 5, 6, 6]], np.float32))
-    assert vn == 1
+    root_entries = int(t.export()["count"][0])
+    vn, ve, vc = rt.visit_stats(t, np.array([[-np.inf, -np.inf, np.inf, np.inf]], np.float32))
+    assert (vn, ve, vc) == (1, root_entries, 20_000)
+    vn, ve, vc = rt.visit_stats(t, np.array([[5, 5, 6, 6]], np.float32))
+    assert (vn, vc) == (1, 0)
 
 
 @pytest.mark.parametrize("fanout,layout", [(16, "soa"), (32, "aos"), (64, "d2"), (32, "soa")])
