@@ -118,7 +118,7 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
             }
             const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
             const bool leaf = node >= t.first_leaf;
-            bool hit = false;
+            bool hit = false, cont = false;
             uint32_t ref = 0;
             if (have && e < F) {
                 if (!leaf)
@@ -128,8 +128,12 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
                 float lx, ly, hx, hy;
                 batch_load(t, nb, e, lx, ly, hx, hy);
                 hit = (lx <= q.z) && (q.x <= hx) && (ly <= q.w) && (q.y <= hy);
+                // internal entry inside the window: its subtree is taken whole
+                cont = hit && !leaf && (q.x <= lx) && (hx <= q.z) && (q.y <= ly) && (hy <= q.w);
             }
             const uint64_t m = (__ballot(hit) >> gbase) & gmask;
+            const uint64_t cm = (__ballot(cont) >> gbase) & gmask;
+            const uint64_t pm = m & ~cm;
             const uint32_t n = (uint32_t)__popcll(m);
             const uint32_t rank = (uint32_t)__popcll(m & below);
             if (have) {
@@ -145,13 +149,58 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
                     }
                     pos += n;
                 } else {
-                    if (hit) {
-                        if (sp + rank < bt.stack_cap)
-                            stk[sp + rank] = ref + e;
+                    const uint32_t first = __shfl(ref, (int)gbase);
+                    if (cm) {   // group-uniform: contained subtrees
+                        if constexpr (MODE == SEL_FILL) {
+                            uint64_t todo = cm;
+                            while (todo) {   // one run of consecutive contained children at a time
+                                const uint32_t j0 = (uint32_t)__builtin_ctzll(todo);
+                                const uint64_t sh = todo >> j0;
+                                const uint32_t len = ~sh ? (uint32_t)__builtin_ctzll(~sh) : 64u - j0;
+                                todo = (j0 + len >= 64) ? 0ull : (todo & (~0ull << (j0 + len)));
+                                const uint32_t l0 = t.range[first + j0].x, l1 = t.range[first + j0 + len - 1].y;
+                                const bool hasp = t.partial_leaf >= l0 && t.partial_leaf < l1;
+                                constexpr uint32_t U = 8;   // leaves in flight per lane
+                                for (uint32_t lb = l0; lb < l1; lb += U) {
+                                    uint32_t v[U];
+                                    uint64_t o[U];
+#pragma unroll
+                                    for (uint32_t u = 0; u < U; ++u) {
+                                        const uint32_t lf = lb + u;
+                                        o[u] = ~0ull;
+                                        v[u] = 0;
+                                        if (lf < l1 && e < F && !(hasp && lf == t.partial_leaf && e >= t.partial_cnt)) {
+                                            o[u] = pos + (uint64_t)(lf - l0) * F + e -
+                                                   ((hasp && lf > t.partial_leaf) ? F - t.partial_cnt : 0u);
+                                            v[u] = batch_ptr(t, t.nodes + (size_t)lf * t.node_bytes, e);
+                                        }
+                                    }
+#pragma unroll
+                                    for (uint32_t u = 0; u < U; ++u) {
+                                        if (o[u] != ~0ull) {
+                                            if (o[u] < end)
+                                                ids[o[u]] = v[u];
+                                            else
+                                                atomicOr(&ctrl->err, kErrBounds);
+                                        }
+                                    }
+                                }
+                                pos += subtree_objects(t, make_uint2(l0, l1));
+                            }
+                        } else {
+                            uint32_t sc = cont ? subtree_objects(t, t.range[first + e]) : 0u;
+                            for (uint32_t d = 1; d < G; d <<= 1) sc += (uint32_t)__shfl_xor((int)sc, (int)d);
+                            pos += sc;
+                        }
+                    }
+                    const uint32_t prank = (uint32_t)__popcll(pm & below);
+                    if (hit && !cont) {
+                        if (sp + prank < bt.stack_cap)
+                            stk[sp + prank] = first + e;
                         else
                             atomicOr(&ctrl->err, kErrStack);
                     }
-                    sp = min(sp + n, bt.stack_cap);
+                    sp = min(sp + (uint32_t)__popcll(pm), bt.stack_cap);
                 }
             }
             __builtin_amdgcn_wave_barrier();

@@ -35,6 +35,14 @@ constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
 constexpr uint32_t kXcds = 8;          // MI355X: 8 XCDs; workgroup i runs on XCD i % 8
 
+// Objects under a node whose leaves are [r.x, r.y): F per leaf, less the
+// missing entries of the one leaf that is not full.
+__device__ __forceinline__ uint32_t subtree_objects(const TreeView &t, uint2 r) {
+    uint32_t c = (r.y - r.x) * t.fanout;
+    if (t.partial_leaf >= r.x && t.partial_leaf < r.y) c -= t.fanout - t.partial_cnt;
+    return c;
+}
+
 // Kernel-side status words at the start of every workspace.
 struct Ctrl {
     uint32_t work[8];        // work-queue counters (one per pass)

@@ -133,14 +133,6 @@ __device__ __forceinline__ Unit next_unit(Ctrl *ctrl, uint32_t slot, uint32_t nq
     }
 }
 
-// Objects under a node whose leaves are [r.x, r.y): F per leaf, less the
-// missing entries of the one leaf that is not full.
-__device__ __forceinline__ uint32_t subtree_objects(const TreeView &t, uint2 r) {
-    uint32_t c = (r.y - r.x) * t.fanout;
-    if (t.partial_leaf >= r.x && t.partial_leaf < r.y) c -= t.fanout - t.partial_cnt;
-    return c;
-}
-
 // LA = 1: lookahead (section 3, optimization O2, as a load issued one node
 // ahead).  A leaf pushes nothing, so after popping a leaf the next node to be
 // visited is already on top of the stack; its entries are loaded right away,
