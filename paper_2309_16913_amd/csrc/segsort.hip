@@ -24,6 +24,8 @@
 //              LDS (class M) or, for class L with a sub-bucket over 4096 ids,
 //              by sorting 16384-id tiles that way and merging runs pairwise
 //              through LDS-staged merge-path windows.
+#include <mutex>
+
 #include "rt_internal.h"
 
 namespace rtk {
@@ -812,6 +814,39 @@ uint64_t segsort_scratch_elems(uint64_t cap) {
     return cap + (cap / (kMidMax + 1) + 1) * (kDesc + kLongDigits);
 }
 
+// The size classes sort disjoint segments, so they run side by side: three
+// extra streams per device (default priority) take the small and mid
+// classes while the caller's stream takes class L, forked and joined with
+// events.  Under stream capture everything stays on the caller's stream.
+// A wait takes the event's latest record, so each fork and join pair is
+// enqueued under the device's lock: calls from several host threads then
+// never wait on one another's records.
+struct SortStreams {
+    hipStream_t st[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    std::mutex mu;
+    bool ok = false;
+};
+
+static SortStreams *sort_streams() {
+    static std::mutex mu;
+    static SortStreams per_dev[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    SortStreams &ss = per_dev[dev];
+    if (!ss.ok) {
+        bool good = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; i < 3 && good; ++i) {
+            good = hipStreamCreateWithFlags(&ss.st[i], hipStreamNonBlocking) == hipSuccess &&
+                   hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming) == hipSuccess;
+        }
+        if (!good) return nullptr;   // keep everything on the caller's stream
+        ss.ok = true;
+    }
+    return &ss;
+}
+
 hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch, uint64_t cap,
                           uint32_t *ws, int id_bits, hipStream_t s) {
     if (nq == 0) return hipSuccess;
@@ -822,12 +857,29 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     if (e != hipSuccess) return e;
     const uint64_t cg = (nq + kClsTile - 1) / kClsTile;
     hipLaunchKernelGGL(seg_classify, dim3((uint32_t)cg), dim3(256), 0, s, offsets, nq, cap, lists, counts);
-    hipLaunchKernelGGL(segsort_small, dim3(cus * 8), dim3(256), 0, s, offsets, ids, lists, counts + 0);
-    hipLaunchKernelGGL((segsort_mid<128, 8>), dim3(cus * 16), dim3(128), 0, s, offsets, ids, lists + nq, counts + 1,
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    hipStreamCaptureStatus cap_st = hipStreamCaptureStatusNone;
+    (void)hipStreamIsCapturing(s, &cap_st);
+    SortStreams *ss = cap_st == hipStreamCaptureStatusNone ? sort_streams() : nullptr;
+    std::unique_lock<std::mutex> enq;
+    if (ss) enq = std::unique_lock<std::mutex>(ss->mu);
+    hipStream_t sa = s, sb = s, sc = s;
+    if (ss) {
+        e = hipEventRecord(ss->fork, s);
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ss->st[i], ss->fork, 0);
+        if (e != hipSuccess) return e;
+        sa = ss->st[0];
+        sb = ss->st[1];
+        sc = ss->st[2];
+    }
+    hipLaunchKernelGGL(segsort_small, dim3(cus * 8), dim3(256), 0, sa, offsets, ids, lists, counts + 0);
+    hipLaunchKernelGGL((segsort_mid<128, 8>), dim3(cus * 16), dim3(128), 0, sa, offsets, ids, lists + nq, counts + 1,
                        id_bits);
-    hipLaunchKernelGGL((segsort_mid<256, 16>), dim3(cus * 8), dim3(256), 0, s, offsets, ids, lists + 2 * nq,
+    hipLaunchKernelGGL((segsort_mid<256, 16>), dim3(cus * 8), dim3(256), 0, sb, offsets, ids, lists + 2 * nq,
                        counts + 2, id_bits);
-    hipLaunchKernelGGL((segsort_mid<1024, 16>), dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + 3 * nq,
+    hipLaunchKernelGGL((segsort_mid<1024, 16>), dim3(cus * 2), dim3(1024), 0, sc, offsets, ids, lists + 3 * nq,
                        counts + 3, id_bits);
     // after the cap ids of scratch: kDesc words per class-L segment (257
     // sub-bucket starts and the group width), then its work items (at most
@@ -844,7 +896,14 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
                        counts + kFallback);
     hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + kFallback * nq,
                        counts + kFallback);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (ss) {
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+            e = hipEventRecord(ss->join[i], ss->st[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, ss->join[i], 0);
+        }
+    }
+    return e;
 }
 
 }  // namespace rtk
