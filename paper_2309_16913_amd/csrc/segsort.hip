@@ -9,16 +9,17 @@
 //   class S    (<= 256 ids)     one wave per segment: the ids sit in
 //              registers (up to 4 per lane) and a bitonic network runs over
 //              them with __shfl_xor for cross-lane partners;
-//   class M    (257 .. 16384, in three block sizes: 128, 256 and 1024
-//              threads)             one block per segment: ids to registers, a
-//              counting sort on the top b id bits (2^b ~ length/4 buckets,
-//              LDS counters), scatter into LDS, then each id counts the
-//              smaller ids of its own bucket and is stored at bucket start +
-//              that count;
-//   class L    (> 16384)        one block per segment: an MSD pass on the top
+//   class M    (257 .. 32768, in four block shapes: 128 x 8, 256 x 16,
+//              512 x 32 and 1024 x 32 threads x ids)  one block per segment:
+//              ids to registers, a counting sort on the top b id bits
+//              (2^b ~ length/4 buckets, LDS counters), scatter into LDS,
+//              then every bucket sorted in place by a register network (or,
+//              for the shortest, each id counts the smaller ids of its own
+//              bucket and is stored at bucket start + that count);
+//   class L    (> 32768)        one block per segment: an MSD pass on the top
 //              8 id bits into global scratch (chunks digit-sorted in LDS and
-//              written as runs), then each of the 256 sub-buckets sorted
-//              back by one wave (<= 256 ids) or the block (<= 4096);
+//              written as runs), then groups of consecutive sub-buckets
+//              (<= 4096 ids each) sorted back by one block each;
 //   fallback   a segment with a bucket too long for the in-bucket ranking
 //              (ids far from uniform) is sorted by a block bitonic network in
 //              LDS (class M) or, for class L with a sub-bucket over 4096 ids,
@@ -31,9 +32,12 @@
 namespace rtk {
 
 constexpr uint32_t kKeyPad = 0xFFFFFFFFu;   // never an object id (ids < 2^32 - 1)
-constexpr uint32_t kMidMax = 16384;         // longest class-M segment
-constexpr uint32_t kListCls = 6;            // S, M1, M2, M3, L, fallback-L
-constexpr uint32_t kFallback = 5;
+constexpr uint32_t kMidMax = 32768;         // longest class-M segment
+constexpr uint32_t kTileMax = 16384;        // tile of the class-L fallback
+constexpr uint32_t kNumCls = 6;             // S, M1, M2, M3, M4, L (by length)
+constexpr uint32_t kLong = 5;
+constexpr uint32_t kFallback = 6;           // fallback-L list
+constexpr uint32_t kListCls = 7;
 
 __device__ __forceinline__ uint32_t ceil_log2(uint32_t v) {
     uint32_t b = 0;
@@ -173,11 +177,11 @@ constexpr uint32_t kClsTile = 256 * kClsPer;       // queries per block
 __global__ void __launch_bounds__(256)
 seg_classify(const uint64_t *__restrict__ offsets, uint64_t nq, uint64_t cap, uint32_t *__restrict__ lists,
              uint32_t *__restrict__ counts) {
-    __shared__ uint32_t bcnt[5], gbase[5];
+    __shared__ uint32_t bcnt[kNumCls], gbase[kNumCls];
     if (offsets[nq] > cap) return;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    if (threadIdx.x < 5) bcnt[threadIdx.x] = 0;
+    if (threadIdx.x < kNumCls) bcnt[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t q0 = (uint64_t)blockIdx.x * kClsTile;
     int cls[kClsPer];
@@ -189,12 +193,12 @@ seg_classify(const uint64_t *__restrict__ offsets, uint64_t nq, uint64_t cap, ui
         if (q < nq) {
             const uint64_t len = offsets[q + 1] - offsets[q];
             if (len >= 2)
-                c = len <= 256 ? 0 : (len <= 1024 ? 1 : (len <= 4096 ? 2 : (len <= kMidMax ? 3 : 4)));
+                c = len <= 256 ? 0 : len <= 1024 ? 1 : len <= 4096 ? 2 : len <= 16384 ? 3 : len <= kMidMax ? 4 : 5;
         }
         cls[k] = c;
         pos[k] = 0;
 #pragma unroll
-        for (int j = 0; j < 5; ++j) {
+        for (int j = 0; j < (int)kNumCls; ++j) {
             const uint64_t m = __ballot(c == j);
             if (m == 0) continue;
             const uint32_t leader = (uint32_t)__builtin_ctzll(m);
@@ -205,7 +209,7 @@ seg_classify(const uint64_t *__restrict__ offsets, uint64_t nq, uint64_t cap, ui
         }
     }
     __syncthreads();
-    if (threadIdx.x < 5)
+    if (threadIdx.x < kNumCls)
         gbase[threadIdx.x] = bcnt[threadIdx.x] ? atomicAdd(&counts[threadIdx.x], bcnt[threadIdx.x]) : 0u;
     __syncthreads();
 #pragma unroll
@@ -360,9 +364,12 @@ __device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, u
 // scatter into LDS, sort every bucket in place, copy out.  The caller
 // guarantees base <= id < base + 2^id_bits for every id.  A bucket longer
 // than kRankMax (ids far from uniform) switches the segment to a block
-// bitonic network.  buf: T*K words, cnt: T*K/4 words, wsum: 2*T/64 words of
-// LDS.
-template <int T, int K>
+// bitonic network.  PLACE: instead of sorting the buckets in place and copying
+// out, every key is stored straight at its final place (faster for short
+// segments, where the bucket networks are mostly padding); cnt must then
+// follow buf in LDS.  buf: T*K words, cnt: T*K/4 words, wsum: 2*T/64 words
+// of LDS.
+template <int T, int K, bool PLACE = false>
 __device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *dst, uint32_t c, int id_bits,
                                                 uint32_t *buf, uint32_t *cnt, uint32_t *wsum, uint32_t base = 0) {
     constexpr uint32_t N = T * K;
@@ -390,7 +397,29 @@ __device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *ds
         if ((uint32_t)k * T + t < c) buf[atomicAdd(&cnt[((key[k] - base) >> shift) & (nbk - 1)], 1u)] = key[k];
     }
     __syncthreads();
-    if (big <= kRankMax) {
+    if (big <= kRankMax && PLACE) {
+        // buckets are contiguous in buf: the key at position i goes to its
+        // bucket's start plus the number of keys of the bucket that precede
+        // it (smaller, or equal and earlier).  A wave's 64 positions land on
+        // a permutation of about the same 64 outputs, so the stores stay
+        // coalesced.  The 4-wide reads run up to 3 words past the keys: buf
+        // must be followed by at least 3 words of LDS (the counters are).
+        for (uint32_t i = t; i < c; i += T) {
+            const uint32_t x = buf[i];
+            const uint32_t b = ((x - base) >> shift) & (nbk - 1);
+            const uint32_t s0 = b ? cnt[b - 1] : 0u;
+            const uint32_t e0 = cnt[b];
+            uint32_t r = s0;
+            for (uint32_t j = s0; j < e0; j += 4) {
+                const uint32_t y0 = buf[j], y1 = buf[j + 1], y2 = buf[j + 2], y3 = buf[j + 3];
+                r += (y0 < x || (y0 == x && j < i)) ? 1u : 0u;
+                r += (j + 1 < e0 && (y1 < x || (y1 == x && j + 1 < i))) ? 1u : 0u;
+                r += (j + 2 < e0 && (y2 < x || (y2 == x && j + 2 < i))) ? 1u : 0u;
+                r += (j + 3 < e0 && (y3 < x || (y3 == x && j + 3 < i))) ? 1u : 0u;
+            }
+            dst[r] = x;
+        }
+    } else if (big <= kRankMax) {
         // buckets are contiguous in buf: sort each in place, then one
         // coalesced copy out
         sort_buckets<T>(buf, cnt, nbk);
@@ -425,41 +454,55 @@ __device__ __forceinline__ void block_sort(const uint32_t *src, uint32_t *dst, u
     block_sort_keys<T, K>(key, dst, c, id_bits, buf, cnt, wsum);
 }
 
-// One block per segment of the class list.  The next segment's ids are
-// loaded into registers before the current one is sorted, so their load
-// overlaps the sort.
-template <int T, int K>
-__global__ void __launch_bounds__(T)
+// One block per segment of the class list.  With PF the next segment's ids
+// are loaded into registers before the current one is sorted, so their load
+// overlaps the sort (it costs K registers, which the widest shape cannot
+// spare: a 1024-thread block has 128 per lane).  Shapes of 16384 ids and up
+// are held to 4 waves per SIMD so that two 512-thread blocks share a CU.
+template <int T, int K, bool PLACE, bool PF>
+__global__ void __launch_bounds__(T, T * K >= 16384 ? 4 : 1)
 segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
             const uint32_t *__restrict__ list_count, int id_bits) {
     constexpr uint32_t N = T * K;
-    __shared__ uint32_t buf[N];
-    __shared__ uint32_t cnt[N / 4];
-    __shared__ uint32_t wsum[2 * (T / 64)];
+    // keys, then the bucket counters; the scan's per-wave sums use the head
+    // of buf, which holds nothing while the counters are scanned
+    __shared__ uint32_t lds[N + N / 4];
+    uint32_t *buf = lds, *cnt = lds + N, *wsum = lds;
     const uint32_t m = *list_count;
-    uint32_t nkey[K];
-    uint64_t no = 0;
-    uint32_t nc = 0;
-    if (blockIdx.x < m) {
-        const uint32_t q = list[blockIdx.x];
-        no = offsets[q];
-        nc = (uint32_t)(offsets[q + 1] - no);
-        load_keys<T, K>(ids + no, nc, nkey);
-    }
-    for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
-        uint32_t key[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) key[k] = nkey[k];
-        const uint64_t o = no;
-        const uint32_t c = nc;
-        const uint32_t ln = li + gridDim.x;
-        if (ln < m) {   // segments are disjoint: this read never meets the writes below
-            const uint32_t q = list[ln];
+    if constexpr (PF) {
+        uint32_t nkey[K];
+        uint64_t no = 0;
+        uint32_t nc = 0;
+        if (blockIdx.x < m) {
+            const uint32_t q = list[blockIdx.x];
             no = offsets[q];
             nc = (uint32_t)(offsets[q + 1] - no);
             load_keys<T, K>(ids + no, nc, nkey);
         }
-        block_sort_keys<T, K>(key, ids + o, c, id_bits, buf, cnt, wsum);
+        for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
+            uint32_t key[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) key[k] = nkey[k];
+            const uint64_t o = no;
+            const uint32_t c = nc;
+            const uint32_t ln = li + gridDim.x;
+            if (ln < m) {   // segments are disjoint: this read never meets the writes below
+                const uint32_t q = list[ln];
+                no = offsets[q];
+                nc = (uint32_t)(offsets[q + 1] - no);
+                load_keys<T, K>(ids + no, nc, nkey);
+            }
+            block_sort_keys<T, K, PLACE>(key, ids + o, c, id_bits, buf, cnt, wsum);
+        }
+    } else {
+        for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
+            const uint32_t q = list[li];
+            const uint64_t o = offsets[q];
+            const uint32_t c = (uint32_t)(offsets[q + 1] - o);
+            uint32_t key[K];
+            load_keys<T, K>(ids + o, c, key);
+            block_sort_keys<T, K, PLACE>(key, ids + o, c, id_bits, buf, cnt, wsum);
+        }
     }
 }
 
@@ -680,14 +723,14 @@ segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
 __global__ void __launch_bounds__(1024)
 segsort_tiles(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
               const uint32_t *__restrict__ list_count) {
-    __shared__ uint32_t buf[kMidMax];
+    __shared__ uint32_t buf[kTileMax];
     const uint32_t m = *list_count;
     for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
         const uint32_t q = list[li];
         const uint64_t o = offsets[q];
         const uint64_t c = offsets[q + 1] - o;
-        for (uint64_t t0 = 0; t0 < c; t0 += kMidMax) {
-            const uint32_t tc = (uint32_t)((c - t0) < kMidMax ? (c - t0) : kMidMax);
+        for (uint64_t t0 = 0; t0 < c; t0 += kTileMax) {
+            const uint32_t tc = (uint32_t)((c - t0) < kTileMax ? (c - t0) : kTileMax);
             uint32_t P = 1;
             while (P < tc) P <<= 1;
             for (uint32_t i = threadIdx.x; i < P; i += 1024) buf[i] = i < tc ? ids[o + t0 + i] : kKeyPad;
@@ -744,7 +787,7 @@ segmerge_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, 
         const uint64_t o = offsets[q];
         const uint64_t c = offsets[q + 1] - o;
         uint32_t *src = ids + o, *dst = scratch + o;
-        for (uint64_t w = kMidMax; w < c; w <<= 1) {
+        for (uint64_t w = kTileMax; w < c; w <<= 1) {
             for (uint64_t r0 = 0; r0 < c; r0 += 2 * w) {
                 const uint64_t la = (c - r0) < w ? (c - r0) : w;
                 const uint64_t rest = c - r0 - la;
@@ -814,16 +857,16 @@ uint64_t segsort_scratch_elems(uint64_t cap) {
     return cap + (cap / (kMidMax + 1) + 1) * (kDesc + kLongDigits);
 }
 
-// The size classes sort disjoint segments, so they run side by side: three
-// extra streams per device (default priority) take the small and mid
-// classes while the caller's stream takes class L, forked and joined with
-// events.  Under stream capture everything stays on the caller's stream.
-// A wait takes the event's latest record, so each fork and join pair is
-// enqueued under the device's lock: calls from several host threads then
-// never wait on one another's records.
+// The size classes sort disjoint segments, so two chains run side by side:
+// classes S and M (shortest first) on an extra stream per device (default
+// priority), class L on the caller's stream, forked and joined with events.
+// Under stream capture everything stays on the caller's stream.  A wait
+// takes the event's latest record, so each fork and join pair is enqueued
+// under the device's lock: calls from several host threads then never wait
+// on one another's records.
 struct SortStreams {
-    hipStream_t st[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    hipStream_t st = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     std::mutex mu;
     bool ok = false;
 };
@@ -836,15 +879,20 @@ static SortStreams *sort_streams() {
     std::lock_guard<std::mutex> lk(mu);
     SortStreams &ss = per_dev[dev];
     if (!ss.ok) {
-        bool good = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess;
-        for (int i = 0; i < 3 && good; ++i) {
-            good = hipStreamCreateWithFlags(&ss.st[i], hipStreamNonBlocking) == hipSuccess &&
-                   hipEventCreateWithFlags(&ss.join[i], hipEventDisableTiming) == hipSuccess;
-        }
+        const bool good = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess &&
+                          hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) == hipSuccess &&
+                          hipStreamCreateWithFlags(&ss.st, hipStreamNonBlocking) == hipSuccess;
         if (!good) return nullptr;   // keep everything on the caller's stream
         ss.ok = true;
     }
     return &ss;
+}
+
+template <typename Kern>
+static uint32_t resident_per_cu(Kern kern, int threads) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, threads, 0) != hipSuccess || n < 1) n = 1;
+    return (uint32_t)n;
 }
 
 hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch, uint64_t cap,
@@ -853,6 +901,15 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     uint32_t *counts = ws;            // class counters
     uint32_t *lists = ws + 64;        // kListCls lists of up to nq query indices
     const uint32_t cus = (uint32_t)num_cus();
+    // blocks per CU that fit at once (registers and LDS): each persistent
+    // grid holds that many, so no block waits for another to finish its share
+    static const uint32_t g_small = resident_per_cu(segsort_small, 256);
+    static const uint32_t g_m1 = resident_per_cu(segsort_mid<128, 8, true, true>, 128);
+    static const uint32_t g_m2 = resident_per_cu(segsort_mid<256, 16, false, true>, 256);
+    static const uint32_t g_m3 = resident_per_cu(segsort_mid<512, 32, false, true>, 512);
+    static const uint32_t g_m4 = resident_per_cu(segsort_mid<1024, 32, false, false>, 1024);
+    static const uint32_t g_long = resident_per_cu(segsort_long<512>, 512);
+    static const uint32_t g_sub = resident_per_cu(segsort_sub, 256);
     hipError_t e = launch_zero(counts, 64 * 4, s);
     if (e != hipSuccess) return e;
     const uint64_t cg = (nq + kClsTile - 1) / kClsTile;
@@ -865,43 +922,41 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     SortStreams *ss = cap_st == hipStreamCaptureStatusNone ? sort_streams() : nullptr;
     std::unique_lock<std::mutex> enq;
     if (ss) enq = std::unique_lock<std::mutex>(ss->mu);
-    hipStream_t sa = s, sb = s, sc = s;
+    hipStream_t sm = s;
     if (ss) {
         e = hipEventRecord(ss->fork, s);
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamWaitEvent(ss->st[i], ss->fork, 0);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ss->st, ss->fork, 0);
         if (e != hipSuccess) return e;
-        sa = ss->st[0];
-        sb = ss->st[1];
-        sc = ss->st[2];
+        sm = ss->st;
     }
-    hipLaunchKernelGGL(segsort_small, dim3(cus * 8), dim3(256), 0, sa, offsets, ids, lists, counts + 0);
-    hipLaunchKernelGGL((segsort_mid<128, 8>), dim3(cus * 16), dim3(128), 0, sa, offsets, ids, lists + nq, counts + 1,
-                       id_bits);
-    hipLaunchKernelGGL((segsort_mid<256, 16>), dim3(cus * 8), dim3(256), 0, sb, offsets, ids, lists + 2 * nq,
-                       counts + 2, id_bits);
-    hipLaunchKernelGGL((segsort_mid<1024, 16>), dim3(cus * 2), dim3(1024), 0, sc, offsets, ids, lists + 3 * nq,
-                       counts + 3, id_bits);
+    hipLaunchKernelGGL(segsort_small, dim3(cus * g_small), dim3(256), 0, sm, offsets, ids, lists, counts + 0);
+    hipLaunchKernelGGL((segsort_mid<128, 8, true, true>), dim3(cus * g_m1), dim3(128), 0, sm, offsets, ids, lists + nq,
+                       counts + 1, id_bits);
+    hipLaunchKernelGGL((segsort_mid<256, 16, false, true>), dim3(cus * g_m2), dim3(256), 0, sm, offsets, ids,
+                       lists + 2 * nq, counts + 2, id_bits);
+    hipLaunchKernelGGL((segsort_mid<512, 32, false, true>), dim3(cus * g_m3), dim3(512), 0, sm, offsets, ids,
+                       lists + 3 * nq, counts + 3, id_bits);
+    hipLaunchKernelGGL((segsort_mid<1024, 32, false, false>), dim3(cus * g_m4), dim3(1024), 0, sm, offsets, ids,
+                       lists + 4 * nq, counts + 4, id_bits);
     // after the cap ids of scratch: kDesc words per class-L segment (257
     // sub-bucket starts and the group width), then its work items (at most
     // 256 groups per segment)
     const uint64_t nlong = cap / (kMidMax + 1) + 1;
     uint32_t *desc = scratch + cap;
     uint32_t *sub_list = desc + nlong * kDesc;
-    hipLaunchKernelGGL(segsort_long<512>, dim3(cus * 4), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
-                       counts + kSubCounts, lists + 4 * nq, counts + 4, lists + kFallback * nq, counts + kFallback,
-                       id_bits);
-    hipLaunchKernelGGL(segsort_sub, dim3(cus * 8), dim3(256), 0, s, offsets, ids, scratch, desc, sub_list,
-                       counts + kSubCounts, lists + 4 * nq, id_bits);
+    hipLaunchKernelGGL(segsort_long<512>, dim3(cus * g_long), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
+                       counts + kSubCounts, lists + kLong * nq, counts + kLong, lists + kFallback * nq,
+                       counts + kFallback, id_bits);
+    hipLaunchKernelGGL(segsort_sub, dim3(cus * g_sub), dim3(256), 0, s, offsets, ids, scratch, desc, sub_list,
+                       counts + kSubCounts, lists + kLong * nq, id_bits);
     hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + kFallback * nq,
                        counts + kFallback);
     hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + kFallback * nq,
                        counts + kFallback);
     e = hipGetLastError();
-    if (ss) {
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) {
-            e = hipEventRecord(ss->join[i], ss->st[i]);
-            if (e == hipSuccess) e = hipStreamWaitEvent(s, ss->join[i], 0);
-        }
+    if (ss && e == hipSuccess) {
+        e = hipEventRecord(ss->join, ss->st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, ss->join, 0);
     }
     return e;
 }

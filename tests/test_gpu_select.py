@@ -89,6 +89,36 @@ def test_select_long_segments(rt, ora):
         assert int(np.diff(want[0].astype(np.int64)).max()) == r.shape[0]
 
 
+SORT_CLASS_EDGES = [0, 1, 2, 3, 255, 256, 257, 1023, 1024, 1025, 4095, 4096, 4097, 16383, 16384, 16385,
+                    32767, 32768, 32769, 65537, 150_000]
+
+
+@pytest.mark.parametrize("permuted", [True, False])
+def test_sort_class_edges(rt, ora, permuted):
+    """Results of exactly the lengths that bound the segmented sort's size
+    classes (one wave, the block shapes, the two-level pass): points on a
+    line, windows covering runs of them.  Unpermuted, the ids of a window are
+    one contiguous range, so the top-bit buckets are as uneven as they get
+    and the bitonic and tile-and-merge fallbacks run."""
+    n = 400_000
+    x = np.arange(n, dtype=np.float32)
+    r = np.stack([x, np.zeros(n, np.float32), x, np.zeros(n, np.float32)], axis=1)
+    if permuted:
+        r = rtgen.permute(r, 77)
+    g = np.random.default_rng(78)
+    q = []
+    for c in SORT_CLASS_EDGES:
+        a = int(g.integers(0, n - c))
+        q.append([a - 0.5, -1.0, a + c - 0.5, 1.0])
+    q = np.array(q, np.float32)
+    want = ora.select(ora.build_str(r, 16), q)
+    assert np.array_equal(np.diff(want[0].astype(np.int64)), SORT_CLASS_EDGES)
+    for fanout, layout in [(16, "soa"), (64, "aos")]:
+        say(f"case sort class edges permuted={permuted} F={fanout} {layout}")
+        t = rt.build_str(r, fanout, layout)
+        assert_csr_equal(rt.range_select(t, q), want, f"class edges F={fanout} {layout}")
+
+
 def test_lookahead_parity(rt, ora):
     """Lookahead loads (on after every leaf) with Morton-ordered batches, the
     split mapping and every layout: results equal the oracle's."""
