@@ -858,12 +858,15 @@ uint64_t segsort_scratch_elems(uint64_t cap) {
 }
 
 // The size classes sort disjoint segments, so two chains run side by side:
-// classes S and M (shortest first) on an extra stream per device (default
-// priority), class L on the caller's stream, forked and joined with events.
-// Under stream capture everything stays on the caller's stream.  A wait
-// takes the event's latest record, so each fork and join pair is enqueued
-// under the device's lock: calls from several host threads then never wait
-// on one another's records.
+// classes S, M1, M2 and M4 (shortest first) on an extra stream per device
+// (default priority), M3 and then class L on the caller's stream, forked and
+// joined with events; the two chains carry about equal work on uniform ids.
+// The fallback kernels (almost always empty, but each block needs 64 KB of
+// LDS to start) run after the join, when the chip is free.  Under stream
+// capture everything stays on the caller's stream.  A wait takes the event's
+// latest record, so each fork and join pair is enqueued under the device's
+// lock: calls from several host threads then never wait on one another's
+// records.
 struct SortStreams {
     hipStream_t st = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
@@ -929,35 +932,37 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
         if (e != hipSuccess) return e;
         sm = ss->st;
     }
-    hipLaunchKernelGGL(segsort_small, dim3(cus * g_small), dim3(256), 0, sm, offsets, ids, lists, counts + 0);
-    hipLaunchKernelGGL((segsort_mid<128, 8, true, true>), dim3(cus * g_m1), dim3(128), 0, sm, offsets, ids, lists + nq,
-                       counts + 1, id_bits);
-    hipLaunchKernelGGL((segsort_mid<256, 16, false, true>), dim3(cus * g_m2), dim3(256), 0, sm, offsets, ids,
-                       lists + 2 * nq, counts + 2, id_bits);
-    hipLaunchKernelGGL((segsort_mid<512, 32, false, true>), dim3(cus * g_m3), dim3(512), 0, sm, offsets, ids,
-                       lists + 3 * nq, counts + 3, id_bits);
-    hipLaunchKernelGGL((segsort_mid<1024, 32, false, false>), dim3(cus * g_m4), dim3(1024), 0, sm, offsets, ids,
-                       lists + 4 * nq, counts + 4, id_bits);
     // after the cap ids of scratch: kDesc words per class-L segment (257
     // sub-bucket starts and the group width), then its work items (at most
     // 256 groups per segment)
     const uint64_t nlong = cap / (kMidMax + 1) + 1;
     uint32_t *desc = scratch + cap;
     uint32_t *sub_list = desc + nlong * kDesc;
+    hipLaunchKernelGGL(segsort_small, dim3(cus * g_small), dim3(256), 0, sm, offsets, ids, lists, counts + 0);
+    hipLaunchKernelGGL((segsort_mid<128, 8, true, true>), dim3(cus * g_m1), dim3(128), 0, sm, offsets, ids,
+                       lists + nq, counts + 1, id_bits);
+    hipLaunchKernelGGL((segsort_mid<256, 16, false, true>), dim3(cus * g_m2), dim3(256), 0, sm, offsets, ids,
+                       lists + 2 * nq, counts + 2, id_bits);
+    hipLaunchKernelGGL((segsort_mid<1024, 32, false, false>), dim3(cus * g_m4), dim3(1024), 0, sm, offsets, ids,
+                       lists + 4 * nq, counts + 4, id_bits);
+    hipLaunchKernelGGL((segsort_mid<512, 32, false, true>), dim3(cus * g_m3), dim3(512), 0, s, offsets, ids,
+                       lists + 3 * nq, counts + 3, id_bits);
     hipLaunchKernelGGL(segsort_long<512>, dim3(cus * g_long), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
                        counts + kSubCounts, lists + kLong * nq, counts + kLong, lists + kFallback * nq,
                        counts + kFallback, id_bits);
     hipLaunchKernelGGL(segsort_sub, dim3(cus * g_sub), dim3(256), 0, s, offsets, ids, scratch, desc, sub_list,
                        counts + kSubCounts, lists + kLong * nq, id_bits);
-    hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + kFallback * nq,
-                       counts + kFallback);
-    hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + kFallback * nq,
-                       counts + kFallback);
     e = hipGetLastError();
     if (ss && e == hipSuccess) {
         e = hipEventRecord(ss->join, ss->st);
         if (e == hipSuccess) e = hipStreamWaitEvent(s, ss->join, 0);
     }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + kFallback * nq,
+                       counts + kFallback);
+    hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + kFallback * nq,
+                       counts + kFallback);
+    e = hipGetLastError();
     return e;
 }
 
