@@ -31,7 +31,7 @@ struct rt_batch {
     void *d_trees = nullptr, *d_items = nullptr, *d_q = nullptr, *d_counts = nullptr, *d_off = nullptr;
     void *d_ids = nullptr, *d_scratch = nullptr, *d_ctrl = nullptr, *d_scan = nullptr, *d_status = nullptr;
     void *d_plain_off = nullptr, *d_lists = nullptr;
-    int id_bits = 0;
+    uint64_t id_range = 0;   // largest object count of the batch's trees
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -75,7 +75,7 @@ static hipError_t enqueue_all(rt_batch *b, hipStream_t s) {
     if (e == hipSuccess)
         e = launch_segsort(static_cast<uint64_t *>(b->d_off), b->total_q, static_cast<uint32_t *>(b->d_ids),
                            static_cast<uint32_t *>(b->d_scratch), b->cap, static_cast<uint32_t *>(b->d_lists),
-                           b->id_bits, s);
+                           b->id_range, s);
     if (e == hipSuccess)
         e = launch_finalize(static_cast<uint64_t *>(b->d_off), b->total_q, b->cap, ctrl,
                             static_cast<uint64_t *>(b->d_status), s);
@@ -127,7 +127,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
             bt[i].nq = (uint32_t)nq[i];
             bt[i].stack_cap = stack_bound(t->height, t->fanout);
             b->q_begin[i] = qb;
-            b->id_bits = std::max(b->id_bits, id_bits_for(t->n_objects));
+            b->id_range = std::max<uint64_t>(b->id_range, t->n_objects);
             const uint32_t G = group_width(t->fanout);
             b->wave_words = std::max(b->wave_words, (64 / G) * bt[i].stack_cap);
             if (nq[i]) std::memcpy(hq.data() + 4 * qb, queries[i], nq[i] * 16);
@@ -247,7 +247,7 @@ extern "C" int rt_batch_run_plain(rt_batch *b, void *stream) {
                                    (uint32_t)n, s);
         if (e == hipSuccess)
             e = launch_segsort(off, n, ids + base, scratch + base, cap, static_cast<uint32_t *>(b->d_lists),
-                               id_bits_for(b->trees[i]->n_objects), s);
+                               b->trees[i]->n_objects, s);
     }
     return e == hipSuccess ? RT_OK : hip_fail(e, "plain batch launches");
 }

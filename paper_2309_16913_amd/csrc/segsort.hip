@@ -359,10 +359,11 @@ __device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, u
 }
 
 // Sort c <= T*K ids, given in registers (key[k] holds id k*T + thread, pad
-// beyond c), into dst with one block: counting sort on the top b of the
-// id_bits significant bits of (id - base) (2^b ~ c/4 buckets, LDS counters),
-// scatter into LDS, sort every bucket in place, copy out.  The caller
-// guarantees base <= id < base + 2^id_bits for every id.  A bucket longer
+// beyond c), into dst with one block: counting sort into nbk = 2^b ~ c/4
+// buckets of equal width over the id range (bucket of id x: (x - base) *
+// nbk / range, as a 32-bit multiply-high; LDS counters), scatter into LDS,
+// sort every bucket in place, copy out.  The caller guarantees base <= id <
+// base + range for every id.  A bucket longer
 // than kRankMax (ids far from uniform) switches the segment to a block
 // bitonic network.  PLACE: instead of sorting the buckets in place and copying
 // out, every key is stored straight at its final place (faster for short
@@ -370,7 +371,7 @@ __device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, u
 // follow buf in LDS.  buf: T*K words, cnt: T*K/4 words, wsum: 2*T/64 words
 // of LDS.
 template <int T, int K, bool PLACE = false>
-__device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *dst, uint32_t c, int id_bits,
+__device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *dst, uint32_t c, uint32_t range,
                                                 uint32_t *buf, uint32_t *cnt, uint32_t *wsum, uint32_t base = 0) {
     constexpr uint32_t N = T * K;
     constexpr uint32_t NB = N / 4;   // most buckets
@@ -378,8 +379,11 @@ __device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *ds
     uint32_t nb = ceil_log2((c + 3) / 4);
     const uint32_t nbmax = ceil_log2(NB);
     nb = nb < 1 ? 1 : (nb > nbmax ? nbmax : nb);
-    const int shift = id_bits > (int)nb ? id_bits - (int)nb : 0;
     const uint32_t nbk = 1u << nb;
+    // floor(y * mul / 2^32) < nbk for every y < range, and it never decreases
+    // with y; the min() only guards against ids outside the promised range
+    const uint32_t mul = range > nbk ? (uint32_t)(((uint64_t)nbk << 32) / range) : 0xFFFFFFFFu;
+    auto bucket = [&](uint32_t x) { return min(__umulhi(x - base, mul), nbk - 1); };
     for (uint32_t b = t; b < nbk; b += T) cnt[b] = 0;
     __syncthreads();
     // rows k with k*T >= c hold nothing: the (block-uniform) row loops stop
@@ -387,14 +391,14 @@ __device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *ds
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if ((uint32_t)k * T >= c) break;
-        if ((uint32_t)k * T + t < c) atomicAdd(&cnt[((key[k] - base) >> shift) & (nbk - 1)], 1u);
+        if ((uint32_t)k * T + t < c) atomicAdd(&cnt[bucket(key[k])], 1u);
     }
     __syncthreads();
     const uint32_t big = block_scan_counters<T>(cnt, nbk, wsum, nullptr);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         if ((uint32_t)k * T >= c) break;
-        if ((uint32_t)k * T + t < c) buf[atomicAdd(&cnt[((key[k] - base) >> shift) & (nbk - 1)], 1u)] = key[k];
+        if ((uint32_t)k * T + t < c) buf[atomicAdd(&cnt[bucket(key[k])], 1u)] = key[k];
     }
     __syncthreads();
     if (big <= kRankMax && PLACE) {
@@ -406,7 +410,7 @@ __device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *ds
         // must be followed by at least 3 words of LDS (the counters are).
         for (uint32_t i = t; i < c; i += T) {
             const uint32_t x = buf[i];
-            const uint32_t b = ((x - base) >> shift) & (nbk - 1);
+            const uint32_t b = bucket(x);
             const uint32_t s0 = b ? cnt[b - 1] : 0u;
             const uint32_t e0 = cnt[b];
             uint32_t r = s0;
@@ -445,15 +449,6 @@ __device__ __forceinline__ void load_keys(const uint32_t *src, uint32_t c, uint3
     }
 }
 
-// The same from src (src may equal dst).
-template <int T, int K>
-__device__ __forceinline__ void block_sort(const uint32_t *src, uint32_t *dst, uint32_t c, int id_bits, uint32_t *buf,
-                                           uint32_t *cnt, uint32_t *wsum) {
-    uint32_t key[K];
-    load_keys<T, K>(src, c, key);
-    block_sort_keys<T, K>(key, dst, c, id_bits, buf, cnt, wsum);
-}
-
 // One block per segment of the class list.  With PF the next segment's ids
 // are loaded into registers before the current one is sorted, so their load
 // overlaps the sort (it costs K registers, which the widest shape cannot
@@ -462,7 +457,7 @@ __device__ __forceinline__ void block_sort(const uint32_t *src, uint32_t *dst, u
 template <int T, int K, bool PLACE, bool PF>
 __global__ void __launch_bounds__(T, T * K >= 16384 ? 4 : 1)
 segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
-            const uint32_t *__restrict__ list_count, int id_bits) {
+            const uint32_t *__restrict__ list_count, uint32_t id_range) {
     constexpr uint32_t N = T * K;
     // keys, then the bucket counters; the scan's per-wave sums use the head
     // of buf, which holds nothing while the counters are scanned
@@ -492,7 +487,7 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
                 nc = (uint32_t)(offsets[q + 1] - no);
                 load_keys<T, K>(ids + no, nc, nkey);
             }
-            block_sort_keys<T, K, PLACE>(key, ids + o, c, id_bits, buf, cnt, wsum);
+            block_sort_keys<T, K, PLACE>(key, ids + o, c, id_range, buf, cnt, wsum);
         }
     } else {
         for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
@@ -501,7 +496,7 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
             const uint32_t c = (uint32_t)(offsets[q + 1] - o);
             uint32_t key[K];
             load_keys<T, K>(ids + o, c, key);
-            block_sort_keys<T, K, PLACE>(key, ids + o, c, id_bits, buf, cnt, wsum);
+            block_sort_keys<T, K, PLACE>(key, ids + o, c, id_range, buf, cnt, wsum);
         }
     }
 }
@@ -672,7 +667,8 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
 __global__ void __launch_bounds__(256)
 segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ scratch,
             const uint32_t *__restrict__ desc, const uint32_t *__restrict__ items,
-            const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list, int id_bits) {
+            const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list, int id_bits,
+            uint32_t id_range) {
     constexpr uint32_t T = 256, K = kSubMax / T;
     __shared__ uint32_t buf[T * K];
     __shared__ uint32_t cnt[T * K / 4];
@@ -682,8 +678,7 @@ segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
     const int sh = id_bits - db;
     struct Grp {
         uint64_t o;
-        uint32_t n, base;
-        int bits;
+        uint32_t n, base, range;
     };
     auto group = [&](uint32_t k) {
         const uint32_t it = items[k], li = it >> 8, g = it & 255u;
@@ -694,12 +689,13 @@ segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
         Grp r;
         r.o = offsets[list[li]] + s0;
         r.n = dsc[d1] - s0;
-        r.base = d0 << sh;
-        r.bits = sh + (int)ceil_log2(d1 - d0);
+        r.base = d0 << sh;   // ids of digits [d0, d1): [d0 << sh, d1 << sh) within [0, id_range)
+        const uint64_t hi = (uint64_t)d1 << sh;
+        r.range = (uint32_t)((hi < id_range ? hi : (uint64_t)id_range) - r.base);
         return r;
     };
     uint32_t nkey[K];
-    Grp nx{0, 0, 0, 0};
+    Grp nx{0, 0, 0, 1};
     if (blockIdx.x < m) {
         nx = group(blockIdx.x);
         load_keys<T, K>(scratch + nx.o, nx.n, nkey);
@@ -713,7 +709,7 @@ segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
             nx = group(k + gridDim.x);
             load_keys<T, K>(scratch + nx.o, nx.n, nkey);
         }
-        block_sort_keys<T, K>(key, ids + cu.o, cu.n, cu.bits, buf, cnt, wsum, cu.base);
+        block_sort_keys<T, K>(key, ids + cu.o, cu.n, cu.range, buf, cnt, wsum, cu.base);
     }
 }
 
@@ -899,8 +895,10 @@ static uint32_t resident_per_cu(Kern kern, int threads) {
 }
 
 hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch, uint64_t cap,
-                          uint32_t *ws, int id_bits, hipStream_t s) {
+                          uint32_t *ws, uint64_t id_range, hipStream_t s) {
     if (nq == 0) return hipSuccess;
+    const int id_bits = id_bits_for(id_range);
+    const uint32_t range = (uint32_t)(id_range < 0xFFFFFFFFull ? id_range : 0xFFFFFFFFull);
     uint32_t *counts = ws;            // class counters
     uint32_t *lists = ws + 64;        // kListCls lists of up to nq query indices
     const uint32_t cus = (uint32_t)num_cus();
@@ -940,18 +938,18 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     uint32_t *sub_list = desc + nlong * kDesc;
     hipLaunchKernelGGL(segsort_small, dim3(cus * g_small), dim3(256), 0, sm, offsets, ids, lists, counts + 0);
     hipLaunchKernelGGL((segsort_mid<128, 8, true, true>), dim3(cus * g_m1), dim3(128), 0, sm, offsets, ids,
-                       lists + nq, counts + 1, id_bits);
+                       lists + nq, counts + 1, range);
     hipLaunchKernelGGL((segsort_mid<256, 16, false, true>), dim3(cus * g_m2), dim3(256), 0, sm, offsets, ids,
-                       lists + 2 * nq, counts + 2, id_bits);
+                       lists + 2 * nq, counts + 2, range);
     hipLaunchKernelGGL((segsort_mid<1024, 32, false, false>), dim3(cus * g_m4), dim3(1024), 0, sm, offsets, ids,
-                       lists + 4 * nq, counts + 4, id_bits);
+                       lists + 4 * nq, counts + 4, range);
     hipLaunchKernelGGL((segsort_mid<512, 32, false, true>), dim3(cus * g_m3), dim3(512), 0, s, offsets, ids,
-                       lists + 3 * nq, counts + 3, id_bits);
+                       lists + 3 * nq, counts + 3, range);
     hipLaunchKernelGGL(segsort_long<512>, dim3(cus * g_long), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
                        counts + kSubCounts, lists + kLong * nq, counts + kLong, lists + kFallback * nq,
                        counts + kFallback, id_bits);
     hipLaunchKernelGGL(segsort_sub, dim3(cus * g_sub), dim3(256), 0, s, offsets, ids, scratch, desc, sub_list,
-                       counts + kSubCounts, lists + kLong * nq, id_bits);
+                       counts + kSubCounts, lists + kLong * nq, id_bits, range);
     e = hipGetLastError();
     if (ss && e == hipSuccess) {
         e = hipEventRecord(ss->join, ss->st);
