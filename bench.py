@@ -420,7 +420,7 @@ def main():
     dom = "fill" if s["avg"]["fill"] >= s["avg"]["count"] else "count"
     dom_bytes = s["bytes_fill"] if dom == "fill" else s["bytes_count"]
     achieved = dom_bytes / (s["avg"][dom] / 1e3) / 1e9
-    src = source_hash("select.hip")
+    src = source_hash("select.hip", "rt_internal.h")
     traffic = read_traffic(f"select_{dom}_c2_f{args.fanout}_{args.layout}", src)
     result = {
         "metric": METRIC, "value": qps, "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
