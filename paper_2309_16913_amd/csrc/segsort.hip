@@ -452,10 +452,16 @@ __device__ __forceinline__ void load_keys(const uint32_t *src, uint32_t c, uint3
 // One block per segment of the class list.  With PF the next segment's ids
 // are loaded into registers before the current one is sorted, so their load
 // overlaps the sort (it costs K registers, which the widest shape cannot
-// spare: a 1024-thread block has 128 per lane).  Shapes of 16384 ids and up
-// are held to 4 waves per SIMD so that two 512-thread blocks share a CU.
+// spare: a 1024-thread block has 128 per lane).  Register budgets: shapes of
+// 16384 ids and up are held to 4 waves per SIMD, so that two 512-thread
+// blocks share a CU; 256-thread blocks to 6 (six blocks of 20 KB LDS each).
+template <int T, int K>
+constexpr int mid_waves_per_simd() {
+    return T * K >= 16384 ? 4 : (T == 256 ? 6 : 1);
+}
+
 template <int T, int K, bool PLACE, bool PF>
-__global__ void __launch_bounds__(T, T * K >= 16384 ? 4 : 1)
+__global__ void __launch_bounds__(T, (mid_waves_per_simd<T, K>()))
 segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
             const uint32_t *__restrict__ list_count, uint32_t id_range) {
     constexpr uint32_t N = T * K;
@@ -664,7 +670,7 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
 // each, sorted from scratch into place; the ids of a group lie in
 // [gG << sh, (gG + G) << sh).  The next group's ids are loaded before the
 // current one is sorted.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 6)   // as the 256-thread class-M blocks
 segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ scratch,
             const uint32_t *__restrict__ desc, const uint32_t *__restrict__ items,
             const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list, int id_bits,
