@@ -293,22 +293,24 @@ __device__ uint32_t block_scan_counters(uint32_t *cnt, uint32_t nbk, uint32_t *w
     return mxall;
 }
 
-// Bitonic network over N registers (all indices fixed at compile time).
+// Batcher's odd-even merge sort over N registers (19 comparators for 8
+// inputs, 63 for 16, against 24 and 80 for a bitonic network; all indices
+// fixed at compile time).
 template <int N>
-__device__ __forceinline__ void reg_bitonic(uint32_t (&v)[N]) {
+__device__ __forceinline__ void reg_oem(uint32_t (&v)[N]) {
 #pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
+    for (int p = 1; p < N; p <<= 1) {
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int k = p; k >= 1; k >>= 1) {
 #pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint32_t a = v[i], b = v[l];
-                    const uint32_t lo = a < b ? a : b, hi = a < b ? b : a;
-                    const bool up = (i & k) == 0;
-                    v[i] = up ? lo : hi;
-                    v[l] = up ? hi : lo;
+            for (int j = k % p; j + k < N; j += 2 * k) {
+#pragma unroll
+                for (int i = 0; i < k; ++i) {
+                    if (i < N - j - k && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                        const uint32_t x = v[i + j], y = v[i + j + k];
+                        v[i + j] = x < y ? x : y;
+                        v[i + j + k] = x < y ? y : x;
+                    }
                 }
             }
         }
@@ -320,7 +322,7 @@ __device__ __forceinline__ void sort_run_regs(uint32_t *a, uint32_t s0, uint32_t
     uint32_t v[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) v[j] = (uint32_t)j < k ? a[s0 + j] : kKeyPad;
-    reg_bitonic<N>(v);
+    reg_oem<N>(v);
 #pragma unroll
     for (int j = 0; j < N; ++j)
         if ((uint32_t)j < k) a[s0 + j] = v[j];
