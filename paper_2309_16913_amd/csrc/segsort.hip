@@ -293,11 +293,14 @@ __device__ uint32_t block_scan_counters(uint32_t *cnt, uint32_t nbk, uint32_t *w
     return mxall;
 }
 
-// Batcher's odd-even merge sort over N registers (19 comparators for 8
-// inputs, 63 for 16, against 24 and 80 for a bitonic network; all indices
-// fixed at compile time).
-template <int N>
-__device__ __forceinline__ void reg_oem(uint32_t (&v)[N]) {
+// Batcher's odd-even merge sort of N = 2^k inputs, restricted to its first M
+// (all indices fixed at compile time).  With inputs M.. taken as +inf, every
+// comparator touching them is a no-op (a +inf never leaves the top M..N-1
+// positions), so dropping those comparators sorts any M values: 12, 19, 32,
+// 42 and 63 comparators for M = 6, 8, 10, 12, 16 (bitonic over 8 and 16
+// inputs: 24 and 80).
+template <int N, int M>
+__device__ __forceinline__ void reg_oem(uint32_t (&v)[M]) {
 #pragma unroll
     for (int p = 1; p < N; p <<= 1) {
 #pragma unroll
@@ -306,7 +309,7 @@ __device__ __forceinline__ void reg_oem(uint32_t (&v)[N]) {
             for (int j = k % p; j + k < N; j += 2 * k) {
 #pragma unroll
                 for (int i = 0; i < k; ++i) {
-                    if (i < N - j - k && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
+                    if (i + j + k < M && (i + j) / (2 * p) == (i + j + k) / (2 * p)) {
                         const uint32_t x = v[i + j], y = v[i + j + k];
                         v[i + j] = x < y ? x : y;
                         v[i + j + k] = x < y ? y : x;
@@ -317,20 +320,22 @@ __device__ __forceinline__ void reg_oem(uint32_t (&v)[N]) {
     }
 }
 
-template <int N>
+// Sort the k <= M ids a[s0 .. s0 + k) in place through M registers.
+template <int M>
 __device__ __forceinline__ void sort_run_regs(uint32_t *a, uint32_t s0, uint32_t k) {
-    uint32_t v[N];
+    uint32_t v[M];
 #pragma unroll
-    for (int j = 0; j < N; ++j) v[j] = (uint32_t)j < k ? a[s0 + j] : kKeyPad;
-    reg_oem<N>(v);
+    for (int j = 0; j < M; ++j) v[j] = (uint32_t)j < k ? a[s0 + j] : kKeyPad;
+    reg_oem<(M <= 8 ? 8 : 16), M>(v);
 #pragma unroll
-    for (int j = 0; j < N; ++j)
+    for (int j = 0; j < M; ++j)
         if ((uint32_t)j < k) a[s0 + j] = v[j];
 }
 
 // Sort every bucket [end(b-1), end(b)) of a in place, one lane per bucket:
 // the ids of a bucket go through a register network sized by the longest
-// bucket in the wave (8 or 16), longer buckets (rare) are insertion-sorted.
+// bucket in the wave (6, 8, 10, 12 or 16 inputs), longer buckets (rare) are
+// insertion-sorted.
 template <int T>
 __device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, uint32_t nbk) {
     for (uint32_t b0 = 0; b0 < nbk; b0 += T) {
@@ -342,8 +347,14 @@ __device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, u
         }
         uint32_t kmax = k;
         for (int d = 32; d >= 1; d >>= 1) kmax = max(kmax, (uint32_t)__shfl_xor((int)kmax, d));
-        if (kmax <= 8) {
+        if (kmax <= 6) {
+            sort_run_regs<6>(a, s0, k);
+        } else if (kmax <= 8) {
             sort_run_regs<8>(a, s0, k);
+        } else if (kmax <= 10) {
+            sort_run_regs<10>(a, s0, k);
+        } else if (kmax <= 12) {
+            sort_run_regs<12>(a, s0, k);
         } else if (kmax <= 16) {
             sort_run_regs<16>(a, s0, k);
         } else {
