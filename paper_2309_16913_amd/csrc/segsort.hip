@@ -326,7 +326,7 @@ __device__ __forceinline__ void sort_run_regs(uint32_t *a, uint32_t s0, uint32_t
     uint32_t v[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) v[j] = (uint32_t)j < k ? a[s0 + j] : kKeyPad;
-    reg_oem<(M <= 8 ? 8 : 16), M>(v);
+    reg_oem<(M <= 8 ? 8 : (M <= 16 ? 16 : 32)), M>(v);
 #pragma unroll
     for (int j = 0; j < M; ++j)
         if ((uint32_t)j < k) a[s0 + j] = v[j];
@@ -334,9 +334,9 @@ __device__ __forceinline__ void sort_run_regs(uint32_t *a, uint32_t s0, uint32_t
 
 // Sort every bucket [end(b-1), end(b)) of a in place, one lane per bucket:
 // the ids of a bucket go through a register network sized by the longest
-// bucket in the wave (6, 8, 10, 12 or 16 inputs), longer buckets (rare) are
-// insertion-sorted.
-template <int T>
+// bucket in the wave (6, 8, 10, 12 or 16 inputs, and 20 or 24 with WIDE),
+// longer buckets (rare) are insertion-sorted.
+template <int T, bool WIDE>
 __device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, uint32_t nbk) {
     for (uint32_t b0 = 0; b0 < nbk; b0 += T) {
         const uint32_t b = b0 + threadIdx.x;
@@ -358,7 +358,17 @@ __device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, u
         } else if (kmax <= 16) {
             sort_run_regs<16>(a, s0, k);
         } else {
-            for (uint32_t i = 1; i < k; ++i) {
+            bool done = false;
+            if constexpr (WIDE) {
+                if (kmax <= 20) {
+                    sort_run_regs<20>(a, s0, k);
+                    done = true;
+                } else if (kmax <= 24) {
+                    sort_run_regs<24>(a, s0, k);
+                    done = true;
+                }
+            }
+            for (uint32_t i = 1; !done && i < k; ++i) {
                 const uint32_t x = a[s0 + i];
                 uint32_t j = i;
                 while (j > 0 && a[s0 + j - 1] > x) {
@@ -376,20 +386,20 @@ __device__ __forceinline__ void sort_buckets(uint32_t *a, const uint32_t *end, u
 // buckets of equal width over the id range (bucket of id x: (x - base) *
 // nbk / range, as a 32-bit multiply-high; LDS counters), scatter into LDS,
 // sort every bucket in place, copy out.  The caller guarantees base <= id <
-// base + range for every id.  A bucket longer
-// than kRankMax (ids far from uniform) switches the segment to a block
-// bitonic network.  PLACE: instead of sorting the buckets in place and copying
+// base + range for every id.  A: target ids per bucket (nbk ~ c/A, at most
+// T*K/A; with A = 8 the bucket networks go up to 24 inputs).  A bucket longer than kRankMax (ids far from uniform) switches the
+// segment to a block bitonic network.  PLACE: instead of sorting the buckets in place and copying
 // out, every key is stored straight at its final place (faster for short
 // segments, where the bucket networks are mostly padding); cnt must then
-// follow buf in LDS.  buf: T*K words, cnt: T*K/4 words, wsum: 2*T/64 words
+// follow buf in LDS.  buf: T*K words, cnt: T*K/A words, wsum: 2*T/64 words
 // of LDS.
-template <int T, int K, bool PLACE = false>
+template <int T, int K, bool PLACE = false, int A = 4>
 __device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *dst, uint32_t c, uint32_t range,
                                                 uint32_t *buf, uint32_t *cnt, uint32_t *wsum, uint32_t base = 0) {
     constexpr uint32_t N = T * K;
-    constexpr uint32_t NB = N / 4;   // most buckets
+    constexpr uint32_t NB = N / A;   // most buckets
     const uint32_t t = threadIdx.x;
-    uint32_t nb = ceil_log2((c + 3) / 4);
+    uint32_t nb = ceil_log2((c + A - 1) / A);
     const uint32_t nbmax = ceil_log2(NB);
     nb = nb < 1 ? 1 : (nb > nbmax ? nbmax : nb);
     const uint32_t nbk = 1u << nb;
@@ -439,7 +449,7 @@ __device__ __forceinline__ void block_sort_keys(uint32_t (&key)[K], uint32_t *ds
     } else if (big <= kRankMax) {
         // buckets are contiguous in buf: sort each in place, then one
         // coalesced copy out
-        sort_buckets<T>(buf, cnt, nbk);
+        sort_buckets<T, (A >= 8)>(buf, cnt, nbk);
         __syncthreads();
         for (uint32_t i = t; i < c; i += T) dst[i] = buf[i];
     } else {   // ids far from uniform: block bitonic over the whole segment
@@ -473,14 +483,14 @@ constexpr int mid_waves_per_simd() {
     return T * K >= 16384 ? 4 : (T == 256 ? 6 : 1);
 }
 
-template <int T, int K, bool PLACE, bool PF>
+template <int T, int K, bool PLACE, bool PF, int A>
 __global__ void __launch_bounds__(T, (mid_waves_per_simd<T, K>()))
 segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
             const uint32_t *__restrict__ list_count, uint32_t id_range) {
     constexpr uint32_t N = T * K;
     // keys, then the bucket counters; the scan's per-wave sums use the head
     // of buf, which holds nothing while the counters are scanned
-    __shared__ uint32_t lds[N + N / 4];
+    __shared__ uint32_t lds[N + N / A];
     uint32_t *buf = lds, *cnt = lds + N, *wsum = lds;
     const uint32_t m = *list_count;
     if constexpr (PF) {
@@ -506,7 +516,7 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
                 nc = (uint32_t)(offsets[q + 1] - no);
                 load_keys<T, K>(ids + no, nc, nkey);
             }
-            block_sort_keys<T, K, PLACE>(key, ids + o, c, id_range, buf, cnt, wsum);
+            block_sort_keys<T, K, PLACE, A>(key, ids + o, c, id_range, buf, cnt, wsum);
         }
     } else {
         for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
@@ -515,7 +525,7 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
             const uint32_t c = (uint32_t)(offsets[q + 1] - o);
             uint32_t key[K];
             load_keys<T, K>(ids + o, c, key);
-            block_sort_keys<T, K, PLACE>(key, ids + o, c, id_range, buf, cnt, wsum);
+            block_sort_keys<T, K, PLACE, A>(key, ids + o, c, id_range, buf, cnt, wsum);
         }
     }
 }
@@ -924,10 +934,10 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     // blocks per CU that fit at once (registers and LDS): each persistent
     // grid holds that many, so no block waits for another to finish its share
     static const uint32_t g_small = resident_per_cu(segsort_small, 256);
-    static const uint32_t g_m1 = resident_per_cu(segsort_mid<128, 8, true, true>, 128);
-    static const uint32_t g_m2 = resident_per_cu(segsort_mid<256, 16, false, true>, 256);
-    static const uint32_t g_m3 = resident_per_cu(segsort_mid<512, 32, false, true>, 512);
-    static const uint32_t g_m4 = resident_per_cu(segsort_mid<1024, 32, false, false>, 1024);
+    static const uint32_t g_m1 = resident_per_cu(segsort_mid<128, 8, true, true, 4>, 128);
+    static const uint32_t g_m2 = resident_per_cu(segsort_mid<256, 16, false, true, 4>, 256);
+    static const uint32_t g_m3 = resident_per_cu(segsort_mid<512, 32, false, true, 8>, 512);
+    static const uint32_t g_m4 = resident_per_cu(segsort_mid<1024, 32, false, false, 8>, 1024);
     static const uint32_t g_long = resident_per_cu(segsort_long<512>, 512);
     static const uint32_t g_sub = resident_per_cu(segsort_sub, 256);
     hipError_t e = launch_zero(counts, 64 * 4, s);
@@ -956,13 +966,13 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     uint32_t *desc = scratch + cap;
     uint32_t *sub_list = desc + nlong * kDesc;
     hipLaunchKernelGGL(segsort_small, dim3(cus * g_small), dim3(256), 0, sm, offsets, ids, lists, counts + 0);
-    hipLaunchKernelGGL((segsort_mid<128, 8, true, true>), dim3(cus * g_m1), dim3(128), 0, sm, offsets, ids,
+    hipLaunchKernelGGL((segsort_mid<128, 8, true, true, 4>), dim3(cus * g_m1), dim3(128), 0, sm, offsets, ids,
                        lists + nq, counts + 1, range);
-    hipLaunchKernelGGL((segsort_mid<256, 16, false, true>), dim3(cus * g_m2), dim3(256), 0, sm, offsets, ids,
+    hipLaunchKernelGGL((segsort_mid<256, 16, false, true, 4>), dim3(cus * g_m2), dim3(256), 0, sm, offsets, ids,
                        lists + 2 * nq, counts + 2, range);
-    hipLaunchKernelGGL((segsort_mid<1024, 32, false, false>), dim3(cus * g_m4), dim3(1024), 0, sm, offsets, ids,
+    hipLaunchKernelGGL((segsort_mid<1024, 32, false, false, 8>), dim3(cus * g_m4), dim3(1024), 0, sm, offsets, ids,
                        lists + 4 * nq, counts + 4, range);
-    hipLaunchKernelGGL((segsort_mid<512, 32, false, true>), dim3(cus * g_m3), dim3(512), 0, s, offsets, ids,
+    hipLaunchKernelGGL((segsort_mid<512, 32, false, true, 8>), dim3(cus * g_m3), dim3(512), 0, s, offsets, ids,
                        lists + 3 * nq, counts + 3, range);
     hipLaunchKernelGGL(segsort_long<512>, dim3(cus * g_long), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
                        counts + kSubCounts, lists + kLong * nq, counts + kLong, lists + kFallback * nq,
