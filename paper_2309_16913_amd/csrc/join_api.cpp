@@ -5,10 +5,12 @@
 // child pairs, a scan turns the counts into output offsets, the host reads
 // the total, and a fill pass writes the next frontier (or, at the leaves,
 // the (idA << 32 | idB) keys).  The keys are radix sorted into the canonical
-// lexicographic order.  Device buffers are kept across levels and grown
-// geometrically, so a join allocates only a handful of times.
+// lexicographic order.  Device buffers are kept across levels and across
+// calls (a per-device pool of workspaces, grown geometrically), so a join
+// allocates only when it outgrows every earlier one on its device.
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -44,6 +46,38 @@ struct JoinRun {
     uint64_t npairs = 0;
     const uint64_t *sorted = nullptr;   // device, npairs keys
     uint64_t tests = 0;
+};
+
+// Workspaces are pooled per device: a call takes one (or makes one) and
+// returns it when done, after its stream has drained, so concurrent calls
+// never share buffers.  Pooled device memory is held until the process
+// ends (hipFree would stall the device on every call).
+constexpr int kMaxDevices = 64;
+struct JoinPool {
+    std::mutex mu;
+    std::vector<JoinRun *> idle;
+};
+JoinPool g_join_pool[kMaxDevices];
+
+struct PooledRun {
+    int dev;
+    hipStream_t s;
+    JoinRun *w = nullptr;
+    PooledRun(int d, hipStream_t st) : dev(d), s(st) {
+        JoinPool &p = g_join_pool[dev];
+        std::lock_guard<std::mutex> lk(p.mu);
+        if (!p.idle.empty()) {
+            w = p.idle.back();
+            p.idle.pop_back();
+        }
+        if (!w) w = new JoinRun();
+    }
+    ~PooledRun() {
+        (void)hipStreamSynchronize(s);   // nothing of this call may still use the buffers
+        JoinPool &p = g_join_pool[dev];
+        std::lock_guard<std::mutex> lk(p.mu);
+        p.idle.push_back(w);
+    }
 };
 
 // Runs the join up to the sorted keys on the device.
@@ -137,6 +171,7 @@ int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, h
 int check_join_args(const rt_tree *a, const rt_tree *b, int32_t *flags) {
     if (!a || !b) return fail(RT_EINVAL, "tree is NULL");
     if (a->device != b->device) return fail(RT_EINVAL, "trees are on different devices");
+    if (a->device < 0 || a->device >= kMaxDevices) return fail(RT_EINVAL, "device %d out of range", a->device);
     const bool both_sorted = a->sorted_lx && b->sorted_lx;
     // measured fastest: candidate lists with O3 + O5 on sorted trees, else the
     // full tile (candidate lists without pruning cost more than they save)
@@ -166,7 +201,8 @@ extern "C" int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t fl
     try {
         DevSet ds(a->device);
         hipStream_t s = nullptr;
-        JoinRun w;
+        PooledRun run(a->device, s);
+        JoinRun &w = *run.w;
         rc = join_keys(a, b, flags, tests != nullptr, s, w);
         if (rc) return rc;
         if (tests) *tests = w.tests;
@@ -209,7 +245,8 @@ extern "C" int rt_spatial_join_device(const rt_tree *a, const rt_tree *b, int32_
     try {
         DevSet ds(a->device);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        JoinRun w;
+        PooledRun run(a->device, s);
+        JoinRun &w = *run.w;
         rc = join_keys(a, b, flags, false, s, w);
         if (rc) return rc;
         *n_pairs = w.npairs;
