@@ -25,8 +25,6 @@
 //              LDS (class M) or, for class L with a sub-bucket over 4096 ids,
 //              by sorting 16384-id tiles that way and merging runs pairwise
 //              through LDS-staged merge-path windows.
-#include <mutex>
-
 #include "rt_internal.h"
 
 namespace rtk {
@@ -882,40 +880,6 @@ uint64_t segsort_scratch_elems(uint64_t cap) {
     return cap + (cap / (kMidMax + 1) + 1) * (kDesc + kLongDigits);
 }
 
-// The size classes sort disjoint segments, so two chains run side by side:
-// classes S, M1, M2 and M4 (shortest first) on an extra stream per device
-// (default priority), M3 and then class L on the caller's stream, forked and
-// joined with events; the two chains carry about equal work on uniform ids.
-// The fallback kernels (almost always empty, but each block needs 64 KB of
-// LDS to start) run after the join, when the chip is free.  Under stream
-// capture everything stays on the caller's stream.  A wait takes the event's
-// latest record, so each fork and join pair is enqueued under the device's
-// lock: calls from several host threads then never wait on one another's
-// records.
-struct SortStreams {
-    hipStream_t st = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-    std::mutex mu;
-    bool ok = false;
-};
-
-static SortStreams *sort_streams() {
-    static std::mutex mu;
-    static SortStreams per_dev[64];
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
-    std::lock_guard<std::mutex> lk(mu);
-    SortStreams &ss = per_dev[dev];
-    if (!ss.ok) {
-        const bool good = hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) == hipSuccess &&
-                          hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) == hipSuccess &&
-                          hipStreamCreateWithFlags(&ss.st, hipStreamNonBlocking) == hipSuccess;
-        if (!good) return nullptr;   // keep everything on the caller's stream
-        ss.ok = true;
-    }
-    return &ss;
-}
-
 template <typename Kern>
 static uint32_t resident_per_cu(Kern kern, int threads) {
     int n = 0;
@@ -946,45 +910,30 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     hipLaunchKernelGGL(seg_classify, dim3((uint32_t)cg), dim3(256), 0, s, offsets, nq, cap, lists, counts);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-
-    hipStreamCaptureStatus cap_st = hipStreamCaptureStatusNone;
-    (void)hipStreamIsCapturing(s, &cap_st);
-    SortStreams *ss = cap_st == hipStreamCaptureStatusNone ? sort_streams() : nullptr;
-    std::unique_lock<std::mutex> enq;
-    if (ss) enq = std::unique_lock<std::mutex>(ss->mu);
-    hipStream_t sm = s;
-    if (ss) {
-        e = hipEventRecord(ss->fork, s);
-        if (e == hipSuccess) e = hipStreamWaitEvent(ss->st, ss->fork, 0);
-        if (e != hipSuccess) return e;
-        sm = ss->st;
-    }
+    // every class on the caller's stream, shortest first (an extra stream
+    // per call site would take one of the device's few hardware queues from
+    // whatever else the process runs concurrently)
     // after the cap ids of scratch: kDesc words per class-L segment (257
     // sub-bucket starts and the group width), then its work items (at most
     // 256 groups per segment)
     const uint64_t nlong = cap / (kMidMax + 1) + 1;
     uint32_t *desc = scratch + cap;
     uint32_t *sub_list = desc + nlong * kDesc;
-    hipLaunchKernelGGL(segsort_small, dim3(cus * g_small), dim3(256), 0, sm, offsets, ids, lists, counts + 0);
-    hipLaunchKernelGGL((segsort_mid<128, 8, true, true, 4>), dim3(cus * g_m1), dim3(128), 0, sm, offsets, ids,
+    hipLaunchKernelGGL(segsort_small, dim3(cus * g_small), dim3(256), 0, s, offsets, ids, lists, counts + 0);
+    hipLaunchKernelGGL((segsort_mid<128, 8, true, true, 4>), dim3(cus * g_m1), dim3(128), 0, s, offsets, ids,
                        lists + nq, counts + 1, range);
-    hipLaunchKernelGGL((segsort_mid<256, 16, false, true, 4>), dim3(cus * g_m2), dim3(256), 0, sm, offsets, ids,
+    hipLaunchKernelGGL((segsort_mid<256, 16, false, true, 4>), dim3(cus * g_m2), dim3(256), 0, s, offsets, ids,
                        lists + 2 * nq, counts + 2, range);
-    hipLaunchKernelGGL((segsort_mid<1024, 32, false, false, 8>), dim3(cus * g_m4), dim3(1024), 0, sm, offsets, ids,
-                       lists + 4 * nq, counts + 4, range);
     hipLaunchKernelGGL((segsort_mid<512, 32, false, true, 8>), dim3(cus * g_m3), dim3(512), 0, s, offsets, ids,
                        lists + 3 * nq, counts + 3, range);
+    hipLaunchKernelGGL((segsort_mid<1024, 32, false, false, 8>), dim3(cus * g_m4), dim3(1024), 0, s, offsets, ids,
+                       lists + 4 * nq, counts + 4, range);
     hipLaunchKernelGGL(segsort_long<512>, dim3(cus * g_long), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
                        counts + kSubCounts, lists + kLong * nq, counts + kLong, lists + kFallback * nq,
                        counts + kFallback, id_bits);
     hipLaunchKernelGGL(segsort_sub, dim3(cus * g_sub), dim3(256), 0, s, offsets, ids, scratch, desc, sub_list,
                        counts + kSubCounts, lists + kLong * nq, id_bits, range);
-    e = hipGetLastError();
-    if (ss && e == hipSuccess) {
-        e = hipEventRecord(ss->join, ss->st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(s, ss->join, 0);
-    }
-    if (e != hipSuccess) return e;
+    // the fallback kernels: almost always empty
     hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + kFallback * nq,
                        counts + kFallback);
     hipLaunchKernelGGL(segmerge_long, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, scratch, lists + kFallback * nq,
