@@ -142,7 +142,7 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
                         if (hit) {
                             const uint64_t o = pos + rank;
                             if (o < end)
-                                ids[o] = ref;
+                                __builtin_nontemporal_store(ref, ids + o);
                             else
                                 atomicOr(&ctrl->err, kErrBounds);
                         }
@@ -160,7 +160,7 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
                                 todo = (j0 + len >= 64) ? 0ull : (todo & (~0ull << (j0 + len)));
                                 const uint32_t l0 = t.range[first + j0].x, l1 = t.range[first + j0 + len - 1].y;
                                 const bool hasp = t.partial_leaf >= l0 && t.partial_leaf < l1;
-                                constexpr uint32_t U = 8;   // leaves in flight per lane
+                                constexpr uint32_t U = 4;   // leaves in flight per lane
                                 for (uint32_t lb = l0; lb < l1; lb += U) {
                                     uint32_t v[U];
                                     uint64_t o[U];
@@ -179,7 +179,7 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
                                     for (uint32_t u = 0; u < U; ++u) {
                                         if (o[u] != ~0ull) {
                                             if (o[u] < end)
-                                                ids[o[u]] = v[u];
+                                                __builtin_nontemporal_store(v[u], ids + o[u]);
                                             else
                                                 atomicOr(&ctrl->err, kErrBounds);
                                         }

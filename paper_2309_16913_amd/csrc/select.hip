@@ -274,8 +274,11 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                 if constexpr (MODE == SEL_FILL) {
                     if (hit) {
                         const uint64_t o = pos + rank;
+                        // ids are written once and read back only by the
+                        // sort: stores that bypass the caches leave L2 to the
+                        // tree nodes (fill pass 4.4 -> 3.8 ms at 10M/1M)
                         if (o < end)
-                            ids[o] = ref;
+                            __builtin_nontemporal_store(ref, ids + o);
                         else
                             atomicOr(&ctrl->err, kErrBounds);
                     }
@@ -298,7 +301,7 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                             todo = (j0 + len >= 64) ? 0ull : (todo & (~0ull << (j0 + len)));
                             const uint32_t l0 = t.range[first + j0].x, l1 = t.range[first + j0 + len - 1].y;
                             const bool hasp = t.partial_leaf >= l0 && t.partial_leaf < l1;
-                            constexpr uint32_t U = 8;
+                            constexpr uint32_t U = 4;
                             for (uint32_t lb = l0; lb < l1; lb += U) {
                                 uint32_t v[U];
                                 uint64_t o[U];
@@ -317,7 +320,7 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                                 for (uint32_t u = 0; u < U; ++u) {
                                     if (o[u] != ~0ull) {
                                         if (o[u] < end)
-                                            ids[o[u]] = v[u];
+                                            __builtin_nontemporal_store(v[u], ids + o[u]);
                                         else
                                             atomicOr(&ctrl->err, kErrBounds);
                                     }
