@@ -531,7 +531,7 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
 // Class L: two levels.  First (segsort_long, one block per segment) the
 // segment is split by its top 8 id bits into 256 sub-buckets in global
 // scratch: a histogram (per-wave LDS counters, eight loads in flight per
-// thread), a scan, then chunks of 4096
+// thread), a scan, then chunks of 8192
 // ids are counting-sorted by that digit in LDS and written out as contiguous
 // runs, one run per digit and chunk; the 257 sub-bucket starts go to the
 // segment's descriptor.  Then groups of G consecutive sub-buckets (G chosen
@@ -540,7 +540,7 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
 // a sub-bucket over 4096 ids (ids far from uniform, or more than about a
 // million ids) is left as it is and goes to the fallback list.
 constexpr uint32_t kLongDigits = 256;
-constexpr uint32_t kLongChunk = 4096;   // ids per chunk: 1024 threads x 4
+constexpr uint32_t kLongChunk = 8192;   // ids per chunk: 512 threads x 16
 constexpr uint32_t kSubMax = 4096;      // longest sub-bucket sorted by one block
 constexpr uint32_t kDesc = kLongDigits + 2;   // 257 sub-bucket starts, group width
 constexpr uint32_t kSubCounts = 8;      // counter of the group work list (in the class counter block)
