@@ -58,17 +58,19 @@ __device__ __forceinline__ uint32_t ptr_any(const TreeView &t, uint32_t node, ui
 template <int MODE, bool FILL>
 __global__ void __launch_bounds__(256)
 join_level_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t nfr,
-                  uint32_t *__restrict__ counts, const uint64_t *__restrict__ offsets,
-                  uint2 *__restrict__ next, uint64_t *__restrict__ keys, Ctrl *__restrict__ ctrl) {
+                  const uint64_t *__restrict__ nfr_dev, uint32_t *__restrict__ counts,
+                  const uint64_t *__restrict__ offsets, uint2 *__restrict__ next, uint64_t *__restrict__ keys,
+                  uint64_t out_cap, Ctrl *__restrict__ ctrl) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (nfr_dev && *nfr_dev < nfr) nfr = (uint32_t)*nfr_dev;
     if (p >= nfr) return;   // whole wave leaves together
     const uint2 pr = fr[p];
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     uint64_t pos = 0, end = 0;
     if (FILL) {
         pos = offsets[p];
-        end = offsets[p + 1];
+        end = min(offsets[p + 1], out_cap);
     }
     uint32_t total = 0;
 
@@ -91,7 +93,7 @@ join_level_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t
             const uint32_t c = ptr_any(D, node, lane);
             if (o < end)
                 next[o] = (MODE == JOIN_DESC_A) ? make_uint2(c, pr.y) : make_uint2(pr.x, c);
-            else
+            else if (o < out_cap)
                 atomicOr(&ctrl->err, kErrBounds);
         }
     } else {
@@ -119,7 +121,7 @@ join_level_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t
                         keys[o] = ((uint64_t)ca << 32) | cb;
                     else
                         next[o] = make_uint2(ca, cb);
-                } else {
+                } else if (o < out_cap) {
                     atomicOr(&ctrl->err, kErrBounds);
                 }
             }
@@ -175,11 +177,13 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane, ui
 
 template <int MODE, bool FILL, bool O3, int SHRINK>
 __global__ void __launch_bounds__(256)
-join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t nfr, uint32_t *__restrict__ counts,
+join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t nfr,
+                 const uint64_t *__restrict__ nfr_dev, uint32_t *__restrict__ counts,
                  const uint64_t *__restrict__ offsets, uint2 *__restrict__ next, uint64_t *__restrict__ keys,
-                 Ctrl *__restrict__ ctrl, unsigned long long *__restrict__ tests_acc) {
+                 uint64_t out_cap, Ctrl *__restrict__ ctrl, unsigned long long *__restrict__ tests_acc) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (nfr_dev && *nfr_dev < nfr) nfr = (uint32_t)*nfr_dev;
     if (p >= nfr) return;   // whole wave leaves together
     const uint2 pr = fr[p];
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -236,7 +240,7 @@ join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t 
     uint64_t pos = 0, end = 0;
     if (FILL) {
         pos = offsets[p];
-        end = offsets[p + 1];
+        end = min(offsets[p + 1], out_cap);
     }
     uint32_t total = 0;
     for (uint32_t base = 0; base < T; base += 64) {
@@ -261,7 +265,7 @@ join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t 
                     keys[o] = ((uint64_t)ca << 32) | cb;
                 else
                     next[o] = make_uint2(ca, cb);
-            } else {
+            } else if (o < out_cap) {
                 atomicOr(&ctrl->err, kErrBounds);
             }
         }
@@ -275,70 +279,76 @@ join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t 
 }
 
 template <int MODE, bool O3, int SHRINK>
-static hipError_t launch_cand(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr, bool fill,
-                              uint32_t *counts, const uint64_t *offsets, uint2 *next, uint64_t *keys, Ctrl *ctrl,
+static hipError_t launch_cand(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr,
+                              const uint64_t *nfr_dev, bool fill, uint32_t *counts, const uint64_t *offsets,
+                              uint2 *next, uint64_t *keys, uint64_t out_cap, Ctrl *ctrl,
                               unsigned long long *tests_acc, hipStream_t s) {
     const uint32_t blocks = (nfr + 3) / 4;
     if (fill)
         hipLaunchKernelGGL((join_cand_kernel<MODE, true, O3, SHRINK>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr,
-                           counts, offsets, next, keys, ctrl, (unsigned long long *)nullptr);
+                           nfr_dev, counts, offsets, next, keys, out_cap, ctrl, (unsigned long long *)nullptr);
     else
         hipLaunchKernelGGL((join_cand_kernel<MODE, false, O3, SHRINK>), dim3(blocks), dim3(256), 0, s, a, b, fr,
-                           nfr, counts, offsets, next, keys, ctrl, tests_acc);
+                           nfr, nfr_dev, counts, offsets, next, keys, out_cap, ctrl, tests_acc);
     return hipGetLastError();
 }
 
 template <int MODE>
-static hipError_t launch_cand_flags(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr, bool fill,
-                                    uint32_t *counts, const uint64_t *offsets, uint2 *next, uint64_t *keys,
-                                    Ctrl *ctrl, int flags, unsigned long long *ta, hipStream_t s) {
+static hipError_t launch_cand_flags(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr,
+                                    const uint64_t *nd, bool fill, uint32_t *counts, const uint64_t *offsets,
+                                    uint2 *next, uint64_t *keys, uint64_t cap, Ctrl *ctrl, int flags,
+                                    unsigned long long *ta, hipStream_t s) {
     const bool o3 = flags & JOIN_O3;
     const int sh = (flags & JOIN_O5) ? 5 : ((flags & JOIN_O4) ? 4 : 0);
     if (o3) {
-        if (sh == 5) return launch_cand<MODE, true, 5>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
-        if (sh == 4) return launch_cand<MODE, true, 4>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
-        return launch_cand<MODE, true, 0>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
+        if (sh == 5)
+            return launch_cand<MODE, true, 5>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
+        if (sh == 4)
+            return launch_cand<MODE, true, 4>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
+        return launch_cand<MODE, true, 0>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
     }
-    if (sh == 5) return launch_cand<MODE, false, 5>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
-    if (sh == 4) return launch_cand<MODE, false, 4>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
-    return launch_cand<MODE, false, 0>(a, b, fr, nfr, fill, counts, offsets, next, keys, ctrl, ta, s);
+    if (sh == 5)
+        return launch_cand<MODE, false, 5>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
+    if (sh == 4)
+        return launch_cand<MODE, false, 4>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
+    return launch_cand<MODE, false, 0>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
 }
 
 template <int MODE>
-static hipError_t launch_mode(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr, bool fill,
-                              uint32_t *counts, const uint64_t *offsets, uint2 *next, uint64_t *keys,
-                              Ctrl *ctrl, hipStream_t s) {
+static hipError_t launch_mode(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr, const uint64_t *nd,
+                              bool fill, uint32_t *counts, const uint64_t *offsets, uint2 *next, uint64_t *keys,
+                              uint64_t cap, Ctrl *ctrl, hipStream_t s) {
     const uint32_t blocks = (nfr + 3) / 4;
     if (fill)
-        hipLaunchKernelGGL((join_level_kernel<MODE, true>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr, counts,
-                           offsets, next, keys, ctrl);
+        hipLaunchKernelGGL((join_level_kernel<MODE, true>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr, nd, counts,
+                           offsets, next, keys, cap, ctrl);
     else
-        hipLaunchKernelGGL((join_level_kernel<MODE, false>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr,
-                           counts, offsets, next, keys, ctrl);
+        hipLaunchKernelGGL((join_level_kernel<MODE, false>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr, nd,
+                           counts, offsets, next, keys, cap, ctrl);
     return hipGetLastError();
 }
 
 hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *frontier, uint32_t nfr,
-                             int mode, bool fill, uint32_t *counts, const uint64_t *offsets, uint2 *next,
-                             uint64_t *keys, Ctrl *ctrl, int flags, unsigned long long *tests_acc,
-                             hipStream_t s) {
+                             const uint64_t *nd, int mode, bool fill, uint32_t *counts, const uint64_t *offsets,
+                             uint2 *next, uint64_t *keys, uint64_t cap, Ctrl *ctrl, int flags,
+                             unsigned long long *tests_acc, hipStream_t s) {
     if (nfr == 0) return hipSuccess;
     if (!(flags & JOIN_TILE) && (mode == JOIN_BOTH || mode == JOIN_EMIT)) {
         if (mode == JOIN_BOTH)
-            return launch_cand_flags<JOIN_BOTH>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, flags,
-                                                tests_acc, s);
-        return launch_cand_flags<JOIN_EMIT>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, flags,
-                                            tests_acc, s);
+            return launch_cand_flags<JOIN_BOTH>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl,
+                                                flags, tests_acc, s);
+        return launch_cand_flags<JOIN_EMIT>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl,
+                                            flags, tests_acc, s);
     }
     switch (mode) {
     case JOIN_BOTH:
-        return launch_mode<JOIN_BOTH>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, s);
+        return launch_mode<JOIN_BOTH>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, s);
     case JOIN_EMIT:
-        return launch_mode<JOIN_EMIT>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, s);
+        return launch_mode<JOIN_EMIT>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, s);
     case JOIN_DESC_A:
-        return launch_mode<JOIN_DESC_A>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, s);
+        return launch_mode<JOIN_DESC_A>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, s);
     default:
-        return launch_mode<JOIN_DESC_B>(a, b, frontier, nfr, fill, counts, offsets, next, keys, ctrl, s);
+        return launch_mode<JOIN_DESC_B>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, s);
     }
 }
 

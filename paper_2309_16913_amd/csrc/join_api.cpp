@@ -42,10 +42,13 @@ struct Grow {
 };
 
 struct JoinRun {
-    Grow ctrl, fr[2], cnt, off, stmp, keys, ktmp, hist, hscan, rtmp, tacc;
+    Grow ctrl, fr[2], cnt, off, stmp, keys, ktmp, hist, hscan, rtmp, tacc, lvl;
     uint64_t npairs = 0;
     const uint64_t *sorted = nullptr;   // device, npairs keys
     uint64_t tests = 0;
+    // frontier size of every level in the last join run level by level with
+    // host reads (empty: none yet); sizes the grids of the replayed levels
+    std::vector<uint64_t> last_levels;
 };
 
 // Workspaces are pooled per device: a call takes one (or makes one) and
@@ -80,10 +83,122 @@ struct PooledRun {
     }
 };
 
+// Sorts the total keys in w.keys into the canonical order (only the digits
+// that can be nonzero).
+int sort_keys(const rt_tree *a, const rt_tree *b, uint64_t total, hipStream_t s, JoinRun &w) {
+    int shifts[16], np = 0;
+    const int bb = bits_for(b->n_objects ? b->n_objects - 1 : 0);
+    const int ba = bits_for(a->n_objects ? a->n_objects - 1 : 0);
+    for (int sft = 0; sft < bb; sft += 8) shifts[np++] = sft;
+    for (int sft = 32; sft < 32 + ba; sft += 8) shifts[np++] = sft;
+    const uint64_t he = radix_hist_elems(total);
+    hipError_t e = w.ktmp.need(total * 8);
+    if (e == hipSuccess) e = w.hist.need(he * 4);
+    if (e == hipSuccess) e = w.hscan.need((he + 1) * 8);
+    if (e == hipSuccess) e = w.rtmp.need(scan_tmp_elems(he) * 8);
+    bool in_tmp = false;
+    if (e == hipSuccess)
+        e = launch_radix_sort_u64(w.keys.as<uint64_t>(), w.ktmp.as<uint64_t>(), total, shifts, np,
+                                  w.hist.as<uint32_t>(), w.hscan.as<uint64_t>(), w.rtmp.as<uint64_t>(), &in_tmp, s);
+    if (e != hipSuccess) return hip_fail(e, "join sort");
+    w.npairs = total;
+    w.sorted = in_tmp ? w.ktmp.as<uint64_t>() : w.keys.as<uint64_t>();
+    return RT_OK;
+}
+
+constexpr int kReplayMiss = -1000;   // not an RT_ code: the replay did not fit, run level by level
+
+inline int mode_of(int la, int lb) {
+    return la > lb ? JOIN_DESC_A : (lb > la ? JOIN_DESC_B : (la == 0 ? JOIN_EMIT : JOIN_BOTH));
+}
+
+inline void descend(int mode, int &la, int &lb) {
+    if (mode == JOIN_DESC_A) --la;
+    else if (mode == JOIN_DESC_B) --lb;
+    else { --la; --lb; }
+}
+
+// The levels of the last run replayed without host reads: each level's
+// frontier size stays on the device (the scan writes it, clamped to what the
+// next level's buffers and grid allow), grids are sized from the last run's
+// level sizes plus slack, and the host reads only the key count at the end.
+// A level that outgrew those bounds marks the run, which then returns
+// kReplayMiss (the caller runs level by level, growing the buffers).
+int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t s, JoinRun &w) {
+    const std::vector<uint64_t> rec = w.last_levels;
+    const size_t H = rec.size();
+    if (H == 0) return kReplayMiss;
+    const TreeView va = view_of(a), vb = view_of(b);
+    hipError_t e = w.lvl.need((H + 2) * 8);
+    if (e != hipSuccess) return hip_fail(e, "join setup");
+    uint64_t *lv = w.lvl.as<uint64_t>();                      // lv[L]: size of level L (L >= 1); lv[H]: keys
+    uint32_t *over = reinterpret_cast<uint32_t *>(lv + H + 1);
+    Ctrl *ctrl = w.ctrl.as<Ctrl>();
+    // frontier pairs a level can hold in fr[k] and the per-level buffers
+    auto level_cap = [&](int k) {
+        uint64_t c = w.fr[k].cap / 8;
+        c = std::min(c, w.cnt.cap / 4);
+        c = std::min(c, w.off.cap / 8 ? w.off.cap / 8 - 1 : 0);
+        const uint64_t st = w.stmp.cap / 8;
+        c = std::min(c, st > 1 ? (st - 1) * scan_tile_elems() : 0);
+        return std::min<uint64_t>(c, 0xFFFFFFFFull);
+    };
+    auto with_slack = [](uint64_t n) { return n + n / 4 + 1024; };
+    e = launch_zero(ctrl, sizeof(Ctrl), s);
+    if (e == hipSuccess) e = launch_zero(lv, (H + 2) * 8, s);   // and the overflow flag
+    if (e == hipSuccess) e = launch_zero(w.fr[0].b.p, 8, s);   // (root A, root B) = (0, 0)
+    if (e != hipSuccess) return hip_fail(e, "join setup");
+    int la = (int)a->height - 1, lb = (int)b->height - 1;
+    int cur = 0;
+    uint64_t lim = 1;   // level 0: the pair of roots
+    for (size_t L = 0; L < H; ++L) {
+        const int mode = mode_of(la, lb);
+        const bool emit = mode == JOIN_EMIT;
+        if (emit != (L + 1 == H)) return kReplayMiss;   // not the shape of the last run
+        if (lim == 0) return kReplayMiss;
+        const uint64_t next_lim =
+            emit ? w.keys.cap / 8 : std::min<uint64_t>(with_slack(rec[L + 1]), level_cap(1 - cur));
+        const uint64_t *nd = L == 0 ? nullptr : lv + L;
+        const uint2 *fr = w.fr[cur].as<uint2>();
+        uint64_t *off = w.off.as<uint64_t>();
+        e = launch_join_level(va, vb, fr, (uint32_t)lim, nd, mode, false, w.cnt.as<uint32_t>(), nullptr, nullptr,
+                              nullptr, 0, ctrl, flags, nullptr, s);
+        if (e == hipSuccess)
+            e = launch_scan_u32_dev(w.cnt.as<uint32_t>(), nd, lim, off, w.stmp.as<uint64_t>(), lv + L + 1,
+                                    next_lim, over, s);
+        if (e == hipSuccess)
+            e = launch_join_level(va, vb, fr, (uint32_t)lim, nd, mode, true, nullptr, off,
+                                  emit ? nullptr : w.fr[1 - cur].as<uint2>(), emit ? w.keys.as<uint64_t>() : nullptr,
+                                  next_lim, ctrl, flags, nullptr, s);
+        if (e != hipSuccess) return hip_fail(e, "join level");
+        cur = 1 - cur;
+        lim = next_lim;
+        descend(mode, la, lb);
+    }
+    uint64_t tail[2] = {0, 0};   // key count, overflow flag
+    uint32_t err = 0;
+    e = hipMemcpyAsync(tail, lv + H, 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&err, &ctrl->err, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "join status");
+    if (err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", err);
+    if (tail[1] & 1u) return kReplayMiss;
+    w.npairs = 0;
+    w.sorted = nullptr;
+    w.tests = 0;
+    return tail[0] ? sort_keys(a, b, tail[0], s, w) : RT_OK;
+}
+
 // Runs the join up to the sorted keys on the device.
 int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, hipStream_t s, JoinRun &w) {
-    const TreeView va = view_of(a), vb = view_of(b);
     hipError_t e = w.ctrl.need(sizeof(Ctrl));
+    if (e != hipSuccess) return hip_fail(e, "join setup");
+    if (!count_tests) {
+        const int rc = join_keys_replay(a, b, flags, s, w);
+        if (rc != kReplayMiss) return rc;
+    }
+    // level by level, each level's size read on the host
+    const TreeView va = view_of(a), vb = view_of(b);
     if (e == hipSuccess) e = w.fr[0].need(8);
     if (e == hipSuccess && count_tests) e = w.tacc.need(kTestSlots * 16 * 8);
     if (e != hipSuccess) return hip_fail(e, "join setup");
@@ -98,16 +213,18 @@ int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, h
     int la = (int)a->height - 1, lb = (int)b->height - 1;
     w.npairs = 0;
     w.sorted = nullptr;
+    std::vector<uint64_t> levels;
     while (nfr) {
-        const int mode = la > lb ? JOIN_DESC_A : (lb > la ? JOIN_DESC_B : (la == 0 ? JOIN_EMIT : JOIN_BOTH));
+        levels.push_back(nfr);
+        const int mode = mode_of(la, lb);
         e = w.cnt.need(nfr * 4);
         if (e == hipSuccess) e = w.off.need((nfr + 1) * 8);
         if (e == hipSuccess) e = w.stmp.need(scan_tmp_elems(nfr) * 8);
         if (e != hipSuccess) return hip_fail(e, "join frontier");
         const uint2 *fr = w.fr[cur].as<uint2>();
         uint64_t *off = w.off.as<uint64_t>();
-        e = launch_join_level(va, vb, fr, (uint32_t)nfr, mode, false, w.cnt.as<uint32_t>(), nullptr, nullptr,
-                              nullptr, ctrl, flags, tacc, s);
+        e = launch_join_level(va, vb, fr, (uint32_t)nfr, nullptr, mode, false, w.cnt.as<uint32_t>(), nullptr,
+                              nullptr, nullptr, 0, ctrl, flags, tacc, s);
         if (e == hipSuccess) e = launch_scan_u32(w.cnt.as<uint32_t>(), nfr, off, w.stmp.as<uint64_t>(), s);
         uint64_t total = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&total, off + nfr, 8, hipMemcpyDeviceToHost, s);
@@ -117,47 +234,29 @@ int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, h
         if (mode == JOIN_EMIT) {
             e = w.keys.need(total * 8);
             if (e == hipSuccess)
-                e = launch_join_level(va, vb, fr, (uint32_t)nfr, mode, true, nullptr, off, nullptr,
-                                      w.keys.as<uint64_t>(), ctrl, flags, nullptr, s);
+                e = launch_join_level(va, vb, fr, (uint32_t)nfr, nullptr, mode, true, nullptr, off, nullptr,
+                                      w.keys.as<uint64_t>(), total, ctrl, flags, nullptr, s);
             if (e != hipSuccess) return hip_fail(e, "join emit");
-            // canonical order: sort only the digits that can be nonzero
-            int shifts[16], np = 0;
-            const int bb = bits_for(b->n_objects ? b->n_objects - 1 : 0);
-            const int ba = bits_for(a->n_objects ? a->n_objects - 1 : 0);
-            for (int sft = 0; sft < bb; sft += 8) shifts[np++] = sft;
-            for (int sft = 32; sft < 32 + ba; sft += 8) shifts[np++] = sft;
-            const uint64_t he = radix_hist_elems(total);
-            e = w.ktmp.need(total * 8);
-            if (e == hipSuccess) e = w.hist.need(he * 4);
-            if (e == hipSuccess) e = w.hscan.need((he + 1) * 8);
-            if (e == hipSuccess) e = w.rtmp.need(scan_tmp_elems(he) * 8);
-            bool in_tmp = false;
-            if (e == hipSuccess)
-                e = launch_radix_sort_u64(w.keys.as<uint64_t>(), w.ktmp.as<uint64_t>(), total, shifts, np,
-                                          w.hist.as<uint32_t>(), w.hscan.as<uint64_t>(), w.rtmp.as<uint64_t>(),
-                                          &in_tmp, s);
-            if (e != hipSuccess) return hip_fail(e, "join sort");
-            w.npairs = total;
-            w.sorted = in_tmp ? w.ktmp.as<uint64_t>() : w.keys.as<uint64_t>();
+            const int rc = sort_keys(a, b, total, s, w);
+            if (rc) return rc;
             break;
         }
         if (total >= 0xFFFFFFFFull) return fail(RT_ENOMEM, "join frontier too large");
         e = w.fr[1 - cur].need(total * 8);
         if (e == hipSuccess)
-            e = launch_join_level(va, vb, fr, (uint32_t)nfr, mode, true, nullptr, off, w.fr[1 - cur].as<uint2>(),
-                                  nullptr, ctrl, flags, nullptr, s);
+            e = launch_join_level(va, vb, fr, (uint32_t)nfr, nullptr, mode, true, nullptr, off,
+                                  w.fr[1 - cur].as<uint2>(), nullptr, total, ctrl, flags, nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "join expand");
         cur = 1 - cur;
         nfr = total;
-        if (mode == JOIN_DESC_A) --la;
-        else if (mode == JOIN_DESC_B) --lb;
-        else { --la; --lb; }
+        descend(mode, la, lb);
     }
     Ctrl hc;
     e = hipMemcpyAsync(&hc, ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "join status");
     if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
+    w.last_levels = levels;
     w.tests = 0;
     if (tacc) {
         std::vector<unsigned long long> h(kTestSlots * 16);

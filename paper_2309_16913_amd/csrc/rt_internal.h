@@ -121,8 +121,14 @@ constexpr uint32_t kOrderMinQueries = 8192;   // smaller batches keep input orde
 // Exclusive scan of n uint32 into n+1 uint64 (out[n] = total).  tmp needs
 // scan_tmp_elems(n) uint64.
 uint64_t scan_tmp_elems(uint64_t n);
+uint64_t scan_tile_elems();   // elements per scan tile: scan_tmp_elems(n) = ceil(n / that) + 1
 hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp,
                            hipStream_t s);
+// The same with the count on the device: *n_dev <= n_max elements (tmp needs
+// scan_tmp_elems(n_max)).  If next is not NULL, min(total, next_cap) is stored
+// in *next and *over gets bit 0 when the total exceeds next_cap.
+hipError_t launch_scan_u32_dev(const uint32_t *in, const uint64_t *n_dev, uint64_t n_max, uint64_t *out,
+                               uint64_t *tmp, uint64_t *next, uint64_t next_cap, uint32_t *over, hipStream_t s);
 
 // Sort every CSR segment ascending.  scratch: segsort_scratch_elems(capacity)
 // uint32 (segments longer than one LDS tile are bucketed through it); ws:
@@ -165,9 +171,12 @@ enum JoinFlags : int { JOIN_O3 = 1, JOIN_O4 = 2, JOIN_O5 = 4, JOIN_TILE = 8 };
 // candidate kernels adds the number of pair predicates it evaluates to
 // tests_acc[(pair % kTestSlots) * 16]; the sum over the slots is the total.
 constexpr uint32_t kTestSlots = 256;
+// nfr_dev (if not NULL): the frontier size on the device, at most nfr (the
+// grid is sized for nfr).  The fill pass writes no output index at or past
+// out_cap (the caller detects that case from the scan's total).
 hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *frontier,
-                             uint32_t nfr, int mode, bool fill, uint32_t *counts,
-                             const uint64_t *offsets, uint2 *next, uint64_t *keys, Ctrl *ctrl,
+                             uint32_t nfr, const uint64_t *nfr_dev, int mode, bool fill, uint32_t *counts,
+                             const uint64_t *offsets, uint2 *next, uint64_t *keys, uint64_t out_cap, Ctrl *ctrl,
                              int flags, unsigned long long *tests_acc, hipStream_t s);
 hipError_t launch_keys_to_pairs(const uint64_t *keys, uint64_t n, uint32_t *pairs, hipStream_t s);
 

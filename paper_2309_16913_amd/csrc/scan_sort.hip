@@ -45,8 +45,12 @@ __device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *total)
 constexpr uint32_t kScanPer = 8;                 // elements per thread
 constexpr uint32_t kScanTile = 256 * kScanPer;   // elements per block
 
+// n_dev (if not NULL) holds the element count on the device, at most the n
+// the grid was sized for.
 __global__ void __launch_bounds__(256) scan_tile_sums(const uint32_t *__restrict__ in, uint64_t n,
+                                                      const uint64_t *__restrict__ n_dev,
                                                       uint64_t *__restrict__ sums) {
+    if (n_dev) n = min(n, *n_dev);
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
     uint64_t s = 0;
 #pragma unroll
@@ -71,9 +75,16 @@ __global__ void __launch_bounds__(256) scan_sums(uint64_t *__restrict__ sums, ui
     }
 }
 
+// With n_dev, the block holding element n - 1 (block 0 for n = 0) writes
+// out[n]; with next (not NULL) it also stores min(total, next_cap) there and
+// sets *over when the total exceeds next_cap.
 __global__ void __launch_bounds__(256) scan_tiles(const uint32_t *__restrict__ in, uint64_t n,
+                                                  const uint64_t *__restrict__ n_dev,
                                                   const uint64_t *__restrict__ sums,
-                                                  uint64_t *__restrict__ out) {
+                                                  uint64_t *__restrict__ out, uint64_t *__restrict__ next,
+                                                  uint64_t next_cap, uint32_t *__restrict__ over) {
+    const bool dev = n_dev != nullptr;
+    if (dev) n = min(n, *n_dev);
     const uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
     uint32_t v[kScanPer];
     uint64_t s = 0;
@@ -89,12 +100,21 @@ __global__ void __launch_bounds__(256) scan_tiles(const uint32_t *__restrict__ i
         if (base + k < n) out[base + k] = run;
         run += v[k];
     }
-    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 255) out[n] = sums[blockIdx.x] + tot;
+    const uint64_t last = dev ? (n ? (n - 1) / kScanTile : 0) : gridDim.x - 1;
+    if (blockIdx.x == last && threadIdx.x == 255) {
+        const uint64_t total = sums[blockIdx.x] + tot;
+        out[n] = total;
+        if (next) {
+            next[0] = total < next_cap ? total : next_cap;
+            if (total > next_cap) atomicOr(over, 1u);
+        }
+    }
 }
 
 __global__ void write_zero_total(uint64_t *out) { out[0] = 0; }
 
 uint64_t scan_tmp_elems(uint64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+uint64_t scan_tile_elems() { return kScanTile; }
 
 hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, uint64_t *out, uint64_t *tmp, hipStream_t s) {
     if (n == 0) {
@@ -102,9 +122,20 @@ hipError_t launch_scan_u32(const uint32_t *in, uint64_t n, uint64_t *out, uint64
         return hipGetLastError();
     }
     const uint64_t nt = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(scan_tile_sums, dim3((uint32_t)nt), dim3(256), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(scan_tile_sums, dim3((uint32_t)nt), dim3(256), 0, s, in, n, (const uint64_t *)nullptr, tmp);
     hipLaunchKernelGGL(scan_sums, dim3(1), dim3(256), 0, s, tmp, nt);
-    hipLaunchKernelGGL(scan_tiles, dim3((uint32_t)nt), dim3(256), 0, s, in, n, tmp, out);
+    hipLaunchKernelGGL(scan_tiles, dim3((uint32_t)nt), dim3(256), 0, s, in, n, (const uint64_t *)nullptr, tmp, out,
+                       (uint64_t *)nullptr, (uint64_t)0, (uint32_t *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_u32_dev(const uint32_t *in, const uint64_t *n_dev, uint64_t n_max, uint64_t *out,
+                               uint64_t *tmp, uint64_t *next, uint64_t next_cap, uint32_t *over, hipStream_t s) {
+    const uint64_t nt = n_max ? (n_max + kScanTile - 1) / kScanTile : 1;
+    hipLaunchKernelGGL(scan_tile_sums, dim3((uint32_t)nt), dim3(256), 0, s, in, n_max, n_dev, tmp);
+    hipLaunchKernelGGL(scan_sums, dim3(1), dim3(256), 0, s, tmp, nt);
+    hipLaunchKernelGGL(scan_tiles, dim3((uint32_t)nt), dim3(256), 0, s, in, n_max, n_dev, tmp, out, next, next_cap,
+                       over);
     return hipGetLastError();
 }
 

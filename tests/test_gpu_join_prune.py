@@ -147,3 +147,28 @@ def test_join_device_output(rt, ora):
     # empty relation
     te = rt.build_str(np.zeros((0, 4), np.float32), 16)
     assert rt.spatial_join_device(te, ta, 0, 0) == 0
+
+
+def test_join_workspace_reuse(rt, ora):
+    """Joins run in a sequence reuse one pooled workspace: a repeated join
+    replays its levels with the sizes kept on the device, a smaller one
+    replays inside the larger buffers, a larger one (or one with another
+    level structure) outgrows them and runs level by level.  Every result
+    equals the oracle's."""
+    cases = [("big", 60_000, 32, 41), ("big again", 60_000, 32, 41), ("small", 3_000, 32, 42),
+             ("larger", 120_000, 32, 43), ("other shape", 20_000, 8, 44), ("big last", 60_000, 32, 41)]
+    for name, n, F, seed in cases:
+        say(f"case workspace reuse {name} n={n} F={F}")
+        A = rtgen.uniform_rects(n, 2e-3, seed)
+        B = rtgen.clustered_rects(n, 16, 0.05, 2e-3, seed + 100)
+        want = ora.join(ora.build_str(A, 16), ora.build_str(B, 16))
+        ta = rt.build_str(A, F, "soa", sort_lx=True)
+        tb = rt.build_str(B, F, "soa", sort_lx=True)
+        assert np.array_equal(rt.spatial_join(ta, tb), want), name
+        import torch
+        m = rt.spatial_join_device(ta, tb, 0, 0)
+        assert m == want.shape[0], name
+        buf = torch.empty(2 * max(m, 1), dtype=torch.int32, device="cuda")
+        assert rt.spatial_join_device(ta, tb, buf.data_ptr(), m) == m
+        got = buf[:2 * m].cpu().numpy().view(np.uint32).reshape(-1, 2)
+        assert np.array_equal(got, want), name
