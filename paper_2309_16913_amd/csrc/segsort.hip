@@ -19,10 +19,11 @@
 //   class L    (> 32768)        one block per segment: an MSD pass on the top
 //              8 id bits into global scratch (chunks digit-sorted in LDS and
 //              written as runs), then groups of consecutive sub-buckets
-//              (<= 4096 ids each) sorted back by one block each;
+//              (<= 4096 ids each, or <= 32768 when a sub-bucket holds more)
+//              sorted back by one block each;
 //   fallback   a segment with a bucket too long for the in-bucket ranking
 //              (ids far from uniform) is sorted by a block bitonic network in
-//              LDS (class M) or, for class L with a sub-bucket over 4096 ids,
+//              LDS (class M) or, for class L with a sub-bucket over 32768 ids,
 //              by sorting 16384-id tiles that way and merging runs pairwise
 //              through LDS-staged merge-path windows.
 #include "rt_internal.h"
@@ -541,14 +542,16 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
 // million ids) is left as it is and goes to the fallback list.
 constexpr uint32_t kLongDigits = 256;
 constexpr uint32_t kLongChunk = 8192;   // ids per chunk: 512 threads x 16
-constexpr uint32_t kSubMax = 4096;      // longest sub-bucket sorted by one block
+constexpr uint32_t kSubMax = 4096;      // longest group sorted by a 256-thread block
+constexpr uint32_t kSubBigMax = 32768;  // longest group sorted by a 1024-thread block
 constexpr uint32_t kDesc = kLongDigits + 2;   // 257 sub-bucket starts, group width
-constexpr uint32_t kSubCounts = 8;      // counter of the group work list (in the class counter block)
+constexpr uint32_t kSubCounts = 8;      // counters of the two group work lists (in the class counter block)
 
 template <int T>
 __global__ void __launch_bounds__(T)
 segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint32_t *__restrict__ scratch,
-             uint32_t *__restrict__ desc, uint32_t *__restrict__ sub_lists, uint32_t *__restrict__ sub_counts,
+             uint32_t *__restrict__ desc, uint32_t *__restrict__ sub_lists, uint32_t *__restrict__ sub_lists_wide,
+             uint32_t *__restrict__ sub_counts,
              const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_count,
              uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, int id_bits) {
     constexpr uint32_t W = T / 64, R = kLongChunk / T;
@@ -617,23 +620,26 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
             if (lane == 0) big = mx;
         }
         __syncthreads();
-        if (big > kSubMax) {   // leave the segment to the fallback
+        if (big > kSubBigMax) {   // leave the segment to the fallback
             if (t == 0) fb_list[atomicAdd(fb_count, 1u)] = q;
             __syncthreads();
             continue;
         }
         // sub-bucket groups for the block sorts: G consecutive digits each,
-        // G = kSubMax / (largest digit count), so a group never exceeds
-        // kSubMax ids; work items are li << 8 | group
-        const uint32_t G = kSubMax / (big ? big : 1u);
+        // G = (group limit) / (largest digit count), so a group never exceeds
+        // the limit: kSubMax ids for the 256-thread sort, or, when a digit
+        // holds more (segments of about a million ids), kSubBigMax for the
+        // 1024-thread sort (its own list); work items are li << 8 | group
+        const bool wide = big > kSubMax;
+        const uint32_t G = (wide ? kSubBigMax : kSubMax) / (big ? big : 1u);
         const uint32_t ngroups = (kLongDigits + G - 1) / G;
         for (uint32_t d = t; d <= kLongDigits; d += T) dsc[d] = start[d];
         if (t == 0) {
             dsc[kLongDigits + 1] = G;
-            subbase[0] = atomicAdd(&sub_counts[0], ngroups);
+            subbase[0] = atomicAdd(&sub_counts[wide ? 1 : 0], ngroups);
         }
         __syncthreads();
-        if (t < ngroups) sub_lists[subbase[0] + t] = (li << 8) | t;
+        if (t < ngroups) (wide ? sub_lists_wide : sub_lists)[subbase[0] + t] = (li << 8) | t;
         // chunks, digit-sorted in LDS, written out as runs
         for (uint32_t base = 0; base < c; base += kLongChunk) {
             const uint32_t len = (c - base) < kLongChunk ? (c - base) : kLongChunk;
@@ -687,18 +693,25 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
     }
 }
 
-// Groups of sub-buckets (<= kSubMax ids, digits [gG, gG + G)): one block
-// each, sorted from scratch into place; the ids of a group lie in
-// [gG << sh, (gG + G) << sh).  The next group's ids are loaded before the
-// current one is sorted.
-__global__ void __launch_bounds__(256, 6)   // as the 256-thread class-M blocks
+// Groups of sub-buckets (digits [gG, gG + G)): one block each, sorted from
+// scratch into place; the ids of a group lie in [gG << sh, (gG + G) << sh).
+// Two shapes: 256 x 16 for groups of at most kSubMax ids, 1024 x 32 for the
+// groups of segments whose digits hold more.  With PF the next group's ids
+// are loaded before the current one is sorted.
+template <int T, int K>
+constexpr int sub_waves_per_simd() {
+    return T == 256 ? 6 : 4;
+}
+
+template <int T, int K, int A, bool PF>
+__global__ void __launch_bounds__(T, (sub_waves_per_simd<T, K>()))
 segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ scratch,
             const uint32_t *__restrict__ desc, const uint32_t *__restrict__ items,
             const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list, int id_bits,
             uint32_t id_range) {
-    constexpr uint32_t T = 256, K = kSubMax / T;
-    __shared__ uint32_t buf[T * K];
-    __shared__ uint32_t cnt[T * K / 4];
+    constexpr uint32_t N = T * K;
+    __shared__ uint32_t buf[N];
+    __shared__ uint32_t cnt[N / A];
     __shared__ uint32_t wsum[2 * (T / 64)];
     const uint32_t m = *item_count;
     const int db = id_bits < 8 ? id_bits : 8;
@@ -721,22 +734,31 @@ segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
         r.range = (uint32_t)((hi < id_range ? hi : (uint64_t)id_range) - r.base);
         return r;
     };
-    uint32_t nkey[K];
-    Grp nx{0, 0, 0, 1};
-    if (blockIdx.x < m) {
-        nx = group(blockIdx.x);
-        load_keys<T, K>(scratch + nx.o, nx.n, nkey);
-    }
-    for (uint32_t k = blockIdx.x; k < m; k += gridDim.x) {
-        uint32_t key[K];
-#pragma unroll
-        for (int r = 0; r < (int)K; ++r) key[r] = nkey[r];
-        const Grp cu = nx;
-        if (k + gridDim.x < m) {
-            nx = group(k + gridDim.x);
+    if constexpr (PF) {
+        uint32_t nkey[K];
+        Grp nx{0, 0, 0, 1};
+        if (blockIdx.x < m) {
+            nx = group(blockIdx.x);
             load_keys<T, K>(scratch + nx.o, nx.n, nkey);
         }
-        block_sort_keys<T, K>(key, ids + cu.o, cu.n, cu.range, buf, cnt, wsum, cu.base);
+        for (uint32_t k = blockIdx.x; k < m; k += gridDim.x) {
+            uint32_t key[K];
+#pragma unroll
+            for (int r = 0; r < (int)K; ++r) key[r] = nkey[r];
+            const Grp cu = nx;
+            if (k + gridDim.x < m) {
+                nx = group(k + gridDim.x);
+                load_keys<T, K>(scratch + nx.o, nx.n, nkey);
+            }
+            block_sort_keys<T, K, false, A>(key, ids + cu.o, cu.n, cu.range, buf, cnt, wsum, cu.base);
+        }
+    } else {
+        for (uint32_t k = blockIdx.x; k < m; k += gridDim.x) {
+            const Grp cu = group(k);
+            uint32_t key[K];
+            load_keys<T, K>(scratch + cu.o, cu.n, key);
+            block_sort_keys<T, K, false, A>(key, ids + cu.o, cu.n, cu.range, buf, cnt, wsum, cu.base);
+        }
     }
 }
 
@@ -875,9 +897,9 @@ segmerge_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, 
 uint64_t segsort_ws_elems(uint64_t nq) { return (uint64_t)kListCls * nq + 64; }
 
 // cap ids, then for each possible class-L segment (> kMidMax ids) its
-// descriptor and up to 256 work items
+// descriptor, then two lists with room for 256 work items per segment
 uint64_t segsort_scratch_elems(uint64_t cap) {
-    return cap + (cap / (kMidMax + 1) + 1) * (kDesc + kLongDigits);
+    return cap + (cap / (kMidMax + 1) + 1) * (kDesc + 2 * kLongDigits);
 }
 
 template <typename Kern>
@@ -903,7 +925,8 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     static const uint32_t g_m3 = resident_per_cu(segsort_mid<512, 32, false, true, 8>, 512);
     static const uint32_t g_m4 = resident_per_cu(segsort_mid<1024, 32, false, false, 8>, 1024);
     static const uint32_t g_long = resident_per_cu(segsort_long<512>, 512);
-    static const uint32_t g_sub = resident_per_cu(segsort_sub, 256);
+    static const uint32_t g_sub = resident_per_cu(segsort_sub<256, 16, 4, true>, 256);
+    static const uint32_t g_subw = resident_per_cu(segsort_sub<1024, 32, 8, false>, 1024);
     hipError_t e = launch_zero(counts, 64 * 4, s);
     if (e != hipSuccess) return e;
     const uint64_t cg = (nq + kClsTile - 1) / kClsTile;
@@ -919,6 +942,7 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     const uint64_t nlong = cap / (kMidMax + 1) + 1;
     uint32_t *desc = scratch + cap;
     uint32_t *sub_list = desc + nlong * kDesc;
+    uint32_t *sub_list_wide = sub_list + nlong * kLongDigits;
     hipLaunchKernelGGL(segsort_small, dim3(cus * g_small), dim3(256), 0, s, offsets, ids, lists, counts + 0);
     hipLaunchKernelGGL((segsort_mid<128, 8, true, true, 4>), dim3(cus * g_m1), dim3(128), 0, s, offsets, ids,
                        lists + nq, counts + 1, range);
@@ -929,10 +953,12 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     hipLaunchKernelGGL((segsort_mid<1024, 32, false, false, 8>), dim3(cus * g_m4), dim3(1024), 0, s, offsets, ids,
                        lists + 4 * nq, counts + 4, range);
     hipLaunchKernelGGL(segsort_long<512>, dim3(cus * g_long), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
-                       counts + kSubCounts, lists + kLong * nq, counts + kLong, lists + kFallback * nq,
+                       sub_list_wide, counts + kSubCounts, lists + kLong * nq, counts + kLong, lists + kFallback * nq,
                        counts + kFallback, id_bits);
-    hipLaunchKernelGGL(segsort_sub, dim3(cus * g_sub), dim3(256), 0, s, offsets, ids, scratch, desc, sub_list,
-                       counts + kSubCounts, lists + kLong * nq, id_bits, range);
+    hipLaunchKernelGGL((segsort_sub<256, 16, 4, true>), dim3(cus * g_sub), dim3(256), 0, s, offsets, ids, scratch,
+                       desc, sub_list, counts + kSubCounts, lists + kLong * nq, id_bits, range);
+    hipLaunchKernelGGL((segsort_sub<1024, 32, 8, false>), dim3(cus * g_subw), dim3(1024), 0, s, offsets, ids,
+                       scratch, desc, sub_list_wide, counts + kSubCounts + 1, lists + kLong * nq, id_bits, range);
     // the fallback kernels: almost always empty
     hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + kFallback * nq,
                        counts + kFallback);

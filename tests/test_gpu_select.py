@@ -137,8 +137,8 @@ def test_lookahead_parity(rt, ora):
 
 def test_select_all_windows(rt):
     """64 windows covering all 2M rectangles: 2M-id segments, whose
-    sub-buckets exceed one block tile, take the sort's tile-and-merge
-    fallback; every window gets every id, ascending."""
+    sub-buckets hold 8192 ids each, sorted by the wide (1024 x 32) group
+    sorts; every window gets every id, ascending."""
     n = 2_000_000
     r = rtgen.uniform_rects(n, 1e-4, 55)
     t = rt.build_str(r, 16, "soa")
@@ -292,3 +292,26 @@ def test_select_split_mapping(rt, ora, kmin, fanout, layout):
         got = rt.range_select(t, q)
         want = ora.select(ora.build_str(r, fanout), q)
         assert_csr_equal(got, want, f"split kmin={kmin} F={fanout} {layout} nq={nq}")
+
+
+def test_sort_dense_id_runs(rt):
+    """9M points on a 4096-wide grid, numbered row by row, and windows over
+    whole rows: each result is one run of consecutive ids (known in closed
+    form).  The top-8-bit sub-buckets of such class-L segments hold up to
+    65536 ids: runs that split into two halves of 24576 take the wide
+    (1024 x 32) group sorts, longer ones the tile-and-merge fallback."""
+    W, rows = 4096, 2198
+    n = W * rows
+    i = np.arange(n, dtype=np.int64)
+    x = (i % W).astype(np.float32)
+    y = (i // W).astype(np.float32)
+    r = np.stack([x, y, x, y], axis=1)
+    # (first row, rows): ids [first * W, (first + rows) * W)
+    runs = [(250, 12), (0, 10), (250, 17), (700, 74), (1200, 489)]
+    q = np.array([[-0.5, f - 0.5, W - 0.5, f + k - 0.5] for f, k in runs], np.float32)
+    say("case dense id runs")
+    t = rt.build_str(r, 32, "soa")
+    off, ids = rt.range_select(t, q)
+    assert np.array_equal(np.diff(off.astype(np.int64)), [k * W for _, k in runs])
+    for j, (f, k) in enumerate(runs):
+        assert np.array_equal(ids[off[j]:off[j + 1]], np.arange(f * W, (f + k) * W, dtype=np.uint32)), (f, k)
