@@ -31,6 +31,7 @@ struct rt_batch {
     void *d_trees = nullptr, *d_items = nullptr, *d_q = nullptr, *d_counts = nullptr, *d_off = nullptr;
     void *d_ids = nullptr, *d_scratch = nullptr, *d_ctrl = nullptr, *d_scan = nullptr, *d_status = nullptr;
     void *d_plain_off = nullptr, *d_lists = nullptr;
+    void *d_qrange = nullptr;   // per query: its tree's object count (the bound of its ids)
     uint64_t id_range = 0;   // largest object count of the batch's trees
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -42,7 +43,8 @@ void rtk::batch_release(rt_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     void *bufs[] = {b->d_trees, b->d_items, b->d_q,    b->d_counts, b->d_off,       b->d_ids,
-                    b->d_scratch, b->d_ctrl, b->d_scan, b->d_status, b->d_plain_off, b->d_lists};
+                    b->d_scratch, b->d_ctrl, b->d_scan, b->d_status, b->d_plain_off, b->d_lists,
+                    b->d_qrange};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     b->~rt_batch();
@@ -75,7 +77,7 @@ static hipError_t enqueue_all(rt_batch *b, hipStream_t s) {
     if (e == hipSuccess)
         e = launch_segsort(static_cast<uint64_t *>(b->d_off), b->total_q, static_cast<uint32_t *>(b->d_ids),
                            static_cast<uint32_t *>(b->d_scratch), b->cap, static_cast<uint32_t *>(b->d_lists),
-                           b->id_range, s);
+                           b->id_range, static_cast<const uint32_t *>(b->d_qrange), s);
     if (e == hipSuccess)
         e = launch_finalize(static_cast<uint64_t *>(b->d_off), b->total_q, b->cap, ctrl,
                             static_cast<uint64_t *>(b->d_status), s);
@@ -119,6 +121,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         };
         std::vector<Cand> cand;
         std::vector<float> hq((size_t)total * 4);
+        std::vector<uint32_t> hrange((size_t)total);
         uint64_t qb = 0;
         for (uint32_t i = 0; i < ntrees; ++i) {
             const rt_tree *t = trees[i];
@@ -131,6 +134,8 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
             const uint32_t G = group_width(t->fanout);
             b->wave_words = std::max(b->wave_words, (64 / G) * bt[i].stack_cap);
             if (nq[i]) std::memcpy(hq.data() + 4 * qb, queries[i], nq[i] * 16);
+            std::fill(hrange.begin() + qb, hrange.begin() + qb + nq[i],
+                      (uint32_t)std::min<uint64_t>(t->n_objects, 0xFFFFFFFFull));
             // chunks of 8 queries per group; cost ~ expected hits + per-query path length
             const uint32_t chunk = 8 * (64 / G);
             const double area_scale = (double)t->n_objects;
@@ -161,6 +166,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         if (e == hipSuccess) e = dmalloc(&b->d_scan, scan_tmp_elems(std::max<uint64_t>(total, 1)) * 8);
         if (e == hipSuccess) e = dmalloc(&b->d_status, 16);
         if (e == hipSuccess) e = dmalloc(&b->d_lists, segsort_ws_elems(std::max<uint64_t>(total, 1)) * 4);
+        if (e == hipSuccess) e = dmalloc(&b->d_qrange, std::max<uint64_t>(total, 1) * 4);
         uint64_t plain_total = 0;
         b->plain_begin.resize(ntrees);
         for (uint32_t i = 0; i < ntrees; ++i) {
@@ -172,6 +178,8 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         if (e == hipSuccess && !items.empty())
             e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice);
         if (e == hipSuccess && total) e = hipMemcpy(b->d_q, hq.data(), total * 16, hipMemcpyHostToDevice);
+        if (e == hipSuccess && total)
+            e = hipMemcpy(b->d_qrange, hrange.data(), total * 4, hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(hip_fail(e, "batch setup"));
 
         // one eager count pass: output size and the per-instance bases
@@ -247,7 +255,7 @@ extern "C" int rt_batch_run_plain(rt_batch *b, void *stream) {
                                    (uint32_t)n, s);
         if (e == hipSuccess)
             e = launch_segsort(off, n, ids + base, scratch + base, cap, static_cast<uint32_t *>(b->d_lists),
-                               b->trees[i]->n_objects, s);
+                               b->trees[i]->n_objects, nullptr, s);
     }
     return e == hipSuccess ? RT_OK : hip_fail(e, "plain batch launches");
 }

@@ -392,7 +392,7 @@ int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, u
         e = launch_select_pass(v, dq, (uint32_t)nq, SEL_FILL, nullptr, fo, d_ids, cap, w.ctrl, 1, plan, no, s);
         if (e == hipSuccess) e = mark(3);
         if (e == hipSuccess)
-            e = launch_segsort(d_off, nq, d_ids, w.scratch, cap, w.lists, t->n_objects, s);
+            e = launch_segsort(d_off, nq, d_ids, w.scratch, cap, w.lists, t->n_objects, nullptr, s);
         if (e == hipSuccess) e = mark(4);
         if (e == hipSuccess && d_status) e = launch_finalize(d_off, nq, cap, w.ctrl, d_status, s);
         if (e != hipSuccess) return hip_fail(e, "fill stage");

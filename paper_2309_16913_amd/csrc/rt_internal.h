@@ -133,12 +133,14 @@ hipError_t launch_scan_u32_dev(const uint32_t *in, const uint64_t *n_dev, uint64
 // Sort every CSR segment ascending.  scratch: segsort_scratch_elems(capacity)
 // uint32 (segments longer than one LDS tile are bucketed through it); ws:
 // segsort_ws_elems(nq) uint32;
-// id_range: every id is below it (the object count).  Skips all work if
-// offsets[nq] > capacity.
+// id_range: every id is below it (the object count); seg_range (NULL, or nq
+// entries): the bound of each segment's ids when segments come from trees of
+// different sizes.  Skips all work if offsets[nq] > capacity.
 uint64_t segsort_ws_elems(uint64_t nq);
 uint64_t segsort_scratch_elems(uint64_t capacity);
 hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch,
-                          uint64_t capacity, uint32_t *ws, uint64_t id_range, hipStream_t s);
+                          uint64_t capacity, uint32_t *ws, uint64_t id_range, const uint32_t *seg_range,
+                          hipStream_t s);
 inline int id_bits_for(uint64_t n_objects) {
     int b = 0;
     const uint64_t m = n_objects ? n_objects - 1 : 0;

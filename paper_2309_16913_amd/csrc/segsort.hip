@@ -38,6 +38,17 @@ constexpr uint32_t kLong = 5;
 constexpr uint32_t kFallback = 6;           // fallback-L list
 constexpr uint32_t kListCls = 7;
 
+// Significant bits of the largest id below range (0 for range <= 1).
+__device__ __forceinline__ int range_bits(uint32_t range) {
+    return range > 1 ? 32 - __clz((int)(range - 1)) : 0;
+}
+
+// The id range of segment q: its own (seg_range, when given per segment) or
+// the common one.
+__device__ __forceinline__ uint32_t seg_id_range(const uint32_t *seg_range, uint32_t q, uint32_t id_range) {
+    return seg_range ? seg_range[q] : id_range;
+}
+
 __device__ __forceinline__ uint32_t ceil_log2(uint32_t v) {
     uint32_t b = 0;
     while (b < 31 && (1u << b) < v) ++b;
@@ -485,7 +496,7 @@ constexpr int mid_waves_per_simd() {
 template <int T, int K, bool PLACE, bool PF, int A>
 __global__ void __launch_bounds__(T, (mid_waves_per_simd<T, K>()))
 segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
-            const uint32_t *__restrict__ list_count, uint32_t id_range) {
+            const uint32_t *__restrict__ list_count, uint32_t id_range, const uint32_t *__restrict__ seg_range) {
     constexpr uint32_t N = T * K;
     // keys, then the bucket counters; the scan's per-wave sums use the head
     // of buf, which holds nothing while the counters are scanned
@@ -495,11 +506,12 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
     if constexpr (PF) {
         uint32_t nkey[K];
         uint64_t no = 0;
-        uint32_t nc = 0;
+        uint32_t nc = 0, nr = id_range;
         if (blockIdx.x < m) {
             const uint32_t q = list[blockIdx.x];
             no = offsets[q];
             nc = (uint32_t)(offsets[q + 1] - no);
+            nr = seg_id_range(seg_range, q, id_range);
             load_keys<T, K>(ids + no, nc, nkey);
         }
         for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
@@ -507,15 +519,16 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
 #pragma unroll
             for (int k = 0; k < K; ++k) key[k] = nkey[k];
             const uint64_t o = no;
-            const uint32_t c = nc;
+            const uint32_t c = nc, rng = nr;
             const uint32_t ln = li + gridDim.x;
             if (ln < m) {   // segments are disjoint: this read never meets the writes below
                 const uint32_t q = list[ln];
                 no = offsets[q];
                 nc = (uint32_t)(offsets[q + 1] - no);
+                nr = seg_id_range(seg_range, q, id_range);
                 load_keys<T, K>(ids + no, nc, nkey);
             }
-            block_sort_keys<T, K, PLACE, A>(key, ids + o, c, id_range, buf, cnt, wsum);
+            block_sort_keys<T, K, PLACE, A>(key, ids + o, c, rng, buf, cnt, wsum);
         }
     } else {
         for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
@@ -524,7 +537,7 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
             const uint32_t c = (uint32_t)(offsets[q + 1] - o);
             uint32_t key[K];
             load_keys<T, K>(ids + o, c, key);
-            block_sort_keys<T, K, PLACE, A>(key, ids + o, c, id_range, buf, cnt, wsum);
+            block_sort_keys<T, K, PLACE, A>(key, ids + o, c, seg_id_range(seg_range, q, id_range), buf, cnt, wsum);
         }
     }
 }
@@ -553,7 +566,8 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
              uint32_t *__restrict__ desc, uint32_t *__restrict__ sub_lists, uint32_t *__restrict__ sub_lists_wide,
              uint32_t *__restrict__ sub_counts,
              const uint32_t *__restrict__ list, const uint32_t *__restrict__ list_count,
-             uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, int id_bits) {
+             uint32_t *__restrict__ fb_list, uint32_t *__restrict__ fb_count, uint32_t id_range,
+             const uint32_t *__restrict__ seg_range) {
     constexpr uint32_t W = T / 64, R = kLongChunk / T;
     static_assert(T >= kLongDigits, "one thread per digit");
     __shared__ uint32_t whist[W * kLongDigits];   // per-wave digit counts
@@ -564,11 +578,12 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
     __shared__ uint32_t big, subbase[1];
     const uint32_t m = *list_count;
     const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
-    const int db = id_bits < 8 ? id_bits : 8;
-    const int sh = id_bits - db;
-    const uint32_t dmask = (1u << db) - 1u;
     for (uint32_t li = blockIdx.x; li < m; li += gridDim.x) {
         const uint32_t q = list[li];
+        const int id_bits = range_bits(seg_id_range(seg_range, q, id_range));
+        const int db = id_bits < 8 ? id_bits : 8;
+        const int sh = id_bits - db;
+        const uint32_t dmask = (1u << db) - 1u;
         const uint64_t o = offsets[q];
         const uint32_t c = (uint32_t)(offsets[q + 1] - o);
         const uint32_t *seg = ids + o;
@@ -707,15 +722,13 @@ template <int T, int K, int A, bool PF>
 __global__ void __launch_bounds__(T, (sub_waves_per_simd<T, K>()))
 segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ scratch,
             const uint32_t *__restrict__ desc, const uint32_t *__restrict__ items,
-            const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list, int id_bits,
-            uint32_t id_range) {
+            const uint32_t *__restrict__ item_count, const uint32_t *__restrict__ list, uint32_t id_range,
+            const uint32_t *__restrict__ seg_range) {
     constexpr uint32_t N = T * K;
     __shared__ uint32_t buf[N];
     __shared__ uint32_t cnt[N / A];
     __shared__ uint32_t wsum[2 * (T / 64)];
     const uint32_t m = *item_count;
-    const int db = id_bits < 8 ? id_bits : 8;
-    const int sh = id_bits - db;
     struct Grp {
         uint64_t o;
         uint32_t n, base, range;
@@ -726,12 +739,16 @@ segsort_sub(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
         const uint32_t G = dsc[kLongDigits + 1];
         const uint32_t d0 = g * G, d1 = (d0 + G) < kLongDigits ? (d0 + G) : kLongDigits;
         const uint32_t s0 = dsc[d0];
+        const uint32_t q = list[li];
+        const uint32_t rng = seg_id_range(seg_range, q, id_range);
+        const int id_bits = range_bits(rng);
+        const int sh = id_bits - (id_bits < 8 ? id_bits : 8);
         Grp r;
-        r.o = offsets[list[li]] + s0;
+        r.o = offsets[q] + s0;
         r.n = dsc[d1] - s0;
-        r.base = d0 << sh;   // ids of digits [d0, d1): [d0 << sh, d1 << sh) within [0, id_range)
+        r.base = d0 << sh;   // ids of digits [d0, d1): [d0 << sh, d1 << sh) within [0, rng)
         const uint64_t hi = (uint64_t)d1 << sh;
-        r.range = (uint32_t)((hi < id_range ? hi : (uint64_t)id_range) - r.base);
+        r.range = (uint32_t)((hi < rng ? hi : (uint64_t)rng) - r.base);
         return r;
     };
     if constexpr (PF) {
@@ -910,9 +927,8 @@ static uint32_t resident_per_cu(Kern kern, int threads) {
 }
 
 hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, uint32_t *scratch, uint64_t cap,
-                          uint32_t *ws, uint64_t id_range, hipStream_t s) {
+                          uint32_t *ws, uint64_t id_range, const uint32_t *seg_range, hipStream_t s) {
     if (nq == 0) return hipSuccess;
-    const int id_bits = id_bits_for(id_range);
     const uint32_t range = (uint32_t)(id_range < 0xFFFFFFFFull ? id_range : 0xFFFFFFFFull);
     uint32_t *counts = ws;            // class counters
     uint32_t *lists = ws + 64;        // kListCls lists of up to nq query indices
@@ -945,20 +961,20 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     uint32_t *sub_list_wide = sub_list + nlong * kLongDigits;
     hipLaunchKernelGGL(segsort_small, dim3(cus * g_small), dim3(256), 0, s, offsets, ids, lists, counts + 0);
     hipLaunchKernelGGL((segsort_mid<128, 8, true, true, 4>), dim3(cus * g_m1), dim3(128), 0, s, offsets, ids,
-                       lists + nq, counts + 1, range);
+                       lists + nq, counts + 1, range, seg_range);
     hipLaunchKernelGGL((segsort_mid<256, 16, false, true, 4>), dim3(cus * g_m2), dim3(256), 0, s, offsets, ids,
-                       lists + 2 * nq, counts + 2, range);
+                       lists + 2 * nq, counts + 2, range, seg_range);
     hipLaunchKernelGGL((segsort_mid<512, 32, false, true, 8>), dim3(cus * g_m3), dim3(512), 0, s, offsets, ids,
-                       lists + 3 * nq, counts + 3, range);
+                       lists + 3 * nq, counts + 3, range, seg_range);
     hipLaunchKernelGGL((segsort_mid<1024, 32, false, false, 8>), dim3(cus * g_m4), dim3(1024), 0, s, offsets, ids,
-                       lists + 4 * nq, counts + 4, range);
+                       lists + 4 * nq, counts + 4, range, seg_range);
     hipLaunchKernelGGL(segsort_long<512>, dim3(cus * g_long), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
                        sub_list_wide, counts + kSubCounts, lists + kLong * nq, counts + kLong, lists + kFallback * nq,
-                       counts + kFallback, id_bits);
+                       counts + kFallback, range, seg_range);
     hipLaunchKernelGGL((segsort_sub<256, 16, 4, true>), dim3(cus * g_sub), dim3(256), 0, s, offsets, ids, scratch,
-                       desc, sub_list, counts + kSubCounts, lists + kLong * nq, id_bits, range);
+                       desc, sub_list, counts + kSubCounts, lists + kLong * nq, range, seg_range);
     hipLaunchKernelGGL((segsort_sub<1024, 32, 8, false>), dim3(cus * g_subw), dim3(1024), 0, s, offsets, ids,
-                       scratch, desc, sub_list_wide, counts + kSubCounts + 1, lists + kLong * nq, id_bits, range);
+                       scratch, desc, sub_list_wide, counts + kSubCounts + 1, lists + kLong * nq, range, seg_range);
     // the fallback kernels: almost always empty
     hipLaunchKernelGGL(segsort_tiles, dim3(cus * 2), dim3(1024), 0, s, offsets, ids, lists + kFallback * nq,
                        counts + kFallback);
