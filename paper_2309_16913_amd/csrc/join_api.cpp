@@ -86,12 +86,15 @@ struct PooledRun {
 // Sorts the total keys in w.keys into the canonical order (only the digits
 // that can be nonzero).
 int sort_keys(const rt_tree *a, const rt_tree *b, uint64_t total, hipStream_t s, JoinRun &w) {
+    // 11-bit digits: 4 passes for two 21-bit ids instead of 6 (each pass
+    // costs about the same few launches whatever its width)
+    constexpr int kDigit = 11;
     int shifts[16], np = 0;
     const int bb = bits_for(b->n_objects ? b->n_objects - 1 : 0);
     const int ba = bits_for(a->n_objects ? a->n_objects - 1 : 0);
-    for (int sft = 0; sft < bb; sft += 8) shifts[np++] = sft;
-    for (int sft = 32; sft < 32 + ba; sft += 8) shifts[np++] = sft;
-    const uint64_t he = radix_hist_elems(total);
+    for (int sft = 0; sft < bb; sft += kDigit) shifts[np++] = sft;
+    for (int sft = 32; sft < 32 + ba; sft += kDigit) shifts[np++] = sft;
+    const uint64_t he = radix_hist_elems(total, kDigit);
     hipError_t e = w.ktmp.need(total * 8);
     if (e == hipSuccess) e = w.hist.need(he * 4);
     if (e == hipSuccess) e = w.hscan.need((he + 1) * 8);
@@ -99,7 +102,8 @@ int sort_keys(const rt_tree *a, const rt_tree *b, uint64_t total, hipStream_t s,
     bool in_tmp = false;
     if (e == hipSuccess)
         e = launch_radix_sort_u64(w.keys.as<uint64_t>(), w.ktmp.as<uint64_t>(), total, shifts, np,
-                                  w.hist.as<uint32_t>(), w.hscan.as<uint64_t>(), w.rtmp.as<uint64_t>(), &in_tmp, s);
+                                  w.hist.as<uint32_t>(), w.hscan.as<uint64_t>(), w.rtmp.as<uint64_t>(), &in_tmp, s,
+                                  kDigit);
     if (e != hipSuccess) return hip_fail(e, "join sort");
     w.npairs = total;
     w.sorted = in_tmp ? w.ktmp.as<uint64_t>() : w.keys.as<uint64_t>();

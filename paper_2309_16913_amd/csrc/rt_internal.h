@@ -148,14 +148,14 @@ inline int id_bits_for(uint64_t n_objects) {
     return b;
 }
 
-// LSD radix sort of n uint64 keys over the listed 8-bit digit positions.
-// Result ends in keys (if even number of passes) or tmp; returns which via
-// *in_tmp.  hist needs radix_hist_elems(n) uint32, hscan radix_hist_elems+1
-// uint64 plus scan_tmp_elems of it.
-uint64_t radix_hist_elems(uint64_t n);
+// LSD radix sort of n uint64 keys over the listed digit positions, digits of
+// digit_bits (8 or 11) bits.  Result ends in keys (if even number of passes)
+// or tmp; returns which via *in_tmp.  hist needs radix_hist_elems(n,
+// digit_bits) uint32, hscan that + 1 uint64 plus scan_tmp_elems of it.
+uint64_t radix_hist_elems(uint64_t n, int digit_bits = 8);
 hipError_t launch_radix_sort_u64(uint64_t *keys, uint64_t *tmp, uint64_t n, const int *shifts,
                                  int npasses, uint32_t *hist, uint64_t *hscan, uint64_t *stmp,
-                                 bool *in_tmp, hipStream_t s);
+                                 bool *in_tmp, hipStream_t s, int digit_bits = 8);
 
 // Status finalizer: status[0] = offsets[nq], status[1] = flags.
 hipError_t launch_finalize(const uint64_t *offsets, uint64_t nq, uint64_t capacity,

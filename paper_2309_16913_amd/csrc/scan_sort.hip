@@ -174,39 +174,46 @@ hipError_t launch_finalize(const uint64_t *offsets, uint64_t nq, uint64_t cap, c
 }
 
 // ---------------------------------------------------------------------------
-// LSD radix sort of uint64 keys (8-bit digits)
+// LSD radix sort of uint64 keys (8- or 11-bit digits)
 // ---------------------------------------------------------------------------
 constexpr uint32_t kRadixPer = 16;                    // keys per lane
 constexpr uint32_t kRadixWaveKeys = 64 * kRadixPer;   // 1024
 constexpr uint32_t kRadixTile = 4 * kRadixWaveKeys;   // 4096 per block
 
-uint64_t radix_hist_elems(uint64_t n) {
+uint64_t radix_hist_elems(uint64_t n, int digit_bits) {
     const uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
-    return nb * 256;
+    return nb << digit_bits;
 }
 
 // hist[digit * nblocks + block]
+template <int DB>
 __global__ void __launch_bounds__(256) radix_hist(const uint64_t *__restrict__ keys, uint64_t n, int shift,
                                                   uint32_t *__restrict__ hist) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    constexpr uint32_t D = 1u << DB;
+    __shared__ uint32_t h[D];
+    for (uint32_t d = threadIdx.x; d < D; d += 256) h[d] = 0;
     __syncthreads();
     const uint64_t base = (uint64_t)blockIdx.x * kRadixTile;
     for (uint32_t k = threadIdx.x; k < kRadixTile; k += 256) {
         const uint64_t i = base + k;
-        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (D - 1)], 1u);
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+    for (uint32_t d = threadIdx.x; d < D; d += 256) hist[(uint64_t)d * gridDim.x + blockIdx.x] = h[d];
 }
 
+// Stable within a block: a key's rank among the equal digits of its wave
+// comes from DB ballots (one per digit bit), the waves' counts are added in
+// wave order.
+template <int DB>
 __global__ void __launch_bounds__(256) radix_scatter(const uint64_t *__restrict__ in, uint64_t n, int shift,
                                                      const uint64_t *__restrict__ hscan,
                                                      uint64_t *__restrict__ out) {
-    __shared__ uint32_t wcnt[4][256];
-    __shared__ uint64_t dbase[256];
+    constexpr uint32_t D = 1u << DB;
+    __shared__ uint32_t wcnt[4][D];
+    __shared__ uint64_t dbase[D];
     const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
-    for (uint32_t d = threadIdx.x; d < 256; d += 256) {
+    for (uint32_t d = threadIdx.x; d < D; d += 256) {
         for (int i = 0; i < 4; ++i) wcnt[i][d] = 0;
         dbase[d] = hscan[(uint64_t)d * gridDim.x + blockIdx.x];
     }
@@ -220,10 +227,10 @@ __global__ void __launch_bounds__(256) radix_scatter(const uint64_t *__restrict_
         const uint64_t i = base + (uint64_t)k * 64 + lane;
         const bool ok = i < n;
         key[k] = ok ? in[i] : 0ull;
-        const uint32_t dg = (uint32_t)(key[k] >> shift) & 255u;
+        const uint32_t dg = (uint32_t)(key[k] >> shift) & (D - 1);
         uint64_t peers = __ballot(ok);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < DB; ++b) {
             const uint64_t bb = __ballot((dg >> b) & 1u);
             peers &= ((dg >> b) & 1u) ? bb : ~bb;
         }
@@ -241,7 +248,7 @@ __global__ void __launch_bounds__(256) radix_scatter(const uint64_t *__restrict_
     for (uint32_t k = 0; k < kRadixPer; ++k) {
         const uint64_t i = base + (uint64_t)k * 64 + lane;
         if (i < n) {
-            const uint32_t dg = (uint32_t)(key[k] >> shift) & 255u;
+            const uint32_t dg = (uint32_t)(key[k] >> shift) & (D - 1);
             uint64_t o = dbase[dg];
             for (uint32_t ww = 0; ww < w; ++ww) o += wcnt[ww][dg];
             out[o + pos[k]] = key[k];
@@ -249,24 +256,32 @@ __global__ void __launch_bounds__(256) radix_scatter(const uint64_t *__restrict_
     }
 }
 
-hipError_t launch_radix_sort_u64(uint64_t *keys, uint64_t *tmp, uint64_t n, const int *shifts, int npasses,
-                                 uint32_t *hist, uint64_t *hscan, uint64_t *stmp, bool *in_tmp,
-                                 hipStream_t s) {
-    *in_tmp = false;
-    if (n < 2 || npasses == 0) return hipSuccess;
+template <int DB>
+static hipError_t radix_passes(uint64_t *keys, uint64_t *tmp, uint64_t n, const int *shifts, int npasses,
+                               uint32_t *hist, uint64_t *hscan, uint64_t *stmp, bool *in_tmp, hipStream_t s) {
     const uint64_t nb = (n + kRadixTile - 1) / kRadixTile;
     uint64_t *src = keys, *dst = tmp;
     for (int p = 0; p < npasses; ++p) {
-        hipLaunchKernelGGL(radix_hist, dim3((uint32_t)nb), dim3(256), 0, s, src, n, shifts[p], hist);
-        hipError_t e = launch_scan_u32(hist, nb * 256, hscan, stmp, s);
+        hipLaunchKernelGGL(radix_hist<DB>, dim3((uint32_t)nb), dim3(256), 0, s, src, n, shifts[p], hist);
+        hipError_t e = launch_scan_u32(hist, nb << DB, hscan, stmp, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(radix_scatter, dim3((uint32_t)nb), dim3(256), 0, s, src, n, shifts[p], hscan, dst);
+        hipLaunchKernelGGL(radix_scatter<DB>, dim3((uint32_t)nb), dim3(256), 0, s, src, n, shifts[p], hscan, dst);
         uint64_t *t = src;
         src = dst;
         dst = t;
     }
     *in_tmp = (src == tmp);
     return hipGetLastError();
+}
+
+hipError_t launch_radix_sort_u64(uint64_t *keys, uint64_t *tmp, uint64_t n, const int *shifts, int npasses,
+                                 uint32_t *hist, uint64_t *hscan, uint64_t *stmp, bool *in_tmp, hipStream_t s,
+                                 int digit_bits) {
+    *in_tmp = false;
+    if (n < 2 || npasses == 0) return hipSuccess;
+    if (digit_bits == 11) return radix_passes<11>(keys, tmp, n, shifts, npasses, hist, hscan, stmp, in_tmp, s);
+    if (digit_bits != 8) return hipErrorInvalidValue;
+    return radix_passes<8>(keys, tmp, n, shifts, npasses, hist, hscan, stmp, in_tmp, s);
 }
 
 }  // namespace rtk
