@@ -23,6 +23,9 @@
 
 namespace rtk {
 
+constexpr uint32_t kSlotHits = 15;     // hit records kept per pair by the count pass
+constexpr uint32_t kSlotStride = 16;   // uint16 per pair (32 bytes)
+
 __device__ __forceinline__ void load_any(const TreeView &t, uint32_t node, uint32_t e, float &lx, float &ly,
                                          float &hx, float &hy) {
     const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
@@ -175,18 +178,40 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane, ui
     return inc - v;
 }
 
+// slots (if not NULL): kSlotHits hit records (i << 8 | j) per pair, written
+// by the count pass; the fill pass of a pair with at most that many hits
+// takes its children from there instead of testing the candidates again.
 template <int MODE, bool FILL, bool O3, int SHRINK>
 __global__ void __launch_bounds__(256)
 join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t nfr,
                  const uint64_t *__restrict__ nfr_dev, uint32_t *__restrict__ counts,
                  const uint64_t *__restrict__ offsets, uint2 *__restrict__ next, uint64_t *__restrict__ keys,
-                 uint64_t out_cap, Ctrl *__restrict__ ctrl, unsigned long long *__restrict__ tests_acc) {
+                 uint64_t out_cap, uint16_t *__restrict__ slots, Ctrl *__restrict__ ctrl,
+                 unsigned long long *__restrict__ tests_acc) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t p = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (nfr_dev && *nfr_dev < nfr) nfr = (uint32_t)*nfr_dev;
     if (p >= nfr) return;   // whole wave leaves together
     const uint2 pr = fr[p];
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    if (FILL && slots) {
+        const uint64_t pos = offsets[p], end = min(offsets[p + 1], out_cap);
+        const uint64_t n = offsets[p + 1] - pos;
+        if (n <= kSlotHits) {   // wave-uniform
+            if (lane < n) {
+                const uint32_t h = slots[(uint64_t)p * kSlotStride + lane];
+                const uint32_t ca = ptr_any(A, pr.x, h >> 8), cb = ptr_any(B, pr.y, h & 255u);
+                const uint64_t o = pos + lane;
+                if (o < end) {
+                    if (MODE == JOIN_EMIT)
+                        keys[o] = ((uint64_t)ca << 32) | cb;
+                    else
+                        next[o] = make_uint2(ca, cb);
+                }
+            }
+            return;
+        }
+    }
     float alx = NAN, aly = NAN, ahx = NAN, ahy = NAN, blx = NAN, bly = NAN, bhx = NAN, bhy = NAN;
     if (lane < A.fanout) load_any(A, pr.x, lane, alx, aly, ahx, ahy);
     if (lane < B.fanout) load_any(B, pr.y, lane, blx, bly, bhx, bhy);
@@ -257,6 +282,10 @@ join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t 
         const float ihx = __shfl(bhx, (int)j), ihy = __shfl(bhy, (int)j);
         const bool hit = t < T && (olx <= ihx) && (ilx <= ohx) && (oly <= ihy) && (ily <= ohy);
         const uint64_t m = __ballot(hit);
+        if (!FILL && slots && hit) {
+            const uint32_t r = total + (uint32_t)__popcll(m & below);
+            if (r < kSlotHits) slots[(uint64_t)p * kSlotStride + r] = (uint16_t)((i << 8) | j);
+        }
         if (FILL && hit) {
             const uint64_t o = pos + total + (uint64_t)__popcll(m & below);
             const uint32_t ca = ptr_any(A, pr.x, i), cb = ptr_any(B, pr.y, j);
@@ -281,37 +310,40 @@ join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t 
 template <int MODE, bool O3, int SHRINK>
 static hipError_t launch_cand(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr,
                               const uint64_t *nfr_dev, bool fill, uint32_t *counts, const uint64_t *offsets,
-                              uint2 *next, uint64_t *keys, uint64_t out_cap, Ctrl *ctrl,
+                              uint2 *next, uint64_t *keys, uint64_t out_cap, uint16_t *slots, Ctrl *ctrl,
                               unsigned long long *tests_acc, hipStream_t s) {
     const uint32_t blocks = (nfr + 3) / 4;
     if (fill)
         hipLaunchKernelGGL((join_cand_kernel<MODE, true, O3, SHRINK>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr,
-                           nfr_dev, counts, offsets, next, keys, out_cap, ctrl, (unsigned long long *)nullptr);
+                           nfr_dev, counts, offsets, next, keys, out_cap, slots, ctrl,
+                           (unsigned long long *)nullptr);
     else
         hipLaunchKernelGGL((join_cand_kernel<MODE, false, O3, SHRINK>), dim3(blocks), dim3(256), 0, s, a, b, fr,
-                           nfr, nfr_dev, counts, offsets, next, keys, out_cap, ctrl, tests_acc);
+                           nfr, nfr_dev, counts, offsets, next, keys, out_cap, slots, ctrl, tests_acc);
     return hipGetLastError();
 }
 
 template <int MODE>
 static hipError_t launch_cand_flags(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr,
                                     const uint64_t *nd, bool fill, uint32_t *counts, const uint64_t *offsets,
-                                    uint2 *next, uint64_t *keys, uint64_t cap, Ctrl *ctrl, int flags,
+                                    uint2 *next, uint64_t *keys, uint64_t cap, uint16_t *sl, Ctrl *ctrl, int flags,
                                     unsigned long long *ta, hipStream_t s) {
     const bool o3 = flags & JOIN_O3;
     const int sh = (flags & JOIN_O5) ? 5 : ((flags & JOIN_O4) ? 4 : 0);
     if (o3) {
         if (sh == 5)
-            return launch_cand<MODE, true, 5>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
+            return launch_cand<MODE, true, 5>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, sl, ctrl, ta,
+                                              s);
         if (sh == 4)
-            return launch_cand<MODE, true, 4>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
-        return launch_cand<MODE, true, 0>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
+            return launch_cand<MODE, true, 4>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, sl, ctrl, ta,
+                                              s);
+        return launch_cand<MODE, true, 0>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, sl, ctrl, ta, s);
     }
     if (sh == 5)
-        return launch_cand<MODE, false, 5>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
+        return launch_cand<MODE, false, 5>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, sl, ctrl, ta, s);
     if (sh == 4)
-        return launch_cand<MODE, false, 4>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
-    return launch_cand<MODE, false, 0>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, ta, s);
+        return launch_cand<MODE, false, 4>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, sl, ctrl, ta, s);
+    return launch_cand<MODE, false, 0>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, sl, ctrl, ta, s);
 }
 
 template <int MODE>
@@ -330,15 +362,15 @@ static hipError_t launch_mode(const TreeView &a, const TreeView &b, const uint2 
 
 hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *frontier, uint32_t nfr,
                              const uint64_t *nd, int mode, bool fill, uint32_t *counts, const uint64_t *offsets,
-                             uint2 *next, uint64_t *keys, uint64_t cap, Ctrl *ctrl, int flags,
+                             uint2 *next, uint64_t *keys, uint64_t cap, uint16_t *slots, Ctrl *ctrl, int flags,
                              unsigned long long *tests_acc, hipStream_t s) {
     if (nfr == 0) return hipSuccess;
     if (!(flags & JOIN_TILE) && (mode == JOIN_BOTH || mode == JOIN_EMIT)) {
         if (mode == JOIN_BOTH)
-            return launch_cand_flags<JOIN_BOTH>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl,
-                                                flags, tests_acc, s);
-        return launch_cand_flags<JOIN_EMIT>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl,
-                                            flags, tests_acc, s);
+            return launch_cand_flags<JOIN_BOTH>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap,
+                                                slots, ctrl, flags, tests_acc, s);
+        return launch_cand_flags<JOIN_EMIT>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, slots,
+                                            ctrl, flags, tests_acc, s);
     }
     switch (mode) {
     case JOIN_BOTH:
@@ -351,6 +383,8 @@ hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *
         return launch_mode<JOIN_DESC_B>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, s);
     }
 }
+
+uint64_t join_slot_bytes(uint64_t nfr) { return nfr * kSlotStride * sizeof(uint16_t); }
 
 __global__ void keys_to_pairs_kernel(const uint64_t *__restrict__ keys, uint64_t n, uint32_t *__restrict__ pairs) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {

@@ -42,7 +42,7 @@ struct Grow {
 };
 
 struct JoinRun {
-    Grow ctrl, fr[2], cnt, off, stmp, keys, ktmp, hist, hscan, rtmp, tacc, lvl;
+    Grow ctrl, fr[2], cnt, off, stmp, keys, ktmp, hist, hscan, rtmp, tacc, lvl, slot;
     uint64_t npairs = 0;
     const uint64_t *sorted = nullptr;   // device, npairs keys
     uint64_t tests = 0;
@@ -145,6 +145,7 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
         c = std::min(c, w.off.cap / 8 ? w.off.cap / 8 - 1 : 0);
         const uint64_t st = w.stmp.cap / 8;
         c = std::min(c, st > 1 ? (st - 1) * scan_tile_elems() : 0);
+        c = std::min(c, w.slot.cap / join_slot_bytes(1));
         return std::min<uint64_t>(c, 0xFFFFFFFFull);
     };
     auto with_slack = [](uint64_t n) { return n + n / 4 + 1024; };
@@ -165,15 +166,16 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
         const uint64_t *nd = L == 0 ? nullptr : lv + L;
         const uint2 *fr = w.fr[cur].as<uint2>();
         uint64_t *off = w.off.as<uint64_t>();
+        uint16_t *slots = w.slot.as<uint16_t>();
         e = launch_join_level(va, vb, fr, (uint32_t)lim, nd, mode, false, w.cnt.as<uint32_t>(), nullptr, nullptr,
-                              nullptr, 0, ctrl, flags, nullptr, s);
+                              nullptr, 0, slots, ctrl, flags, nullptr, s);
         if (e == hipSuccess)
             e = launch_scan_u32_dev(w.cnt.as<uint32_t>(), nd, lim, off, w.stmp.as<uint64_t>(), lv + L + 1,
                                     next_lim, over, s);
         if (e == hipSuccess)
             e = launch_join_level(va, vb, fr, (uint32_t)lim, nd, mode, true, nullptr, off,
                                   emit ? nullptr : w.fr[1 - cur].as<uint2>(), emit ? w.keys.as<uint64_t>() : nullptr,
-                                  next_lim, ctrl, flags, nullptr, s);
+                                  next_lim, slots, ctrl, flags, nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "join level");
         cur = 1 - cur;
         lim = next_lim;
@@ -222,13 +224,15 @@ int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, h
         levels.push_back(nfr);
         const int mode = mode_of(la, lb);
         e = w.cnt.need(nfr * 4);
+        if (e == hipSuccess) e = w.slot.need(join_slot_bytes(nfr));
         if (e == hipSuccess) e = w.off.need((nfr + 1) * 8);
         if (e == hipSuccess) e = w.stmp.need(scan_tmp_elems(nfr) * 8);
         if (e != hipSuccess) return hip_fail(e, "join frontier");
         const uint2 *fr = w.fr[cur].as<uint2>();
         uint64_t *off = w.off.as<uint64_t>();
+        uint16_t *slots = w.slot.as<uint16_t>();
         e = launch_join_level(va, vb, fr, (uint32_t)nfr, nullptr, mode, false, w.cnt.as<uint32_t>(), nullptr,
-                              nullptr, nullptr, 0, ctrl, flags, tacc, s);
+                              nullptr, nullptr, 0, slots, ctrl, flags, tacc, s);
         if (e == hipSuccess) e = launch_scan_u32(w.cnt.as<uint32_t>(), nfr, off, w.stmp.as<uint64_t>(), s);
         uint64_t total = 0;
         if (e == hipSuccess) e = hipMemcpyAsync(&total, off + nfr, 8, hipMemcpyDeviceToHost, s);
@@ -239,7 +243,7 @@ int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, h
             e = w.keys.need(total * 8);
             if (e == hipSuccess)
                 e = launch_join_level(va, vb, fr, (uint32_t)nfr, nullptr, mode, true, nullptr, off, nullptr,
-                                      w.keys.as<uint64_t>(), total, ctrl, flags, nullptr, s);
+                                      w.keys.as<uint64_t>(), total, slots, ctrl, flags, nullptr, s);
             if (e != hipSuccess) return hip_fail(e, "join emit");
             const int rc = sort_keys(a, b, total, s, w);
             if (rc) return rc;
@@ -249,7 +253,7 @@ int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, h
         e = w.fr[1 - cur].need(total * 8);
         if (e == hipSuccess)
             e = launch_join_level(va, vb, fr, (uint32_t)nfr, nullptr, mode, true, nullptr, off,
-                                  w.fr[1 - cur].as<uint2>(), nullptr, total, ctrl, flags, nullptr, s);
+                                  w.fr[1 - cur].as<uint2>(), nullptr, total, slots, ctrl, flags, nullptr, s);
         if (e != hipSuccess) return hip_fail(e, "join expand");
         cur = 1 - cur;
         nfr = total;

@@ -175,11 +175,15 @@ enum JoinFlags : int { JOIN_O3 = 1, JOIN_O4 = 2, JOIN_O5 = 4, JOIN_TILE = 8 };
 constexpr uint32_t kTestSlots = 256;
 // nfr_dev (if not NULL): the frontier size on the device, at most nfr (the
 // grid is sized for nfr).  The fill pass writes no output index at or past
-// out_cap (the caller detects that case from the scan's total).
+// out_cap (the caller detects that case from the scan's total).  slots (NULL,
+// or join_slot_bytes(nfr) of device memory, the same for the count and the
+// fill pass of a level): hit records that spare the candidate kernels'
+// fill pass the tests of pairs with few hits.
+uint64_t join_slot_bytes(uint64_t nfr);
 hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *frontier,
                              uint32_t nfr, const uint64_t *nfr_dev, int mode, bool fill, uint32_t *counts,
-                             const uint64_t *offsets, uint2 *next, uint64_t *keys, uint64_t out_cap, Ctrl *ctrl,
-                             int flags, unsigned long long *tests_acc, hipStream_t s);
+                             const uint64_t *offsets, uint2 *next, uint64_t *keys, uint64_t out_cap,
+                             uint16_t *slots, Ctrl *ctrl, int flags, unsigned long long *tests_acc, hipStream_t s);
 hipError_t launch_keys_to_pairs(const uint64_t *keys, uint64_t n, uint32_t *pairs, hipStream_t s);
 
 // ---- batch --------------------------------------------------------------
