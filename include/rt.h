@@ -75,10 +75,16 @@ enum { RT_LAYOUT_AOS = 0, RT_LAYOUT_SOA = 1, RT_LAYOUT_AUTO = 2, RT_LAYOUT_D2 = 
  *                 O4)
  *   RT_JOIN_TILE  no candidate lists: every one of the Fa x Fb child pairs
  *                 is tested (cannot be combined with the others)
- * O3, O4 and O5 need both trees built with RT_BUILD_SORT_LX.  No flag gives
- * candidate lists without pruning.  RT_JOIN_DEFAULT picks O3|O5 when both
- * trees are sorted, else RT_JOIN_TILE. */
-enum { RT_JOIN_O3 = 1, RT_JOIN_O4 = 2, RT_JOIN_O5 = 4, RT_JOIN_TILE = 8, RT_JOIN_DEFAULT = -1 };
+ *   RT_JOIN_LB    (not in the paper; only as RT_JOIN_O3 | RT_JOIN_O5 |
+ *                 RT_JOIN_LB) the inner scan also starts late: inner
+ *                 children whose low x lies below the outer low x minus the
+ *                 widest inner child (less a margin that covers rounding)
+ *                 end left of the outer child and are skipped, found by the
+ *                 same many-to-many search
+ * O3, O4, O5 and LB need both trees built with RT_BUILD_SORT_LX.  No flag
+ * gives candidate lists without pruning.  RT_JOIN_DEFAULT picks
+ * O3|O5|LB when both trees are sorted, else RT_JOIN_TILE. */
+enum { RT_JOIN_O3 = 1, RT_JOIN_O4 = 2, RT_JOIN_O5 = 4, RT_JOIN_TILE = 8, RT_JOIN_LB = 16, RT_JOIN_DEFAULT = -1 };
 
 typedef struct rt_tree rt_tree;   /* opaque; device-resident; immutable */
 

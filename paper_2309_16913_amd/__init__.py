@@ -25,7 +25,7 @@ LIB_PATH = os.path.join(_HERE, "librt_mi355x.so")
 
 RT_OK, RT_EINVAL, RT_ENOMEM, RT_EDEVICE = 0, -1, -2, -3
 BUILD_SORT_LX = 0x100
-JOIN_O3, JOIN_O4, JOIN_O5, JOIN_TILE, JOIN_DEFAULT = 1, 2, 4, 8, -1
+JOIN_O3, JOIN_O4, JOIN_O5, JOIN_TILE, JOIN_LB, JOIN_DEFAULT = 1, 2, 4, 8, 16, -1
 LAYOUT_AOS, LAYOUT_SOA, LAYOUT_AUTO, LAYOUT_D2 = 0, 1, 2, 3
 _LAYOUTS = {"aos": LAYOUT_AOS, "soa": LAYOUT_SOA, "auto": LAYOUT_AUTO, "d2": LAYOUT_D2,
             LAYOUT_AOS: LAYOUT_AOS, LAYOUT_SOA: LAYOUT_SOA, LAYOUT_AUTO: LAYOUT_AUTO, LAYOUT_D2: LAYOUT_D2}
@@ -205,9 +205,9 @@ def range_select(tree: Tree, queries):
 
 def spatial_join(a: Tree, b: Tree, flags: int | None = None, with_tests: bool = False):
     """All intersecting (a, b) as an (n, 2) uint32 array in lexicographic
-    order.  flags: JOIN_O3 | JOIN_O4 | JOIN_O5, JOIN_TILE, 0, or None for the
-    library default.  with_tests: also return the number of child-pair
-    predicates evaluated."""
+    order.  flags: JOIN_O3 | JOIN_O4 | JOIN_O5, JOIN_O3 | JOIN_O5 | JOIN_LB,
+    JOIN_TILE, 0, or None for the library default.  with_tests: also return
+    the number of child-pair predicates evaluated."""
     p = C.POINTER(_Pairs)()
     tests = _u64(0)
     if flags is None and not with_tests:

@@ -181,7 +181,37 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t lane, ui
 // slots (if not NULL): kSlotHits hit records (i << 8 | j) per pair, written
 // by the count pass; the fill pass of a pair with at most that many hits
 // takes its children from there instead of testing the candidates again.
-template <int MODE, bool FILL, bool O3, int SHRINK>
+// Every lane searches the values v (lane g holds entry g; entries 0..n-1 are
+// sorted so that pred holds on a prefix) for the first entry where pred
+// fails, n if none: the many-to-many search of section 4.2 (gather at n/2,
+// compare, step by halves, log2(n)+1 rounds), each lane with its own pred.
+template <class Pred>
+__device__ __forceinline__ uint32_t first_failing(float v_lane, uint32_t n, Pred pred) {
+    uint32_t npow = 1, lg = 0;
+    while (npow < n) {
+        npow <<= 1;
+        ++lg;
+    }
+    int g = (int)(npow >> 1);
+    uint32_t flip = npow;
+    for (uint32_t it = 0; it <= lg; ++it) {
+        const float v = __shfl(v_lane, g & 63);
+        const bool in = g >= 0 && (uint32_t)g < npow;
+        const bool bit = (uint32_t)g < n && pred(v);
+        const int step = (it + 2 <= lg) ? (int)(npow >> (it + 2)) : 1;
+        if (in) {
+            if (bit) {
+                g += step;
+            } else {
+                flip = (uint32_t)g;
+                g -= step;
+            }
+        }
+    }
+    return flip;
+}
+
+template <int MODE, bool FILL, bool O3, int SHRINK, bool LB>
 __global__ void __launch_bounds__(256)
 join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t nfr,
                  const uint64_t *__restrict__ nfr_dev, uint32_t *__restrict__ counts,
@@ -236,32 +266,24 @@ join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t 
             if (lane == i) f = stop;
         }
     } else if (SHRINK == 5) {
-        uint32_t npow = 1, lg = 0;
-        while (npow < nb) {
-            npow <<= 1;
-            ++lg;
-        }
-        int g = (int)(npow >> 1);
-        uint32_t flip = npow;
-        for (uint32_t it = 0; it <= lg; ++it) {
-            const float v = __shfl(blx, g & 63);
-            const bool in = g >= 0 && (uint32_t)g < npow;
-            const bool bit = (uint32_t)g < nb && v <= ahx;
-            const int step = (it + 2 <= lg) ? (int)(npow >> (it + 2)) : 1;
-            if (in) {
-                if (bit) {
-                    g += step;
-                } else {
-                    flip = (uint32_t)g;
-                    g -= step;
-                }
-            }
-        }
-        f = flip;
+        f = first_failing(blx, nb, [&](float v) { return v <= ahx; });
     }
-    if (!act) f = 0;
+    // LB (lower bound, not in the paper): inner children are sorted by low
+    // x and none is wider than wmax, so one whose low x lies below
+    // olx - wmax ends left of the outer child and cannot qualify.  The bound
+    // is lowered by a margin far above the rounding of its two subtractions,
+    // so no qualifying pair is ever cut; candidates are j in [lo, f).
+    uint32_t lo = 0;
+    if (LB) {
+        const float wmax = wave_max(bv ? bhx - blx : -INFINITY);
+        const float thr = (alx - wmax) - (fabsf(alx) + wmax) * 0x1p-20f;
+        lo = first_failing(blx, nb, [&](float v) { return v < thr; });
+        lo = min(lo, f);
+    }
+    if (!act) f = lo = 0;
     uint32_t T = 0;
-    const uint32_t pre = wave_excl_scan(f, lane, &T);
+    const uint32_t pre = wave_excl_scan(f - lo, lane, &T);
+    const int jbase = (int)lo - (int)pre;   // j = t + jbase of the outer child
     uint64_t pos = 0, end = 0;
     if (FILL) {
         pos = offsets[p];
@@ -275,7 +297,7 @@ join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t 
             const uint32_t c = __shfl(pre, (int)(i + sft));
             if (c <= t) i += sft;
         }
-        const uint32_t j = min(t - __shfl(pre, (int)i), 63u);
+        const uint32_t j = min((uint32_t)((int)t + __shfl(jbase, (int)i)), 63u);
         const float olx = __shfl(alx, (int)i), oly = __shfl(aly, (int)i);
         const float ohx = __shfl(ahx, (int)i), ohy = __shfl(ahy, (int)i);
         const float ilx = __shfl(blx, (int)j), ily = __shfl(bly, (int)j);
@@ -307,18 +329,18 @@ join_cand_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t 
     }
 }
 
-template <int MODE, bool O3, int SHRINK>
+template <int MODE, bool O3, int SHRINK, bool LB = false>
 static hipError_t launch_cand(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr,
                               const uint64_t *nfr_dev, bool fill, uint32_t *counts, const uint64_t *offsets,
                               uint2 *next, uint64_t *keys, uint64_t out_cap, uint16_t *slots, Ctrl *ctrl,
                               unsigned long long *tests_acc, hipStream_t s) {
     const uint32_t blocks = (nfr + 3) / 4;
     if (fill)
-        hipLaunchKernelGGL((join_cand_kernel<MODE, true, O3, SHRINK>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr,
+        hipLaunchKernelGGL((join_cand_kernel<MODE, true, O3, SHRINK, LB>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr,
                            nfr_dev, counts, offsets, next, keys, out_cap, slots, ctrl,
                            (unsigned long long *)nullptr);
     else
-        hipLaunchKernelGGL((join_cand_kernel<MODE, false, O3, SHRINK>), dim3(blocks), dim3(256), 0, s, a, b, fr,
+        hipLaunchKernelGGL((join_cand_kernel<MODE, false, O3, SHRINK, LB>), dim3(blocks), dim3(256), 0, s, a, b, fr,
                            nfr, nfr_dev, counts, offsets, next, keys, out_cap, slots, ctrl, tests_acc);
     return hipGetLastError();
 }
@@ -330,6 +352,10 @@ static hipError_t launch_cand_flags(const TreeView &a, const TreeView &b, const 
                                     unsigned long long *ta, hipStream_t s) {
     const bool o3 = flags & JOIN_O3;
     const int sh = (flags & JOIN_O5) ? 5 : ((flags & JOIN_O4) ? 4 : 0);
+    if (flags & JOIN_LB) {   // only with O3 + O5 (checked by the caller)
+        return launch_cand<MODE, true, 5, true>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, sl, ctrl,
+                                                ta, s);
+    }
     if (o3) {
         if (sh == 5)
             return launch_cand<MODE, true, 5>(a, b, fr, nfr, nd, fill, counts, offsets, next, keys, cap, sl, ctrl, ta,

@@ -280,14 +280,17 @@ int check_join_args(const rt_tree *a, const rt_tree *b, int32_t *flags) {
     if (a->device != b->device) return fail(RT_EINVAL, "trees are on different devices");
     if (a->device < 0 || a->device >= kMaxDevices) return fail(RT_EINVAL, "device %d out of range", a->device);
     const bool both_sorted = a->sorted_lx && b->sorted_lx;
-    // measured fastest: candidate lists with O3 + O5 on sorted trees, else the
-    // full tile (candidate lists without pruning cost more than they save)
-    if (*flags == RT_JOIN_DEFAULT) *flags = both_sorted ? (RT_JOIN_O3 | RT_JOIN_O5) : RT_JOIN_TILE;
-    if (*flags & ~(RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5 | RT_JOIN_TILE))
+    // measured fastest: candidate lists with O3 + O5 + the lower bound on
+    // sorted trees, else the full tile (candidate lists without pruning cost
+    // more than they save)
+    if (*flags == RT_JOIN_DEFAULT) *flags = both_sorted ? (RT_JOIN_O3 | RT_JOIN_O5 | RT_JOIN_LB) : RT_JOIN_TILE;
+    if (*flags & ~(RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5 | RT_JOIN_TILE | RT_JOIN_LB))
         return fail(RT_EINVAL, "unknown join flags 0x%x", (unsigned)*flags);
     if ((*flags & RT_JOIN_TILE) && (*flags & ~RT_JOIN_TILE))
         return fail(RT_EINVAL, "RT_JOIN_TILE cannot be combined with pruning");
-    if ((*flags & (RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5)) && !both_sorted)
+    if ((*flags & RT_JOIN_LB) && (*flags & (RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5)) != (RT_JOIN_O3 | RT_JOIN_O5))
+        return fail(RT_EINVAL, "RT_JOIN_LB goes with RT_JOIN_O3 | RT_JOIN_O5 only");
+    if ((*flags & (RT_JOIN_O3 | RT_JOIN_O4 | RT_JOIN_O5 | RT_JOIN_LB)) && !both_sorted)
         return fail(RT_EINVAL, "join pruning needs both trees built with RT_BUILD_SORT_LX");
     return RT_OK;
 }

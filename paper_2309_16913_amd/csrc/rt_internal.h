@@ -168,7 +168,7 @@ enum JoinMode : int { JOIN_BOTH = 0, JOIN_EMIT = 1, JOIN_DESC_A = 2, JOIN_DESC_B
 // expansion variants (same values as the public RT_JOIN_* flags): outer
 // slicing, one-to-many / many-to-many inner shrinking (need nodes sorted by
 // low x), or the full Fa x Fb tile without candidate lists
-enum JoinFlags : int { JOIN_O3 = 1, JOIN_O4 = 2, JOIN_O5 = 4, JOIN_TILE = 8 };
+enum JoinFlags : int { JOIN_O3 = 1, JOIN_O4 = 2, JOIN_O5 = 4, JOIN_TILE = 8, JOIN_LB = 16 };
 // tests_acc (NULL: not counted): the count pass (fill = false) of the
 // candidate kernels adds the number of pair predicates it evaluates to
 // tests_acc[(pair % kTestSlots) * 16]; the sum over the slots is the total.

@@ -2,7 +2,9 @@
 slicing (O3), one-to-many (O4) and many-to-many (O5) inner shrinking.  Every
 variant returns exactly the oracle's pair set, and evaluates exactly as many
 child-pair predicates as the oracle's pruned join does on the same trees
-(which pins the GPU's slicing and flip indices, not only its results)."""
+(which pins the GPU's slicing and flip indices, not only its results).  The
+lower bound on the inner scan (LB, not in the paper) is held to the oracle's
+pair set and to evaluating no more predicates than O3 + O5."""
 
 import sys
 
@@ -84,9 +86,13 @@ def test_pruned_join_parity(rt, ora, case):
             p, otests = ora.join_opt(oa, ob, flags)
             assert np.array_equal(p, want)
             assert tests == otests, f"{name} flags {flags}: GPU evaluated {tests}, oracle {otests}"
+    lb = rt.JOIN_O3 | rt.JOIN_O5 | rt.JOIN_LB
+    got, tests_lb = rt.spatial_join(ta, tb, lb, with_tests=True)
+    assert np.array_equal(got, want), f"{name} flags {lb}"
+    assert tests_lb <= rt.spatial_join(ta, tb, rt.JOIN_O3 | rt.JOIN_O5, with_tests=True)[1]
     got = rt.spatial_join(ta, tb, rt.JOIN_TILE)
     assert np.array_equal(got, want)
-    assert np.array_equal(rt.spatial_join(ta, tb), want)   # default: O3|O5 on sorted trees
+    assert np.array_equal(rt.spatial_join(ta, tb), want)   # default: O3|O5|LB on sorted trees
 
 
 def test_pruned_join_c3_sample(rt, ora):
@@ -104,8 +110,48 @@ def test_pruned_join_c3_sample(rt, ora):
         assert np.array_equal(got, want), flags
         assert tests == ora.join_opt(oa, ob, flags)[1], flags
         res[flags] = tests
+    lb = rt.JOIN_O3 | rt.JOIN_O5 | rt.JOIN_LB
+    got, res[lb] = rt.spatial_join(ta, tb, lb, with_tests=True)
+    assert np.array_equal(got, want)
     say("tests per variant", res)
-    assert res[rt.JOIN_O3 | rt.JOIN_O5] == res[rt.JOIN_O3 | rt.JOIN_O4] < res[rt.JOIN_O3] <= res[0]
+    assert res[lb] < res[rt.JOIN_O3 | rt.JOIN_O5] == res[rt.JOIN_O3 | rt.JOIN_O4] < res[rt.JOIN_O3] <= res[0]
+
+
+def _edge_rects(n, seed):
+    """Rectangles that stress the lower bound's margin: infinite and
+    half-infinite extents, huge and tiny magnitudes, points, duplicates, and
+    rectangles that touch exactly at the bound."""
+    g = np.random.default_rng(seed)
+    r = rtgen.adversarial_rects(n, seed, grid=64).astype(np.float32)
+    k = g.integers(0, 64, size=n)
+    inf = np.float32(np.inf)
+    r[k == 0, 0] = -inf                                   # open to the left
+    r[k == 1, 2] = inf                                    # open to the right
+    r[g.integers(0, n, size=2)] = (-inf, -inf, inf, inf)  # whole plane
+    big = g.uniform(-3e37, 3e37, size=(int((k == 3).sum()), 1)).astype(np.float32)
+    r[k == 3] = np.hstack([big, big, big + np.abs(big) * np.float32(1e-6), big])
+    tiny = g.integers(-40, 40, size=(int((k == 4).sum()), 2)).astype(np.float32) * np.float32(1e-40)
+    r[k == 4] = np.hstack([tiny, tiny + np.float32(1e-40)])
+    # a run of rectangles whose high x equals the next one's low x exactly
+    e = np.flatnonzero(k == 5)
+    x = np.float32(0.125) * np.arange(e.size, dtype=np.float32)
+    r[e] = np.stack([x, np.zeros_like(x), x + np.float32(0.125), np.full_like(x, 0.01)], 1)
+    return r
+
+
+@pytest.mark.parametrize("n,F,seed", [(5_000, 8, 61), (40_000, 32, 62), (20_000, 64, 63)])
+def test_join_lower_bound_edges(rt, ora, n, F, seed):
+    """The lower bound never cuts a qualifying pair, with infinite extents
+    (where the bound turns off), widths near the largest float, subnormal
+    coordinates and pairs that touch exactly."""
+    A, B = _edge_rects(n, seed), _edge_rects(n // 2 + 1, seed + 1000)
+    say(f"case lower bound n={n} F={F} seed={seed}")
+    want = ora.join(ora.build_str(A, F), ora.build_str(B, F))
+    ta, tb = rt.build_str(A, F, "soa", sort_lx=True), rt.build_str(B, F, "aos", sort_lx=True)
+    for flags in (rt.JOIN_O3 | rt.JOIN_O5 | rt.JOIN_LB, rt.JOIN_O3 | rt.JOIN_O5, None):
+        got = rt.spatial_join(ta, tb, flags)
+        assert np.array_equal(got, want), flags
+        assert np.array_equal(rt.spatial_join(tb, ta, flags), want[np.lexsort((want[:, 0], want[:, 1]))][:, ::-1])
 
 
 def test_pruning_needs_sorted_trees(rt):
@@ -119,6 +165,12 @@ def test_pruning_needs_sorted_trees(rt):
         rt.spatial_join(ts, ts, rt.JOIN_TILE | rt.JOIN_O3)
     with pytest.raises(rt.RTError):
         rt.spatial_join(ts, ts, 64)
+    for flags in (rt.JOIN_LB, rt.JOIN_LB | rt.JOIN_O3, rt.JOIN_LB | rt.JOIN_O5,
+                  rt.JOIN_LB | rt.JOIN_O3 | rt.JOIN_O4, rt.JOIN_LB | rt.JOIN_O3 | rt.JOIN_O4 | rt.JOIN_O5):
+        with pytest.raises(rt.RTError):
+            rt.spatial_join(ts, ts, flags)
+    with pytest.raises(rt.RTError):
+        rt.spatial_join(ts, tu, rt.JOIN_O3 | rt.JOIN_O5 | rt.JOIN_LB)
     # unsorted trees still join without pruning, in both kernels
     want = rt.spatial_join(ts, ts, rt.JOIN_O3 | rt.JOIN_O5)
     assert np.array_equal(rt.spatial_join(tu, tu, 0), want)
