@@ -25,7 +25,8 @@
 // (h-1)(F-1)+1 entries instead of a whole tree level.
 //
 // Work distribution: the grid is persistent; a group that empties its stack
-// takes the next query index from a device counter.  Both passes walk the same
+// takes the next query index from a device counter (the count pass two at a
+// time, see grab_chunk).  Both passes walk the same
 // tree with the same predicate, so the fill pass writes exactly the count
 // pass's number of ids for every query.
 #include "rt_internal.h"
@@ -105,10 +106,10 @@ struct Unit {
     uint32_t q, node, oslot;
 };
 
-// Next unit for a group leader: split items first (they are the long ones),
-// then whole queries from the XCD slices, skipping queries that were split.
-__device__ __forceinline__ Unit next_unit(Ctrl *ctrl, uint32_t slot, uint32_t nq, const SelectPlan &plan,
-                                          uint32_t home, uint32_t &visited, uint32_t &hvisited) {
+// Next split item for a group leader (split items are the long ones and go
+// first), or q = nq when every list is drained.
+__device__ __forceinline__ Unit next_split_item(Ctrl *ctrl, uint32_t slot, uint32_t nq, const SelectPlan &plan,
+                                                uint32_t home, uint32_t &hvisited) {
     while (hvisited < kXcds) {
         const uint32_t x = (home + hvisited) % kXcds;
         const uint32_t nh = ctrl->hlist[x][0];
@@ -124,13 +125,44 @@ __device__ __forceinline__ Unit next_unit(Ctrl *ctrl, uint32_t slot, uint32_t nq
         }
         hvisited += 1;
     }
-    while (true) {
-        const uint32_t q = grab_query(ctrl, slot, nq, plan.order, home, visited, nullptr, plan.heavy != nullptr);
-        if (q >= nq) return Unit{nq, 0u, 0u};
-        if (!plan.slot_first) return Unit{q, 0u, q};
-        const uint64_t s0 = plan.slot_first[q], s1 = plan.slot_first[q + 1];
-        if (s1 - s0 == 1) return Unit{q, 0u, (uint32_t)s0};
+    return Unit{nq, 0u, 0u};
+}
+
+// Whole queries are handed out K at a time: one atomic on the slice counter
+// takes K consecutive positions of the processing order, and the group loads
+// their query indices and windows in one round (lane i holds the i-th).  The
+// slice counters are single addresses that every group of an XCD updates, and
+// their atomics are serialized: with one query per atomic the count pass (a
+// few nodes per query) waits on them.  The fill pass keeps K = 1: its queries
+// take longer, and a group holding several of them widens the XCD's front in
+// the processing order, which costs L2 hits.  Returns the number taken (0:
+// all handed out) and the first position in *p0.
+template <uint32_t K>
+__device__ __forceinline__ uint32_t grab_chunk(Ctrl *ctrl, uint32_t slot, uint32_t nq, uint32_t home,
+                                               uint32_t &visited, bool look_first, uint32_t *p0) {
+    while (visited < kXcds) {
+        const uint32_t x = (home + visited) % kXcds;
+        const uint32_t b0 = (uint32_t)(((uint64_t)x * nq) / kXcds);
+        const uint32_t b1 = (uint32_t)(((uint64_t)(x + 1) * nq) / kXcds);
+        if (look_first && visited > 0 &&
+            __hip_atomic_load(&ctrl->xwork[slot][x][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b1 - b0) {
+            visited += 1;
+            continue;
+        }
+        const uint32_t k = atomicAdd(&ctrl->xwork[slot][x][0], K);
+        if (k < b1 - b0) {
+            *p0 = b0 + k;
+            return min(K, b1 - b0 - k);
+        }
+        visited += 1;
     }
+    return 0;
+}
+
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+    const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v, src);
+    const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // LA = 1: lookahead (section 3, optimization O2, as a load issued one node
@@ -140,6 +172,8 @@ __device__ __forceinline__ Unit next_unit(Ctrl *ctrl, uint32_t slot, uint32_t nq
 // them without waiting for a fresh load.  After an internal node the next
 // node is one of its children, decided only by the comparison, so nothing is
 // loaded ahead there.
+constexpr uint32_t kCountChunk = 2;
+
 template <int G, int LAYOUT, int MODE, int LA>
 __global__ void __launch_bounds__(256)
 select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *__restrict__ counts,
@@ -161,6 +195,12 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
     const uint32_t home = blockIdx.x % kXcds;
     uint32_t visited = 0;
     uint32_t hvisited = plan.heavy ? 0u : kXcds;
+    // the group's chunk of whole queries: lane i < cn holds query cq, its
+    // window cw and output slot cs (kNoNode: split); ci = next to start
+    // (and, fill pass, its output range [cpos, cend))
+    uint32_t cn = 0, ci = 0, cq = 0, cs = 0;
+    float4 cw = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint64_t cpos = 0, cend = 0;
     uint32_t oslot = 0;
     bool have = false, done = false;
     uint32_t sp = 0;
@@ -179,22 +219,69 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                 }
             }
             Unit u{nq, 0u, 0u};
-            if (e == 0) u = next_unit(ctrl, slot, nq, plan, home, visited, hvisited);
-            u.q = __shfl(u.q, (int)gbase);
-            u.node = __shfl(u.node, (int)gbase);
-            u.oslot = __shfl(u.oslot, (int)gbase);
-            if (u.q < nq) {
-                oslot = u.oslot;
-                have = true;
-                q = qs[u.q];
-                stk[0] = u.node;
-                sp = 1;
+            bool from_chunk = false;
+            if (hvisited < kXcds) {
+                if (e == 0) u = next_split_item(ctrl, slot, nq, plan, home, hvisited);
+                u.q = __shfl(u.q, (int)gbase);
+                u.node = __shfl(u.node, (int)gbase);
+                u.oslot = __shfl(u.oslot, (int)gbase);
+                hvisited = __shfl(hvisited, (int)gbase);
+                if (u.q < nq) q = qs[u.q];
+            }
+            // whole queries from the group's chunk, skipping split ones
+            while (u.q >= nq) {
+                if (ci >= cn) {
+                    uint32_t p0 = 0, c = 0;
+                    if (e == 0)
+                        c = grab_chunk<MODE == SEL_FILL ? 1u : kCountChunk>(ctrl, slot, nq, home, visited,
+                                                                             plan.heavy != nullptr, &p0);
+                    c = __shfl(c, (int)gbase);
+                    p0 = __shfl(p0, (int)gbase);
+                    visited = __shfl(visited, (int)gbase);
+                    if (c == 0) break;
+                    cn = c;
+                    ci = 0;
+                    if (e < c) {
+                        cq = plan.order ? (uint32_t)plan.order[p0 + e] : p0 + e;
+                        cw = qs[cq];
+                        cs = cq;
+                        if (plan.slot_first) {
+                            const uint64_t s0 = plan.slot_first[cq];
+                            cs = plan.slot_first[cq + 1] - s0 == 1 ? (uint32_t)s0 : kNoNode;
+                        }
+                        if constexpr (MODE == SEL_FILL) {
+                            if (cs != kNoNode) {
+                                cpos = offsets[cs];
+                                cend = offsets[cs + 1];
+                            }
+                        }
+                    }
+                }
+                const int src = (int)(gbase + ci);
+                ci += 1;
+                const uint32_t os = __shfl(cs, src);
+                if (os == kNoNode) continue;   // split: its items cover it
+                u = Unit{(uint32_t)__shfl(cq, src), 0u, os};
+                q = make_float4(__shfl(cw.x, src), __shfl(cw.y, src), __shfl(cw.z, src), __shfl(cw.w, src));
                 if constexpr (MODE == SEL_FILL) {
-                    pos = offsets[oslot];
-                    end = offsets[oslot + 1];
+                    pos = shfl_u64(cpos, src);
+                    end = shfl_u64(cend, src);
+                }
+                from_chunk = true;
+            }
+            if (u.q < nq) {
+                if constexpr (MODE == SEL_FILL) {
+                    if (!from_chunk) {   // a split item
+                        pos = offsets[u.oslot];
+                        end = offsets[u.oslot + 1];
+                    }
                 } else {
                     pos = 0;
                 }
+                oslot = u.oslot;
+                have = true;
+                stk[0] = u.node;
+                sp = 1;
             } else {
                 have = false;
                 done = true;
