@@ -722,8 +722,13 @@ __global__ void query_morton(const float4 *__restrict__ q, uint32_t nq, float lx
 
 static uint64_t al256(uint64_t b) { return (b + 255) & ~255ull; }
 
+// The order sorts on the top 22 bits of the 32-bit Morton code (11 bits per
+// axis, a 2048 x 2048 grid over the tree's MBR) in two 11-bit passes; the
+// order inside a grid cell does not matter for locality.
+constexpr int kOrderDigitBits = 11;
+
 uint64_t order_ws_bytes(uint64_t nq) {
-    const uint64_t he = radix_hist_elems(nq);
+    const uint64_t he = radix_hist_elems(nq, kOrderDigitBits);
     return al256(8 * nq) * 2 + al256(4 * he) + al256(8 * (he + 1)) + al256(8 * scan_tmp_elems(he + 1));
 }
 
@@ -734,7 +739,7 @@ hipError_t launch_query_order(const float4 *q, uint32_t nq, const float *mbr, vo
     p += al256(8 * (uint64_t)nq);
     uint64_t *tmp = reinterpret_cast<uint64_t *>(p);
     p += al256(8 * (uint64_t)nq);
-    const uint64_t he = radix_hist_elems(nq);
+    const uint64_t he = radix_hist_elems(nq, kOrderDigitBits);
     uint32_t *hist = reinterpret_cast<uint32_t *>(p);
     p += al256(4 * he);
     uint64_t *hscan = reinterpret_cast<uint64_t *>(p);
@@ -747,10 +752,11 @@ hipError_t launch_query_order(const float4 *q, uint32_t nq, const float *mbr, vo
     uint32_t blocks = (nq + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(query_morton, dim3(blocks), dim3(256), 0, s, q, nq, lx, ly, sx, sy, keys);
-    // four passes (an even number): the sorted keys end in the first buffer
-    const int shifts[4] = {32, 40, 48, 56};
+    // two passes (an even number): the sorted keys end in the first buffer
+    const int shifts[2] = {42, 53};
     bool in_tmp = false;
-    hipError_t e = launch_radix_sort_u64(keys, tmp, nq, shifts, 4, hist, hscan, stmp, &in_tmp, s);
+    hipError_t e =
+        launch_radix_sort_u64(keys, tmp, nq, shifts, 2, hist, hscan, stmp, &in_tmp, s, kOrderDigitBits);
     *sorted = keys;
     if (e == hipSuccess && in_tmp) e = hipErrorUnknown;
     return e == hipSuccess ? hipGetLastError() : e;
