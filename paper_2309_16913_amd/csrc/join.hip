@@ -19,6 +19,7 @@
 // Trees of unequal height: only the deeper side descends, with each of its
 // children tested against the MBR of the whole shallower tree, until both
 // sides are at the same level (this can only happen at the roots).
+#include "pair_sort.h"
 #include "rt_internal.h"
 
 namespace rtk {
@@ -425,6 +426,133 @@ hipError_t launch_keys_to_pairs(const uint64_t *keys, uint64_t n, uint32_t *pair
     uint64_t blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     hipLaunchKernelGGL(keys_to_pairs_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, keys, n, pairs);
+    return hipGetLastError();
+}
+
+// ---- pair keys: bucket sort by the top digit --------------------------------
+constexpr uint32_t kPairTile = 4096;   // keys per block in the scatter (256 x 16)
+
+__global__ void __launch_bounds__(256)
+pair_bucket_hist(const uint64_t *__restrict__ keys, uint64_t n, int shift, uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t h[kPairBuckets];
+    for (uint32_t i = threadIdx.x; i < kPairBuckets; i += blockDim.x) h[i] = 0;
+    __syncthreads();
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(&h[(uint32_t)(keys[i] >> shift)], 1u);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < kPairBuckets; i += blockDim.x)
+        if (h[i]) atomicAdd(&cnt[i], h[i]);
+}
+
+// One block of 1024: exclusive scan of the counts into start[0 .. kPairBuckets]
+// (start[kPairBuckets] = n) and zeroed cursors.
+__global__ void __launch_bounds__(1024)
+pair_bucket_scan(const uint32_t *__restrict__ cnt, uint32_t *__restrict__ start, uint32_t *__restrict__ cursor) {
+    constexpr uint32_t W = 1024 / 64;
+    __shared__ uint32_t wsum[W];
+    const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+    const uint32_t a = cnt[2 * t], b = cnt[2 * t + 1];
+    uint32_t inc = a + b;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t x = __shfl_up(inc, d);
+        if ((int)lane >= d) inc += x;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+    for (uint32_t i = 0; i < w; ++i) base += wsum[i];
+    const uint32_t ex = base + inc - (a + b);
+    start[2 * t] = ex;
+    start[2 * t + 1] = ex + a;
+    if (t == 1023) start[kPairBuckets] = ex + a + b;
+    cursor[2 * t] = 0;
+    cursor[2 * t + 1] = 0;
+}
+
+// A block takes a tile of keys: LDS ranks per bucket, one global reservation
+// per bucket present in the tile, then every key goes to its bucket.  The
+// order inside a bucket is arbitrary (the bucket is sorted next).
+__global__ void __launch_bounds__(256)
+pair_bucket_scatter(const uint64_t *__restrict__ keys, uint64_t n, int shift, const uint32_t *__restrict__ start,
+                    uint32_t *__restrict__ cursor, uint64_t *__restrict__ out) {
+    constexpr uint32_t R = kPairTile / 256;
+    __shared__ uint32_t c[kPairBuckets];
+    for (uint64_t t0 = (uint64_t)blockIdx.x * kPairTile; t0 < n; t0 += (uint64_t)gridDim.x * kPairTile) {
+        for (uint32_t i = threadIdx.x; i < kPairBuckets; i += 256) c[i] = 0;
+        __syncthreads();
+        uint64_t k[R];
+        uint32_t rk[R];
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            const uint64_t i = t0 + r * 256 + threadIdx.x;
+            k[r] = i < n ? keys[i] : 0ull;
+            rk[r] = i < n ? atomicAdd(&c[(uint32_t)(k[r] >> shift)], 1u) : 0u;
+        }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < kPairBuckets; i += 256)
+            if (c[i]) c[i] = start[i] + atomicAdd(&cursor[i], c[i]);
+        __syncthreads();
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            const uint64_t i = t0 + r * 256 + threadIdx.x;
+            if (i < n) out[c[(uint32_t)(k[r] >> shift)] + rk[r]] = k[r];
+        }
+        __syncthreads();
+    }
+}
+
+// One block per bucket: bitonic sort in LDS over the bucket padded to a power
+// of two (keys are distinct; padding with all ones sorts last).
+__global__ void __launch_bounds__(256)
+pair_bucket_sort(uint64_t *__restrict__ keys, const uint32_t *__restrict__ start, uint32_t *__restrict__ big) {
+    __shared__ uint64_t buf[kPairBucketCap];
+    for (uint32_t bk = blockIdx.x; bk < kPairBuckets; bk += gridDim.x) {
+        const uint32_t s0 = start[bk], c = start[bk + 1] - s0;
+        if (c < 2) continue;
+        if (c > kPairBucketCap) {
+            if (threadIdx.x == 0) atomicAdd(big, 1u);
+            continue;
+        }
+        uint32_t P = 2;
+        while (P < c) P <<= 1;
+        for (uint32_t i = threadIdx.x; i < P; i += 256) buf[i] = i < c ? keys[s0 + i] : ~0ull;
+        __syncthreads();
+        for (uint32_t k = 2; k <= P; k <<= 1) {
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                for (uint32_t t = threadIdx.x; t < P / 2; t += 256) {
+                    const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                    const uint32_t l = i | j;
+                    const uint64_t x = buf[i], y = buf[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        buf[i] = y;
+                        buf[l] = x;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (uint32_t i = threadIdx.x; i < c; i += 256) keys[s0 + i] = buf[i];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_pair_bucket_sort(const uint64_t *keys, uint64_t n, int shift, uint64_t *out, uint32_t *ws,
+                                   uint32_t *big, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    uint32_t *cnt = ws, *start = ws + kPairBuckets, *cursor = ws + 2 * kPairBuckets + 4;
+    hipError_t e = launch_zero(cnt, 4 * kPairBuckets, s);
+    if (e == hipSuccess) e = launch_zero(big, 4, s);
+    if (e != hipSuccess) return e;
+    const uint64_t tiles = (n + kPairTile - 1) / kPairTile;
+    const uint32_t cus = (uint32_t)num_cus();
+    const uint32_t hb = (uint32_t)(tiles < (uint64_t)cus * 4 ? tiles : (uint64_t)cus * 4);
+    hipLaunchKernelGGL(pair_bucket_hist, dim3(hb), dim3(256), 0, s, keys, n, shift, cnt);
+    hipLaunchKernelGGL(pair_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, start, cursor);
+    const uint32_t sb = (uint32_t)(tiles < (uint64_t)cus * 8 ? tiles : (uint64_t)cus * 8);
+    hipLaunchKernelGGL(pair_bucket_scatter, dim3(sb), dim3(256), 0, s, keys, n, shift, start, cursor, out);
+    hipLaunchKernelGGL(pair_bucket_sort, dim3(kPairBuckets), dim3(256), 0, s, out, start, big);
     return hipGetLastError();
 }
 

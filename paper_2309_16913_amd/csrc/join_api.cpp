@@ -12,8 +12,10 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
+#include "pair_sort.h"
 #include "rt_api_internal.h"
 
 using namespace rtk;
@@ -86,27 +88,48 @@ struct PooledRun {
 // Sorts the total keys in w.keys into the canonical order (only the digits
 // that can be nonzero).
 int sort_keys(const rt_tree *a, const rt_tree *b, uint64_t total, hipStream_t s, JoinRun &w) {
+    const int bb = bits_for(b->n_objects ? b->n_objects - 1 : 0);
+    const int ba = bits_for(a->n_objects ? a->n_objects - 1 : 0);
+    hipError_t e = w.ktmp.need(total * 8);
+    if (e != hipSuccess) return hip_fail(e, "join sort");
+    uint64_t *src = w.keys.as<uint64_t>(), *tmp = w.ktmp.as<uint64_t>();
+    // Up to ~1.5K keys per bucket on average: buckets by the top 11 bits of
+    // the key (every key is below 2^(32 + ba)), each sorted in LDS; four
+    // launches against the LSD sort's twenty.  A bucket over the LDS cap
+    // (ids far from uniform) sends the keys to the LSD sort below.
+    if (total <= (uint64_t)kPairBuckets * 1536) {
+        e = w.hist.need((kPairSortWords + 4) * 4);
+        uint32_t *ws = w.hist.as<uint32_t>();
+        uint32_t *big = ws + kPairSortWords;
+        if (e == hipSuccess) e = launch_pair_bucket_sort(src, total, 21 + ba, tmp, ws, big, s);
+        uint32_t nbig = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&nbig, big, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "join sort");
+        if (nbig == 0) {
+            w.npairs = total;
+            w.sorted = tmp;
+            return RT_OK;
+        }
+        std::swap(src, tmp);   // bucketed keys in full through the LSD sort
+    }
     // 11-bit digits: 4 passes for two 21-bit ids instead of 6 (each pass
     // costs about the same few launches whatever its width)
     constexpr int kDigit = 11;
     int shifts[16], np = 0;
-    const int bb = bits_for(b->n_objects ? b->n_objects - 1 : 0);
-    const int ba = bits_for(a->n_objects ? a->n_objects - 1 : 0);
     for (int sft = 0; sft < bb; sft += kDigit) shifts[np++] = sft;
     for (int sft = 32; sft < 32 + ba; sft += kDigit) shifts[np++] = sft;
     const uint64_t he = radix_hist_elems(total, kDigit);
-    hipError_t e = w.ktmp.need(total * 8);
-    if (e == hipSuccess) e = w.hist.need(he * 4);
+    e = w.hist.need(he * 4);
     if (e == hipSuccess) e = w.hscan.need((he + 1) * 8);
     if (e == hipSuccess) e = w.rtmp.need(scan_tmp_elems(he) * 8);
     bool in_tmp = false;
     if (e == hipSuccess)
-        e = launch_radix_sort_u64(w.keys.as<uint64_t>(), w.ktmp.as<uint64_t>(), total, shifts, np,
-                                  w.hist.as<uint32_t>(), w.hscan.as<uint64_t>(), w.rtmp.as<uint64_t>(), &in_tmp, s,
-                                  kDigit);
+        e = launch_radix_sort_u64(src, tmp, total, shifts, np, w.hist.as<uint32_t>(), w.hscan.as<uint64_t>(),
+                                  w.rtmp.as<uint64_t>(), &in_tmp, s, kDigit);
     if (e != hipSuccess) return hip_fail(e, "join sort");
     w.npairs = total;
-    w.sorted = in_tmp ? w.ktmp.as<uint64_t>() : w.keys.as<uint64_t>();
+    w.sorted = in_tmp ? tmp : src;
     return RT_OK;
 }
 

@@ -224,3 +224,25 @@ def test_join_workspace_reuse(rt, ora):
         assert rt.spatial_join_device(ta, tb, buf.data_ptr(), m) == m
         got = buf[:2 * m].cpu().numpy().view(np.uint32).reshape(-1, 2)
         assert np.array_equal(got, want), name
+
+
+def test_join_key_sort_paths(rt, ora):
+    """The pair keys are split into 2048 buckets by their top bits and every
+    bucket is sorted in LDS; a bucket over the LDS cap (one object meeting
+    20000 others) and a result over the bucketing limit (3.4M pairs) go
+    through the LSD radix sort instead.  Every path gives the oracle's pairs."""
+    B = rtgen.uniform_rects(20_000, 0.01, 71)
+    small = rtgen.uniform_rects(9_999, 0.01, 72)
+    whole = np.array([[-1.0, -1.0, 2.0, 2.0]], np.float32)
+    cases = [("lds buckets", small),
+             ("bucket over the cap", np.concatenate([small[:5000], whole, small[5000:]])),
+             ("over the bucketing limit", np.concatenate([np.repeat(whole, 170, 0), small[:100]]))]
+    tb = rt.build_str(B, 32, "soa", sort_lx=True)
+    ob = ora.build_str(B, 32)
+    for name, A in cases:
+        say(f"case key sort {name} nA={A.shape[0]}")
+        want = ora.join(ora.build_str(A, 32), ob)
+        ta = rt.build_str(A, 32, "soa", sort_lx=True)
+        for flags in (None, rt.JOIN_TILE):
+            got = rt.spatial_join(ta, tb, flags)
+            assert np.array_equal(got, want), (name, flags, got.shape, want.shape)
