@@ -14,7 +14,8 @@
 // from one broadcast outer MBR to several.  Qualifying pairs are compacted
 // with __ballot + popcount ranks into the next frontier (count pass, scan,
 // fill pass) or, at the leaf level, written out as 64-bit (idA << 32 | idB)
-// keys.
+// keys, which are then sorted (bucket sort at the end of this file) into the
+// canonical pair order.
 //
 // Trees of unequal height: only the deeper side descends, with each of its
 // children tested against the MBR of the whole shallower tree, until both
