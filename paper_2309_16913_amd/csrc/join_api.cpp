@@ -51,6 +51,13 @@ struct JoinRun {
     // frontier size of every level in the last join run level by level with
     // host reads (empty: none yet); sizes the grids of the replayed levels
     std::vector<uint64_t> last_levels;
+    // the replayed levels' launches as a graph: captured when the same join
+    // (same trees, flags, level sizes and buffers) is replayed a second time
+    // in a row, relaunched while it stays the same
+    std::vector<uint64_t> replay_key, graph_key;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 // Workspaces are pooled per device: a call takes one (or makes one) and
@@ -172,37 +179,91 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
         return std::min<uint64_t>(c, 0xFFFFFFFFull);
     };
     auto with_slack = [](uint64_t n) { return n + n / 4 + 1024; };
-    e = launch_zero(ctrl, sizeof(Ctrl), s);
-    if (e == hipSuccess) e = launch_zero(lv, (H + 2) * 8, s);   // and the overflow flag
-    if (e == hipSuccess) e = launch_zero(w.fr[0].b.p, 8, s);   // (root A, root B) = (0, 0)
-    if (e != hipSuccess) return hip_fail(e, "join setup");
-    int la = (int)a->height - 1, lb = (int)b->height - 1;
-    int cur = 0;
-    uint64_t lim = 1;   // level 0: the pair of roots
-    for (size_t L = 0; L < H; ++L) {
-        const int mode = mode_of(la, lb);
-        const bool emit = mode == JOIN_EMIT;
-        if (emit != (L + 1 == H)) return kReplayMiss;   // not the shape of the last run
-        if (lim == 0) return kReplayMiss;
-        const uint64_t next_lim =
-            emit ? w.keys.cap / 8 : std::min<uint64_t>(with_slack(rec[L + 1]), level_cap(1 - cur));
-        const uint64_t *nd = L == 0 ? nullptr : lv + L;
-        const uint2 *fr = w.fr[cur].as<uint2>();
-        uint64_t *off = w.off.as<uint64_t>();
-        uint16_t *slots = w.slot.as<uint16_t>();
-        e = launch_join_level(va, vb, fr, (uint32_t)lim, nd, mode, false, w.cnt.as<uint32_t>(), nullptr, nullptr,
-                              nullptr, 0, slots, ctrl, flags, nullptr, s);
-        if (e == hipSuccess)
-            e = launch_scan_u32_dev(w.cnt.as<uint32_t>(), nd, lim, off, w.stmp.as<uint64_t>(), lv + L + 1,
-                                    next_lim, over, s);
-        if (e == hipSuccess)
-            e = launch_join_level(va, vb, fr, (uint32_t)lim, nd, mode, true, nullptr, off,
-                                  emit ? nullptr : w.fr[1 - cur].as<uint2>(), emit ? w.keys.as<uint64_t>() : nullptr,
-                                  next_lim, slots, ctrl, flags, nullptr, s);
-        if (e != hipSuccess) return hip_fail(e, "join level");
-        cur = 1 - cur;
-        lim = next_lim;
-        descend(mode, la, lb);
+    // every launch of the replay; RT_OK, kReplayMiss or an error
+    auto enqueue = [&](hipStream_t st) -> int {
+        hipError_t e2 = launch_zero(ctrl, sizeof(Ctrl), st);
+        if (e2 == hipSuccess) e2 = launch_zero(lv, (H + 2) * 8, st);   // and the overflow flag
+        if (e2 == hipSuccess) e2 = launch_zero(w.fr[0].b.p, 8, st);   // (root A, root B) = (0, 0)
+        if (e2 != hipSuccess) return hip_fail(e2, "join setup");
+        int la = (int)a->height - 1, lb = (int)b->height - 1;
+        int cur = 0;
+        uint64_t lim = 1;   // level 0: the pair of roots
+        for (size_t L = 0; L < H; ++L) {
+            const int mode = mode_of(la, lb);
+            const bool emit = mode == JOIN_EMIT;
+            if (emit != (L + 1 == H)) return kReplayMiss;   // not the shape of the last run
+            if (lim == 0) return kReplayMiss;
+            const uint64_t next_lim =
+                emit ? w.keys.cap / 8 : std::min<uint64_t>(with_slack(rec[L + 1]), level_cap(1 - cur));
+            const uint64_t *nd = L == 0 ? nullptr : lv + L;
+            const uint2 *fr = w.fr[cur].as<uint2>();
+            uint64_t *off = w.off.as<uint64_t>();
+            uint16_t *slots = w.slot.as<uint16_t>();
+            e2 = launch_join_level(va, vb, fr, (uint32_t)lim, nd, mode, false, w.cnt.as<uint32_t>(), nullptr,
+                                   nullptr, nullptr, 0, slots, ctrl, flags, nullptr, st);
+            if (e2 == hipSuccess)
+                e2 = launch_scan_u32_dev(w.cnt.as<uint32_t>(), nd, lim, off, w.stmp.as<uint64_t>(), lv + L + 1,
+                                         next_lim, over, st);
+            if (e2 == hipSuccess)
+                e2 = launch_join_level(va, vb, fr, (uint32_t)lim, nd, mode, true, nullptr, off,
+                                       emit ? nullptr : w.fr[1 - cur].as<uint2>(),
+                                       emit ? w.keys.as<uint64_t>() : nullptr, next_lim, slots, ctrl, flags,
+                                       nullptr, st);
+            if (e2 != hipSuccess) return hip_fail(e2, "join level");
+            cur = 1 - cur;
+            lim = next_lim;
+            descend(mode, la, lb);
+        }
+        return RT_OK;
+    };
+    // what the launches depend on: both tree views, the flags, the level
+    // sizes of the last run and every buffer's address and size
+    std::vector<uint64_t> key;
+    auto put = [&key](const void *p, size_t n) {
+        const size_t w0 = key.size();
+        key.resize(w0 + (n + 7) / 8, 0);
+        std::memcpy(key.data() + w0, p, n);
+    };
+    put(&va, sizeof(va));
+    put(&vb, sizeof(vb));
+    key.push_back((uint64_t)(uint32_t)flags);
+    key.push_back(H);
+    key.insert(key.end(), rec.begin(), rec.end());
+    for (const Grow *g : {&w.ctrl, &w.lvl, &w.fr[0], &w.fr[1], &w.cnt, &w.off, &w.stmp, &w.slot, &w.keys}) {
+        key.push_back(reinterpret_cast<uint64_t>(g->b.p));
+        key.push_back(g->cap);
+    }
+    if (w.graph_exec && key == w.graph_key) {
+        e = hipGraphLaunch(w.graph_exec, s);
+        if (e != hipSuccess) return hip_fail(e, "join graph launch");
+    } else if (key == w.replay_key) {
+        // second replay of the same join in a row: capture it
+        if (w.graph_exec) (void)hipGraphExecDestroy(w.graph_exec);
+        if (w.graph) (void)hipGraphDestroy(w.graph);
+        w.graph_exec = nullptr;
+        w.graph = nullptr;
+        w.graph_key.clear();
+        if (!w.capture_stream) e = hipStreamCreateWithFlags(&w.capture_stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(w.capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "join graph capture");
+        const int rc = enqueue(w.capture_stream);
+        e = hipStreamEndCapture(w.capture_stream, &w.graph);
+        if (rc != RT_OK) {
+            if (w.graph) (void)hipGraphDestroy(w.graph);
+            w.graph = nullptr;
+            return rc;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&w.graph_exec, w.graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            w.graph_exec = nullptr;
+            return hip_fail(e, "join graph capture");
+        }
+        w.graph_key = key;
+        e = hipGraphLaunch(w.graph_exec, s);
+        if (e != hipSuccess) return hip_fail(e, "join graph launch");
+    } else {
+        w.replay_key = key;
+        if (int rc = enqueue(s)) return rc;
     }
     uint64_t tail[2] = {0, 0};   // key count, overflow flag
     uint32_t err = 0;

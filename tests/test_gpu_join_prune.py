@@ -246,3 +246,32 @@ def test_join_key_sort_paths(rt, ora):
         for flags in (None, rt.JOIN_TILE):
             got = rt.spatial_join(ta, tb, flags)
             assert np.array_equal(got, want), (name, flags, got.shape, want.shape)
+
+
+def test_join_graph_replays(rt, ora):
+    """A join repeated with the same trees is replayed from a captured graph
+    (from its third run on); other joins in between, host- and device-output
+    calls and a buffer that is too small all leave every result equal to the
+    oracle's."""
+    import torch
+    A = rtgen.uniform_rects(80_000, 2e-3, 81)
+    B = rtgen.clustered_rects(80_000, 16, 0.05, 2e-3, 82)
+    C = rtgen.uniform_rects(5_000, 5e-3, 83)
+    want = ora.join(ora.build_str(A, 32), ora.build_str(B, 32))
+    want_c = ora.join(ora.build_str(C, 32), ora.build_str(B, 32))
+    ta, tb = rt.build_str(A, 32, "soa", sort_lx=True), rt.build_str(B, 32, "soa", sort_lx=True)
+    tc = rt.build_str(C, 32, "soa", sort_lx=True)
+    n = want.shape[0]
+    buf = torch.empty(2 * n, dtype=torch.int32, device="cuda")
+    for rep in range(6):
+        say(f"case graph replay {rep}")
+        buf.fill_(7)
+        assert rt.spatial_join_device(ta, tb, buf.data_ptr(), n) == n
+        got = buf.cpu().numpy().view(np.uint32).reshape(-1, 2)
+        assert np.array_equal(got, want), rep
+        assert np.array_equal(rt.spatial_join(ta, tb), want), rep
+        if rep % 2:
+            assert np.array_equal(rt.spatial_join(tc, tb), want_c), rep
+        small = torch.full((2 * 10,), 7, dtype=torch.int32, device="cuda")
+        assert rt.spatial_join_device(ta, tb, small.data_ptr(), 10) == n
+        assert bool((small == 7).all())
