@@ -503,48 +503,86 @@ pair_bucket_scatter(const uint64_t *__restrict__ keys, uint64_t n, int shift, co
     }
 }
 
+// Bitonic sort of P (a power of two) keys in LDS by the block.
+__device__ __forceinline__ void lds_bitonic_u64(uint64_t *buf, uint32_t P) {
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const uint32_t l = i | j;
+                const uint64_t x = buf[i], y = buf[l];
+                const bool up = (i & k) == 0;
+                if ((x > y) == up) {
+                    buf[i] = y;
+                    buf[l] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Number of keys in v[0 .. n) below x (v sorted).
+__device__ __forceinline__ uint32_t count_below(const uint64_t *v, uint32_t n, uint64_t x) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (v[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // One block per bucket: bitonic sort in LDS over the bucket padded to a power
-// of two (keys are distinct; padding with all ones sorts last).
+// of two (keys are distinct; padding with all ones sorts last).  A bucket over
+// the LDS cap (ids far from uniform) is sorted in runs of the cap, which are
+// then merged pairwise through tmp (the partition's input, free by now) at the
+// bucket's own positions: every key finds its place as its index in its run
+// plus the number of keys below it in the other run.
 __global__ void __launch_bounds__(256)
-pair_bucket_sort(uint64_t *__restrict__ keys, const uint32_t *__restrict__ start, uint32_t *__restrict__ big) {
+pair_bucket_sort(uint64_t *__restrict__ keys, uint64_t *__restrict__ tmp, const uint32_t *__restrict__ start) {
     __shared__ uint64_t buf[kPairBucketCap];
     for (uint32_t bk = blockIdx.x; bk < kPairBuckets; bk += gridDim.x) {
         const uint32_t s0 = start[bk], c = start[bk + 1] - s0;
         if (c < 2) continue;
-        if (c > kPairBucketCap) {
-            if (threadIdx.x == 0) atomicAdd(big, 1u);
-            continue;
+        for (uint32_t r0 = 0; r0 < c; r0 += kPairBucketCap) {
+            const uint32_t rc = min(c - r0, kPairBucketCap);
+            uint32_t P = 2;
+            while (P < rc) P <<= 1;
+            for (uint32_t i = threadIdx.x; i < P; i += blockDim.x) buf[i] = i < rc ? keys[s0 + r0 + i] : ~0ull;
+            __syncthreads();
+            lds_bitonic_u64(buf, P);
+            for (uint32_t i = threadIdx.x; i < rc; i += blockDim.x) keys[s0 + r0 + i] = buf[i];
+            __syncthreads();
         }
-        uint32_t P = 2;
-        while (P < c) P <<= 1;
-        for (uint32_t i = threadIdx.x; i < P; i += 256) buf[i] = i < c ? keys[s0 + i] : ~0ull;
-        __syncthreads();
-        for (uint32_t k = 2; k <= P; k <<= 1) {
-            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-                for (uint32_t t = threadIdx.x; t < P / 2; t += 256) {
-                    const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                    const uint32_t l = i | j;
-                    const uint64_t x = buf[i], y = buf[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        buf[i] = y;
-                        buf[l] = x;
-                    }
-                }
-                __syncthreads();
+        if (c <= kPairBucketCap) continue;
+        uint64_t *src = keys + s0, *dst = tmp + s0;
+        for (uint32_t w = kPairBucketCap; w < c; w *= 2) {
+            for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) {
+                const uint32_t a0 = i / (2 * w) * (2 * w);
+                const uint32_t b0 = min(a0 + w, c), b1 = min(a0 + 2 * w, c);
+                const uint64_t x = src[i];
+                const uint32_t pos = i < b0 ? i + count_below(src + b0, b1 - b0, x)
+                                            : (i - b0) + a0 + count_below(src + a0, b0 - a0, x);
+                dst[pos] = x;
             }
+            __syncthreads();
+            uint64_t *t2 = src;
+            src = dst;
+            dst = t2;
         }
-        for (uint32_t i = threadIdx.x; i < c; i += 256) keys[s0 + i] = buf[i];
-        __syncthreads();
+        if (src != keys + s0) {
+            for (uint32_t i = threadIdx.x; i < c; i += blockDim.x) keys[s0 + i] = src[i];
+            __syncthreads();
+        }
     }
 }
 
-hipError_t launch_pair_bucket_sort(const uint64_t *keys, uint64_t n, int shift, uint64_t *out, uint32_t *ws,
-                                   uint32_t *big, hipStream_t s) {
+hipError_t launch_pair_bucket_sort(uint64_t *keys, uint64_t n, int shift, uint64_t *out, uint32_t *ws,
+                                   hipStream_t s) {
     if (n == 0) return hipSuccess;
     uint32_t *cnt = ws, *start = ws + kPairBuckets, *cursor = ws + 2 * kPairBuckets + 4;
     hipError_t e = launch_zero(cnt, 4 * kPairBuckets, s);
-    if (e == hipSuccess) e = launch_zero(big, 4, s);
     if (e != hipSuccess) return e;
     const uint64_t tiles = (n + kPairTile - 1) / kPairTile;
     const uint32_t cus = (uint32_t)num_cus();
@@ -553,7 +591,7 @@ hipError_t launch_pair_bucket_sort(const uint64_t *keys, uint64_t n, int shift, 
     hipLaunchKernelGGL(pair_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, start, cursor);
     const uint32_t sb = (uint32_t)(tiles < (uint64_t)cus * 8 ? tiles : (uint64_t)cus * 8);
     hipLaunchKernelGGL(pair_bucket_scatter, dim3(sb), dim3(256), 0, s, keys, n, shift, start, cursor, out);
-    hipLaunchKernelGGL(pair_bucket_sort, dim3(kPairBuckets), dim3(256), 0, s, out, start, big);
+    hipLaunchKernelGGL(pair_bucket_sort, dim3(kPairBuckets), dim3(256), 0, s, out, keys, start);
     return hipGetLastError();
 }
 

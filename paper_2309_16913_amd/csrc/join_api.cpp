@@ -102,23 +102,15 @@ int sort_keys(const rt_tree *a, const rt_tree *b, uint64_t total, hipStream_t s,
     uint64_t *src = w.keys.as<uint64_t>(), *tmp = w.ktmp.as<uint64_t>();
     // Up to ~1.5K keys per bucket on average: buckets by the top 11 bits of
     // the key (every key is below 2^(32 + ba)), each sorted in LDS; four
-    // launches against the LSD sort's twenty.  A bucket over the LDS cap
-    // (ids far from uniform) sends the keys to the LSD sort below.
+    // launches against the LSD sort's twenty.  Larger results keep the LSD
+    // sort (most buckets would exceed the LDS cap).
     if (total <= (uint64_t)kPairBuckets * 1536) {
         e = w.hist.need((kPairSortWords + 4) * 4);
-        uint32_t *ws = w.hist.as<uint32_t>();
-        uint32_t *big = ws + kPairSortWords;
-        if (e == hipSuccess) e = launch_pair_bucket_sort(src, total, 21 + ba, tmp, ws, big, s);
-        uint32_t nbig = 0;
-        if (e == hipSuccess) e = hipMemcpyAsync(&nbig, big, 4, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = launch_pair_bucket_sort(src, total, 21 + ba, tmp, w.hist.as<uint32_t>(), s);
         if (e != hipSuccess) return hip_fail(e, "join sort");
-        if (nbig == 0) {
-            w.npairs = total;
-            w.sorted = tmp;
-            return RT_OK;
-        }
-        std::swap(src, tmp);   // bucketed keys in full through the LSD sort
+        w.npairs = total;
+        w.sorted = tmp;
+        return RT_OK;
     }
     // 11-bit digits: 4 passes for two 21-bit ids instead of 6 (each pass
     // costs about the same few launches whatever its width)

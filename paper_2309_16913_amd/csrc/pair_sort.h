@@ -1,8 +1,9 @@
 // Sort of the join's pair keys ((idA << 32) | idB, all distinct) by their top
 // digit: the keys are split into kPairBuckets buckets by key >> shift (the
 // bucket order is the key order), and every bucket is then sorted on its own
-// in LDS.  Four launches where an LSD radix sort of two 21-bit ids needs four
-// passes of five.
+// in LDS (a bucket over the LDS cap in runs, merged through global memory).
+// Four launches where an LSD radix sort of two 21-bit ids needs four passes
+// of five.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,15 +15,14 @@ namespace rtk {
 constexpr uint32_t kPairBuckets = 2048;      // 11-bit top digit
 constexpr uint32_t kPairBucketCap = 4096;    // keys a bucket may hold to be sorted in LDS
 
-// Workspace (uint32 words) of launch_pair_bucket_sort: counts, starts,
-// cursors and the count of buckets over the cap.
+// Workspace (uint32 words) of launch_pair_bucket_sort: counts, starts and
+// cursors.
 constexpr uint64_t kPairSortWords = 3 * kPairBuckets + 8;
 
-// keys (n) -> out (n), sorted, except inside buckets of more than
-// kPairBucketCap keys: their number is stored in *big (device), and the
-// caller then sorts out in full by other means.  shift: every key is below
-// 2^(shift + 11).  ws: kPairSortWords uint32.
-hipError_t launch_pair_bucket_sort(const uint64_t *keys, uint64_t n, int shift, uint64_t *out, uint32_t *ws,
-                                   uint32_t *big, hipStream_t s);
+// keys (n) -> out (n), sorted; keys is overwritten (merge space for buckets
+// over the LDS cap).  shift: every key is below 2^(shift + 11).  ws:
+// kPairSortWords uint32.
+hipError_t launch_pair_bucket_sort(uint64_t *keys, uint64_t n, int shift, uint64_t *out, uint32_t *ws,
+                                   hipStream_t s);
 
 }  // namespace rtk

@@ -229,8 +229,9 @@ def test_join_workspace_reuse(rt, ora):
 def test_join_key_sort_paths(rt, ora):
     """The pair keys are split into 2048 buckets by their top bits and every
     bucket is sorted in LDS; a bucket over the LDS cap (one object meeting
-    20000 others) and a result over the bucketing limit (3.4M pairs) go
-    through the LSD radix sort instead.  Every path gives the oracle's pairs."""
+    20000 others) is sorted in runs merged through global memory, and a
+    result over the bucketing limit (3.4M pairs) goes through the LSD radix
+    sort instead.  Every path gives the oracle's pairs."""
     B = rtgen.uniform_rects(20_000, 0.01, 71)
     small = rtgen.uniform_rects(9_999, 0.01, 72)
     whole = np.array([[-1.0, -1.0, 2.0, 2.0]], np.float32)
