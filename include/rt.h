@@ -157,6 +157,11 @@ int rt_range_select(const rt_tree *t, const float *queries, uint64_t nq, rt_ids 
  * R-tree spatial join (section 4): all intersecting (a, b), a from tree a's
  * relation and b from tree b's.  Both trees must live on the same device.
  * Same as rt_spatial_join_ex(a, b, RT_JOIN_DEFAULT, out, NULL).
+ * All join calls draw their device workspaces from a per-device pool that
+ * the library keeps until the process ends; a join repeated with the same
+ * trees and flags is replayed from a HIP graph captured in that workspace
+ * (results are the same either way).  Concurrent calls use separate
+ * workspaces.
  */
 int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **out);
 
