@@ -422,6 +422,30 @@ __global__ void keys_to_pairs_kernel(const uint64_t *__restrict__ keys, uint64_t
     }
 }
 
+// The same with the count on the device (at most n_max): writes nothing if the
+// count exceeds capacity or *skip has bit 0 set.
+__global__ void keys_to_pairs_dev_kernel(const uint64_t *__restrict__ keys, const uint64_t *__restrict__ n_dev,
+                                         uint64_t capacity, const uint32_t *__restrict__ skip,
+                                         uint32_t *__restrict__ pairs) {
+    const uint64_t n = *n_dev;
+    if (n > capacity || (*skip & 1u)) return;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t k = keys[i];
+        pairs[2 * i] = (uint32_t)(k >> 32);
+        pairs[2 * i + 1] = (uint32_t)k;
+    }
+}
+
+hipError_t launch_keys_to_pairs_dev(const uint64_t *keys, const uint64_t *n_dev, uint64_t n_max, uint64_t capacity,
+                                    const uint32_t *skip, uint32_t *pairs, hipStream_t s) {
+    uint64_t blocks = (n_max + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(keys_to_pairs_dev_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, keys, n_dev, capacity, skip,
+                       pairs);
+    return hipGetLastError();
+}
+
 hipError_t launch_keys_to_pairs(const uint64_t *keys, uint64_t n, uint32_t *pairs, hipStream_t s) {
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + 255) / 256;
@@ -434,8 +458,10 @@ hipError_t launch_keys_to_pairs(const uint64_t *keys, uint64_t n, uint32_t *pair
 constexpr uint32_t kPairTile = 4096;   // keys per block in the scatter (256 x 16)
 
 __global__ void __launch_bounds__(256)
-pair_bucket_hist(const uint64_t *__restrict__ keys, uint64_t n, int shift, uint32_t *__restrict__ cnt) {
+pair_bucket_hist(const uint64_t *__restrict__ keys, uint64_t n, const uint64_t *__restrict__ n_dev, int shift,
+                 uint32_t *__restrict__ cnt) {
     __shared__ uint32_t h[kPairBuckets];
+    if (n_dev) n = min(n, *n_dev);
     for (uint32_t i = threadIdx.x; i < kPairBuckets; i += blockDim.x) h[i] = 0;
     __syncthreads();
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
@@ -475,10 +501,11 @@ pair_bucket_scan(const uint32_t *__restrict__ cnt, uint32_t *__restrict__ start,
 // per bucket present in the tile, then every key goes to its bucket.  The
 // order inside a bucket is arbitrary (the bucket is sorted next).
 __global__ void __launch_bounds__(256)
-pair_bucket_scatter(const uint64_t *__restrict__ keys, uint64_t n, int shift, const uint32_t *__restrict__ start,
-                    uint32_t *__restrict__ cursor, uint64_t *__restrict__ out) {
+pair_bucket_scatter(const uint64_t *__restrict__ keys, uint64_t n, const uint64_t *__restrict__ n_dev, int shift,
+                    const uint32_t *__restrict__ start, uint32_t *__restrict__ cursor, uint64_t *__restrict__ out) {
     constexpr uint32_t R = kPairTile / 256;
     __shared__ uint32_t c[kPairBuckets];
+    if (n_dev) n = min(n, *n_dev);
     for (uint64_t t0 = (uint64_t)blockIdx.x * kPairTile; t0 < n; t0 += (uint64_t)gridDim.x * kPairTile) {
         for (uint32_t i = threadIdx.x; i < kPairBuckets; i += 256) c[i] = 0;
         __syncthreads();
@@ -579,7 +606,7 @@ pair_bucket_sort(uint64_t *__restrict__ keys, uint64_t *__restrict__ tmp, const 
 }
 
 hipError_t launch_pair_bucket_sort(uint64_t *keys, uint64_t n, int shift, uint64_t *out, uint32_t *ws,
-                                   hipStream_t s) {
+                                   hipStream_t s, const uint64_t *n_dev) {
     if (n == 0) return hipSuccess;
     uint32_t *cnt = ws, *start = ws + kPairBuckets, *cursor = ws + 2 * kPairBuckets + 4;
     hipError_t e = launch_zero(cnt, 4 * kPairBuckets, s);
@@ -587,10 +614,10 @@ hipError_t launch_pair_bucket_sort(uint64_t *keys, uint64_t n, int shift, uint64
     const uint64_t tiles = (n + kPairTile - 1) / kPairTile;
     const uint32_t cus = (uint32_t)num_cus();
     const uint32_t hb = (uint32_t)(tiles < (uint64_t)cus * 4 ? tiles : (uint64_t)cus * 4);
-    hipLaunchKernelGGL(pair_bucket_hist, dim3(hb), dim3(256), 0, s, keys, n, shift, cnt);
+    hipLaunchKernelGGL(pair_bucket_hist, dim3(hb), dim3(256), 0, s, keys, n, n_dev, shift, cnt);
     hipLaunchKernelGGL(pair_bucket_scan, dim3(1), dim3(1024), 0, s, cnt, start, cursor);
     const uint32_t sb = (uint32_t)(tiles < (uint64_t)cus * 8 ? tiles : (uint64_t)cus * 8);
-    hipLaunchKernelGGL(pair_bucket_scatter, dim3(sb), dim3(256), 0, s, keys, n, shift, start, cursor, out);
+    hipLaunchKernelGGL(pair_bucket_scatter, dim3(sb), dim3(256), 0, s, keys, n, n_dev, shift, start, cursor, out);
     hipLaunchKernelGGL(pair_bucket_sort, dim3(kPairBuckets), dim3(256), 0, s, out, keys, start);
     return hipGetLastError();
 }

@@ -48,6 +48,7 @@ struct JoinRun {
     uint64_t npairs = 0;
     const uint64_t *sorted = nullptr;   // device, npairs keys
     uint64_t tests = 0;
+    bool pairs_done = false;            // the (a, b) words are already written (replay with sort)
     // frontier size of every level in the last join run level by level with
     // host reads (empty: none yet); sizes the grids of the replayed levels
     std::vector<uint64_t> last_levels;
@@ -150,7 +151,8 @@ inline void descend(int mode, int &la, int &lb) {
 // level sizes plus slack, and the host reads only the key count at the end.
 // A level that outgrew those bounds marks the run, which then returns
 // kReplayMiss (the caller runs level by level, growing the buffers).
-int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t s, JoinRun &w) {
+int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t s, JoinRun &w, uint32_t *d_out,
+                     uint64_t out_cap) {
     const std::vector<uint64_t> rec = w.last_levels;
     const size_t H = rec.size();
     if (H == 0) return kReplayMiss;
@@ -171,6 +173,21 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
         return std::min<uint64_t>(c, 0xFFFFFFFFull);
     };
     auto with_slack = [](uint64_t n) { return n + n / 4 + 1024; };
+    // When the key buffer is small enough for the bucket sort, the sort and
+    // the (a, b) words follow the levels with the key count on the device,
+    // so the whole join needs one host read: out receives the words (the
+    // caller's buffer, or for a host copy the key buffer, free by then),
+    // unless the count exceeds its capacity or a level overflowed.
+    const uint64_t kmax = w.keys.cap / 8;
+    const bool fused = kmax > 0 && kmax <= (uint64_t)kPairBuckets * 1536;
+    uint32_t *out = d_out ? d_out : w.keys.as<uint32_t>();
+    const uint64_t cap_out = d_out ? out_cap : kmax;
+    const int ba = bits_for(a->n_objects ? a->n_objects - 1 : 0);
+    if (fused) {
+        e = w.ktmp.need(kmax * 8);
+        if (e == hipSuccess) e = w.hist.need((kPairSortWords + 4) * 4);
+        if (e != hipSuccess) return hip_fail(e, "join setup");
+    }
     // every launch of the replay; RT_OK, kReplayMiss or an error
     auto enqueue = [&](hipStream_t st) -> int {
         hipError_t e2 = launch_zero(ctrl, sizeof(Ctrl), st);
@@ -206,6 +223,13 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
             lim = next_lim;
             descend(mode, la, lb);
         }
+        if (fused) {
+            e2 = launch_pair_bucket_sort(w.keys.as<uint64_t>(), kmax, 21 + ba, w.ktmp.as<uint64_t>(),
+                                         w.hist.as<uint32_t>(), st, lv + H);
+            if (e2 == hipSuccess)
+                e2 = launch_keys_to_pairs_dev(w.ktmp.as<uint64_t>(), lv + H, kmax, cap_out, over, out, st);
+            if (e2 != hipSuccess) return hip_fail(e2, "join sort");
+        }
         return RT_OK;
     };
     // what the launches depend on: both tree views, the flags, the level
@@ -221,10 +245,14 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
     key.push_back((uint64_t)(uint32_t)flags);
     key.push_back(H);
     key.insert(key.end(), rec.begin(), rec.end());
-    for (const Grow *g : {&w.ctrl, &w.lvl, &w.fr[0], &w.fr[1], &w.cnt, &w.off, &w.stmp, &w.slot, &w.keys}) {
+    for (const Grow *g : {&w.ctrl, &w.lvl, &w.fr[0], &w.fr[1], &w.cnt, &w.off, &w.stmp, &w.slot, &w.keys, &w.ktmp,
+                          &w.hist}) {
         key.push_back(reinterpret_cast<uint64_t>(g->b.p));
         key.push_back(g->cap);
     }
+    key.push_back(fused);
+    key.push_back(reinterpret_cast<uint64_t>(out));
+    key.push_back(cap_out);
     if (w.graph_exec && key == w.graph_key) {
         e = hipGraphLaunch(w.graph_exec, s);
         if (e != hipSuccess) return hip_fail(e, "join graph launch");
@@ -268,15 +296,25 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
     w.npairs = 0;
     w.sorted = nullptr;
     w.tests = 0;
+    if (fused) {
+        w.npairs = tail[0];
+        w.sorted = w.ktmp.as<uint64_t>();
+        w.pairs_done = true;
+        return RT_OK;
+    }
     return tail[0] ? sort_keys(a, b, tail[0], s, w) : RT_OK;
 }
 
-// Runs the join up to the sorted keys on the device.
-int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, hipStream_t s, JoinRun &w) {
+// Runs the join up to the sorted keys on the device; a replay may also write
+// the (a, b) words (w.pairs_done): to d_out if not NULL and the pairs fit
+// out_cap, else to the key buffer.
+int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, hipStream_t s, JoinRun &w,
+              uint32_t *d_out, uint64_t out_cap) {
     hipError_t e = w.ctrl.need(sizeof(Ctrl));
     if (e != hipSuccess) return hip_fail(e, "join setup");
+    w.pairs_done = false;
     if (!count_tests) {
-        const int rc = join_keys_replay(a, b, flags, s, w);
+        const int rc = join_keys_replay(a, b, flags, s, w, d_out, out_cap);
         if (rc != kReplayMiss) return rc;
     }
     // level by level, each level's size read on the host
@@ -389,7 +427,7 @@ extern "C" int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t fl
         hipStream_t s = nullptr;
         PooledRun run(a->device, s);
         JoinRun &w = *run.w;
-        rc = join_keys(a, b, flags, tests != nullptr, s, w);
+        rc = join_keys(a, b, flags, tests != nullptr, s, w, nullptr, 0);
         if (rc) return rc;
         if (tests) *tests = w.tests;
         void *mem = obj_alloc(KIND_PAIRS, sizeof(rt_pairs));
@@ -402,10 +440,11 @@ extern "C" int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t fl
             return fail(RT_ENOMEM, "host allocation failed");
         }
         if (w.npairs) {
-            // reuse the sort's other buffer for the (a, b) words
+            // reuse the sort's other buffer for the (a, b) words (where a
+            // replay has already written them)
             uint32_t *dp = const_cast<uint32_t *>(reinterpret_cast<const uint32_t *>(
                 w.sorted == w.keys.as<uint64_t>() ? w.ktmp.as<uint64_t>() : w.keys.as<uint64_t>()));
-            hipError_t e = launch_keys_to_pairs(w.sorted, w.npairs, dp, s);
+            hipError_t e = w.pairs_done ? hipSuccess : launch_keys_to_pairs(w.sorted, w.npairs, dp, s);
             if (e == hipSuccess) e = hipMemcpy(r->pairs, dp, w.npairs * 8, hipMemcpyDeviceToHost);
             if (e != hipSuccess) {
                 rt_free(r);
@@ -433,12 +472,13 @@ extern "C" int rt_spatial_join_device(const rt_tree *a, const rt_tree *b, int32_
         hipStream_t s = static_cast<hipStream_t>(stream);
         PooledRun run(a->device, s);
         JoinRun &w = *run.w;
-        rc = join_keys(a, b, flags, false, s, w);
+        rc = join_keys(a, b, flags, false, s, w, d_pairs, capacity);
         if (rc) return rc;
         *n_pairs = w.npairs;
         if (w.npairs > capacity)
             return fail(RT_ENOMEM, "join has %llu pairs, capacity %llu", (unsigned long long)w.npairs,
                         (unsigned long long)capacity);
+        if (w.pairs_done) return RT_OK;   // written and waited for by the replay
         hipError_t e = launch_keys_to_pairs(w.sorted, w.npairs, d_pairs, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "writing the pairs");

@@ -21,8 +21,14 @@ constexpr uint64_t kPairSortWords = 3 * kPairBuckets + 8;
 
 // keys (n) -> out (n), sorted; keys is overwritten (merge space for buckets
 // over the LDS cap).  shift: every key is below 2^(shift + 11).  ws:
-// kPairSortWords uint32.
+// kPairSortWords uint32.  n_dev (if not NULL): the key count on the device,
+// at most n (n then only sizes the grids).
 hipError_t launch_pair_bucket_sort(uint64_t *keys, uint64_t n, int shift, uint64_t *out, uint32_t *ws,
-                                   hipStream_t s);
+                                   hipStream_t s, const uint64_t *n_dev = nullptr);
+
+// Keys to (a, b) words with the count on the device (at most n_max): writes
+// nothing when the count exceeds capacity or bit 0 of *skip is set.
+hipError_t launch_keys_to_pairs_dev(const uint64_t *keys, const uint64_t *n_dev, uint64_t n_max, uint64_t capacity,
+                                    const uint32_t *skip, uint32_t *pairs, hipStream_t s);
 
 }  // namespace rtk
