@@ -56,7 +56,6 @@ struct JoinRun {
     // (same trees, flags, level sizes and buffers) is replayed a second time
     // in a row, relaunched while it stays the same
     std::vector<uint64_t> replay_key, graph_key;
-    hipStream_t capture_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
 };
@@ -263,11 +262,19 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
         w.graph_exec = nullptr;
         w.graph = nullptr;
         w.graph_key.clear();
-        if (!w.capture_stream) e = hipStreamCreateWithFlags(&w.capture_stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamBeginCapture(w.capture_stream, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return hip_fail(e, "join graph capture");
-        const int rc = enqueue(w.capture_stream);
-        e = hipStreamEndCapture(w.capture_stream, &w.graph);
+        // a stream of its own for the capture, destroyed right after: a
+        // stream kept alive holds one of the process's few hardware queues,
+        // which the caller's own streams would then share
+        hipStream_t cs = nullptr;
+        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            if (cs) (void)hipStreamDestroy(cs);
+            return hip_fail(e, "join graph capture");
+        }
+        const int rc = enqueue(cs);
+        e = hipStreamEndCapture(cs, &w.graph);
+        (void)hipStreamDestroy(cs);
         if (rc != RT_OK) {
             if (w.graph) (void)hipGraphDestroy(w.graph);
             w.graph = nullptr;
