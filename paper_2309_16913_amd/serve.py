@@ -25,6 +25,7 @@ events only.
 
 from __future__ import annotations
 
+import gc
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -287,6 +288,17 @@ class Server:
         real time.  `sink(req, offsets, ids)` receives every result as views
         into pinned staging memory that is reused by later batches (copy what
         must be kept)."""
+        # no garbage collection pass while serving: a full pass over the
+        # loop's objects stalls every request in flight for milliseconds
+        gc_was_on = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests, sink, time_scale)
+        finally:
+            if gc_was_on:
+                gc.enable()
+
+    def _run(self, requests, sink, time_scale: float) -> dict:
         reqs = sorted(requests, key=lambda r: r.t_arrival)
         adm = Admission(self.max_windows, self.slot_ids, self.pool_ids, self.one_per_batch)
         st = Stats()
