@@ -446,6 +446,13 @@ hipError_t launch_keys_to_pairs_dev(const uint64_t *keys, const uint64_t *n_dev,
     return hipGetLastError();
 }
 
+__global__ void copy_err_kernel(const Ctrl *__restrict__ ctrl, uint32_t *__restrict__ dst) { *dst = ctrl->err; }
+
+hipError_t launch_copy_err(const Ctrl *ctrl, uint32_t *dst, hipStream_t s) {
+    hipLaunchKernelGGL(copy_err_kernel, dim3(1), dim3(1), 0, s, ctrl, dst);
+    return hipGetLastError();
+}
+
 hipError_t launch_keys_to_pairs(const uint64_t *keys, uint64_t n, uint32_t *pairs, hipStream_t s) {
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + 255) / 256;

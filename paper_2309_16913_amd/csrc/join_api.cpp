@@ -57,6 +57,7 @@ struct JoinRun {
     // in a row, relaunched while it stays the same
     std::vector<uint64_t> replay_key, graph_key;
     hipGraph_t graph = nullptr;
+    uint64_t *host_tail = nullptr;      // pinned: key count, overflow flag | error word << 32
     hipGraphExec_t graph_exec = nullptr;
 };
 
@@ -229,6 +230,9 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
                 e2 = launch_keys_to_pairs_dev(w.ktmp.as<uint64_t>(), lv + H, kmax, cap_out, over, out, st);
             if (e2 != hipSuccess) return hip_fail(e2, "join sort");
         }
+        // the error word beside the overflow flag: the status is one read
+        e2 = launch_copy_err(ctrl, over + 1, st);
+        if (e2 != hipSuccess) return hip_fail(e2, "join status");
         return RT_OK;
     };
     // what the launches depend on: both tree views, the flags, the level
@@ -292,12 +296,18 @@ int join_keys_replay(const rt_tree *a, const rt_tree *b, int flags, hipStream_t 
         w.replay_key = key;
         if (int rc = enqueue(s)) return rc;
     }
-    uint64_t tail[2] = {0, 0};   // key count, overflow flag
-    uint32_t err = 0;
-    e = hipMemcpyAsync(tail, lv + H, 16, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(&err, &ctrl->err, 4, hipMemcpyDeviceToHost, s);
+    if (!w.host_tail) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&w.host_tail), 16, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            w.host_tail = nullptr;
+            return hip_fail(e, "join status buffer");
+        }
+    }
+    e = hipMemcpyAsync(w.host_tail, lv + H, 16, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "join status");
+    const uint64_t tail[2] = {w.host_tail[0], w.host_tail[1] & 0xFFFFFFFFull};   // key count, overflow flag
+    const uint32_t err = (uint32_t)(w.host_tail[1] >> 32);
     if (err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", err);
     if (tail[1] & 1u) return kReplayMiss;
     w.npairs = 0;

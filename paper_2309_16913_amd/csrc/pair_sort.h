@@ -31,4 +31,8 @@ hipError_t launch_pair_bucket_sort(uint64_t *keys, uint64_t n, int shift, uint64
 hipError_t launch_keys_to_pairs_dev(const uint64_t *keys, const uint64_t *n_dev, uint64_t n_max, uint64_t capacity,
                                     const uint32_t *skip, uint32_t *pairs, hipStream_t s);
 
+// Join status for a single read: *dst = ctrl->err (one thread).
+struct Ctrl;
+hipError_t launch_copy_err(const Ctrl *ctrl, uint32_t *dst, hipStream_t s);
+
 }  // namespace rtk
