@@ -720,7 +720,9 @@ int ora_check_tree(const ora_tree *t, const float *rects, char *msg, int msglen)
                 if (p >= t->n_nodes) { rc = fail(msg, msglen, 11, "child out of range", u, p); break; }
                 if (seen_node[p]) { rc = fail(msg, msglen, 12, "node reached twice", p, 0); break; }
                 seen_node[p] = 1;
+#if ORA_MUTANT != 11          /* mutant 11: levels are not compared */
                 if (t->level[p] + 1 != t->level[u]) { rc = fail(msg, msglen, 13, "child level", u, p); break; }
+#endif
                 uint32_t cc = t->count[p];
                 if (cc == 0 || t->first[p] + cc > t->n_entries) { rc = fail(msg, msglen, 14, "child entries", p, cc); break; }
                 float ulx = INFINITY, uly = INFINITY, uhx = -INFINITY, uhy = -INFINITY;
@@ -730,9 +732,11 @@ int ora_check_tree(const ora_tree *t, const float *rects, char *msg, int msglen)
                     if (t->hx[f] > uhx) uhx = t->hx[f];
                     if (t->hy[f] > uhy) uhy = t->hy[f];
                 }
+#if ORA_MUTANT != 10          /* mutant 10: the union comparison is skipped */
                 if (ulx != lx || uly != ly || uhx != hx || uhy != hy) {
                     rc = fail(msg, msglen, 15, "parent MBR != union of child entries", u, p); break;
                 }
+#endif
                 stack[sp++] = p;
             }
         }

@@ -291,3 +291,121 @@ ALL_PINS = [pin_handworked, pin_select_vs_brute, pin_join_vs_brute, pin_join_is_
             pin_closed_form_uniform, pin_closed_form_join, pin_tree_shape, pin_special_cases,
             pin_results_canonical, pin_m2m_worked_example, pin_m2m_flip_is_lower_bound,
             pin_join_pruned_vs_brute]
+
+
+# ---------------------------------------------------------------------------
+# the invariant checker rejects broken trees (section 2.3: a node holds up to
+# F entries (MBR, ptr) plus its level and entry count; an internal entry's MBR
+# bounds its child's entries)
+# ---------------------------------------------------------------------------
+
+def _corrupt_cases(A, rects):
+    """(name, arrays, rects to check against, expected code) for one fault
+    each, applied to the node/entry arrays A of a valid tree (height >= 3)."""
+    def cp():
+        return {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in A.items()}
+    lev, cnt, first, ptr = A["level"], A["count"], A["first"], A["ptr"]
+    root = int(A["root"])
+    r0 = int(first[root])                      # the root's first entry
+    child = int(ptr[r0])                       # an internal child of the root
+    assert lev[child] >= 1
+    leaves = np.nonzero(lev == 0)[0]
+    le = [int(first[u]) for u in leaves if cnt[u] >= 1]
+    out = []
+
+    B = cp()
+    B["hx"][r0] = np.nextafter(B["hx"][r0], np.float32(np.inf))
+    out.append(("parent MBR grown", B, rects, 15))
+    B = cp()
+    B["lx"][r0] = np.nextafter(B["lx"][r0], np.float32(np.inf))
+    out.append(("parent MBR shrunk", B, rects, 15))
+    B = cp()
+    B["ptr"][le[1]] = B["ptr"][le[0]]
+    out.append(("object twice", B, None, 9))
+    B = cp()
+    B["n_objects"] = int(A["n_objects"]) + 1
+    out.append(("object missing (count claims one more)", B, rects, 16))
+    # a real missing object: drop from a leaf an entry that lies strictly
+    # inside the union of its siblings (so no MBR above changes)
+    for u in leaves:
+        f0, c = int(first[u]), int(cnt[u])
+        if c < 3:
+            continue
+        E = np.stack([A["lx"][f0:f0 + c], A["ly"][f0:f0 + c], A["hx"][f0:f0 + c], A["hy"][f0:f0 + c]], 1)
+        for j in range(c):
+            o = np.delete(E, j, 0)
+            if (E[j, 0] > o[:, 0].min() and E[j, 1] > o[:, 1].min() and E[j, 2] < o[:, 2].max()
+                    and E[j, 3] < o[:, 3].max()):
+                B = cp()
+                last = f0 + c - 1
+                for k in ("lx", "ly", "hx", "hy", "ptr"):
+                    B[k][f0 + j], B[k][last] = B[k][last], B[k][f0 + j]
+                B["count"][u] = c - 1
+                out.append(("object missing (dropped from its leaf)", B, rects, 16))
+                break
+        else:
+            continue
+        break
+    else:
+        raise AssertionError("no leaf entry strictly inside its siblings' union")
+    R = np.array(rects, np.float32, copy=True)
+    k = int(ptr[le[2]])
+    R[k, 2] = np.nextafter(R[k, 2], np.float32(np.inf))
+    out.append(("leaf rectangle differs from the input", cp(), R, 10))
+    B = cp()
+    B["level"][child] += 1
+    out.append(("child level", B, rects, 13))
+    B = cp()
+    B["level"][root] += 1
+    out.append(("root level", B, rects, 3))
+    B = cp()
+    B["fanout"] = int(A["fanout"]) - 1
+    out.append(("count > F", B, rects, 4))
+    B = cp()
+    B["count"][child] = 0
+    out.append(("empty non-root node", B, rects, 14))
+    B = cp()
+    for k, v in (("level", 0), ("count", 1), ("first", 0)):
+        B[k] = np.append(B[k], np.array([v], B[k].dtype))
+    out.append(("unreachable node", B, rects, 17))
+    B = cp()
+    B["ptr"][r0 + 1] = B["ptr"][r0]
+    out.append(("node reached twice", B, rects, 12))
+    B = cp()
+    B["ptr"][r0] = B["level"].shape[0]
+    out.append(("child out of range", B, rects, 11))
+    B = cp()
+    B["lx"][r0] = np.float32(np.nan)
+    out.append(("NaN entry", B, rects, 7))
+    return out
+
+
+def pin_checker_rejects_corruptions(o):
+    """The invariant checker accepts the oracle's STR tree and the library's
+    tree shape (the numpy statement in str_shape.py), and returns the
+    distinct code of each single planted fault: parent MBR grown or shrunk,
+    an object twice or missing, a leaf rectangle unlike the input, a wrong
+    level, a node over F entries, an empty or unreachable node, a node
+    reached twice, a child out of range, a NaN entry."""
+    from str_shape import expected_export
+    r = rtgen.uniform_rects(2000, 2e-2, 4242)
+    trees = []
+    t = o.build_str(r, 8)
+    trees.append(("oracle STR", t.arrays()))
+    ex = expected_export(r, 8)
+    ex.update(root=0, fanout=8, n_objects=r.shape[0])
+    trees.append(("library shape", ex))
+    for what, A in trees:
+        assert int(A["height"]) >= 3
+        good = o.tree_from_arrays(**{k: A[k] for k in ("fanout", "height", "root", "n_objects", "level", "count",
+                                                       "first", "lx", "ly", "hx", "hy", "ptr")})
+        rc, msg = o.check(good, r)
+        assert rc == 0, (what, msg)
+        for name, B, rr, code in _corrupt_cases(A, r):
+            bad = o.tree_from_arrays(**{k: B[k] for k in ("fanout", "height", "root", "n_objects", "level",
+                                                          "count", "first", "lx", "ly", "hx", "hy", "ptr")})
+            rc, msg = o.check(bad, rr)
+            assert rc == code, f"{what}, {name}: checker returned {rc} ({msg}), expected {code}"
+
+
+ALL_PINS.append(pin_checker_rejects_corruptions)
