@@ -28,7 +28,7 @@ _lock = threading.Lock()
 
 def build(out_path: str = LIB_PATH, mutant: int = 0) -> str:
     """Compile the oracle with gcc (plain C99, -O2, no vector intrinsics)."""
-    cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-D_GNU_SOURCE",
+    cmd = ["gcc", "-std=c99", "-O2", "-fPIC", "-shared", "-pthread", "-D_GNU_SOURCE",
            f"-DORA_MUTANT={int(mutant)}", _SRC, "-o", out_path + ".tmp", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(out_path + ".tmp", out_path)
@@ -77,6 +77,9 @@ class Oracle:
         L.ora_select.argtypes = [T, C.POINTER(C.c_float), C.c_uint64, C.POINTER(C.c_uint64),
                                  C.POINTER(C.POINTER(C.c_uint32)), C.POINTER(C.c_uint64)]
         L.ora_join.argtypes = [T, T, C.POINTER(C.POINTER(C.c_uint32)), C.POINTER(C.c_uint64)]
+        L.ora_select_mt.argtypes = [T, C.POINTER(C.c_float), C.c_uint64, C.c_int, C.POINTER(C.c_uint64),
+                                    C.POINTER(C.POINTER(C.c_uint32)), C.POINTER(C.c_uint64)]
+        L.ora_join_mt.argtypes = [T, T, C.c_int, C.POINTER(C.POINTER(C.c_uint32)), C.POINTER(C.c_uint64)]
         L.ora_brute_select.argtypes = [C.POINTER(C.c_float), C.c_uint64, C.POINTER(C.c_float),
                                        C.c_uint64, C.POINTER(C.c_uint64),
                                        C.POINTER(C.POINTER(C.c_uint32)), C.POINTER(C.c_uint64)]
@@ -124,6 +127,19 @@ class Oracle:
             raise MemoryError("oracle select failed")
         return off, self._take_ids(pids, total)
 
+    def select_mt(self, tree: "OraTree", queries, nthreads: int):
+        """select() with the queries cut into nthreads contiguous parts, one
+        host thread each (a timing baseline; same result as select())."""
+        q = _rects(queries)
+        off = np.zeros(q.shape[0] + 1, dtype=np.uint64)
+        pids = C.POINTER(C.c_uint32)()
+        total = C.c_uint64()
+        rc = self.L.ora_select_mt(C.byref(tree.t), _fptr(q), q.shape[0], int(nthreads), _u64ptr(off),
+                                  C.byref(pids), C.byref(total))
+        if rc:
+            raise MemoryError("oracle select failed")
+        return off, self._take_ids(pids, total)
+
     def brute_select(self, rects, queries):
         r, q = _rects(rects), _rects(queries)
         off = np.zeros(q.shape[0] + 1, dtype=np.uint64)
@@ -147,6 +163,15 @@ class Oracle:
         pp = C.POINTER(C.c_uint32)()
         n = C.c_uint64()
         if self.L.ora_join(C.byref(a.t), C.byref(b.t), C.byref(pp), C.byref(n)):
+            raise MemoryError("oracle join failed")
+        return self._take_pairs(pp, n)
+
+    def join_mt(self, a: "OraTree", b: "OraTree", nthreads: int) -> np.ndarray:
+        """join() with the intersecting root-entry pairs dealt to nthreads host
+        threads (a timing baseline; same result as join())."""
+        pp = C.POINTER(C.c_uint32)()
+        n = C.c_uint64()
+        if self.L.ora_join_mt(C.byref(a.t), C.byref(b.t), int(nthreads), C.byref(pp), C.byref(n)):
             raise MemoryError("oracle join failed")
         return self._take_pairs(pp, n)
 

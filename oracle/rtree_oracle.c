@@ -48,6 +48,10 @@
  *     the same stop for a batch of 16 outer children by the gather / compare /
  *     update rounds of the many-to-many approach.  Same pairs as the join.
  *   - Brute force: nested loops over the plain definitions above.
+ *   - Threaded drivers (ora_select_mt, ora_join_mt): the same search and
+ *     join run on several host threads over a static partition of the
+ *     queries (or of the intersecting root-entry pairs), for the all-cores
+ *     timing baseline; the results are those of the single-thread calls.
  *   - Tree invariants: every parent entry MBR equals the exact union of its
  *     child's entries, every object appears in exactly one leaf entry with its
  *     own rectangle, levels decrease by one per edge down to 0 at every leaf,
@@ -57,6 +61,7 @@
  * only by the test that shows the pins catch such mistakes).
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -381,6 +386,21 @@ static int join_fixed_b(const ora_tree *A, uint32_t u, const ora_tree *B, uint64
     return 0;
 }
 
+static int join_nodes(const ora_tree *A, uint32_t u, const ora_tree *B, uint32_t v, vec64 *out);
+
+/* entry e of A's node u and entry f of B's node v intersect: emit the pair
+ * (both leaves), descend both (both internal), or descend the internal side
+ * with the leaf entry fixed */
+static int join_entries(const ora_tree *A, uint32_t u, uint64_t e, const ora_tree *B, uint32_t v, uint64_t f,
+                        vec64 *out)
+{
+    int la = A->level[u] == 0, lb = B->level[v] == 0;
+    if (la && lb) return emit(out, A->ptr[e], B->ptr[f]);
+    if (!la && !lb) return join_nodes(A, A->ptr[e], B, B->ptr[f], out);
+    if (la) return join_fixed_a(A, e, B, B->ptr[f], out);
+    return join_fixed_b(A, A->ptr[e], B, f, out);
+}
+
 static int join_nodes(const ora_tree *A, uint32_t u, const ora_tree *B, uint32_t v, vec64 *out)
 {
     uint64_t e0 = A->first[u], e1 = e0 + A->count[u];
@@ -390,12 +410,7 @@ static int join_nodes(const ora_tree *A, uint32_t u, const ora_tree *B, uint32_t
             if (!overlap4(A->lx[e], A->ly[e], A->hx[e], A->hy[e],
                           B->lx[f], B->ly[f], B->hx[f], B->hy[f]))
                 continue;
-            int la = A->level[u] == 0, lb = B->level[v] == 0;
-            int rc;
-            if (la && lb) rc = emit(out, A->ptr[e], B->ptr[f]);
-            else if (!la && !lb) rc = join_nodes(A, A->ptr[e], B, B->ptr[f], out);
-            else if (la) rc = join_fixed_a(A, e, B, B->ptr[f], out);
-            else rc = join_fixed_b(A, A->ptr[e], B, f, out);
+            int rc = join_entries(A, u, e, B, v, f, out);
             if (rc) return rc;
         }
     }
@@ -409,6 +424,145 @@ int ora_join(const ora_tree *A, const ora_tree *B, uint32_t **pairs_out, uint64_
     if (A->n_nodes > 0 && B->n_nodes > 0 && A->n_objects > 0 && B->n_objects > 0) {
         if (join_nodes(A, A->root, B, B->root, &acc)) { free(acc.v); return -2; }
     }
+    qsort(acc.v, acc.n, sizeof(uint64_t), cmp_u64);
+    uint32_t *p = (uint32_t *)malloc((acc.n ? acc.n : 1) * 2 * sizeof(uint32_t));
+    if (!p) { free(acc.v); return -2; }
+    for (size_t i = 0; i < acc.n; i++) {
+        p[2 * i] = (uint32_t)(acc.v[i] >> 32);
+        p[2 * i + 1] = (uint32_t)(acc.v[i] & 0xFFFFFFFFu);
+    }
+    free(acc.v);
+    *pairs_out = p;
+    *n_out = acc.n;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* the same select and join spread over host threads (a timing baseline for  */
+/* all host cores; results are those of ora_select and ora_join)             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    const ora_tree *t;
+    const float *q;
+    uint64_t q0, q1;          /* this thread's queries [q0, q1) */
+    uint64_t *counts;         /* ids per query, indexed like the queries */
+    vec32 ids;
+    int rc;
+} sel_part;
+
+static void *sel_worker(void *arg)
+{
+    sel_part *p = (sel_part *)arg;
+    for (uint64_t k = p->q0; k < p->q1; k++) {
+        size_t start = p->ids.n;
+        if (p->t->n_nodes > 0 && search(p->t, p->t->root, p->q + 4 * k, &p->ids)) { p->rc = -2; return NULL; }
+#if ORA_MUTANT != 6
+        qsort(p->ids.v + start, p->ids.n - start, sizeof(uint32_t), cmp_u32);
+#endif
+        p->counts[k] = p->ids.n - start;
+    }
+    return NULL;
+}
+
+/* ora_select with the queries cut into nthreads contiguous parts, one thread
+ * each (static partition) */
+int ora_select_mt(const ora_tree *t, const float *queries, uint64_t nq, int nthreads,
+                  uint64_t *offsets, uint32_t **ids_out, uint64_t *total)
+{
+    if (nthreads < 1) nthreads = 1;
+    sel_part *parts = (sel_part *)calloc((size_t)nthreads, sizeof(sel_part));
+    pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!parts || !th) { free(parts); free(th); return -2; }
+    for (int i = 0; i < nthreads; i++) {
+        parts[i].t = t;
+        parts[i].q = queries;
+        parts[i].q0 = nq * (uint64_t)i / (uint64_t)nthreads;
+        parts[i].q1 = nq * (uint64_t)(i + 1) / (uint64_t)nthreads;
+        parts[i].counts = offsets + 1;
+    }
+    int started = 0, rc = 0;
+    for (; started < nthreads; started++)
+        if (pthread_create(&th[started], NULL, sel_worker, &parts[started])) { rc = -2; break; }
+    for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
+    uint64_t n = 0;
+    for (int i = 0; i < nthreads && !rc; i++) {
+        if (parts[i].rc) rc = parts[i].rc;
+        n += parts[i].ids.n;
+    }
+    uint32_t *all = rc ? NULL : (uint32_t *)malloc((size_t)(n ? n : 1) * sizeof(uint32_t));
+    if (!rc && !all) rc = -2;
+    if (!rc) {
+        uint64_t at = 0;
+        for (int i = 0; i < nthreads; i++) {
+            if (parts[i].ids.n) memcpy(all + at, parts[i].ids.v, parts[i].ids.n * sizeof(uint32_t));
+            at += parts[i].ids.n;
+        }
+        offsets[0] = 0;
+        for (uint64_t k = 0; k < nq; k++) offsets[k + 1] += offsets[k];
+        *ids_out = all;
+        *total = n;
+    }
+    for (int i = 0; i < nthreads; i++) free(parts[i].ids.v);
+    free(parts); free(th);
+    return rc;
+}
+
+typedef struct {
+    const ora_tree *A, *B;
+    const uint64_t *pe, *pf;  /* intersecting root entry pairs */
+    uint64_t npairs;
+    int tid, nthreads;        /* this thread takes pairs tid, tid + nthreads, ... */
+    vec64 out;
+    int rc;
+} join_part;
+
+static void *join_worker(void *arg)
+{
+    join_part *p = (join_part *)arg;
+    for (uint64_t k = (uint64_t)p->tid; k < p->npairs; k += (uint64_t)p->nthreads)
+        if (join_entries(p->A, p->A->root, p->pe[k], p->B, p->B->root, p->pf[k], &p->out)) { p->rc = -2; break; }
+    return NULL;
+}
+
+/* ora_join with the intersecting pairs of root entries dealt round-robin to
+ * nthreads threads */
+int ora_join_mt(const ora_tree *A, const ora_tree *B, int nthreads, uint32_t **pairs_out, uint64_t *n_out)
+{
+    if (nthreads < 1) nthreads = 1;
+    vec64 acc = {0, 0, 0};
+    int rc = 0;
+    if (A->n_nodes > 0 && B->n_nodes > 0 && A->n_objects > 0 && B->n_objects > 0) {
+        uint64_t e0 = A->first[A->root], e1 = e0 + A->count[A->root];
+        uint64_t f0 = B->first[B->root], f1 = f0 + B->count[B->root];
+        uint64_t cap = (e1 - e0) * (f1 - f0), np = 0;
+        uint64_t *pe = (uint64_t *)malloc((size_t)(cap ? cap : 1) * sizeof(uint64_t));
+        uint64_t *pf = (uint64_t *)malloc((size_t)(cap ? cap : 1) * sizeof(uint64_t));
+        join_part *parts = (join_part *)calloc((size_t)nthreads, sizeof(join_part));
+        pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+        if (!pe || !pf || !parts || !th) rc = -2;
+        for (uint64_t e = e0; e < e1 && !rc; e++)
+            for (uint64_t f = f0; f < f1; f++)
+                if (overlap4(A->lx[e], A->ly[e], A->hx[e], A->hy[e], B->lx[f], B->ly[f], B->hx[f], B->hy[f])) {
+                    pe[np] = e;
+                    pf[np] = f;
+                    np++;
+                }
+        int started = 0;
+        for (; !rc && started < nthreads; started++) {
+            parts[started] = (join_part){A, B, pe, pf, np, started, nthreads, {0, 0, 0}, 0};
+            if (pthread_create(&th[started], NULL, join_worker, &parts[started])) { rc = -2; break; }
+        }
+        for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
+        for (int i = 0; i < started && !rc; i++) {
+            if (parts[i].rc) { rc = parts[i].rc; break; }
+            for (size_t k = 0; k < parts[i].out.n; k++)
+                if (v64_push(&acc, parts[i].out.v[k])) { rc = -2; break; }
+        }
+        for (int i = 0; i < started; i++) free(parts[i].out.v);
+        free(pe); free(pf); free(parts); free(th);
+    }
+    if (rc) { free(acc.v); return rc; }
     qsort(acc.v, acc.n, sizeof(uint64_t), cmp_u64);
     uint32_t *p = (uint32_t *)malloc((acc.n ? acc.n : 1) * 2 * sizeof(uint32_t));
     if (!p) { free(acc.v); return -2; }

@@ -178,8 +178,12 @@ __global__ void str_write_level(const uint64_t *__restrict__ order, const float4
     }
 }
 
-// Leaf ranges: a leaf covers [g, g + 1); the one leaf with fewer than F
-// entries is reported in partial[0..1] = {leaf, count}.
+// Leaf ranges: a leaf covers [g, g + 1).  Leaves with fewer than F entries
+// are counted in partial[2] and the first one found is reported in
+// partial[0..1] = {leaf, count}.  The packer fills every leaf but the last
+// one of the level, and the contained-subtree arithmetic of the select
+// kernels relies on that (at most one short leaf), so the host refuses a
+// tree whose count is above one.
 __global__ void str_range_leaves(uint32_t first, uint32_t n, uint32_t F, const uint32_t *__restrict__ meta,
                                  uint2 *__restrict__ range, uint32_t *__restrict__ partial) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -187,8 +191,10 @@ __global__ void str_range_leaves(uint32_t first, uint32_t n, uint32_t F, const u
         range[g] = make_uint2(g, g + 1);
         const uint32_t cnt = meta[g] & 0xFFu;
         if (cnt < F) {
-            partial[0] = g;
-            partial[1] = cnt;
+            if (atomicAdd(&partial[2], 1u) == 0u) {
+                partial[0] = g;
+                partial[1] = cnt;
+            }
         }
     }
 }
@@ -376,8 +382,8 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
         e = hipGetLastError();
     }
     // leaf ranges, bottom up, and the leaf that is not full
-    const uint32_t no_partial[2] = {0xFFFFFFFFu, F};
-    if (e == hipSuccess) e = hipMemcpyAsync(partial, no_partial, 8, hipMemcpyHostToDevice, s);
+    const uint32_t no_partial[3] = {0xFFFFFFFFu, F, 0u};
+    if (e == hipSuccess) e = hipMemcpyAsync(partial, no_partial, 12, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(str_range_leaves, dim3(grid_for(nodes[0])), dim3(256), 0, s, (uint32_t)first[0],
                            (uint32_t)nodes[0], F, static_cast<const uint32_t *>(t->d_meta),
@@ -390,8 +396,8 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
                            static_cast<const uint32_t *>(t->d_meta), static_cast<uint2 *>(t->d_range));
         e = hipGetLastError();
     }
-    uint32_t hpartial[2] = {0xFFFFFFFFu, F};
-    if (e == hipSuccess) e = hipMemcpyAsync(hpartial, partial, 8, hipMemcpyDeviceToHost, s);
+    uint32_t hpartial[3] = {0xFFFFFFFFu, F, 0u};
+    if (e == hipSuccess) e = hipMemcpyAsync(hpartial, partial, 12, hipMemcpyDeviceToHost, s);
     float4 root = make_float4(NAN, NAN, NAN, NAN);
     uint32_t hflag = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&root, mbr(H - 1), 16, hipMemcpyDeviceToHost, s);
@@ -399,6 +405,7 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(hip_fail(e, "device build"));
     if (hflag) return bail(fail(RT_EINVAL, "rects contain a NaN coordinate or low > high"));
+    if (hpartial[2] > 1) return bail(fail(RT_EDEVICE, "packing left %u leaves short of %u entries", hpartial[2], F));
     t->partial_leaf = hpartial[0];
     t->partial_cnt = hpartial[1];
     t->mbr[0] = root.x;

@@ -409,3 +409,30 @@ def pin_checker_rejects_corruptions(o):
 
 
 ALL_PINS.append(pin_checker_rejects_corruptions)
+
+
+def pin_threaded_drivers_match(o):
+    """The threaded select and join (timing baseline for all host cores)
+    return exactly the single-thread results, for thread counts that do and
+    do not divide the work, and on empty inputs."""
+    r = rtgen.clustered_rects(30_000, 8, 0.05, 3e-3, 31)
+    q = rtgen.windows_loguniform(777, 1e-6, 1e-2, 32)
+    t = o.build_str(r, 16)
+    off, ids = o.select(t, q)
+    for nt in (1, 3, 8, 1000):
+        off2, ids2 = o.select_mt(t, q, nt)
+        assert np.array_equal(off, off2) and np.array_equal(ids, ids2), nt
+    off2, ids2 = o.select_mt(t, q[:0], 4)
+    assert off2.tolist() == [0] and ids2.size == 0
+    A = rtgen.uniform_rects(8000, 4e-3, 33)
+    B = rtgen.clustered_rects(9000, 4, 0.05, 4e-3, 34)
+    for Fa, Fb in ((8, 8), (4, 32)):   # equal and unequal heights
+        ta, tb = o.build_str(A, Fa), o.build_str(B, Fb)
+        want = o.join(ta, tb)
+        for nt in (1, 5, 64):
+            assert np.array_equal(o.join_mt(ta, tb, nt), want), (Fa, Fb, nt)
+    e = o.build_str(np.zeros((0, 4), np.float32), 8)
+    assert o.join_mt(e, ta, 4).shape == (0, 2)
+
+
+ALL_PINS.append(pin_threaded_drivers_match)
