@@ -53,7 +53,8 @@ enum {
 /* Node storage layouts (section 2.3).  AOS is layout D0: each entry's five
  * fields contiguous.  SOA is layout D1: per node, arrays lx[F], ly[F], hx[F],
  * hy[F], ptr[F].  D2 is layout D2: lo[2F] (x,y pairs), hi[2F], ptr[F].
- * AUTO lets rt_build_str pick (SOA). */
+ * AUTO lets the builder choose among the three by timing (see
+ * rt_build_str). */
 enum { RT_LAYOUT_AOS = 0, RT_LAYOUT_SOA = 1, RT_LAYOUT_AUTO = 2, RT_LAYOUT_D2 = 3 };
 
 /* Build option, OR-ed into the layout argument of the builders: store the
@@ -130,9 +131,20 @@ typedef struct rt_tree_info {
  * the children of every node contiguous in entry order.
  *   rects   host, n*4 floats; NaN or lx > hx or ly > hy -> RT_EINVAL;
  *           +-Inf allowed.  n = 0 gives an empty tree (one empty leaf).
- *   fanout  maximum entries per node F, 2..64 (0 = 32).
- *   layout  RT_LAYOUT_*, optionally OR-ed with RT_BUILD_SORT_LX.
+ *   fanout  maximum entries per node F, 2..64, or 0: chosen by the library.
+ *   layout  RT_LAYOUT_*, optionally OR-ed with RT_BUILD_SORT_LX;
+ *           RT_LAYOUT_AUTO: chosen by the library.
  *   out     receives the tree; free with rt_free.
+ * Library choice (fanout 0 and/or RT_LAYOUT_AUTO): every candidate tree
+ * (fanouts 16, 32, 64 and/or layouts D0, D1, D2) is built on the device and
+ * a probe set of windows drawn from the data (centred on seeded objects,
+ * area log-uniform in [1e-6, 1e-3] of the data's bounding box) is selected on
+ * it; the fastest is kept, together with the faster split mapping
+ * (rt_tree_set_split 0 or 16).  The choice is cached per (device
+ * architecture, log2 n, candidate sets, RT_BUILD_SORT_LX) in memory and
+ * appended to the text file $RT_TUNE_CACHE (empty: memory only; unset:
+ * $HOME/.cache/rt_mi355x_tune.txt), so later builds with the same key do
+ * no timing.  rt_tree_stats reports the choice.
  */
 int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uint32_t layout,
                  rt_tree **out);
@@ -220,6 +232,46 @@ int rt_range_select_device_timed(const rt_tree *t, const float *d_queries, uint6
                                  uint64_t *d_offsets, uint32_t *d_ids, uint64_t ids_capacity,
                                  void *d_work, uint64_t work_bytes, uint64_t *d_status,
                                  void *stream, void *const *events);
+
+/*
+ * Range select (section 3) into caller-owned device buffers, the output
+ * placed by the caller.  The library keeps the workspace (a per-device pool,
+ * held until the process ends; a workspace is reused only after the work
+ * enqueued on it has finished).
+ *   d_queries    device, nq*4 floats, 16-byte aligned (not validated: the
+ *                caller guarantees no NaN and lx <= hx, ly <= hy)
+ *   d_offsets    device, nq+1 uint64: the CSR offsets (always written)
+ *   d_ids        device, ids_capacity uint32: the ids, ascending per query
+ *   d_total      device, 1 uint64: the number of ids of the result (written
+ *                in both outcomes below; all ones if a kernel-side check
+ *                failed, an internal error)
+ *   stream       hipStream_t (NULL = default stream)
+ * The call enqueues the count stage on `stream` and waits for it (it reads
+ * the total back).  If the result has more than ids_capacity ids it returns
+ * RT_ENOMEM and nothing is written to d_ids; otherwise it enqueues the fill
+ * stage and the sort and returns RT_OK without waiting for them: d_ids and
+ * the final *d_total are valid once `stream` has reached this point.
+ * RT_EINVAL for NULL buffers or misaligned queries, RT_EDEVICE for HIP
+ * errors.
+ */
+int rt_range_select_async(const rt_tree *t, const float *d_queries, uint64_t nq, uint64_t *d_offsets,
+                          uint32_t *d_ids, uint64_t ids_capacity, uint64_t *d_total, void *stream);
+
+/* rt_range_select_device in two calls, for callers that decide where the
+ * output goes (or whether it is run at all) once its exact size is known.
+ * The count stage computes d_offsets (nq+1 uint64, d_offsets[nq] = total
+ * ids) and leaves the processing order and split plan in d_work; the fill
+ * stage, enqueued later with the same tree, queries, d_offsets and d_work
+ * (whose first rt_select_workspace_bytes(nq, 0) bytes must be unchanged),
+ * writes the ids and d_status as rt_range_select_device does.  A count stage
+ * may be followed by no fill stage.  Both only enqueue on `stream`.
+ * work_bytes: at least rt_select_workspace_bytes(nq, 0) for the count stage
+ * and rt_select_workspace_bytes(nq, ids_capacity) for the fill stage. */
+int rt_range_select_device_count(const rt_tree *t, const float *d_queries, uint64_t nq, uint64_t *d_offsets,
+                                 void *d_work, uint64_t work_bytes, void *stream);
+int rt_range_select_device_fill(const rt_tree *t, const float *d_queries, uint64_t nq, uint64_t *d_offsets,
+                                uint32_t *d_ids, uint64_t ids_capacity, void *d_work, uint64_t work_bytes,
+                                uint64_t *d_status, void *stream);
 
 /* Count pass only: d_counts[q] = number of objects intersecting query q
  * (device, nq uint32).  Used to size outputs before admitting work. */

@@ -508,10 +508,46 @@ int ora_select_mt(const ora_tree *t, const float *queries, uint64_t nq, int nthr
     return rc;
 }
 
+/* intersecting entry pairs (entry e of A's node u, entry f of B's node v) */
+typedef struct { uint64_t *u, *e, *v, *f; size_t n, cap; } pairvec;
+
+static int pv_push(pairvec *p, uint64_t u, uint64_t e, uint64_t v, uint64_t f)
+{
+    if (p->n == p->cap) {
+        size_t nc = p->cap ? p->cap * 2 : 256;
+        uint64_t *a = (uint64_t *)realloc(p->u, nc * sizeof(uint64_t));
+        if (a) p->u = a;
+        uint64_t *b = (uint64_t *)realloc(p->e, nc * sizeof(uint64_t));
+        if (b) p->e = b;
+        uint64_t *c = (uint64_t *)realloc(p->v, nc * sizeof(uint64_t));
+        if (c) p->v = c;
+        uint64_t *d = (uint64_t *)realloc(p->f, nc * sizeof(uint64_t));
+        if (d) p->f = d;
+        if (!a || !b || !c || !d) return -1;
+        p->cap = nc;
+    }
+    p->u[p->n] = u; p->e[p->n] = e; p->v[p->n] = v; p->f[p->n] = f;
+    p->n++;
+    return 0;
+}
+
+static void pv_free(pairvec *p) { free(p->u); free(p->e); free(p->v); free(p->f); }
+
+/* every intersecting entry pair of A's node u and B's node v */
+static int pv_node_pairs(const ora_tree *A, uint32_t u, const ora_tree *B, uint32_t v, pairvec *out)
+{
+    uint64_t e0 = A->first[u], e1 = e0 + A->count[u];
+    uint64_t f0 = B->first[v], f1 = f0 + B->count[v];
+    for (uint64_t e = e0; e < e1; e++)
+        for (uint64_t f = f0; f < f1; f++)
+            if (overlap4(A->lx[e], A->ly[e], A->hx[e], A->hy[e], B->lx[f], B->ly[f], B->hx[f], B->hy[f]))
+                if (pv_push(out, u, e, v, f)) return -2;
+    return 0;
+}
+
 typedef struct {
     const ora_tree *A, *B;
-    const uint64_t *pe, *pf;  /* intersecting root entry pairs */
-    uint64_t npairs;
+    const pairvec *work;
     int tid, nthreads;        /* this thread takes pairs tid, tid + nthreads, ... */
     vec64 out;
     int rc;
@@ -520,37 +556,51 @@ typedef struct {
 static void *join_worker(void *arg)
 {
     join_part *p = (join_part *)arg;
-    for (uint64_t k = (uint64_t)p->tid; k < p->npairs; k += (uint64_t)p->nthreads)
-        if (join_entries(p->A, p->A->root, p->pe[k], p->B, p->B->root, p->pf[k], &p->out)) { p->rc = -2; break; }
+    const pairvec *w = p->work;
+    for (size_t k = (size_t)p->tid; k < w->n; k += (size_t)p->nthreads)
+        if (join_entries(p->A, (uint32_t)w->u[k], w->e[k], p->B, (uint32_t)w->v[k], w->f[k], &p->out)) {
+            p->rc = -2;
+            break;
+        }
     return NULL;
 }
 
-/* ora_join with the intersecting pairs of root entries dealt round-robin to
- * nthreads threads */
+/* ora_join on nthreads threads.  The intersecting entry pairs of the two
+ * roots are expanded level by level -- a pair of internal entries is
+ * replaced by the intersecting entry pairs of their two children, which is
+ * what the join does next with it -- until there are at least 64 pairs per
+ * thread (or only pairs with a leaf side are left); the pairs are then dealt
+ * round-robin to the threads, each finishing its pairs as the join would. */
 int ora_join_mt(const ora_tree *A, const ora_tree *B, int nthreads, uint32_t **pairs_out, uint64_t *n_out)
 {
     if (nthreads < 1) nthreads = 1;
     vec64 acc = {0, 0, 0};
     int rc = 0;
     if (A->n_nodes > 0 && B->n_nodes > 0 && A->n_objects > 0 && B->n_objects > 0) {
-        uint64_t e0 = A->first[A->root], e1 = e0 + A->count[A->root];
-        uint64_t f0 = B->first[B->root], f1 = f0 + B->count[B->root];
-        uint64_t cap = (e1 - e0) * (f1 - f0), np = 0;
-        uint64_t *pe = (uint64_t *)malloc((size_t)(cap ? cap : 1) * sizeof(uint64_t));
-        uint64_t *pf = (uint64_t *)malloc((size_t)(cap ? cap : 1) * sizeof(uint64_t));
+        pairvec cur = {0}, nxt = {0};
+        rc = pv_node_pairs(A, A->root, B, B->root, &cur);
+        while (!rc && cur.n < (size_t)64 * (size_t)nthreads) {
+            int grew = 0;
+            nxt.n = 0;
+            for (size_t k = 0; k < cur.n && !rc; k++) {
+                uint32_t u = (uint32_t)cur.u[k], v = (uint32_t)cur.v[k];
+                if (A->level[u] > 0 && B->level[v] > 0) {
+                    rc = pv_node_pairs(A, A->ptr[cur.e[k]], B, B->ptr[cur.f[k]], &nxt);
+                    grew = 1;
+                } else {
+                    rc = pv_push(&nxt, u, cur.e[k], v, cur.f[k]) ? -2 : 0;
+                }
+            }
+            pairvec t = cur; cur = nxt; nxt = t;
+            if (!grew) break;
+        }
+        pv_free(&nxt);
         join_part *parts = (join_part *)calloc((size_t)nthreads, sizeof(join_part));
         pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
-        if (!pe || !pf || !parts || !th) rc = -2;
-        for (uint64_t e = e0; e < e1 && !rc; e++)
-            for (uint64_t f = f0; f < f1; f++)
-                if (overlap4(A->lx[e], A->ly[e], A->hx[e], A->hy[e], B->lx[f], B->ly[f], B->hx[f], B->hy[f])) {
-                    pe[np] = e;
-                    pf[np] = f;
-                    np++;
-                }
+        if (!parts || !th) rc = -2;
         int started = 0;
         for (; !rc && started < nthreads; started++) {
-            parts[started] = (join_part){A, B, pe, pf, np, started, nthreads, {0, 0, 0}, 0};
+            parts[started] = (join_part){A, B, &cur, started, nthreads, {0, 0, 0}, 0};
             if (pthread_create(&th[started], NULL, join_worker, &parts[started])) { rc = -2; break; }
         }
         for (int i = 0; i < started; i++) pthread_join(th[i], NULL);
@@ -560,7 +610,8 @@ int ora_join_mt(const ora_tree *A, const ora_tree *B, int nthreads, uint32_t **p
                 if (v64_push(&acc, parts[i].out.v[k])) { rc = -2; break; }
         }
         for (int i = 0; i < started; i++) free(parts[i].out.v);
-        free(pe); free(pf); free(parts); free(th);
+        free(parts); free(th);
+        pv_free(&cur);
     }
     if (rc) { free(acc.v); return rc; }
     qsort(acc.v, acc.n, sizeof(uint64_t), cmp_u64);

@@ -77,6 +77,9 @@ _sig = {
     "rt_range_select_device": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _u64, _vp, _vp], C.c_int),
     "rt_range_select_device_timed": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp], C.c_int),
     "rt_range_count_device": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp], C.c_int),
+    "rt_range_select_device_count": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp], C.c_int),
+    "rt_range_select_device_fill": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _u64, _vp, _vp], C.c_int),
+    "rt_range_select_async": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp], C.c_int),
     "rt_range_select_batch": ([C.POINTER(_vp), _u32, C.POINTER(_fp), C.POINTER(_u64),
                                C.POINTER(C.POINTER(_Ids))], C.c_int),
     "rt_batch_create": ([C.POINTER(_vp), _u32, C.POINTER(_fp), C.POINTER(_u64), _u64,
@@ -264,6 +267,35 @@ def range_select_device_timed(tree: Tree, d_queries: int, nq: int, d_offsets: in
     _check(_L.rt_range_select_device_timed(tree.h, _vp(d_queries), int(nq), _vp(d_offsets), _vp(d_ids),
                                            int(ids_capacity), _vp(d_work), int(work_bytes), _vp(d_status),
                                            _vp(stream), ev))
+
+
+def range_select_device_count(tree: Tree, d_queries: int, nq: int, d_offsets: int, d_work: int, work_bytes: int,
+                              stream: int = 0):
+    """Count stage of a device select: offsets (with the total at [nq]) and
+    the plan in the workspace; nothing waits."""
+    _check(_L.rt_range_select_device_count(tree.h, _vp(d_queries), int(nq), _vp(d_offsets), _vp(d_work),
+                                           int(work_bytes), _vp(stream)))
+
+
+def range_select_device_fill(tree: Tree, d_queries: int, nq: int, d_offsets: int, d_ids: int, ids_capacity: int,
+                             d_work: int, work_bytes: int, d_status: int, stream: int = 0):
+    """Fill stage after range_select_device_count on the same workspace."""
+    _check(_L.rt_range_select_device_fill(tree.h, _vp(d_queries), int(nq), _vp(d_offsets), _vp(d_ids),
+                                          int(ids_capacity), _vp(d_work), int(work_bytes), _vp(d_status),
+                                          _vp(stream)))
+
+
+def range_select_async(tree: Tree, d_queries: int, nq: int, d_offsets: int, d_ids: int, ids_capacity: int,
+                       d_total: int, stream: int = 0) -> bool:
+    """Select into caller device buffers (library-held workspace).  Returns
+    False (RT_ENOMEM, ids untouched) when the result exceeds ids_capacity;
+    the size is then in d_total.  True: the fill runs on `stream`."""
+    rc = _L.rt_range_select_async(tree.h, _vp(d_queries), int(nq), _vp(d_offsets), _vp(d_ids), int(ids_capacity),
+                                  _vp(d_total), _vp(stream))
+    if rc == RT_ENOMEM:
+        return False
+    _check(rc)
+    return True
 
 
 def range_count_device(tree: Tree, d_queries: int, nq: int, d_counts: int, d_work: int, work_bytes: int,

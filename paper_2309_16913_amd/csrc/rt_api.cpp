@@ -204,12 +204,10 @@ extern "C" int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uin
     if (!out) return fail(RT_EINVAL, "out is NULL");
     *out = nullptr;
     try {
-        if (fanout == 0) fanout = 32;
-        if (fanout < 2 || fanout > 64) return fail(RT_EINVAL, "fanout %u not in 2..64", fanout);
+        if (fanout != 0 && (fanout < 2 || fanout > 64)) return fail(RT_EINVAL, "fanout %u not in 2..64", fanout);
         const bool sort_lx = (layout & RT_BUILD_SORT_LX) != 0;
         layout &= ~RT_BUILD_SORT_LX;
-        if (layout == RT_LAYOUT_AUTO) layout = RT_LAYOUT_SOA;
-        if (layout != RT_LAYOUT_AOS && layout != RT_LAYOUT_SOA && layout != RT_LAYOUT_D2)
+        if (layout != RT_LAYOUT_AOS && layout != RT_LAYOUT_SOA && layout != RT_LAYOUT_D2 && layout != RT_LAYOUT_AUTO)
             return fail(RT_EINVAL, "unknown layout %u", layout);
         if (n >= 0xFFFFFFFFull) return fail(RT_EINVAL, "n = %llu does not fit 32-bit ids", (unsigned long long)n);
         int rc = check_rects(rects, n, "rects");
@@ -219,6 +217,8 @@ extern "C" int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uin
         hipError_t e = d.alloc(n ? n * 16 : 16);
         if (e == hipSuccess && n) e = hipMemcpy(d.p, rects, n * 16, hipMemcpyHostToDevice);
         if (e != hipSuccess) return hip_fail(e, "uploading the rectangles");
+        if (fanout == 0 || layout == RT_LAYOUT_AUTO)
+            return build_tuned(static_cast<const float4 *>(d.p), n, fanout, layout, sort_lx, nullptr, out);
         return build_str_on_device(static_cast<const float4 *>(d.p), n, fanout, layout, sort_lx, nullptr, out);
     } catch (const std::bad_alloc &) {
         return fail(RT_ENOMEM, "host allocation failed");
@@ -338,6 +338,15 @@ int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, u
                               uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, int stage,
                               uint32_t *d_counts_out, void *const *events) {
     SelWs w = sel_ws(work, nq);
+    if (nq == 0) {   // no launch of an empty grid: offsets = {0}, status = {0, 0}
+        hipError_t e = hipSuccess;
+        if (stage & 1) {
+            e = launch_zero(w.ctrl, sizeof(Ctrl), s);
+            if (e == hipSuccess && d_off && !d_counts_out) e = launch_zero(d_off, 8, s);
+        }
+        if (e == hipSuccess && (stage & 2) && d_status) e = launch_finalize(d_off, 0, cap, w.ctrl, d_status, s);
+        return e == hipSuccess ? RT_OK : hip_fail(e, "empty select");
+    }
     const TreeView v = view_of(t);
     const SplitCfg sc = d_counts_out ? SplitCfg() : split_cfg(t, nq);
     auto mark = [&](int k) -> hipError_t {
@@ -426,6 +435,36 @@ extern "C" int rt_range_select_device(const rt_tree *t, const float *d_queries, 
                                       uint64_t *d_status, void *stream) {
     return rt_range_select_device_timed(t, d_queries, nq, d_offsets, d_ids, cap, d_work, work_bytes, d_status,
                                         stream, nullptr);
+}
+
+// The two stages of rt_range_select_device as separate calls (the server
+// sizes and places each batch's output between them).
+static int check_stage_args(const rt_tree *t, const float *d_queries, uint64_t nq, const void *d_offsets,
+                            const void *d_work) {
+    if (!t || (nq && !d_queries) || !d_offsets || !d_work) return fail(RT_EINVAL, "NULL argument");
+    if (int rc = check_nq(nq)) return rc;
+    if ((reinterpret_cast<uintptr_t>(d_queries) & 15) != 0) return fail(RT_EINVAL, "queries not 16-byte aligned");
+    return RT_OK;
+}
+
+extern "C" int rt_range_select_device_count(const rt_tree *t, const float *d_queries, uint64_t nq,
+                                            uint64_t *d_offsets, void *d_work, uint64_t work_bytes, void *stream) {
+    if (int rc = check_stage_args(t, d_queries, nq, d_offsets, d_work)) return rc;
+    if (work_bytes < sel_ws_bytes(nq, 0)) return fail(RT_EINVAL, "workspace too small");
+    DevSet ds(t->device);
+    return enqueue_select_stage(t, reinterpret_cast<const float4 *>(d_queries), nq, d_offsets, nullptr, 0, d_work,
+                                nullptr, static_cast<hipStream_t>(stream), 1, nullptr, nullptr);
+}
+
+extern "C" int rt_range_select_device_fill(const rt_tree *t, const float *d_queries, uint64_t nq,
+                                           uint64_t *d_offsets, uint32_t *d_ids, uint64_t cap, void *d_work,
+                                           uint64_t work_bytes, uint64_t *d_status, void *stream) {
+    if (int rc = check_stage_args(t, d_queries, nq, d_offsets, d_work)) return rc;
+    if (!d_status || (cap && !d_ids)) return fail(RT_EINVAL, "NULL argument");
+    if (work_bytes < sel_ws_bytes(nq, cap)) return fail(RT_EINVAL, "workspace too small");
+    DevSet ds(t->device);
+    return enqueue_select_stage(t, reinterpret_cast<const float4 *>(d_queries), nq, d_offsets, d_ids, cap, d_work,
+                                d_status, static_cast<hipStream_t>(stream), 2, nullptr, nullptr);
 }
 
 extern "C" int rt_range_count_device(const rt_tree *t, const float *d_queries, uint64_t nq, uint32_t *d_counts,

@@ -48,6 +48,10 @@ TreeView view_of(const rt_tree *t);
 // stream s; returns after the build has finished.
 int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t fanout, uint32_t layout, bool sort_lx,
                         hipStream_t s, rt_tree **out);
+// fanout 0 and/or layout RT_LAYOUT_AUTO: build every candidate, time a probe
+// select on each and keep the fastest (choice cached per key).
+int build_tuned(const float4 *d_rects, uint64_t n, uint32_t fanout, uint32_t layout, bool sort_lx, hipStream_t s,
+                rt_tree **out);
 int make_ids(uint64_t nq, uint64_t total, rt_ids **out);
 // stage bit 1: count stage (order, split, count pass, offsets); bit 2: fill
 // stage (fill pass, sort, status).  d_counts_out: count-only mode.

@@ -425,16 +425,17 @@ extern "C" int rt_build_str_device(const float *d_rects, uint64_t n, uint32_t fa
     if (!out) return fail(RT_EINVAL, "out is NULL");
     *out = nullptr;
     try {
-        if (fanout == 0) fanout = 32;
-        if (fanout < 2 || fanout > 64) return fail(RT_EINVAL, "fanout %u not in 2..64", fanout);
+        if (fanout != 0 && (fanout < 2 || fanout > 64)) return fail(RT_EINVAL, "fanout %u not in 2..64", fanout);
         const bool sort_lx = (layout & RT_BUILD_SORT_LX) != 0;
         layout &= ~RT_BUILD_SORT_LX;
-        if (layout == RT_LAYOUT_AUTO) layout = RT_LAYOUT_SOA;
-        if (layout != RT_LAYOUT_AOS && layout != RT_LAYOUT_SOA && layout != RT_LAYOUT_D2)
+        if (layout != RT_LAYOUT_AOS && layout != RT_LAYOUT_SOA && layout != RT_LAYOUT_D2 && layout != RT_LAYOUT_AUTO)
             return fail(RT_EINVAL, "unknown layout %u", layout);
         if (n >= 0xFFFFFFFFull) return fail(RT_EINVAL, "n = %llu does not fit 32-bit ids", (unsigned long long)n);
         if (n && !d_rects) return fail(RT_EINVAL, "rects is NULL with n = %llu", (unsigned long long)n);
         if ((reinterpret_cast<uintptr_t>(d_rects) & 15) != 0) return fail(RT_EINVAL, "rects not 16-byte aligned");
+        if (fanout == 0 || layout == RT_LAYOUT_AUTO)
+            return build_tuned(reinterpret_cast<const float4 *>(d_rects), n, fanout, layout, sort_lx,
+                               static_cast<hipStream_t>(stream), out);
         return build_str_on_device(reinterpret_cast<const float4 *>(d_rects), n, fanout, layout, sort_lx,
                                    static_cast<hipStream_t>(stream), out);
     } catch (const std::bad_alloc &) {

@@ -2,24 +2,33 @@
 R-trees (one GPU).
 
 Requests arrive over time (open loop: each has a scheduled arrival time).
-The loop keeps `nslots` batches in flight, one per HIP stream.  Whenever a
-slot is free it admits the requests that have arrived and are waiting --
-range windows are packed together into one select on the range tree, a join
-request (a probe set of rectangles, answered as an index nested loop: every
-probe rectangle is a window on the join tree) runs as its own batch -- and
-launches the whole device select (count, scan, fill, sort) on that slot's
-stream.  Requests that arrive while batches are running wait for the next
-free slot, so work from several batches overlaps on the device.
+The loop keeps up to `nslots` batches in flight, one per HIP stream.  A free
+slot takes the waiting requests -- range windows packed together into one
+select on the range tree; a join request (a probe set of rectangles,
+answered as an index nested loop: every probe rectangle is a window on the
+join tree) as a batch of its own -- and runs it in two stages:
 
-Admission is bounded by output-buffer memory: every slot owns a fixed share
-of the id pool.  A batch whose result does not fit is not truncated and not
-dropped: its exact size is known from the status words, so it is split and
-re-admitted (a single request bigger than a slot waits until every slot is
-idle and then runs with the whole pool).
+1. the count stage of the device select (every window's exact result size,
+   the CSR offsets);
+2. once the batch's exact total is known, it is given a contiguous range of
+   that many ids in the output pool (first fit; ranges of batches in flight
+   never overlap), and the fill stage writes the ids there and copies them to
+   the same range of a pinned host pool.
+
+Admission is thereby bounded by output-buffer memory with exact sizes: a
+batch waits after its count stage until its range is free, and no result is
+ever truncated, dropped or recomputed because it did not fit.  Batches are
+formed so that about `nslots` of them fit in the pool at once (sizes known
+from earlier count stages, others estimated from the running mean of ids per
+window); a batch larger than the whole pool (only possible while sizes are
+unknown) is re-queued with its exact per-request sizes, and a single request
+larger than the pool is an error.  Requests that arrive while batches run
+wait for the next free slot, so work of several batches overlaps on the
+device.
 
 Latency of a request = time its result is in pinned host memory - its
 scheduled arrival.  All GPU work goes through the library's device-pointer
-entry point; torch supplies device memory, pinned host memory, streams and
+entry points; torch supplies device memory, pinned host memory, streams and
 events only.
 """
 
@@ -34,7 +43,8 @@ import numpy as np
 
 
 # ---------------------------------------------------------------------------
-# pure host policy (no GPU): which waiting requests form the next batch
+# pure host policy (no GPU): which waiting requests form the next batch, and
+# where a batch's output goes
 # ---------------------------------------------------------------------------
 
 @dataclass
@@ -43,8 +53,7 @@ class Pending:
     kind: str                    # "select" or "join"
     windows: np.ndarray          # (m, 4) float32
     t_arrival: float
-    known_ids: int = -1          # exact result size once a run has reported it
-    solo: bool = False           # too big for one slot: run alone with the pool
+    known_ids: int = -1          # exact result size once a count stage has reported it
 
 
 @dataclass
@@ -52,25 +61,24 @@ class Batch:
     kind: str
     reqs: list
     windows: np.ndarray
-    whole_pool: bool = False
 
 
 class Admission:
-    """Forms batches from the waiting queue.
+    """Forms batches from the waiting queue, in arrival order.
 
-    * joins run one per batch; range windows are packed up to `max_windows`;
-    * a request whose known size exceeds the slot share is marked solo and
-      waits until every slot is idle (then it gets the whole pool);
-    * requests with a known size are packed only while their sizes fit the
-      slot share; unknown sizes are admitted optimistically (the device
-      reports an overflow without writing past the buffer)."""
+    * a join runs as a batch of its own; windows behind a waiting join are
+      packed with the ones before it;
+    * range windows are packed up to `max_windows` and while the batch's
+      expected size stays within `budget_ids` (a request's known size, else
+      its windows times the running estimate of ids per window); the first
+      request of a batch is always taken, whatever its size."""
 
-    def __init__(self, max_windows: int, slot_ids: int, pool_ids: int, one_per_batch: bool = False):
+    def __init__(self, max_windows: int, budget_ids: int, one_per_batch: bool = False):
         self.max_windows = max_windows
-        self.slot_ids = slot_ids
-        self.pool_ids = pool_ids
+        self.budget_ids = budget_ids
         self.one_per_batch = one_per_batch   # the unbatched baseline: one request per launch
         self.queue: deque = deque()
+        self.ids_per_window = 0.0            # running estimate, from count stages
 
     def push(self, p: Pending):
         self.queue.append(p)
@@ -82,35 +90,31 @@ class Admission:
     def __len__(self):
         return len(self.queue)
 
-    def next_batch(self, all_idle: bool):
+    def expected(self, p: Pending) -> float:
+        return p.known_ids if p.known_ids >= 0 else self.ids_per_window * p.windows.shape[0]
+
+    def next_batch(self):
         if not self.queue:
             return None
         head = self.queue[0]
-        if head.solo:
-            if not all_idle:
-                return None
-            self.queue.popleft()
-            return Batch(head.kind, [head], head.windows, whole_pool=True)
         if head.kind == "join":
             self.queue.popleft()
             return Batch("join", [head], head.windows)
-        # pack waiting range windows in arrival order; join requests and solo
-        # requests stay queued in place (they form batches of their own)
-        reqs, known, nwin = [], 0, 0
+        reqs, size, nwin = [], 0.0, 0
         rest = deque()
         while self.queue:
             p = self.queue.popleft()
-            take = (p.kind == "select" and not p.solo and nwin + p.windows.shape[0] <= self.max_windows
-                    and not (p.known_ids >= 0 and reqs and known + p.known_ids > self.slot_ids)
+            take = (p.kind == "select" and nwin + p.windows.shape[0] <= self.max_windows
+                    and not (reqs and size + self.expected(p) > self.budget_ids)
                     and not (self.one_per_batch and reqs))
             if take:
                 reqs.append(p)
                 nwin += p.windows.shape[0]
-                if p.known_ids >= 0:
-                    known += p.known_ids
+                size += self.expected(p)
             else:
                 rest.append(p)
-                if nwin >= self.max_windows or (self.one_per_batch and reqs):
+                if (nwin >= self.max_windows or (self.one_per_batch and reqs)
+                        or (reqs and p.kind == "select" and size + self.expected(p) > self.budget_ids)):
                     break
         rest.extend(self.queue)
         self.queue = rest
@@ -118,22 +122,60 @@ class Admission:
             return None
         return Batch("select", reqs, np.concatenate([r.windows for r in reqs]))
 
-    def overflowed(self, batch: Batch, counts: np.ndarray):
-        """Re-queue an overflowed batch at the front with exact sizes known:
-        split it so that each part fits a slot; a single request larger than
-        a slot becomes solo."""
-        per_req = []
+    def observe(self, total: int, nwin: int):
+        """A count stage reported `total` ids for `nwin` windows."""
+        if nwin:
+            m = total / nwin
+            self.ids_per_window = m if self.ids_per_window == 0.0 else 0.8 * self.ids_per_window + 0.2 * m
+
+    def sizes_known(self, batch: Batch, counts: np.ndarray):
+        """Record every request's exact size from per-window counts."""
         at = 0
         for r in batch.reqs:
             m = r.windows.shape[0]
             r.known_ids = int(counts[at:at + m].sum())
             at += m
-            if r.known_ids > self.pool_ids:
-                raise MemoryError(f"request {r.rid} needs {r.known_ids} ids, more than the whole pool")
-            if r.known_ids > self.slot_ids or batch.whole_pool:
-                r.solo = True
-            per_req.append(r)
-        self.push_front(per_req)
+
+    def requeue(self, batch: Batch, counts: np.ndarray, pool_ids: int):
+        """A batch too large for the whole pool: back to the front of the
+        queue with exact sizes (the next batches are packed to fit)."""
+        self.sizes_known(batch, counts)
+        for r in batch.reqs:
+            if r.known_ids > pool_ids:
+                raise MemoryError(f"request {r.rid} needs {r.known_ids} ids, more than the whole pool ({pool_ids})")
+        self.push_front(batch.reqs)
+
+
+class IdPool:
+    """First-fit placement of batch outputs in one buffer of `size` ids: a
+    batch gets a contiguous range [start, start + n) and keeps it until its
+    results have been delivered; live ranges never overlap."""
+
+    def __init__(self, size: int):
+        self.size = size
+        self.live = []           # sorted (start, end) of ranges in use
+
+    def alloc(self, n: int):
+        if n == 0:
+            return 0
+        prev = 0
+        for i, (s, e) in enumerate(self.live):
+            if s - prev >= n:
+                self.live.insert(i, (prev, prev + n))
+                return prev
+            prev = e
+        if self.size - prev >= n:
+            self.live.append((prev, prev + n))
+            return prev
+        return None
+
+    def free(self, start: int, n: int):
+        if n == 0:
+            return
+        self.live.remove((start, start + n))
+
+    def in_use(self) -> int:
+        return sum(e - s for s, e in self.live)
 
 
 # ---------------------------------------------------------------------------
@@ -145,10 +187,13 @@ class Stats:
     lat_select: list = field(default_factory=list)
     lat_join: list = field(default_factory=list)
     batches: int = 0
-    overflows: int = 0
+    requeued_batches: int = 0     # batches larger than the whole pool (sizes then known)
+    oversized_batches: int = 0    # batches over the per-batch budget (a single large request)
+    memory_waits: int = 0         # batches that waited after their count stage for pool room
     windows: int = 0
     ids: int = 0
-    gpu_select_ms: float = 0.0    # device time of the selects (incl. overflowed attempts)
+    gpu_count_ms: float = 0.0     # device time of the count stages
+    gpu_fill_ms: float = 0.0      # device time of the fill stages (fill pass + sort)
     gpu_copy_ms: float = 0.0      # device time of the result copies to pinned memory
 
     def summary(self, wall: float, nreq: int) -> dict:
@@ -159,13 +204,17 @@ class Stats:
             "windows_per_s": self.windows / wall if wall > 0 else None,
             "select_p50_ms": pct(self.lat_select, 50), "select_p99_ms": pct(self.lat_select, 99),
             "join_p50_ms": pct(self.lat_join, 50), "join_p99_ms": pct(self.lat_join, 99),
-            "batches": self.batches, "overflow_retries": self.overflows, "ids": self.ids,
-            "gpu_select_ms": self.gpu_select_ms, "gpu_copy_ms": self.gpu_copy_ms,
+            "batches": self.batches, "requeued_batches": self.requeued_batches,
+            "oversized_batches": self.oversized_batches, "memory_waits": self.memory_waits, "ids": self.ids,
+            "gpu_count_ms": self.gpu_count_ms, "gpu_fill_ms": self.gpu_fill_ms, "gpu_copy_ms": self.gpu_copy_ms,
         }
 
 
+IDLE, COUNTING, WAITING, FILLING = 0, 1, 2, 3
+
+
 class _Slot:
-    def __init__(self, torch, rt, max_windows, cap_ids):
+    def __init__(self, torch, rt, max_windows, work_bytes):
         self.stream = torch.cuda.Stream()
         self.dq = torch.empty((max_windows, 4), dtype=torch.float32, device="cuda")
         self.off = torch.empty(max_windows + 1, dtype=torch.int64, device="cuda")
@@ -173,14 +222,13 @@ class _Slot:
         self.hq = torch.empty((max_windows, 4), dtype=torch.float32).pin_memory()
         self.hoff = torch.empty(max_windows + 1, dtype=torch.int64).pin_memory()
         self.hstat = torch.empty(2, dtype=torch.int64).pin_memory()
-        self.cap = cap_ids
-        self.ids = None
-        self.hids = None
-        self.work = None
-        self.wb = 0
+        self.wb = work_bytes
+        self.work = torch.empty(work_bytes, dtype=torch.uint8, device="cuda")
+        self.stage = IDLE
         self.batch = None
-        self.done_ev = None
-        self.stage = 0          # 0 idle, 1 running select, 2 copying results
+        self.ev = None
+        self.start = 0
+        self.total = 0
 
 
 class Server:
@@ -200,94 +248,111 @@ class Server:
         self.one_per_batch = one_per_batch
         self.max_windows = max_windows
         self.pool_ids = pool_ids
-        self.slot_ids = pool_ids // nslots
-        self.slots = [_Slot(torch, rt, max_windows, self.slot_ids) for _ in range(nslots)]
-        # one id pool; every slot views its share, a solo batch uses all of it
-        self.pool = torch.empty(pool_ids, dtype=torch.int32, device="cuda")
-        self.hpool = torch.empty(pool_ids, dtype=torch.int32).pin_memory()
+        # one id pool on the device and its pinned host mirror; a batch owns
+        # the same range of both while it is in flight
+        self.pool = torch.empty(max(pool_ids, 1), dtype=torch.int32, device="cuda")
+        self.hpool = torch.empty(max(pool_ids, 1), dtype=torch.int32).pin_memory()
+        # every slot can fill a batch as large as the whole pool
         wb = rt.select_workspace_bytes(max_windows, pool_ids)
-        self.work = torch.empty(wb, dtype=torch.uint8, device="cuda")
-        self.wb_full = wb
-        for k, sl in enumerate(self.slots):
-            sl.ids = self.pool[k * self.slot_ids:(k + 1) * self.slot_ids]
-            sl.hids = self.hpool[k * self.slot_ids:(k + 1) * self.slot_ids]
-            sl.wb = rt.select_workspace_bytes(max_windows, self.slot_ids)
-            sl.work = torch.empty(sl.wb, dtype=torch.uint8, device="cuda")
+        self.slots = [_Slot(torch, rt, max_windows, wb) for _ in range(nslots)]
 
-    # -- one batch ---------------------------------------------------------
-    def _launch(self, sl: _Slot, b: Batch):
+    # -- stages --------------------------------------------------------------
+    def _launch_count(self, sl: _Slot, b: Batch):
         torch, rt = self.torch, self.rt
         m = b.windows.shape[0]
-        ids, hids, cap, work, wb = sl.ids, sl.hids, sl.cap, sl.work, sl.wb
-        if b.whole_pool:
-            ids, hids, cap, work, wb = self.pool, self.hpool, self.pool_ids, self.work, self.wb_full
-        sl.cur = (ids, hids, cap)
         sl.hq[:m].copy_(torch.from_numpy(b.windows))
         with torch.cuda.stream(sl.stream):
             sl.dq[:m].copy_(sl.hq[:m], non_blocking=True)
-            sl.ev0 = torch.cuda.Event(enable_timing=True)
-            sl.ev0.record(sl.stream)
-            rt.range_select_device(self.trees[b.kind], sl.dq.data_ptr(), m, sl.off.data_ptr(), ids.data_ptr(),
-                                   cap, work.data_ptr(), wb, sl.status.data_ptr(), sl.stream.cuda_stream)
-            sl.hstat.copy_(sl.status, non_blocking=True)
+            sl.ev_c0 = torch.cuda.Event(enable_timing=True)
+            sl.ev_c0.record(sl.stream)
+            rt.range_select_device_count(self.trees[b.kind], sl.dq.data_ptr(), m, sl.off.data_ptr(),
+                                         sl.work.data_ptr(), sl.wb, sl.stream.cuda_stream)
+            sl.ev_c1 = torch.cuda.Event(enable_timing=True)
+            sl.ev_c1.record(sl.stream)
             sl.hoff[:m + 1].copy_(sl.off[:m + 1], non_blocking=True)
-            ev = torch.cuda.Event(enable_timing=True)
+            ev = torch.cuda.Event()
             ev.record(sl.stream)
-        sl.batch, sl.done_ev, sl.stage = b, ev, 1
+        sl.batch, sl.ev, sl.stage = b, ev, COUNTING
 
-    def _finish_stage1(self, sl: _Slot, adm: Admission, st: Stats):
-        """Select done: on overflow re-queue, else start the copy of the ids."""
-        torch = self.torch
+    def _counted(self, sl: _Slot, adm: Admission, st: Stats):
+        """Count stage done: the exact size is known."""
         b = sl.batch
-        st.gpu_select_ms += sl.ev0.elapsed_time(sl.done_ev)
-        sl.ev1 = sl.done_ev
-        tot, flags = int(sl.hstat[0]), int(sl.hstat[1])
+        st.gpu_count_ms += sl.ev_c0.elapsed_time(sl.ev_c1)
         m = b.windows.shape[0]
-        if flags & 2:
-            raise RuntimeError("device reported an internal error while serving")
-        if flags & 1:
-            st.overflows += 1
-            off = sl.hoff[:m + 1].numpy()
-            adm.overflowed(b, np.diff(off))
-            sl.stage, sl.batch = 0, None
+        off = sl.hoff[:m + 1].numpy()
+        sl.total = int(off[m])
+        adm.observe(sl.total, m)
+        if sl.total > self.pool_ids:
+            st.requeued_batches += 1
+            adm.requeue(b, np.diff(off), self.pool_ids)
+            sl.stage, sl.batch = IDLE, None
             return
-        ids, hids, _ = sl.cur
-        with torch.cuda.stream(sl.stream):
-            if tot:
-                hids[:tot].copy_(ids[:tot], non_blocking=True)
-            ev = torch.cuda.Event(enable_timing=True)
-            ev.record(sl.stream)
-        sl.total, sl.done_ev, sl.stage = tot, ev, 2
+        if sl.total > adm.budget_ids:
+            st.oversized_batches += 1
+        sl.stage = WAITING
+        sl.waited = False
 
-    def _finish_stage2(self, sl: _Slot, now: float, st: Stats, sink):
+    def _try_fill(self, sl: _Slot, pool: IdPool, st: Stats) -> bool:
+        torch, rt = self.torch, self.rt
+        start = pool.alloc(sl.total)
+        if start is None:
+            if not sl.waited:
+                st.memory_waits += 1
+                sl.waited = True
+            return False
         b = sl.batch
-        st.gpu_copy_ms += sl.ev1.elapsed_time(sl.done_ev)
+        m = b.windows.shape[0]
+        sl.start = start
+        tot = sl.total
+        with torch.cuda.stream(sl.stream):
+            sl.ev_f0 = torch.cuda.Event(enable_timing=True)
+            sl.ev_f0.record(sl.stream)
+            ids_ptr = self.pool[start:].data_ptr() if tot else 0
+            rt.range_select_device_fill(self.trees[b.kind], sl.dq.data_ptr(), m, sl.off.data_ptr(), ids_ptr, tot,
+                                        sl.work.data_ptr(), sl.wb, sl.status.data_ptr(), sl.stream.cuda_stream)
+            sl.ev_f1 = torch.cuda.Event(enable_timing=True)
+            sl.ev_f1.record(sl.stream)
+            sl.hstat.copy_(sl.status, non_blocking=True)
+            if tot:
+                self.hpool[start:start + tot].copy_(self.pool[start:start + tot], non_blocking=True)
+            sl.ev = torch.cuda.Event(enable_timing=True)
+            sl.ev.record(sl.stream)
+        sl.stage = FILLING
+        return True
+
+    def _delivered(self, sl: _Slot, pool: IdPool, now: float, st: Stats, sink):
+        b = sl.batch
+        st.gpu_fill_ms += sl.ev_f0.elapsed_time(sl.ev_f1)
+        st.gpu_copy_ms += sl.ev_f1.elapsed_time(sl.ev)
+        tot, flags = int(sl.hstat[0]), int(sl.hstat[1])
+        if flags or tot != sl.total:
+            raise RuntimeError(f"device reported status {tot}/{flags} for a batch of {sl.total} ids")
         m = b.windows.shape[0]
         off = sl.hoff[:m + 1].numpy().copy()
-        _, hids, _ = sl.cur
-        # views into the slot's pinned buffer: valid until the slot is reused,
-        # so a sink that keeps results must copy them
-        ids = hids[:sl.total].numpy().view(np.uint32) if sl.total else np.zeros(0, np.uint32)
+        # views into the pinned pool: valid until the range is given to a
+        # later batch, so a sink that keeps results must copy them
+        ids = (self.hpool[sl.start:sl.start + tot].numpy().view(np.uint32) if tot
+               else np.zeros(0, np.uint32))
         at = 0
         for r in b.reqs:
             k = r.windows.shape[0]
             lo, hi = int(off[at]), int(off[at + k])
-            lat = now - r.t_arrival
-            (st.lat_join if r.kind == "join" else st.lat_select).append(lat)
+            (st.lat_join if r.kind == "join" else st.lat_select).append(now - r.t_arrival)
             if sink is not None:
                 sink(r, off[at:at + k + 1] - lo, ids[lo:hi])
             at += k
+        pool.free(sl.start, tot)
         st.batches += 1
         st.windows += m
-        st.ids += sl.total
-        sl.stage, sl.batch = 0, None
+        st.ids += tot
+        sl.stage, sl.batch = IDLE, None
 
     # -- the loop ------------------------------------------------------------
     def run(self, requests, sink=None, time_scale: float = 1.0) -> dict:
         """Serve `requests` (objects with t_arrival, kind, payload, rid) in
         real time.  `sink(req, offsets, ids)` receives every result as views
-        into pinned staging memory that is reused by later batches (copy what
-        must be kept)."""
+        into pinned staging memory that later batches reuse (copy what must
+        be kept)."""
         # no garbage collection pass while serving: a full pass over the
         # loop's objects stalls every request in flight for milliseconds
         gc_was_on = gc.isenabled()
@@ -300,10 +365,12 @@ class Server:
 
     def _run(self, requests, sink, time_scale: float) -> dict:
         reqs = sorted(requests, key=lambda r: r.t_arrival)
-        adm = Admission(self.max_windows, self.slot_ids, self.pool_ids, self.one_per_batch)
+        budget = max(1, self.pool_ids // self.nslots)
+        adm = Admission(self.max_windows, budget, self.one_per_batch)
+        pool = IdPool(self.pool_ids)
         st = Stats()
         n = len(reqs)
-        nxt, finished = 0, 0
+        nxt = 0
         t0 = time.perf_counter()
         done_count = [0]
 
@@ -322,30 +389,36 @@ class Server:
                 nxt += 1
             progressed = False
             for sl in self.slots:
-                if sl.stage and sl.done_ev.query():
-                    if sl.stage == 1:
-                        self._finish_stage1(sl, adm, st)
+                if sl.stage in (COUNTING, FILLING) and sl.ev.query():
+                    if sl.stage == COUNTING:
+                        self._counted(sl, adm, st)
                     else:
-                        self._finish_stage2(sl, (time.perf_counter() - t0) / time_scale, st, counted_sink)
+                        self._delivered(sl, pool, (time.perf_counter() - t0) / time_scale, st, counted_sink)
                     progressed = True
-            all_idle = all(s.stage == 0 for s in self.slots)
+            # batches waiting for pool room, oldest first
+            waiting = [sl for sl in self.slots if sl.stage == WAITING]
+            waiting.sort(key=lambda s: s.batch.reqs[0].t_arrival)
+            for sl in waiting:
+                if self._try_fill(sl, pool, st):
+                    progressed = True
+                else:
+                    break   # keep arrival order: later batches do not overtake
             for sl in self.slots:
-                if sl.stage == 0 and len(adm):
-                    b = adm.next_batch(all_idle)
+                if sl.stage == IDLE and len(adm):
+                    b = adm.next_batch()
                     if b is None:
                         break
-                    self._launch(sl, b)
-                    all_idle = False
+                    self._launch_count(sl, b)
                     progressed = True
-            if not progressed and nxt < n and not len(adm) and all(s.stage == 0 for s in self.slots):
+            if not progressed and nxt < n and not len(adm) and all(s.stage == IDLE for s in self.slots):
                 # nothing to do until the next arrival
                 wait = reqs[nxt].t_arrival - now
                 if wait > 2e-4:
                     time.sleep(min(wait, 1e-3) * time_scale)
         wall = (time.perf_counter() - t0) / time_scale
-        finished = done_count[0]
-        out = st.summary(wall, finished)
+        out = st.summary(wall, done_count[0])
         out["nslots"] = self.nslots
         out["max_windows"] = self.max_windows
         out["pool_ids"] = self.pool_ids
+        out["batch_budget_ids"] = budget
         return out
