@@ -224,6 +224,27 @@ int rt_range_select_device(const rt_tree *t, const float *d_queries, uint64_t nq
                            uint64_t *d_offsets, uint32_t *d_ids, uint64_t ids_capacity,
                            void *d_work, uint64_t work_bytes, uint64_t *d_status, void *stream);
 
+/* Size of the fixed device scratch of rt_range_select_device_noalloc. */
+#define RT_NOALLOC_SCRATCH_BYTES (32ull << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * select as rt_range_select_device, with the same arguments and d_status
+ * contract, but its workspace is a fixed array of RT_NOALLOC_SCRATCH_BYTES
+ * (32 MiB) in the library's device code, which every device that runs the
+ * library holds until the process ends.  The call allocates nothing and only
+ * enqueues on `stream`.  A size whose workspace
+ * (rt_select_workspace_bytes(nq, ids_capacity)) exceeds the scratch ->
+ * RT_EINVAL with a message, before anything is enqueued (for instance up to
+ * 65536 queries with room for 4M ids fit).  All calls on one device share
+ * that device's scratch: calls whose work overlaps in time on one device
+ * (different host threads, or different streams without ordering between
+ * them) race and must not be issued; calls ordered on one stream are safe.
+ */
+int rt_range_select_device_noalloc(const rt_tree *t, const float *d_queries, uint64_t nq, uint64_t *d_offsets,
+                                   uint32_t *d_ids, uint64_t ids_capacity, uint64_t *d_status, void *stream);
+
 /* rt_range_select_device plus phase timing: events (hipEvent_t[5], created by
  * the caller) are recorded on `stream` before the count pass, after it, after
  * the scan, after the fill pass and after the segmented sort, so the caller can

@@ -80,6 +80,7 @@ _sig = {
     "rt_range_select_device_count": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp], C.c_int),
     "rt_range_select_device_fill": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _u64, _vp, _vp], C.c_int),
     "rt_range_select_async": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp], C.c_int),
+    "rt_range_select_device_noalloc": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _vp], C.c_int),
     "rt_range_select_batch": ([C.POINTER(_vp), _u32, C.POINTER(_fp), C.POINTER(_u64),
                                C.POINTER(C.POINTER(_Ids))], C.c_int),
     "rt_batch_create": ([C.POINTER(_vp), _u32, C.POINTER(_fp), C.POINTER(_u64), _u64,
@@ -283,6 +284,17 @@ def range_select_device_fill(tree: Tree, d_queries: int, nq: int, d_offsets: int
     _check(_L.rt_range_select_device_fill(tree.h, _vp(d_queries), int(nq), _vp(d_offsets), _vp(d_ids),
                                           int(ids_capacity), _vp(d_work), int(work_bytes), _vp(d_status),
                                           _vp(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 32 << 20
+
+
+def range_select_device_noalloc(tree: Tree, d_queries: int, nq: int, d_offsets: int, d_ids: int,
+                                ids_capacity: int, d_status: int, stream: int = 0):
+    """range_select_device with the library's fixed device scratch as its
+    workspace (allocates nothing; calls overlapping on one device race)."""
+    _check(_L.rt_range_select_device_noalloc(tree.h, _vp(d_queries), int(nq), _vp(d_offsets), _vp(d_ids),
+                                             int(ids_capacity), _vp(d_status), _vp(stream)))
 
 
 def range_select_async(tree: Tree, d_queries: int, nq: int, d_offsets: int, d_ids: int, ids_capacity: int,

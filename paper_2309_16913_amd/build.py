@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "librt_mi355x.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["select.hip", "scan_sort.hip", "segsort.hip", "join.hip", "batch_kernels.hip", "str_device.hip",
-           "select_async.hip", "tune.hip", "rt_api.cpp", "join_api.cpp", "batch.cpp"]
+           "select_async.hip", "tune.hip", "noalloc.hip", "rt_api.cpp", "join_api.cpp", "batch.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950", "-fno-gpu-rdc",
