@@ -180,10 +180,23 @@ int rt_spatial_join(const rt_tree *a, const rt_tree *b, rt_pairs **out);
 /* Join with an explicit expansion variant (RT_JOIN_* flags above; results
  * never depend on it).  tests, if not NULL, receives the number of child-pair
  * predicates evaluated in expansions where both nodes are at the same level
- * (0 for RT_JOIN_TILE, which does not count).  Pruning flags on a tree built
+ * (for RT_JOIN_TILE: the real entry pairs n_u * n_v of every such node
+ * pair; padding slots are not counted).  Pruning flags on a tree built
  * without RT_BUILD_SORT_LX, unknown bits, or TILE combined with pruning ->
  * RT_EINVAL. */
 int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t flags, rt_pairs **out, uint64_t *tests);
+
+/* Work of the plain synchronized traversal of section 4 (the tile
+ * expansion, no pruning) for the byte and operation model of the join:
+ * node_pairs = node pairs visited over all levels (including the root pair
+ * and the pairs where only the deeper tree descends), entry_pairs = entry
+ * predicates evaluated (n_u * n_v real entries per node pair at equal
+ * levels, plus the deeper node's entries against the other tree's bounding
+ * box where one side descends alone), entries = real entries loaded.  Runs
+ * the join once (results discarded).  Same argument rules as
+ * rt_spatial_join. */
+int rt_join_visit_stats(const rt_tree *a, const rt_tree *b, uint64_t *node_pairs, uint64_t *entry_pairs,
+                        uint64_t *entries);
 
 /* Join with the result left in device memory: d_pairs (2 * capacity uint32
  * on the trees' device, caller-owned) receives pairs[2k] = a,

@@ -72,6 +72,7 @@ _sig = {
     "rt_spatial_join": ([_vp, _vp, C.POINTER(C.POINTER(_Pairs))], C.c_int),
     "rt_spatial_join_ex": ([_vp, _vp, C.c_int32, C.POINTER(C.POINTER(_Pairs)), C.POINTER(_u64)], C.c_int),
     "rt_spatial_join_device": ([_vp, _vp, C.c_int32, _vp, _u64, C.POINTER(_u64), _vp], C.c_int),
+    "rt_join_visit_stats": ([_vp, _vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)], C.c_int),
     "rt_free": ([_vp], None),
     "rt_select_workspace_bytes": ([_u64, _u64], _u64),
     "rt_range_select_device": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _u64, _vp, _vp], C.c_int),
@@ -238,6 +239,14 @@ def spatial_join_device(a: Tree, b: Tree, d_pairs: int, capacity: int, flags: in
         return int(n.value)
     _check(rc)
     return int(n.value)
+
+
+def join_visit_stats(a: Tree, b: Tree):
+    """(node pairs visited, entry predicates, real entries loaded) of the
+    plain synchronized-traversal join of a and b."""
+    n, p, e = _u64(), _u64(), _u64()
+    _check(_L.rt_join_visit_stats(a.h, b.h, C.byref(n), C.byref(p), C.byref(e)))
+    return int(n.value), int(p.value), int(e.value)
 
 
 def visit_stats(tree: Tree, queries):

@@ -59,13 +59,17 @@ __device__ __forceinline__ uint32_t ptr_any(const TreeView &t, uint32_t node, ui
     return t.layout == LAYOUT_AOS ? u[5 * e + 4] : u[4 * t.fanout + e];
 }
 
-// One wave per frontier pair; 4 pairs per block.
+// One wave per frontier pair; 4 pairs per block.  tests_acc (count pass
+// only, NULL: not counted): per pair, the entry-pair predicates of a pair at
+// equal levels (n_u * n_v real entries) are added to slot word 0, the real
+// entries loaded (n_u + n_v, or the deeper node's n) to word 1 and the
+// entry-versus-tree predicates of a descending pair to word 2.
 template <int MODE, bool FILL>
 __global__ void __launch_bounds__(256)
 join_level_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t nfr,
                   const uint64_t *__restrict__ nfr_dev, uint32_t *__restrict__ counts,
                   const uint64_t *__restrict__ offsets, uint2 *__restrict__ next, uint64_t *__restrict__ keys,
-                  uint64_t out_cap, Ctrl *__restrict__ ctrl) {
+                  uint64_t out_cap, Ctrl *__restrict__ ctrl, unsigned long long *__restrict__ tests_acc) {
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t p = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (nfr_dev && *nfr_dev < nfr) nfr = (uint32_t)*nfr_dev;
@@ -85,14 +89,22 @@ join_level_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t
         const TreeView &D = (MODE == JOIN_DESC_A) ? A : B;
         const TreeView &S = (MODE == JOIN_DESC_A) ? B : A;
         const uint32_t node = (MODE == JOIN_DESC_A) ? pr.x : pr.y;
-        bool hit = false;
+        bool hit = false, real = false;
         if (lane < D.fanout) {
             float lx, ly, hx, hy;
             load_any(D, node, lane, lx, ly, hx, hy);
             hit = (lx <= S.mbr[2]) && (S.mbr[0] <= hx) && (ly <= S.mbr[3]) && (S.mbr[1] <= hy);
+            real = lx == lx;   // not a padding slot
         }
         const uint64_t m = __ballot(hit);
         total = (uint32_t)__popcll(m);
+        if (!FILL && tests_acc) {
+            const uint32_t nd = (uint32_t)__popcll(__ballot(real));
+            if (lane == 0) {
+                atomicAdd(&tests_acc[(p % kTestSlots) * 16 + 1], (unsigned long long)nd);
+                atomicAdd(&tests_acc[(p % kTestSlots) * 16 + 2], (unsigned long long)nd);
+            }
+        }
         if (FILL && hit) {
             const uint64_t o = pos + (uint64_t)__popcll(m & below);
             const uint32_t c = ptr_any(D, node, lane);
@@ -107,17 +119,20 @@ join_level_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t
         // lane's (i, j) for round 0 and the per-round advance
         uint32_t i = lane / Fb, j = lane % Fb;
         const uint32_t di = 64 / Fb, dj = 64 % Fb;
+        uint32_t real_pairs = 0;
         for (uint32_t base = 0; base < tile; base += 64) {
             const bool in = base + lane < tile;
-            bool hit = false;
+            bool hit = false, real = false;
             if (in) {
                 float alx, aly, ahx, ahy, blx, bly, bhx, bhy;
                 load_any(A, pr.x, i, alx, aly, ahx, ahy);
                 load_any(B, pr.y, j, blx, bly, bhx, bhy);
                 hit = (alx <= bhx) && (blx <= ahx) && (aly <= bhy) && (bly <= ahy);
+                real = (alx == alx) && (blx == blx);   // neither is a padding slot
             }
             const uint64_t m = __ballot(hit);
             const uint32_t n = (uint32_t)__popcll(m);
+            if (!FILL && tests_acc) real_pairs += (uint32_t)__popcll(__ballot(real));
             if (FILL && hit) {
                 const uint64_t o = pos + total + (uint64_t)__popcll(m & below);
                 const uint32_t ca = ptr_any(A, pr.x, i), cb = ptr_any(B, pr.y, j);
@@ -136,6 +151,23 @@ join_level_kernel(TreeView A, TreeView B, const uint2 *__restrict__ fr, uint32_t
             if (j >= Fb) {
                 j -= Fb;
                 i += 1;
+            }
+        }
+        if (!FILL && tests_acc) {
+            float x, y, z, w;
+            bool ra = false, rb = false;
+            if (lane < Fa) {
+                load_any(A, pr.x, lane, x, y, z, w);
+                ra = x == x;
+            }
+            if (lane < Fb) {
+                load_any(B, pr.y, lane, x, y, z, w);
+                rb = x == x;
+            }
+            const uint32_t ne = (uint32_t)(__popcll(__ballot(ra)) + __popcll(__ballot(rb)));
+            if (lane == 0) {
+                atomicAdd(&tests_acc[(p % kTestSlots) * 16], (unsigned long long)real_pairs);
+                atomicAdd(&tests_acc[(p % kTestSlots) * 16 + 1], (unsigned long long)ne);
             }
         }
     }
@@ -377,14 +409,14 @@ static hipError_t launch_cand_flags(const TreeView &a, const TreeView &b, const 
 template <int MODE>
 static hipError_t launch_mode(const TreeView &a, const TreeView &b, const uint2 *fr, uint32_t nfr, const uint64_t *nd,
                               bool fill, uint32_t *counts, const uint64_t *offsets, uint2 *next, uint64_t *keys,
-                              uint64_t cap, Ctrl *ctrl, hipStream_t s) {
+                              uint64_t cap, Ctrl *ctrl, unsigned long long *tests_acc, hipStream_t s) {
     const uint32_t blocks = (nfr + 3) / 4;
     if (fill)
         hipLaunchKernelGGL((join_level_kernel<MODE, true>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr, nd, counts,
-                           offsets, next, keys, cap, ctrl);
+                           offsets, next, keys, cap, ctrl, (unsigned long long *)nullptr);
     else
         hipLaunchKernelGGL((join_level_kernel<MODE, false>), dim3(blocks), dim3(256), 0, s, a, b, fr, nfr, nd,
-                           counts, offsets, next, keys, cap, ctrl);
+                           counts, offsets, next, keys, cap, ctrl, tests_acc);
     return hipGetLastError();
 }
 
@@ -402,13 +434,17 @@ hipError_t launch_join_level(const TreeView &a, const TreeView &b, const uint2 *
     }
     switch (mode) {
     case JOIN_BOTH:
-        return launch_mode<JOIN_BOTH>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, s);
+        return launch_mode<JOIN_BOTH>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, tests_acc,
+                                      s);
     case JOIN_EMIT:
-        return launch_mode<JOIN_EMIT>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, s);
+        return launch_mode<JOIN_EMIT>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, tests_acc,
+                                      s);
     case JOIN_DESC_A:
-        return launch_mode<JOIN_DESC_A>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, s);
+        return launch_mode<JOIN_DESC_A>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl,
+                                        tests_acc, s);
     default:
-        return launch_mode<JOIN_DESC_B>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl, s);
+        return launch_mode<JOIN_DESC_B>(a, b, frontier, nfr, nd, fill, counts, offsets, next, keys, cap, ctrl,
+                                        tests_acc, s);
     }
 }
 

@@ -47,7 +47,10 @@ struct JoinRun {
     Grow ctrl, fr[2], cnt, off, stmp, keys, ktmp, hist, hscan, rtmp, tacc, lvl, slot;
     uint64_t npairs = 0;
     const uint64_t *sorted = nullptr;   // device, npairs keys
-    uint64_t tests = 0;
+    uint64_t tests = 0;                 // entry-pair predicates at equal levels (counted runs)
+    uint64_t test_entries = 0;          // real entries loaded by the tile expansion (counted runs)
+    uint64_t test_desc = 0;             // entry-versus-tree predicates of descending pairs
+    uint64_t node_pairs = 0;            // node pairs visited over all levels (level-by-level runs)
     bool pairs_done = false;            // the (a, b) words are already written (replay with sort)
     // frontier size of every level in the last join run level by level with
     // host reads (empty: none yet); sizes the grids of the replayed levels
@@ -396,12 +399,18 @@ int join_keys(const rt_tree *a, const rt_tree *b, int flags, bool count_tests, h
     if (e != hipSuccess) return hip_fail(e, "join status");
     if (hc.err) return fail(RT_EDEVICE, "kernel check failed (flags %u)", hc.err);
     w.last_levels = levels;
-    w.tests = 0;
+    w.tests = w.test_entries = w.test_desc = 0;
+    w.node_pairs = 0;
+    for (uint64_t l : levels) w.node_pairs += l;
     if (tacc) {
         std::vector<unsigned long long> h(kTestSlots * 16);
         e = hipMemcpy(h.data(), tacc, h.size() * 8, hipMemcpyDeviceToHost);
         if (e != hipSuccess) return hip_fail(e, "join statistics");
-        for (uint32_t k = 0; k < kTestSlots; ++k) w.tests += h[k * 16];
+        for (uint32_t k = 0; k < kTestSlots; ++k) {
+            w.tests += h[k * 16];
+            w.test_entries += h[k * 16 + 1];
+            w.test_desc += h[k * 16 + 2];
+        }
     }
     return RT_OK;
 }
@@ -469,6 +478,31 @@ extern "C" int rt_spatial_join_ex(const rt_tree *a, const rt_tree *b, int32_t fl
             }
         }
         *out = r;
+        return RT_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(RT_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(RT_EDEVICE, "unexpected failure");
+    }
+}
+
+extern "C" int rt_join_visit_stats(const rt_tree *a, const rt_tree *b, uint64_t *node_pairs, uint64_t *entry_pairs,
+                                   uint64_t *entries) {
+    if (!node_pairs || !entry_pairs || !entries) return fail(RT_EINVAL, "NULL argument");
+    *node_pairs = *entry_pairs = *entries = 0;
+    int32_t flags = RT_JOIN_TILE;
+    int rc = check_join_args(a, b, &flags);
+    if (rc) return rc;
+    try {
+        DevSet ds(a->device);
+        hipStream_t s = nullptr;
+        PooledRun run(a->device, s);
+        JoinRun &w = *run.w;
+        rc = join_keys(a, b, flags, true, s, w, nullptr, 0);
+        if (rc) return rc;
+        *node_pairs = w.node_pairs;
+        *entry_pairs = w.tests + w.test_desc;
+        *entries = w.test_entries;
         return RT_OK;
     } catch (const std::bad_alloc &) {
         return fail(RT_ENOMEM, "host allocation failed");

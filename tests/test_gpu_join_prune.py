@@ -276,3 +276,73 @@ def test_join_graph_replays(rt, ora):
         small = torch.full((2 * 10,), 7, dtype=torch.int32, device="cuda")
         assert rt.spatial_join_device(ta, tb, small.data_ptr(), 10) == n
         assert bool((small == 7).all())
+
+
+def _walk_counts(ea, eb):
+    """Node pairs, entry predicates and real entries of the synchronized
+    traversal, walked on the host over two exported trees (the deeper tree
+    descends alone against the other tree's bounding box until the levels
+    meet)."""
+    def entries(ex, u):
+        f0, c = int(ex["first"][u]), int(ex["count"][u])
+        return np.stack([ex["lx"][f0:f0 + c], ex["ly"][f0:f0 + c], ex["hx"][f0:f0 + c], ex["hy"][f0:f0 + c]], 1), \
+            ex["ptr"][f0:f0 + c]
+
+    def mbr(ex):
+        e, _ = entries(ex, 0)
+        return np.array([e[:, 0].min(), e[:, 1].min(), e[:, 2].max(), e[:, 3].max()], np.float32)
+
+    la, lb = int(ea["height"]) - 1, int(eb["height"]) - 1
+    fr = [(0, 0)]
+    pairs = preds = ents = 0
+    while fr:
+        pairs += len(fr)
+        nxt = []
+        for u, v in fr:
+            if la > lb or lb > la:
+                deep, other, node = (ea, eb, u) if la > lb else (eb, ea, v)
+                e, p = entries(deep, node)
+                m = mbr(other)
+                hit = (e[:, 0] <= m[2]) & (m[0] <= e[:, 2]) & (e[:, 1] <= m[3]) & (m[1] <= e[:, 3])
+                preds += e.shape[0]
+                ents += e.shape[0]
+                nxt += [(int(c), v) if la > lb else (u, int(c)) for c in p[hit]]
+            else:
+                a, pa = entries(ea, u)
+                b, pb = entries(eb, v)
+                preds += a.shape[0] * b.shape[0]
+                ents += a.shape[0] + b.shape[0]
+                if la == 0:
+                    continue
+                hit = ((a[:, None, 0] <= b[None, :, 2]) & (b[None, :, 0] <= a[:, None, 2]) &
+                       (a[:, None, 1] <= b[None, :, 3]) & (b[None, :, 1] <= a[:, None, 3]))
+                ii, jj = np.nonzero(hit)
+                nxt += list(zip(pa[ii].tolist(), pb[jj].tolist()))
+        if la > lb:
+            la -= 1
+        elif lb > la:
+            lb -= 1
+        else:
+            if la == 0:
+                break
+            la -= 1
+            lb -= 1
+        fr = nxt
+    return pairs, preds, ents
+
+
+@pytest.mark.parametrize("na,Fa,nb,Fb", [(3000, 8, 2500, 8), (4000, 16, 200, 4), (300, 32, 5000, 5)])
+def test_join_visit_stats(rt, ora, na, Fa, nb, Fb):
+    """The byte/operation model's counts of the plain traversal equal a host
+    walk over the exported trees; at equal heights the tile expansion's
+    predicate count equals the oracle's unpruned join count."""
+    A = rtgen.uniform_rects(na, 0.02, 41)
+    B = rtgen.clustered_rects(nb, 4, 0.05, 0.02, 42)
+    ta, tb = rt.build_str(A, Fa, "soa", sort_lx=True), rt.build_str(B, Fb, "aos", sort_lx=True)
+    got = rt.join_visit_stats(ta, tb)
+    want = _walk_counts(ta.export(), tb.export())
+    assert got == want, (got, want)
+    if ta.info().height == tb.info().height:
+        _, tile_tests = rt.spatial_join(ta, tb, rt.JOIN_TILE, with_tests=True)
+        oa, ob = ora.tree_from_arrays(**ta.export()), ora.tree_from_arrays(**tb.export())
+        assert tile_tests == ora.join_opt(oa, ob, 0)[1] == got[1]
