@@ -1,8 +1,10 @@
 // Batched range select over many independent trees.
 //
-// rt_batch_create copies every instance's queries to the device, builds a
-// work queue of (tree, query-chunk) items ordered by estimated cost (largest
-// first, so the long items start early and the tail stays short), runs one
+// rt_batch_create copies every instance's queries to the device, orders each
+// tree's queries by the Morton code of their centres, builds per-XCD work
+// lists of (tree, query-chunk) items (trees by decreasing estimated cost, so
+// the long items start early and the tail stays short; a tree's items on one
+// XCD unless it is large), runs one
 // count pass to size the output pool, and captures the whole select -- zero
 // the counters, persistent count pass, scan, persistent fill pass, segmented
 // sort, status -- into one HIP graph.  rt_batch_run replays that graph.
@@ -32,6 +34,8 @@ struct rt_batch {
     void *d_ids = nullptr, *d_scratch = nullptr, *d_ctrl = nullptr, *d_scan = nullptr, *d_status = nullptr;
     void *d_plain_off = nullptr, *d_lists = nullptr;
     void *d_qrange = nullptr;   // per query: its tree's object count (the bound of its ids)
+    void *d_qorder = nullptr;   // per position of a tree's processing order: the local query index
+    void *d_list_begin = nullptr;   // kXcds + 1 item list bounds
     uint64_t id_range = 0;   // largest object count of the batch's trees
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -44,7 +48,7 @@ void rtk::batch_release(rt_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     void *bufs[] = {b->d_trees, b->d_items, b->d_q,    b->d_counts, b->d_off,       b->d_ids,
                     b->d_scratch, b->d_ctrl, b->d_scan, b->d_status, b->d_plain_off, b->d_lists,
-                    b->d_qrange};
+                    b->d_qrange, b->d_qorder, b->d_list_begin};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     b->~rt_batch();
@@ -57,9 +61,11 @@ static hipError_t enqueue_count_scan(rt_batch *b, hipStream_t s) {
     Ctrl *ctrl = static_cast<Ctrl *>(b->d_ctrl);
     hipError_t e = launch_zero(ctrl, sizeof(Ctrl), s);
     if (e == hipSuccess)
-        e = launch_batch_pass(static_cast<BatchTree *>(b->d_trees), static_cast<BatchItem *>(b->d_items), b->nitems,
-                              static_cast<float4 *>(b->d_q), SEL_COUNT, static_cast<uint32_t *>(b->d_counts), nullptr,
-                              nullptr, 0, b->total_q, ctrl, 0, b->wave_words, s);
+        e = launch_batch_pass(static_cast<BatchTree *>(b->d_trees), static_cast<BatchItem *>(b->d_items),
+                              static_cast<const uint32_t *>(b->d_list_begin), b->nitems,
+                              static_cast<const uint32_t *>(b->d_qorder), static_cast<float4 *>(b->d_q), SEL_COUNT,
+                              static_cast<uint32_t *>(b->d_counts), nullptr, nullptr, 0, b->total_q, ctrl, 0,
+                              b->wave_words, s);
     if (e == hipSuccess)
         e = launch_scan_u32(static_cast<uint32_t *>(b->d_counts), b->total_q, static_cast<uint64_t *>(b->d_off),
                             static_cast<uint64_t *>(b->d_scan), s);
@@ -70,10 +76,11 @@ static hipError_t enqueue_all(rt_batch *b, hipStream_t s) {
     hipError_t e = enqueue_count_scan(b, s);
     Ctrl *ctrl = static_cast<Ctrl *>(b->d_ctrl);
     if (e == hipSuccess)
-        e = launch_batch_pass(static_cast<BatchTree *>(b->d_trees), static_cast<BatchItem *>(b->d_items), b->nitems,
-                              static_cast<float4 *>(b->d_q), SEL_FILL, static_cast<uint32_t *>(b->d_counts),
-                              static_cast<uint64_t *>(b->d_off), static_cast<uint32_t *>(b->d_ids), b->cap, b->total_q,
-                              ctrl, 1, b->wave_words, s);
+        e = launch_batch_pass(static_cast<BatchTree *>(b->d_trees), static_cast<BatchItem *>(b->d_items),
+                              static_cast<const uint32_t *>(b->d_list_begin), b->nitems,
+                              static_cast<const uint32_t *>(b->d_qorder), static_cast<float4 *>(b->d_q), SEL_FILL,
+                              static_cast<uint32_t *>(b->d_counts), static_cast<uint64_t *>(b->d_off),
+                              static_cast<uint32_t *>(b->d_ids), b->cap, b->total_q, ctrl, 1, b->wave_words, s);
     if (e == hipSuccess)
         e = launch_segsort(static_cast<uint64_t *>(b->d_off), b->total_q, static_cast<uint32_t *>(b->d_ids),
                            static_cast<uint32_t *>(b->d_scratch), b->cap, static_cast<uint32_t *>(b->d_lists),
@@ -119,9 +126,11 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
             BatchItem it;
             double cost;
         };
-        std::vector<Cand> cand;
+        std::vector<std::vector<Cand>> per_tree(ntrees);
+        std::vector<double> tree_cost(ntrees, 0.0);
         std::vector<float> hq((size_t)total * 4);
-        std::vector<uint32_t> hrange((size_t)total);
+        std::vector<uint32_t> hrange((size_t)total), horder((size_t)total);
+        std::vector<uint64_t> code;
         uint64_t qb = 0;
         for (uint32_t i = 0; i < ntrees; ++i) {
             const rt_tree *t = trees[i];
@@ -136,25 +145,82 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
             if (nq[i]) std::memcpy(hq.data() + 4 * qb, queries[i], nq[i] * 16);
             std::fill(hrange.begin() + qb, hrange.begin() + qb + nq[i],
                       (uint32_t)std::min<uint64_t>(t->n_objects, 0xFFFFFFFFull));
-            // chunks of 8 queries per group; cost ~ expected hits + per-query path length
+            // processing order: Morton code of the window centres on a
+            // 65536 x 65536 grid over the tree's MBR (only the order of the
+            // work depends on it)
+            const double mw = (double)t->mbr[2] - t->mbr[0], mh = (double)t->mbr[3] - t->mbr[1];
+            const bool grid = mw > 0 && mh > 0 && mw < 1e300 && mh < 1e300;
+            code.resize(nq[i]);
+            for (uint64_t k = 0; k < nq[i]; ++k) {
+                const float *w = queries[i] + 4 * k;
+                uint64_t c = 0;
+                if (grid) {
+                    double cx = ((0.5 * w[0] + 0.5 * w[2]) - t->mbr[0]) / mw * 65535.0;
+                    double cy = ((0.5 * w[1] + 0.5 * w[3]) - t->mbr[1]) / mh * 65535.0;
+                    cx = cx > 0 ? (cx < 65535.0 ? cx : 65535.0) : 0.0;   // NaN -> 0
+                    cy = cy > 0 ? (cy < 65535.0 ? cy : 65535.0) : 0.0;
+                    const uint32_t ix = (uint32_t)cx, iy = (uint32_t)cy;
+                    for (int bit = 0; bit < 16; ++bit)
+                        c |= (uint64_t)((ix >> bit) & 1u) << (2 * bit) | (uint64_t)((iy >> bit) & 1u) << (2 * bit + 1);
+                }
+                code[k] = (c << 32) | k;
+            }
+            std::sort(code.begin(), code.end());
+            for (uint64_t k = 0; k < nq[i]; ++k) horder[qb + k] = (uint32_t)(code[k] & 0xFFFFFFFFu);
+            // chunks of 8 queries per group in that order; cost ~ expected
+            // hits + per-query path length (window area as a fraction of the
+            // tree's MBR)
             const uint32_t chunk = 8 * (64 / G);
-            const double area_scale = (double)t->n_objects;
+            const double area = grid ? mw * mh : 1.0;
             for (uint64_t q0 = 0; q0 < nq[i]; q0 += chunk) {
                 const uint64_t q1 = std::min<uint64_t>(nq[i], q0 + chunk);
                 double c = 0;
                 for (uint64_t k = q0; k < q1; ++k) {
-                    const float *w = queries[i] + 4 * k;
-                    double a = (double)(w[2] - w[0]) * (double)(w[3] - w[1]);
+                    const float *w = queries[i] + 4 * horder[qb + k];
+                    double a = (double)(w[2] - w[0]) * (double)(w[3] - w[1]) / area;
                     if (!(a < 1.0)) a = 1.0;
-                    c += a * area_scale / t->fanout + t->height;
+                    c += a * (double)t->n_objects / t->fanout + t->height;
                 }
-                cand.push_back({BatchItem{i, (uint32_t)q0, (uint32_t)q1, 0u}, c});
+                per_tree[i].push_back({BatchItem{i, (uint32_t)q0, (uint32_t)q1, 0u}, c});
+                tree_cost[i] += c;
             }
             qb += nq[i];
         }
-        std::stable_sort(cand.begin(), cand.end(), [](const Cand &x, const Cand &y) { return x.cost > y.cost; });
-        std::vector<BatchItem> items(cand.size());
-        for (size_t k = 0; k < cand.size(); ++k) items[k] = cand[k].it;
+        // XCD lists: trees by decreasing cost; a tree costing more than half
+        // of an XCD's fair share is cut into kXcds runs of its order (one per
+        // XCD), every other tree goes whole to the least loaded XCD
+        double all = 0;
+        for (double c : tree_cost) all += c;
+        std::vector<uint32_t> by_cost(ntrees);
+        std::iota(by_cost.begin(), by_cost.end(), 0u);
+        std::stable_sort(by_cost.begin(), by_cost.end(),
+                         [&](uint32_t x, uint32_t y) { return tree_cost[x] > tree_cost[y]; });
+        std::vector<std::vector<BatchItem>> lists(kXcds);
+        std::vector<double> load(kXcds, 0.0);
+        for (uint32_t i : by_cost) {
+            const auto &its = per_tree[i];
+            if (its.empty()) continue;
+            if (tree_cost[i] > 0.5 * all / kXcds && its.size() >= kXcds) {
+                double acc = 0;
+                for (const Cand &c : its) {
+                    const uint32_t x = std::min<uint32_t>(kXcds - 1, (uint32_t)(acc / tree_cost[i] * kXcds));
+                    lists[x].push_back(c.it);
+                    load[x] += c.cost;
+                    acc += c.cost;
+                }
+            } else {
+                const uint32_t x = (uint32_t)(std::min_element(load.begin(), load.end()) - load.begin());
+                for (const Cand &c : its) lists[x].push_back(c.it);
+                load[x] += tree_cost[i];
+            }
+        }
+        std::vector<BatchItem> items;
+        std::vector<uint32_t> list_begin(kXcds + 1, 0);
+        for (uint32_t x = 0; x < kXcds; ++x) {
+            list_begin[x] = (uint32_t)items.size();
+            items.insert(items.end(), lists[x].begin(), lists[x].end());
+        }
+        list_begin[kXcds] = (uint32_t)items.size();
         b->nitems = (uint32_t)items.size();
 
         hipError_t e = dmalloc(&b->d_trees, bt.size() * sizeof(BatchTree));
@@ -167,6 +233,8 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         if (e == hipSuccess) e = dmalloc(&b->d_status, 16);
         if (e == hipSuccess) e = dmalloc(&b->d_lists, segsort_ws_elems(std::max<uint64_t>(total, 1)) * 4);
         if (e == hipSuccess) e = dmalloc(&b->d_qrange, std::max<uint64_t>(total, 1) * 4);
+        if (e == hipSuccess) e = dmalloc(&b->d_qorder, std::max<uint64_t>(total, 1) * 4);
+        if (e == hipSuccess) e = dmalloc(&b->d_list_begin, (kXcds + 1) * 4);
         uint64_t plain_total = 0;
         b->plain_begin.resize(ntrees);
         for (uint32_t i = 0; i < ntrees; ++i) {
@@ -180,6 +248,10 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         if (e == hipSuccess && total) e = hipMemcpy(b->d_q, hq.data(), total * 16, hipMemcpyHostToDevice);
         if (e == hipSuccess && total)
             e = hipMemcpy(b->d_qrange, hrange.data(), total * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && total)
+            e = hipMemcpy(b->d_qorder, horder.data(), total * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_list_begin, list_begin.data(), (kXcds + 1) * 4, hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(hip_fail(e, "batch setup"));
 
         // one eager count pass: output size and the per-instance bases
@@ -265,13 +337,22 @@ extern "C" int rt_batch_status(rt_batch *b, uint64_t *total, uint64_t *flags) {
     DevSet ds(b->device);
     hipError_t e = hipDeviceSynchronize();
     if (b->last_plain) {
+        // the totals the plain launches computed, tree by tree (each tree's
+        // output range was sized by the creation-time count pass)
         Ctrl hc;
         if (e == hipSuccess) e = hipMemcpy(&hc, b->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+        uint64_t t = 0, over = 0;
+        for (uint32_t i = 0; i < b->ntrees && e == hipSuccess; ++i) {
+            if (!b->nq[i]) continue;
+            uint64_t last = 0;
+            e = hipMemcpy(&last, static_cast<uint64_t *>(b->d_plain_off) + b->plain_begin[i] + b->nq[i], 8,
+                          hipMemcpyDeviceToHost);
+            t += last;
+            if (last > b->id_count[i] || b->id_base[i] + last > b->cap) over = 1;
+        }
         if (e != hipSuccess) return hip_fail(e, "batch status");
-        uint64_t t = 0;
-        for (uint32_t i = 0; i < b->ntrees; ++i) t += b->id_count[i];
         *total = t;
-        *flags = (hc.err ? 2u : 0u) | (t > b->cap ? 1u : 0u);
+        *flags = (hc.err ? 2u : 0u) | over;
         return RT_OK;
     }
     uint64_t st[2] = {0, 0};

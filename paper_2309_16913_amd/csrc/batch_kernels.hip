@@ -1,27 +1,31 @@
 // Persistent multi-tree range-select pass.
 //
 // A device work queue holds (tree, query-chunk) items for many independent
-// trees that may differ in fanout and node layout.  Each wave takes one item
-// at a time from a global counter, configures its lanes into groups of
-// G = group_width(F) lanes for that tree, and runs the same per-query
-// depth-first traversal as the single-tree kernel (lanes over node entries,
-// __ballot masks, LDS stacks).  Groups of a wave pick the item's queries in
-// order with a wave-local ballot, so only one global atomic is spent per
-// item.
+// trees that may differ in fanout and node layout.  The items are kept in one
+// list per XCD: a tree's items go to one XCD (a large tree's are cut into
+// contiguous runs of its processing order, one per XCD), so that each tree's
+// nodes are shared in one XCD's L2.  A wave takes one item at a time from its
+// XCD's list (then from the others when that is drained), configures its
+// lanes into groups of G = group_width(F) lanes for that tree, and runs the
+// same per-query depth-first traversal as the single-tree kernel (lanes over
+// node entries, __ballot masks, LDS stacks).  Groups of a wave pick the
+// item's queries in order with a wave-local ballot, so only one global
+// atomic is spent per item; the queries of a tree are visited in the Morton
+// order of their centres, so consecutive queries share nodes.
 #include "rt_internal.h"
 
 namespace rtk {
 
-__device__ __forceinline__ void batch_load(const TreeView &t, const uint8_t *nb, uint32_t e, float &lx, float &ly,
-                                           float &hx, float &hy) {
-    const uint32_t F = t.fanout;
-    if (t.layout == LAYOUT_SOA) {
+template <int LAYOUT>
+__device__ __forceinline__ void batch_load(const uint8_t *nb, uint32_t F, uint32_t e, float &lx, float &ly, float &hx,
+                                           float &hy) {
+    if constexpr (LAYOUT == LAYOUT_SOA) {
         const float *f = reinterpret_cast<const float *>(nb);
         lx = f[e];
         ly = f[F + e];
         hx = f[2 * F + e];
         hy = f[3 * F + e];
-    } else if (t.layout == LAYOUT_AOS) {
+    } else if constexpr (LAYOUT == LAYOUT_AOS) {
         const float *f = reinterpret_cast<const float *>(nb) + 5 * e;
         lx = f[0];
         ly = f[1];
@@ -37,14 +41,167 @@ __device__ __forceinline__ void batch_load(const TreeView &t, const uint8_t *nb,
     }
 }
 
-__device__ __forceinline__ uint32_t batch_ptr(const TreeView &t, const uint8_t *nb, uint32_t e) {
+template <int LAYOUT>
+__device__ __forceinline__ uint32_t batch_ptr(const uint8_t *nb, uint32_t F, uint32_t e) {
     const uint32_t *u = reinterpret_cast<const uint32_t *>(nb);
-    return t.layout == LAYOUT_AOS ? u[5 * e + 4] : u[4 * t.fanout + e];
+    if constexpr (LAYOUT == LAYOUT_AOS) return u[5 * e + 4];
+    return u[4 * F + e];
+}
+
+// Next item for a wave leader: from XCD `home`'s list first, then from the
+// following lists in turn (`visited` counts the lists found drained).
+__device__ __forceinline__ uint32_t grab_item(Ctrl *ctrl, uint32_t slot, const uint32_t *list_begin, uint32_t home,
+                                              uint32_t &visited) {
+    while (visited < kXcds) {
+        const uint32_t x = (home + visited) % kXcds;
+        const uint32_t b0 = list_begin[x], b1 = list_begin[x + 1];
+        // a drained list's counter only grows: a read showing it drained is
+        // final, and the atomic that idle waves would queue on is skipped
+        if (visited > 0 &&
+            __hip_atomic_load(&ctrl->xwork[slot][x][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= b1 - b0) {
+            visited += 1;
+            continue;
+        }
+        const uint32_t k = atomicAdd(&ctrl->xwork[slot][x][0], 1u);
+        if (k < b1 - b0) return b0 + k;
+        visited += 1;
+    }
+    return kNoNode;
+}
+
+// One work item: the queries [item.q0, item.q1) of one tree's processing
+// order, run by the wave's groups of G lanes on a tree of node layout LAYOUT.
+template <int MODE, int G, int LAYOUT>
+__device__ __forceinline__ void batch_item(const BatchTree &bt, const BatchItem &item, const uint32_t *__restrict__ qorder,
+                                           const float4 *__restrict__ qs, uint32_t *__restrict__ counts,
+                                           const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids,
+                                           Ctrl *__restrict__ ctrl, uint32_t *wstk, uint32_t lane,
+                                           uint64_t lanes_below) {
+    const TreeView &t = bt.t;
+    const uint32_t F = t.fanout;
+    const uint32_t e = lane & (G - 1);
+    const uint32_t gbase = lane & ~(G - 1);
+    const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+    const uint64_t below = (e == 0) ? 0ull : (~0ull >> (64 - e));
+    uint32_t *stk = wstk + (lane / G) * bt.stack_cap;
+    uint32_t nextq = item.q0;   // wave-uniform
+    uint64_t gq = 0;            // global query index of the group's query
+    bool have = false, done = false;
+    uint32_t sp = 0;
+    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+    uint64_t pos = 0, end = 0;
+
+    while (true) {
+        const bool need = !done && sp == 0;
+        if (need && have) {
+            if constexpr (MODE == SEL_COUNT) {
+                if (e == 0) counts[gq] = (uint32_t)pos;
+            }
+            have = false;
+        }
+        // leaders of needy groups take consecutive queries of the item
+        const uint64_t lead = __ballot(need && e == 0);
+        const uint32_t r = (uint32_t)__popcll(lead & lanes_below);
+        uint32_t mine = __shfl(nextq + r, (int)gbase);
+        nextq += (uint32_t)__popcll(lead);
+        if (need) {
+            if (mine < item.q1) {
+                gq = bt.q_begin + qorder[bt.q_begin + mine];
+                have = true;
+                q = qs[gq];
+                stk[0] = 0u;
+                sp = 1;
+                if constexpr (MODE == SEL_FILL) {
+                    pos = offsets[gq];
+                    end = offsets[gq + 1];
+                } else {
+                    pos = 0;
+                }
+            } else {
+                done = true;
+            }
+        }
+        if (__all(done)) break;
+        __builtin_amdgcn_wave_barrier();
+
+        uint32_t node = 0;
+        if (have) {
+            sp -= 1;
+            node = stk[sp];
+        }
+        const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
+        const bool leaf = node >= t.first_leaf;
+        bool hit = false, cont = false;
+        uint32_t ref = 0;
+        if (have && e < F) {
+            if (!leaf)
+                ref = batch_ptr<LAYOUT>(nb, F, 0);
+            else if constexpr (MODE == SEL_FILL)
+                ref = batch_ptr<LAYOUT>(nb, F, e);
+            float lx, ly, hx, hy;
+            batch_load<LAYOUT>(nb, F, e, lx, ly, hx, hy);
+            hit = (lx <= q.z) && (q.x <= hx) && (ly <= q.w) && (q.y <= hy);
+            // internal entry inside the window: its subtree is taken whole
+            cont = hit && !leaf && (q.x <= lx) && (hx <= q.z) && (q.y <= ly) && (hy <= q.w);
+        }
+        const uint64_t m = (__ballot(hit) >> gbase) & gmask;
+        const uint64_t cm = (__ballot(cont) >> gbase) & gmask;
+        const uint64_t pm = m & ~cm;
+        const uint32_t n = (uint32_t)__popcll(m);
+        const uint32_t rank = (uint32_t)__popcll(m & below);
+        if (have) {
+            if (leaf) {
+                if constexpr (MODE == SEL_FILL) {
+                    if (hit) {
+                        const uint64_t o = pos + rank;
+                        if (o < end)
+                            put_id(ids + o, ref);
+                        else
+                            atomicOr(&ctrl->err, kErrBounds);
+                    }
+                }
+                pos += n;
+            } else {
+                const uint32_t first = __shfl(ref, (int)gbase);
+                if (cm) {   // group-uniform: contained subtrees
+                    if constexpr (MODE == SEL_FILL) {
+                        // one contiguous run of the leaf-id array per run
+                        // of consecutive contained children
+                        uint64_t todo = cm;
+                        bool bad = false;
+                        while (todo) {
+                            const uint32_t j0 = (uint32_t)__builtin_ctzll(todo);
+                            const uint64_t sh = todo >> j0;
+                            const uint32_t len = ~sh ? (uint32_t)__builtin_ctzll(~sh) : 64u - j0;
+                            todo = (j0 + len >= 64) ? 0ull : (todo & (~0ull << (j0 + len)));
+                            const uint32_t l0 = t.range[first + j0].x, l1 = t.range[first + j0 + len - 1].y;
+                            pos += copy_leaf_run<4>(t, l0, l1, ids, pos, end, e, G, &bad);
+                        }
+                        if (bad && e == 0) atomicOr(&ctrl->err, kErrBounds);
+                    } else {
+                        uint32_t sc = cont ? subtree_objects(t, t.range[first + e]) : 0u;
+                        for (uint32_t d = 1; d < G; d <<= 1) sc += (uint32_t)__shfl_xor((int)sc, (int)d);
+                        pos += sc;
+                    }
+                }
+                const uint32_t prank = (uint32_t)__popcll(pm & below);
+                if (hit && !cont) {
+                    if (sp + prank < bt.stack_cap)
+                        stk[sp + prank] = first + e;
+                    else
+                        atomicOr(&ctrl->err, kErrStack);
+                }
+                sp = min(sp + (uint32_t)__popcll(pm), bt.stack_cap);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
 }
 
 template <int MODE>
 __global__ void __launch_bounds__(256)
-batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ items, uint32_t nitems,
+batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ items,
+             const uint32_t *__restrict__ list_begin, uint32_t nitems, const uint32_t *__restrict__ qorder,
              const float4 *__restrict__ qs, uint32_t *__restrict__ counts, const uint64_t *__restrict__ offsets,
              uint32_t *__restrict__ ids, uint64_t cap, uint64_t total_q, Ctrl *__restrict__ ctrl, uint32_t slot,
              uint32_t wave_words) {
@@ -55,173 +212,53 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t *wstk = smem + (threadIdx.x >> 6) * wave_words;
     const uint64_t lanes_below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const uint32_t home = blockIdx.x % kXcds;
+    uint32_t visited = 0;
 
     while (true) {
-        uint32_t it = 0;
-        if (lane == 0) it = atomicAdd(&ctrl->work[slot], 1u);
+        uint32_t it = kNoNode;
+        if (lane == 0) it = grab_item(ctrl, slot, list_begin, home, visited);
         it = __shfl(it, 0);
+        visited = __shfl(visited, 0);
         if (it >= nitems) break;
         const BatchItem item = items[it];
         const BatchTree bt = trees[item.tree];
-        const TreeView &t = bt.t;
-        const uint32_t F = t.fanout;
-        const uint32_t G = F <= 16 ? 16u : (F <= 32 ? 32u : 64u);
-        const uint32_t e = lane & (G - 1);
-        const uint32_t gbase = lane & ~(G - 1);
-        const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-        const uint64_t below = (e == 0) ? 0ull : (~0ull >> (64 - e));
-        uint32_t *stk = wstk + (lane / G) * bt.stack_cap;
-        uint32_t nextq = item.q0;   // wave-uniform
-        uint64_t gq = 0;            // global query index of the group's query
-        bool have = false, done = false;
-        uint32_t sp = 0;
-        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-        uint64_t pos = 0, end = 0;
-
-        while (true) {
-            const bool need = !done && sp == 0;
-            if (need && have) {
-                if constexpr (MODE == SEL_COUNT) {
-                    if (e == 0) counts[gq] = (uint32_t)pos;
-                }
-                have = false;
-            }
-            // leaders of needy groups take consecutive queries of the item
-            const uint64_t lead = __ballot(need && e == 0);
-            const uint32_t r = (uint32_t)__popcll(lead & lanes_below);
-            uint32_t mine = __shfl(nextq + r, (int)gbase);
-            nextq += (uint32_t)__popcll(lead);
-            if (need) {
-                if (mine < item.q1) {
-                    gq = bt.q_begin + mine;
-                    have = true;
-                    q = qs[gq];
-                    stk[0] = 0u;
-                    sp = 1;
-                    if constexpr (MODE == SEL_FILL) {
-                        pos = offsets[gq];
-                        end = offsets[gq + 1];
-                    } else {
-                        pos = 0;
-                    }
-                } else {
-                    done = true;
-                }
-            }
-            if (__all(done)) break;
-            __builtin_amdgcn_wave_barrier();
-
-            uint32_t node = 0;
-            if (have) {
-                sp -= 1;
-                node = stk[sp];
-            }
-            const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
-            const bool leaf = node >= t.first_leaf;
-            bool hit = false, cont = false;
-            uint32_t ref = 0;
-            if (have && e < F) {
-                if (!leaf)
-                    ref = batch_ptr(t, nb, 0);
-                else if constexpr (MODE == SEL_FILL)
-                    ref = batch_ptr(t, nb, e);
-                float lx, ly, hx, hy;
-                batch_load(t, nb, e, lx, ly, hx, hy);
-                hit = (lx <= q.z) && (q.x <= hx) && (ly <= q.w) && (q.y <= hy);
-                // internal entry inside the window: its subtree is taken whole
-                cont = hit && !leaf && (q.x <= lx) && (hx <= q.z) && (q.y <= ly) && (hy <= q.w);
-            }
-            const uint64_t m = (__ballot(hit) >> gbase) & gmask;
-            const uint64_t cm = (__ballot(cont) >> gbase) & gmask;
-            const uint64_t pm = m & ~cm;
-            const uint32_t n = (uint32_t)__popcll(m);
-            const uint32_t rank = (uint32_t)__popcll(m & below);
-            if (have) {
-                if (leaf) {
-                    if constexpr (MODE == SEL_FILL) {
-                        if (hit) {
-                            const uint64_t o = pos + rank;
-                            if (o < end)
-                                __builtin_nontemporal_store(ref, ids + o);
-                            else
-                                atomicOr(&ctrl->err, kErrBounds);
-                        }
-                    }
-                    pos += n;
-                } else {
-                    const uint32_t first = __shfl(ref, (int)gbase);
-                    if (cm) {   // group-uniform: contained subtrees
-                        if constexpr (MODE == SEL_FILL) {
-                            uint64_t todo = cm;
-                            while (todo) {   // one run of consecutive contained children at a time
-                                const uint32_t j0 = (uint32_t)__builtin_ctzll(todo);
-                                const uint64_t sh = todo >> j0;
-                                const uint32_t len = ~sh ? (uint32_t)__builtin_ctzll(~sh) : 64u - j0;
-                                todo = (j0 + len >= 64) ? 0ull : (todo & (~0ull << (j0 + len)));
-                                const uint32_t l0 = t.range[first + j0].x, l1 = t.range[first + j0 + len - 1].y;
-                                const bool hasp = t.partial_leaf >= l0 && t.partial_leaf < l1;
-                                constexpr uint32_t U = 4;   // leaves in flight per lane
-                                for (uint32_t lb = l0; lb < l1; lb += U) {
-                                    uint32_t v[U];
-                                    uint64_t o[U];
-#pragma unroll
-                                    for (uint32_t u = 0; u < U; ++u) {
-                                        const uint32_t lf = lb + u;
-                                        o[u] = ~0ull;
-                                        v[u] = 0;
-                                        if (lf < l1 && e < F && !(hasp && lf == t.partial_leaf && e >= t.partial_cnt)) {
-                                            o[u] = pos + (uint64_t)(lf - l0) * F + e -
-                                                   ((hasp && lf > t.partial_leaf) ? F - t.partial_cnt : 0u);
-                                            v[u] = batch_ptr(t, t.nodes + (size_t)lf * t.node_bytes, e);
-                                        }
-                                    }
-#pragma unroll
-                                    for (uint32_t u = 0; u < U; ++u) {
-                                        if (o[u] != ~0ull) {
-                                            if (o[u] < end)
-                                                __builtin_nontemporal_store(v[u], ids + o[u]);
-                                            else
-                                                atomicOr(&ctrl->err, kErrBounds);
-                                        }
-                                    }
-                                }
-                                pos += subtree_objects(t, make_uint2(l0, l1));
-                            }
-                        } else {
-                            uint32_t sc = cont ? subtree_objects(t, t.range[first + e]) : 0u;
-                            for (uint32_t d = 1; d < G; d <<= 1) sc += (uint32_t)__shfl_xor((int)sc, (int)d);
-                            pos += sc;
-                        }
-                    }
-                    const uint32_t prank = (uint32_t)__popcll(pm & below);
-                    if (hit && !cont) {
-                        if (sp + prank < bt.stack_cap)
-                            stk[sp + prank] = first + e;
-                        else
-                            atomicOr(&ctrl->err, kErrStack);
-                    }
-                    sp = min(sp + (uint32_t)__popcll(pm), bt.stack_cap);
-                }
-            }
-            __builtin_amdgcn_wave_barrier();
+        const uint32_t G = bt.t.fanout <= 16 ? 16u : (bt.t.fanout <= 32 ? 32u : 64u);
+#define RT_ITEM(G_, L_) \
+    batch_item<MODE, G_, L_>(bt, item, qorder, qs, counts, offsets, ids, ctrl, wstk, lane, lanes_below)
+        if (bt.t.layout == LAYOUT_SOA) {
+            if (G == 16) RT_ITEM(16, LAYOUT_SOA);
+            else if (G == 32) RT_ITEM(32, LAYOUT_SOA);
+            else RT_ITEM(64, LAYOUT_SOA);
+        } else if (bt.t.layout == LAYOUT_AOS) {
+            if (G == 16) RT_ITEM(16, LAYOUT_AOS);
+            else if (G == 32) RT_ITEM(32, LAYOUT_AOS);
+            else RT_ITEM(64, LAYOUT_AOS);
+        } else {
+            if (G == 16) RT_ITEM(16, LAYOUT_D2);
+            else if (G == 32) RT_ITEM(32, LAYOUT_D2);
+            else RT_ITEM(64, LAYOUT_D2);
         }
+#undef RT_ITEM
     }
 }
 
-hipError_t launch_batch_pass(const BatchTree *trees, const BatchItem *items, uint32_t nitems, const float4 *q,
-                             int mode, uint32_t *counts, const uint64_t *offsets, uint32_t *ids, uint64_t cap,
-                             uint64_t total_q, Ctrl *ctrl, uint32_t slot, uint32_t wave_words, hipStream_t s) {
+hipError_t launch_batch_pass(const BatchTree *trees, const BatchItem *items, const uint32_t *list_begin,
+                             uint32_t nitems, const uint32_t *qorder, const float4 *q, int mode, uint32_t *counts,
+                             const uint64_t *offsets, uint32_t *ids, uint64_t cap, uint64_t total_q, Ctrl *ctrl,
+                             uint32_t slot, uint32_t wave_words, hipStream_t s) {
     // wave_words: largest (64 / G) * stack_cap over the trees (one region per wave)
     const size_t smem = (size_t)4 * wave_words * sizeof(uint32_t);
     uint32_t blocks = (uint32_t)num_cus() * 8;
     const uint32_t want = (nitems + 3) / 4;
     if (want < blocks) blocks = want ? want : 1;
+    blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // every XCD gets blocks
     if (mode == SEL_COUNT)
-        hipLaunchKernelGGL(batch_kernel<SEL_COUNT>, dim3(blocks), dim3(256), smem, s, trees, items, nitems, q, counts,
-                           offsets, ids, cap, total_q, ctrl, slot, wave_words);
+        hipLaunchKernelGGL(batch_kernel<SEL_COUNT>, dim3(blocks), dim3(256), smem, s, trees, items, list_begin, nitems,
+                           qorder, q, counts, offsets, ids, cap, total_q, ctrl, slot, wave_words);
     else
-        hipLaunchKernelGGL(batch_kernel<SEL_FILL>, dim3(blocks), dim3(256), smem, s, trees, items, nitems, q, counts,
-                           offsets, ids, cap, total_q, ctrl, slot, wave_words);
+        hipLaunchKernelGGL(batch_kernel<SEL_FILL>, dim3(blocks), dim3(256), smem, s, trees, items, list_begin, nitems,
+                           qorder, q, counts, offsets, ids, cap, total_q, ctrl, slot, wave_words);
     return hipGetLastError();
 }
 

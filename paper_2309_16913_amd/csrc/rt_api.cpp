@@ -57,6 +57,7 @@ void rtk::tree_release(rt_tree *t) {
     if (t->d_nodes) (void)hipFree(t->d_nodes);
     if (t->d_meta) (void)hipFree(t->d_meta);
     if (t->d_range) (void)hipFree(t->d_range);
+    if (t->d_leaf_ids) (void)hipFree(t->d_leaf_ids);
     (void)hipSetDevice(cur);
     t->~rt_tree();
 }
@@ -116,6 +117,7 @@ TreeView rtk::view_of(const rt_tree *t) {
     v.range = static_cast<const uint2 *>(t->d_range);
     v.partial_leaf = t->partial_leaf;
     v.partial_cnt = t->partial_cnt;
+    v.leaf_ids = static_cast<const uint32_t *>(t->d_leaf_ids);
     return v;
 }
 

@@ -21,6 +21,7 @@ struct rt_tree {
     void *d_nodes = nullptr;   // n_nodes * node_bytes
     void *d_meta = nullptr;    // n_nodes uint32: count | level << 8
     void *d_range = nullptr;   // n_nodes uint2: leaves [x, y) under the node
+    void *d_leaf_ids = nullptr;   // n_objects uint32: the leaves' ids, leaf after leaf
     uint32_t partial_leaf = 0xFFFFFFFFu, partial_cnt = 0;   // the leaf with < F entries, if any
 };
 

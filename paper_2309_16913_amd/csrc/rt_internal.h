@@ -30,6 +30,10 @@ struct TreeView {
     // and its entry count
     const uint2 *range;
     uint32_t partial_leaf, partial_cnt;
+    // the object ids of all leaves, leaf after leaf in node order without
+    // padding: leaf l's ids start at leaf_start(l), so the leaves of any
+    // contiguous leaf range hold one contiguous run of ids
+    const uint32_t *leaf_ids;
 };
 constexpr uint32_t kNoNode = 0xFFFFFFFFu;
 
@@ -41,6 +45,103 @@ __device__ __forceinline__ uint32_t subtree_objects(const TreeView &t, uint2 r) 
     uint32_t c = (r.y - r.x) * t.fanout;
     if (t.partial_leaf >= r.x && t.partial_leaf < r.y) c -= t.fanout - t.partial_cnt;
     return c;
+}
+
+// Position of leaf l's first id in TreeView::leaf_ids (l may be one past the
+// last leaf: then the object count).
+__device__ __forceinline__ uint64_t leaf_start(const TreeView &t, uint32_t l) {
+    uint64_t s = (uint64_t)(l - t.first_leaf) * t.fanout;
+    if (t.partial_leaf != kNoNode && l > t.partial_leaf) s -= t.fanout - t.partial_cnt;
+    return s;
+}
+
+// Nontemporal store of an id (written once, read back only by the sort):
+// it leaves L2 and the Infinity Cache to the tree nodes.
+__device__ __forceinline__ void put_id(uint32_t *p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+
+// Copy the ids of a run of contained leaves [l0, l1) -- one contiguous run
+// of TreeView::leaf_ids -- to out[pos, pos + n) with the G lanes of a group
+// (e = lane in the group).  Loads and stores are both aligned to G-id
+// chunks of their own array: load chunk m holds ids m*G - sm + lane, store
+// chunk k writes ids k*G - dm + lane (sm, dm: the misalignment of source and
+// destination in ids), so every load instruction reads whole cache lines and
+// every store instruction writes whole 64-byte granules.  A store chunk takes
+// its ids from two consecutive load chunks, rotated by dl = (sm - dm) mod G
+// lanes (two lane permutes).  Each round loads U+1 chunks and stores U, so a
+// short run costs one memory round trip.  Returns n; writes nothing and sets
+// *bad if the run would pass `end` (the caller's range).
+template <uint32_t U>   // store chunks per round
+__device__ __forceinline__ uint64_t copy_leaf_run(const TreeView &t, uint32_t l0, uint32_t l1,
+                                                  uint32_t *__restrict__ out, uint64_t pos, uint64_t end, uint32_t e,
+                                                  uint32_t G, bool *bad) {
+    const uint64_t s0 = leaf_start(t, l0);
+    const uint64_t n = leaf_start(t, l1) - s0;
+    if (pos + n > end) {
+        *bad = true;
+        return n;
+    }
+    const uint32_t *__restrict__ src = t.leaf_ids + s0;
+    uint32_t *__restrict__ dst = out + pos;
+    const int64_t sm = (int64_t)((reinterpret_cast<uintptr_t>(src) >> 2) & (G - 1));
+    const int64_t dm = (int64_t)((reinterpret_cast<uintptr_t>(dst) >> 2) & (G - 1));
+    const int64_t o = sm >= dm ? 0 : -1;                          // first load chunk of store chunk 0
+    const uint32_t dl = (uint32_t)(sm - dm + (sm >= dm ? 0 : (int64_t)G));   // rotation, in [0, G)
+    const uint32_t from = ((threadIdx.x & 63u) - e) + ((e + dl) & (G - 1));  // wave lane to read
+    const bool upper = e + dl >= G;                                // from the second load chunk
+    const int64_t nk = ((int64_t)n + dm + G - 1) / G;              // store chunks
+    for (int64_t k = 0; k < nk; k += U) {
+        uint32_t L[U + 1];
+#pragma unroll
+        for (uint32_t u = 0; u <= U; ++u) {
+            const int64_t j = (k + o + u) * (int64_t)G - sm + e;
+            L[u] = (j >= 0 && j < (int64_t)n) ? src[j] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t a = (uint32_t)__shfl((int)L[u], (int)from);
+            const uint32_t b = (uint32_t)__shfl((int)L[u + 1], (int)from);
+            const int64_t j = (k + u) * (int64_t)G - dm + e;
+            if (j >= 0 && j < (int64_t)n) put_id(dst + j, upper ? b : a);
+        }
+    }
+    return n;
+}
+
+// Copy the ids of the contained leaves [l0, l1) to out[pos, ...) straight from
+// the leaves' ptr arrays (layouts D1 and D2, where a leaf's ids are 4F
+// contiguous bytes of its node), lane e taking entry e of U leaves per round:
+// the shorter path for runs of a few leaves, whose nodes neighbouring queries
+// also read (so they are likelier to be in L2 than the leaf-id array).
+// Requires G >= F.  Same contract as copy_leaf_run.
+template <uint32_t U>
+__device__ __forceinline__ uint64_t copy_leaves_from_nodes(const TreeView &t, uint32_t l0, uint32_t l1,
+                                                           uint32_t *__restrict__ out, uint64_t pos, uint64_t end,
+                                                           uint32_t e, bool *bad) {
+    const uint32_t F = t.fanout;
+    const uint64_t s0 = leaf_start(t, l0);
+    const uint64_t n = leaf_start(t, l1) - s0;
+    if (pos + n > end) {
+        *bad = true;
+        return n;
+    }
+    for (uint32_t lb = l0; lb < l1; lb += U) {
+        uint32_t v[U];
+        uint64_t o[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t lf = lb + u;
+            o[u] = ~0ull;
+            v[u] = 0;
+            if (lf < l1 && e < F && !(lf == t.partial_leaf && e >= t.partial_cnt)) {
+                o[u] = pos + (leaf_start(t, lf) - s0) + e;
+                v[u] = reinterpret_cast<const uint32_t *>(t.nodes + (size_t)lf * t.node_bytes)[4 * F + e];
+            }
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u)
+            if (o[u] != ~0ull) put_id(out + o[u], v[u]);
+    }
+    return n;
 }
 
 // Kernel-side status words at the start of every workspace.
@@ -195,12 +296,15 @@ struct BatchTree {
 };
 struct BatchItem {           // a chunk of one tree's queries
     uint32_t tree;
-    uint32_t q0, q1;         // local query range [q0, q1)
+    uint32_t q0, q1;         // positions [q0, q1) in the tree's processing order
     uint32_t pad;
 };
-hipError_t launch_batch_pass(const BatchTree *trees, const BatchItem *items, uint32_t nitems,
-                             const float4 *q, int mode, uint32_t *counts, const uint64_t *offsets,
-                             uint32_t *ids, uint64_t capacity, uint64_t total_q, Ctrl *ctrl,
+// Work items in kXcds lists (list x = items[list_begin[x] .. list_begin[x+1])),
+// drained first by the blocks of XCD x; qorder[q_begin + position] = local
+// query index (each tree's queries in the Morton order of their centres).
+hipError_t launch_batch_pass(const BatchTree *trees, const BatchItem *items, const uint32_t *list_begin,
+                             uint32_t nitems, const uint32_t *qorder, const float4 *q, int mode, uint32_t *counts,
+                             const uint64_t *offsets, uint32_t *ids, uint64_t capacity, uint64_t total_q, Ctrl *ctrl,
                              uint32_t work_slot, uint32_t wave_words, hipStream_t s);
 
 int num_cus();

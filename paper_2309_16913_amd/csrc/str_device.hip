@@ -199,6 +199,26 @@ __global__ void str_range_leaves(uint32_t first, uint32_t n, uint32_t F, const u
     }
 }
 
+// The leaves' object ids, leaf after leaf without padding (leaf l's at
+// leaf_start(l)); the short leaf and its count come from partial[0..1].
+__global__ void str_leaf_ids(uint32_t first_leaf, uint32_t nleaves, uint32_t F, uint32_t layout,
+                             const uint8_t *__restrict__ nodes, const uint32_t *__restrict__ meta,
+                             const uint32_t *__restrict__ partial, uint64_t n_objects,
+                             uint32_t *__restrict__ leaf_ids) {
+    const uint32_t pl = partial[0], pc = partial[1];
+    const uint64_t slots = (uint64_t)nleaves * F;
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < slots;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t l = first_leaf + (uint32_t)(i / F), e = (uint32_t)(i % F);
+        if (e >= (meta[l] & 0xFFu)) continue;
+        uint64_t start = (uint64_t)(l - first_leaf) * F;
+        if (pl != kNoNode && l > pl) start -= F - pc;
+        const uint32_t *u = reinterpret_cast<const uint32_t *>(nodes + (uint64_t)l * (20u * F));
+        if (start + e < n_objects)   // always, unless the packing broke its one-short-leaf rule
+            leaf_ids[start + e] = layout == LAYOUT_AOS ? u[5 * e + 4] : u[4 * F + e];
+    }
+}
+
 // Internal node: its children are contiguous from its first pointer, so its
 // leaves run from the first child's first leaf to the last child's end.
 __global__ void str_range_up(uint32_t first, uint32_t n, uint32_t F, uint32_t layout,
@@ -297,6 +317,7 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
     if (e == hipSuccess) e = hipMalloc(&t->d_nodes, total * t->node_bytes);
     if (e == hipSuccess) e = hipMalloc(&t->d_meta, total * 4);
     if (e == hipSuccess) e = hipMalloc(&t->d_range, total * 8);
+    if (e == hipSuccess) e = hipMalloc(&t->d_leaf_ids, n ? n * 4 : 16);
     if (e != hipSuccess) return bail(hip_fail(e, "device build allocation"));
     uint8_t *wb = static_cast<uint8_t *>(work.p);
     auto ord = [&](uint32_t l) {
@@ -388,6 +409,13 @@ int build_str_on_device(const float4 *d_rects, uint64_t n, uint32_t F, uint32_t 
         hipLaunchKernelGGL(str_range_leaves, dim3(grid_for(nodes[0])), dim3(256), 0, s, (uint32_t)first[0],
                            (uint32_t)nodes[0], F, static_cast<const uint32_t *>(t->d_meta),
                            static_cast<uint2 *>(t->d_range), partial);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && n) {
+        hipLaunchKernelGGL(str_leaf_ids, dim3(grid_for(nodes[0] * F)), dim3(256), 0, s, (uint32_t)first[0],
+                           (uint32_t)nodes[0], F, layout, static_cast<const uint8_t *>(t->d_nodes),
+                           static_cast<const uint32_t *>(t->d_meta), partial, n,
+                           static_cast<uint32_t *>(t->d_leaf_ids));
         e = hipGetLastError();
     }
     for (uint32_t l = 1; l < H && e == hipSuccess; ++l) {
