@@ -42,6 +42,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_LANE_OPS_PER_S = 256 * 64 * 2.4e9   # 256 CUs x 64 lanes x 2.4 GHz, one lane-op per lane per clock
 METRIC = "range queries/s and join pairs/s on 1 GPU (bit-exact), % HBM peak; p99 latency"
 SERVE_RATES = [1e4, 3e4, 1e5, 3e5, 1e6]
 
@@ -177,7 +178,7 @@ def pmc_summary(args):
     write_scale = calib_bytes / wk
     phases = {}
     for d, scale, skip, key in ((fetch, fetch_scale, fids, "fetch"), (write, write_scale, wids, "write")):
-        for did, (name, v, s, e) in d.items():
+        for did, (name, v, s, e) in sorted(d.items()):
             if did in skip:
                 continue
             ph = kernel_phase(name)
@@ -194,7 +195,7 @@ def pmc_summary(args):
              f"#   cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write> -o run "
              f"-- python3 /root/repo/bench.py {args.bench_args}",
              f"#   python3 bench.py --pmc-summary --fetch-dir <fetch> --write-dir <write> --tag {args.tag} "
-             f"--calib-copy-mib {args.calib_copy_mib}",
+             f"--calib-copy-mib {args.calib_copy_mib}" + (f" --last {args.last}" if args.last else ""),
              "# FETCH_SIZE / WRITE_SIZE: KiB per dispatch between L2 and the fabric (Infinity Cache hits",
              "# included, so an upper bound on DRAM bytes), scaled by the first three copies of",
              f"# {args.calib_copy_mib} MiB: fetch_scale {fetch_scale:.4f}, write_scale {write_scale:.4f}.",
@@ -205,6 +206,8 @@ def pmc_summary(args):
     for ph, p in sorted(phases.items()):
         if not p["fetch"] or not p["write"]:
             continue
+        if args.last and ph != "sort":   # only the last launches (the timed ones)
+            p = {k: v[-args.last:] for k, v in p.items()}
         per = nsteps if ph == "sort" else max(1, len(p["fetch"]))
         fb = sum(p["fetch"]) / per
         wb = sum(p["write"]) / per
@@ -217,6 +220,47 @@ def pmc_summary(args):
             lines.append(f"{ph}_source_hash: {source_hash(*src)}")
     lines += [f"fetch_scale: {fetch_scale:.4f}", f"write_scale: {write_scale:.4f}"]
     out = os.path.join(ROOT, "profiles", f"{args.tag}_traffic.txt")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out)
+
+
+def pmc_table(args):
+    """Per-kernel averages of the counters of one rocprofv3 --pmc run of
+    this script (weighted by dispatch duration), as a markdown table in
+    profiles/<tag>.md."""
+    rows = _counter_rows(args.fetch_dir)
+    per = {}
+    for r in rows:
+        did = int(r.get("Dispatch_Id") or r.get("Correlation_Id"))
+        d = per.setdefault(did, {"name": r.get("Kernel_Name", ""), "t": 0.0, "c": {}})
+        s_, e_ = int(r.get("Start_Timestamp", 0) or 0), int(r.get("End_Timestamp", 0) or 0)
+        d["t"] = max(d["t"], (e_ - s_) / 1e6)
+        d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    agg = {}
+    for d in per.values():
+        a = agg.setdefault(d["name"], {"n": 0, "t": 0.0, "c": {}})
+        a["n"] += 1
+        a["t"] += d["t"]
+        for k, v in d["c"].items():
+            a["c"][k] = a["c"].get(k, 0.0) + v * d["t"]
+    names = sorted({k for a in agg.values() for k in a["c"]})
+    pat = re.compile(args.kernel_regex) if args.kernel_regex else None
+    lines = [f"# {args.title}",
+             f"# Command: cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc {' '.join(names)} --output-format csv "
+             f"-d <out> -o run -- python3 /root/repo/bench.py {args.bench_args}",
+             f"# Summary: python3 bench.py --pmc-table --fetch-dir <out> --tag {args.tag}"
+             + (f" --kernel-regex '{args.kernel_regex}'" if args.kernel_regex else ""),
+             "# Per kernel: dispatches, total ms under the counter run, and each counter averaged over the",
+             "# dispatches weighted by their duration (derived metrics such as VALUBusy are percentages).", "",
+             "| kernel | dispatches | total ms | " + " | ".join(names) + " |",
+             "|---|---|---|" + "---|" * len(names)]
+    for name, a in sorted(agg.items(), key=lambda kv: -kv[1]["t"]):
+        if pat and not pat.search(name):
+            continue
+        vals = [a["c"].get(k, 0.0) / a["t"] if a["t"] > 0 else 0.0 for k in names]
+        lines.append(f"| `{name[:80]}` | {a['n']} | {a['t']:.2f} | " + " | ".join(f"{v:.4g}" for v in vals) + " |")
+    out = os.path.join(ROOT, "profiles", f"{args.tag}.md")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print(out)
@@ -448,7 +492,20 @@ def join_leg(rt, torch, args):
         all_same &= same
         variants[name] = dict(ms=round(vms, 4), predicate_tests=tests, pairs_equal_default=same)
     ia, ib = ta.info(), tb.info()
+    # byte / operation model of the plain synchronized traversal (section 4):
+    # every visited node pair loads both nodes (20 B per entry + 8 B header
+    # each), every emitted pair is 8 B; 7 lane operations per entry predicate
+    npairs_v, epairs, ents = rt.join_visit_stats(ta, tb)
+    vbytes = 20 * ents + 16 * npairs_v + 8 * n
+    model = {"node_pairs": npairs_v, "entry_predicates": epairs, "entries_loaded": ents,
+             "visit_bytes": vbytes, "effective_GBps": vbytes / (ms / 1e3) / 1e9,
+             "effective_frac": vbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+             "algorithmic_lane_ops": 7 * epairs,
+             "algorithmic_valu_frac": 7 * epairs / (ms / 1e3) / VALU_LANE_OPS_PER_S,
+             "note": "plain-traversal model; the default O3+O5+LB expansion evaluates "
+                     f"{variants['O3+O5+LB']['predicate_tests']} of these predicates"}
     return dict(workload=f"join_uniform{args.join_n}_x_clustered{args.join_n}_f{F}_soa_sorted_lx", pairs=int(n),
+                model=model,
                 ms=ms, pairs_per_s=n / (ms / 1e3), one_off_ms=float(np.median(once)) * 1e3,
                 host_output_ms=float(np.median(hts)) * 1e3, variants_ms=variants,
                 variants_pairs_equal=all_same, tree_bytes=[int(ia.device_bytes), int(ib.device_bytes)],
@@ -485,10 +542,11 @@ def build_leg(rt, torch, args, rects):
 
 def batch_leg(rt, torch, args):
     """256 independent instances in one persistent launch replayed from a
-    HIP graph.  Every tree gets the library's own choice of fanout, layout
-    and mapping (fanout 0, RT_LAYOUT_AUTO); baselines: the same trees with
-    plain per-tree launches, and plain per-tree launches on untuned trees
-    (fanout 32, SoA)."""
+    HIP graph.  Fanout and layout per size class of the trees, chosen by
+    timing each class's batch with every candidate (BatchTuner); beside it
+    the library's own per-tree choice (fanout 0, RT_LAYOUT_AUTO).  Baselines:
+    the same trees with plain per-tree launches, and plain per-tree launches
+    on untuned trees (fanout 32, SoA)."""
     import rtgen
     t0 = time.time()
     inst = rtgen.c4_batch(ntrees=args.batch_trees, scale=args.batch_scale)
@@ -508,8 +566,14 @@ def batch_leg(rt, torch, args):
         assert flags == 0
         return float(np.median(ts)), tot
 
+    # per-size-class fanout and layout, timed in batch context
+    from paper_2309_16913_amd.autotune import BatchTuner
     t0 = time.time()
-    trees = [rt.build_str(x.rects, 0, "auto") for x in inst]
+    bt = BatchTuner()
+    choice = bt.tune(inst)
+    tune_s = time.time() - t0
+    t0 = time.time()
+    trees = bt.build(inst, choice)
     build_s = time.time() - t0
     cfg = {}
     for t in trees:
@@ -519,8 +583,17 @@ def batch_leg(rt, torch, args):
     b = rt.Batch(trees, [x.queries for x in inst])
     out = {}
     for name, fn in (("batched_graph", b.run), ("plain_per_tree", b.run_plain)):
+        if args.batch_tuned_only and name != "batched_graph":
+            continue
         ms, tot = timed(b, fn, args.batch_reps)
         out[name] = dict(ms=ms * 1e3, queries_per_s=nq / ms, ids=tot)
+    if args.batch_tuned_only:
+        b.free()
+        for t in trees:
+            t.free()
+        out["size_class_choice"] = {str(k): {kk: v[kk] for kk in ("fanout", "layout", "trees")}
+                                    for k, v in choice.items()}
+        return out
     # byte model over all trees (same traversal with counters)
     vn = ve = vc = 0
     tree_bytes = 0
@@ -532,10 +605,22 @@ def batch_leg(rt, torch, args):
     visit_fill = 16 * nq + 20 * ve + 8 * vn + 4 * ids + 4 * vc + 8 * (nq + 1)
     comp_fill = 16 * nq + tree_bytes + 8 * (nq + 1) + 4 * ids
     b.free()
+    # the library's own per-tree choice (fanout 0, RT_LAYOUT_AUTO: probe
+    # windows drawn from each tree's data, not the batch's windows)
+    lt = [rt.build_str(x.rects, 0, "auto") for x in inst]
+    bl = rt.Batch(lt, [x.queries for x in inst])
+    ms, tot = timed(bl, bl.run, args.batch_reps)
+    assert tot == out["batched_graph"]["ids"]
+    out["batched_graph_library_choice"] = dict(ms=ms * 1e3, queries_per_s=nq / ms, ids=tot)
+    bl.free()
+    for t in lt:
+        t.free()
     g = out["batched_graph"]["ms"]
     out["speedup_vs_plain"] = out["plain_per_tree"]["ms"] / g
     out.update(workload=f"batch_{len(inst)}_trees_{sum(x.rects.shape[0] for x in inst)}_rects_{nq}_windows",
-               configs=cfg, gen_s=gen_s, build_s=build_s, tree_bytes=tree_bytes,
+               configs=cfg, size_class_choice={str(k): {kk: v[kk] for kk in ("fanout", "layout", "trees")}
+                                               for k, v in choice.items()},
+               tune_s=tune_s, gen_s=gen_s, build_s=build_s, tree_bytes=tree_bytes,
                visited={"nodes": vn, "entries": ve, "ids_from_contained_subtrees": vc},
                bytes_model={"visit_fill": visit_fill, "compulsory_fill": comp_fill},
                effective_GBps=visit_fill / (g / 1e3) / 1e9)
@@ -570,7 +655,7 @@ def serve_leg(rt, torch, args, tb, tj):
            "tree_bytes": info.device_bytes, "tree_height": info.height,
            "requests_per_rate": args.serve_requests, "warmup_requests": args.serve_warmup,
            "open_loop": [], "note": "latency = result in pinned host memory - scheduled arrival"}
-    srv = Server(tb, tj, nslots=args.serve_slots, max_windows=16384, pool_ids=args.serve_pool)
+    srv = Server(tb, tj, nslots=args.serve_slots, max_windows=args.serve_max_windows, pool_ids=args.serve_pool)
     warm = rtgen.c5_requests(args.serve_warmup, rate=1e6, seed_base=5900, probe_n=10_000)
     srv.run(warm)
     for rate in args.serve_rates:
@@ -692,20 +777,29 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=10_000)
     ap.add_argument("--serve-slots", type=int, default=3)
     ap.add_argument("--serve-pool", type=int, default=1 << 29)
+    ap.add_argument("--serve-max-windows", type=int, default=65536)
     ap.add_argument("--serve-rates", type=float, nargs="*", default=SERVE_RATES)
     ap.add_argument("--serve-device-windows", type=int, default=50_000)
     ap.add_argument("--serve-device-reps", type=int, default=3)
     # counter summaries (host only)
     ap.add_argument("--pmc-summary", action="store_true")
+    ap.add_argument("--pmc-table", action="store_true")
+    ap.add_argument("--kernel-regex", default="")
     ap.add_argument("--fetch-dir")
     ap.add_argument("--write-dir")
     ap.add_argument("--tag")
     ap.add_argument("--title", default="")
     ap.add_argument("--bench-args", default="")
     ap.add_argument("--steps-in-run", type=int, default=1)
+    ap.add_argument("--last", type=int, default=0, help="average only the last N launches of each phase")
+    ap.add_argument("--batch-tuned-only", action="store_true",
+                    help="batch leg: after tuning, time only the tuned batch (for counter runs)")
     args = ap.parse_args()
     if args.pmc_summary:
         pmc_summary(args)
+        return
+    if args.pmc_table:
+        pmc_table(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

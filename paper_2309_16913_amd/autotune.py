@@ -122,3 +122,68 @@ class Autotuner:
         t = self.rt.build_str(rects, c["fanout"], c["layout"])
         t.set_split(c["kmin"])
         return t, c
+
+
+class BatchTuner:
+    """Per-size-class choice of fanout and layout for a batch of independent
+    trees, timed in batch context: the instances are grouped by the binary
+    order of magnitude of their object count, every candidate configuration
+    is built for one class's trees and that class's batch (persistent
+    kernels replayed from its graph) is timed; each class keeps its fastest
+    configuration.  The persistent batch kernel serves trees of different
+    fanout and layout in one launch, so the classes' choices combine.
+
+    instances: objects with .rects and .queries (numpy, n x 4 float32)."""
+
+    def __init__(self, fanouts=(16, 32, 64), layouts=("aos", "soa", "d2"), reps: int = 2):
+        import paper_2309_16913_amd as rt
+        import torch
+        self.rt, self.torch = rt, torch
+        self.fanouts, self.layouts, self.reps = tuple(fanouts), tuple(layouts), reps
+
+    @staticmethod
+    def size_class(n: int) -> int:
+        return int(math.log2(max(n, 1)))
+
+    def _time_batch(self, trees, queries) -> float:
+        rt, torch = self.rt, self.torch
+        b = rt.Batch(trees, queries)
+        b.run()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(self.reps):
+            t0 = time.perf_counter()
+            b.run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        _, flags = b.status()
+        b.free()
+        assert flags == 0
+        return float(np.median(ts))
+
+    def tune(self, instances) -> dict:
+        """{size class: {"fanout", "layout", "timings_ms"}}."""
+        classes = {}
+        for k, x in enumerate(instances):
+            classes.setdefault(self.size_class(x.rects.shape[0]), []).append(k)
+        out = {}
+        for c, members in sorted(classes.items()):
+            timings = {}
+            for F in self.fanouts:
+                for lay in self.layouts:
+                    trees = [self.rt.build_str(instances[k].rects, F, lay) for k in members]
+                    timings[f"{F}/{lay}"] = self._time_batch(trees, [instances[k].queries for k in members]) * 1e3
+                    for t in trees:
+                        t.free()
+            best = min(timings, key=timings.get)
+            F, lay = best.split("/")
+            out[c] = {"fanout": int(F), "layout": lay, "trees": len(members), "timings_ms": timings}
+        return out
+
+    def build(self, instances, choice: dict):
+        """Trees with each instance's class choice."""
+        trees = []
+        for x in instances:
+            ch = choice[self.size_class(x.rects.shape[0])]
+            trees.append(self.rt.build_str(x.rects, ch["fanout"], ch["layout"]))
+        return trees

@@ -107,43 +107,6 @@ __device__ __forceinline__ uint64_t copy_leaf_run(const TreeView &t, uint32_t l0
     return n;
 }
 
-// Copy the ids of the contained leaves [l0, l1) to out[pos, ...) straight from
-// the leaves' ptr arrays (layouts D1 and D2, where a leaf's ids are 4F
-// contiguous bytes of its node), lane e taking entry e of U leaves per round:
-// the shorter path for runs of a few leaves, whose nodes neighbouring queries
-// also read (so they are likelier to be in L2 than the leaf-id array).
-// Requires G >= F.  Same contract as copy_leaf_run.
-template <uint32_t U>
-__device__ __forceinline__ uint64_t copy_leaves_from_nodes(const TreeView &t, uint32_t l0, uint32_t l1,
-                                                           uint32_t *__restrict__ out, uint64_t pos, uint64_t end,
-                                                           uint32_t e, bool *bad) {
-    const uint32_t F = t.fanout;
-    const uint64_t s0 = leaf_start(t, l0);
-    const uint64_t n = leaf_start(t, l1) - s0;
-    if (pos + n > end) {
-        *bad = true;
-        return n;
-    }
-    for (uint32_t lb = l0; lb < l1; lb += U) {
-        uint32_t v[U];
-        uint64_t o[U];
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-            const uint32_t lf = lb + u;
-            o[u] = ~0ull;
-            v[u] = 0;
-            if (lf < l1 && e < F && !(lf == t.partial_leaf && e >= t.partial_cnt)) {
-                o[u] = pos + (leaf_start(t, lf) - s0) + e;
-                v[u] = reinterpret_cast<const uint32_t *>(t.nodes + (size_t)lf * t.node_bytes)[4 * F + e];
-            }
-        }
-#pragma unroll
-        for (uint32_t u = 0; u < U; ++u)
-            if (o[u] != ~0ull) put_id(out + o[u], v[u]);
-    }
-    return n;
-}
-
 // Kernel-side status words at the start of every workspace.
 struct Ctrl {
     uint32_t work[8];        // work-queue counters (one per pass)

@@ -3,10 +3,11 @@ R-trees (one GPU).
 
 Requests arrive over time (open loop: each has a scheduled arrival time).
 The loop keeps up to `nslots` batches in flight, one per HIP stream.  A free
-slot takes the waiting requests -- range windows packed together into one
-select on the range tree; a join request (a probe set of rectangles,
-answered as an index nested loop: every probe rectangle is a window on the
-join tree) as a batch of its own -- and runs it in two stages:
+slot takes the waiting requests of one kind -- range windows packed
+together into one select on the range tree, or join requests (probe sets of
+rectangles, answered as an index nested loop: every probe rectangle is a
+window on the join tree) packed together into one select on the join tree
+-- and runs it in two stages:
 
 1. the count stage of the device select (every window's exact result size,
    the CSR offsets);
@@ -66,19 +67,20 @@ class Batch:
 class Admission:
     """Forms batches from the waiting queue, in arrival order.
 
-    * a join runs as a batch of its own; windows behind a waiting join are
-      packed with the ones before it;
-    * range windows are packed up to `max_windows` and while the batch's
+    * a batch holds requests of one kind (range windows on the range tree,
+      or join probe sets on the join tree), the kind of the oldest waiting
+      request; requests of the other kind keep their place in the queue;
+    * requests are packed up to `max_windows` windows and while the batch's
       expected size stays within `budget_ids` (a request's known size, else
-      its windows times the running estimate of ids per window); the first
-      request of a batch is always taken, whatever its size."""
+      its windows times the running estimate of ids per window of its kind);
+      the first request of a batch is always taken, whatever its size."""
 
     def __init__(self, max_windows: int, budget_ids: int, one_per_batch: bool = False):
         self.max_windows = max_windows
         self.budget_ids = budget_ids
         self.one_per_batch = one_per_batch   # the unbatched baseline: one request per launch
         self.queue: deque = deque()
-        self.ids_per_window = 0.0            # running estimate, from count stages
+        self.per_window = {"select": 0.0, "join": 0.0}   # running estimates, from count stages
 
     def push(self, p: Pending):
         self.queue.append(p)
@@ -90,43 +92,41 @@ class Admission:
     def __len__(self):
         return len(self.queue)
 
+    @property
+    def ids_per_window(self) -> float:
+        return self.per_window["select"]
+
     def expected(self, p: Pending) -> float:
-        return p.known_ids if p.known_ids >= 0 else self.ids_per_window * p.windows.shape[0]
+        return p.known_ids if p.known_ids >= 0 else self.per_window[p.kind] * p.windows.shape[0]
 
     def next_batch(self):
         if not self.queue:
             return None
-        head = self.queue[0]
-        if head.kind == "join":
-            self.queue.popleft()
-            return Batch("join", [head], head.windows)
+        kind = self.queue[0].kind
         reqs, size, nwin = [], 0.0, 0
-        rest = deque()
-        while self.queue:
-            p = self.queue.popleft()
-            take = (p.kind == "select" and nwin + p.windows.shape[0] <= self.max_windows
-                    and not (reqs and size + self.expected(p) > self.budget_ids)
-                    and not (self.one_per_batch and reqs))
-            if take:
-                reqs.append(p)
-                nwin += p.windows.shape[0]
-                size += self.expected(p)
-            else:
-                rest.append(p)
-                if (nwin >= self.max_windows or (self.one_per_batch and reqs)
-                        or (reqs and p.kind == "select" and size + self.expected(p) > self.budget_ids)):
-                    break
-        rest.extend(self.queue)
-        self.queue = rest
-        if not reqs:
-            return None
-        return Batch("select", reqs, np.concatenate([r.windows for r in reqs]))
+        skipped = []   # requests of the other kind passed over (they keep their place)
+        q = self.queue
+        while q:
+            p = q[0]
+            if p.kind != kind:
+                skipped.append(q.popleft())
+                continue
+            if (nwin + p.windows.shape[0] > self.max_windows or (reqs and size + self.expected(p) > self.budget_ids)
+                    or (self.one_per_batch and reqs)):
+                break
+            reqs.append(q.popleft())
+            nwin += p.windows.shape[0]
+            size += self.expected(p)
+        for p in reversed(skipped):
+            q.appendleft(p)
+        return Batch(kind, reqs, np.concatenate([r.windows for r in reqs]))
 
-    def observe(self, total: int, nwin: int):
-        """A count stage reported `total` ids for `nwin` windows."""
+    def observe(self, total: int, nwin: int, kind: str = "select"):
+        """A count stage reported `total` ids for `nwin` windows of `kind`."""
         if nwin:
             m = total / nwin
-            self.ids_per_window = m if self.ids_per_window == 0.0 else 0.8 * self.ids_per_window + 0.2 * m
+            old = self.per_window[kind]
+            self.per_window[kind] = m if old == 0.0 else 0.8 * old + 0.2 * m
 
     def sizes_known(self, batch: Batch, counts: np.ndarray):
         """Record every request's exact size from per-window counts."""
@@ -281,7 +281,7 @@ class Server:
         m = b.windows.shape[0]
         off = sl.hoff[:m + 1].numpy()
         sl.total = int(off[m])
-        adm.observe(sl.total, m)
+        adm.observe(sl.total, m, b.kind)
         if sl.total > self.pool_ids:
             st.requeued_batches += 1
             adm.requeue(b, np.diff(off), self.pool_ids)
@@ -380,12 +380,18 @@ class Server:
                 sink(r, off, ids)
         while done_count[0] < n:
             now = (time.perf_counter() - t0) / time_scale
-            while nxt < n and reqs[nxt].t_arrival <= now:
+            # admit what has arrived (a bounded number per pass, so that a
+            # burst does not hold back the launches)
+            stop = min(n, nxt + 4096)
+            while nxt < stop and reqs[nxt].t_arrival <= now:
                 r = reqs[nxt]
-                if np.asarray(r.payload).size // 4 > self.max_windows:
+                w = r.payload
+                if not (isinstance(w, np.ndarray) and w.dtype == np.float32 and w.ndim == 2 and w.shape[1] == 4
+                        and w.flags.c_contiguous):
+                    w = np.ascontiguousarray(w, np.float32).reshape(-1, 4)
+                if w.shape[0] > self.max_windows:
                     raise ValueError(f"request {r.rid} has more windows than a batch holds")
-                adm.push(Pending(r.rid, r.kind, np.ascontiguousarray(r.payload, np.float32).reshape(-1, 4),
-                                 r.t_arrival))
+                adm.push(Pending(r.rid, r.kind, w, r.t_arrival))
                 nxt += 1
             progressed = False
             for sl in self.slots:

@@ -4,8 +4,8 @@ configurations the benchmark times:
 * the 2M uniform x 2M clustered spatial join (fanout 32, SoA, nodes sorted by
   low x): every pair against the oracle's join, and every expansion variant
   against the default;
-* the 256-instance batch (sizes log-uniform in [1e3, 1e6], 3.7M windows),
-  trees built with the library's own choice of fanout and layout, replayed
+* the 256-instance batch (sizes log-uniform in [1e3, 1e6], 4.0M windows),
+  trees built with the fanout and layout chosen per size class, replayed
   from its graph: a seeded sample of windows of every tree against the
   oracle, and for all ids strict ascent per window and intersection with the
   window; the plain per-tree launches give the same bytes;
@@ -97,7 +97,11 @@ def test_fullsize_batch_c4():
     o = oracle.get()
     say("case fullsize batch: 256 instances")
     inst = rtgen.c4_batch()
-    trees = [rt.build_str(x.rects, 0, "auto") for x in inst]
+    # the benchmark's configuration: fanout and layout per size class, timed
+    # in batch context
+    from paper_2309_16913_amd.autotune import BatchTuner
+    tuner = BatchTuner(reps=1)
+    trees = tuner.build(inst, tuner.tune(inst))
     b = rt.Batch(trees, [x.queries for x in inst])
     b.run()
     torch.cuda.synchronize()

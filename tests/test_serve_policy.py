@@ -22,17 +22,34 @@ def test_packs_windows_up_to_limit():
     assert len(a) == 6
 
 
-def test_join_runs_alone_and_does_not_block_windows():
+def test_batches_hold_one_kind_in_arrival_order():
     a = Admission(max_windows=8, budget_ids=100)
     a.push(Pending(0, "select", win(), 0.0))
     a.push(Pending(1, "join", win(5), 0.0))
     a.push(Pending(2, "select", win(), 0.0))
+    a.push(Pending(3, "join", win(3), 0.0))
+    a.push(Pending(4, "join", win(2), 0.0))
     b1 = a.next_batch()
     # windows behind a waiting join are packed with the ones before it
     assert b1.kind == "select" and [r.rid for r in b1.reqs] == [0, 2]
     b2 = a.next_batch()
-    assert b2.kind == "join" and [r.rid for r in b2.reqs] == [1] and b2.windows.shape[0] == 5
+    # join probe sets are packed together up to the window limit (5 + 3 <= 8 < 5 + 3 + 2)
+    assert b2.kind == "join" and [r.rid for r in b2.reqs] == [1, 3] and b2.windows.shape[0] == 8
+    b3 = a.next_batch()
+    assert b3.kind == "join" and [r.rid for r in b3.reqs] == [4]
     assert a.next_batch() is None
+
+
+def test_estimates_are_kept_per_kind():
+    a = Admission(max_windows=100, budget_ids=100)
+    a.observe(total=500, nwin=10, kind="select")      # 50 ids per range window
+    a.observe(total=1, nwin=100, kind="join")         # 0.01 pairs per probe window
+    for i in range(3):
+        a.push(Pending(i, "join", win(20), 0.0))
+    assert len(a.next_batch().reqs) == 3              # 60 probe windows, ~0.6 pairs expected
+    for i in range(3):
+        a.push(Pending(10 + i, "select", win(), 0.0))
+    assert len(a.next_batch().reqs) == 2              # 2 x 50 <= 100 < 3 x 50
 
 
 def test_budget_with_known_and_estimated_sizes():
