@@ -101,6 +101,8 @@ def kernel_phase(name: str):
     m = re.search(r"select_kernel<\d+, \d+, (\d), \d>", name)
     if m:
         return {"0": "count", "1": "fill"}.get(m.group(1))
+    if "bulk_copy_kernel" in name:   # the fill pass's deferred contained runs
+        return "fill"
     if "segsort" in name or "seg_classify" in name:
         return "sort"
     m = re.search(r"batch_kernel<(\d)>", name)
@@ -176,6 +178,7 @@ def pmc_summary(args):
     wk, wids = calib(write)
     fetch_scale = calib_bytes / fk      # FETCH_SIZE of a copy reads 1/scale of its bytes
     write_scale = calib_bytes / wk
+    # phase -> kernel name -> [(dispatch id, bytes)] per counter, and durations
     phases = {}
     for d, scale, skip, key in ((fetch, fetch_scale, fids, "fetch"), (write, write_scale, wids, "write")):
         for did, (name, v, s, e) in sorted(d.items()):
@@ -184,10 +187,18 @@ def pmc_summary(args):
             ph = kernel_phase(name)
             if ph is None:
                 continue
-            p = phases.setdefault(ph, {"fetch": [], "write": [], "ms": []})
-            p[key].append(v * 1024.0 * scale)
+            k = phases.setdefault(ph, {}).setdefault(name, {"fetch": [], "write": [], "ms": []})
+            k[key].append((did, v * 1024.0 * scale))
             if key == "fetch" and e > s:
-                p["ms"].append((e - s) / 1e6)
+                k["ms"].append((did, (e - s) / 1e6))
+    # --last N: only the last N steps, which start at the N-th last launch of
+    # the step's first phase
+    thr = {"fetch": 0, "write": 0}
+    if args.last:
+        first = "batch_count" if "batch_count" in phases else "count"
+        for key in thr:
+            ids = sorted(did for k in phases.get(first, {}).values() for did, _ in k[key])
+            thr[key] = ids[-args.last] if len(ids) >= args.last else 0
     lines = [f"# {args.title}",
              "# Two counter runs of the same command (FETCH_SIZE, then WRITE_SIZE):",
              f"#   cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch> -o run "
@@ -199,23 +210,32 @@ def pmc_summary(args):
              "# FETCH_SIZE / WRITE_SIZE: KiB per dispatch between L2 and the fabric (Infinity Cache hits",
              "# included, so an upper bound on DRAM bytes), scaled by the first three copies of",
              f"# {args.calib_copy_mib} MiB: fetch_scale {fetch_scale:.4f}, write_scale {write_scale:.4f}.",
-             "# Per phase: average over its launches of the bytes of one launch (a phase may be several",
-             "# kernels: the sort sums its kernels per step), and the average kernel duration under the",
-             "# counter run."]
-    nsteps = max(1, args.steps_in_run)
-    for ph, p in sorted(phases.items()):
-        if not p["fetch"] or not p["write"]:
+             "# Per phase: the bytes of one step of the phase (average over launches of each of its",
+             "# kernels, summed over the kernels; the sort sums its kernels per step), and its kernel",
+             "# time per step under the counter run."]
+    nsteps = args.last or max(1, args.steps_in_run)
+    for ph, kernels in sorted(phases.items()):
+        fb = wb = ms = 0.0
+        launches = 0
+        for name, k in kernels.items():
+            kf = [v for did, v in k["fetch"] if did >= thr["fetch"]]
+            kw = [v for did, v in k["write"] if did >= thr["write"]]
+            km = [v for did, v in k["ms"] if did >= thr["fetch"]]
+            if not kf or not kw:
+                continue
+            # the sort launches a varying number of kernels per step: its
+            # sums go per step; any other kernel runs once per step of its phase
+            pf, pw = (nsteps, nsteps) if ph == "sort" else (len(kf), len(kw))
+            fb += sum(kf) / pf
+            wb += sum(kw) / pw
+            ms += sum(km) / (nsteps if ph == "sort" else max(1, len(km))) if km else float("nan")
+            launches += len(kf)
+        if not launches:
             continue
-        if args.last and ph != "sort":   # only the last launches (the timed ones)
-            p = {k: v[-args.last:] for k, v in p.items()}
-        per = nsteps if ph == "sort" else max(1, len(p["fetch"]))
-        fb = sum(p["fetch"]) / per
-        wb = sum(p["write"]) / per
-        ms = (sum(p["ms"]) / per) if p["ms"] else float("nan")
         src = PHASE_SOURCES.get(ph if ph != "batch_count" else "batch")
         lines += [f"{ph}_fetch_bytes_per_launch: {fb:.0f}", f"{ph}_write_bytes_per_launch: {wb:.0f}",
                   f"{ph}_bytes_per_launch: {fb + wb:.0f}", f"{ph}_ms_per_launch: {ms:.4f}",
-                  f"{ph}_launches: {len(p['fetch'])}"]
+                  f"{ph}_launches: {launches}"]
         if src:
             lines.append(f"{ph}_source_hash: {source_hash(*src)}")
     lines += [f"fetch_scale: {fetch_scale:.4f}", f"write_scale: {write_scale:.4f}"]
@@ -260,6 +280,27 @@ def pmc_table(args):
             continue
         vals = [a["c"].get(k, 0.0) / a["t"] if a["t"] > 0 else 0.0 for k in names]
         lines.append(f"| `{name[:80]}` | {a['n']} | {a['t']:.2f} | " + " | ".join(f"{v:.4g}" for v in vals) + " |")
+    out = os.path.join(ROOT, "profiles", f"{args.tag}.md")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(out)
+
+
+def stats_table(args):
+    """profiles/<tag>.md from a rocprofv3 --kernel-trace --stats run of this
+    script (its *kernel_stats.csv): calls, average and total time per kernel."""
+    files = sorted(glob.glob(os.path.join(args.fetch_dir, "**", "*kernel_stats.csv"), recursive=True))
+    if not files:
+        raise SystemExit(f"no *kernel_stats.csv under {args.fetch_dir}")
+    rows = list(csv.DictReader(open(files[0], newline="")))
+    lines = [f"# {args.title}",
+             f"# Command: cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+             f"-d <out> -o run -- python3 /root/repo/bench.py {args.bench_args}",
+             f"# Summary: python3 bench.py --stats-table --fetch-dir <out> --tag {args.tag}", "",
+             "| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for r in rows[:args.top]:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
     out = os.path.join(ROOT, "profiles", f"{args.tag}.md")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -784,6 +825,8 @@ def main():
     # counter summaries (host only)
     ap.add_argument("--pmc-summary", action="store_true")
     ap.add_argument("--pmc-table", action="store_true")
+    ap.add_argument("--stats-table", action="store_true")
+    ap.add_argument("--top", type=int, default=40)
     ap.add_argument("--kernel-regex", default="")
     ap.add_argument("--fetch-dir")
     ap.add_argument("--write-dir")
@@ -800,6 +843,9 @@ def main():
         return
     if args.pmc_table:
         pmc_table(args)
+        return
+    if args.stats_table:
+        stats_table(args)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "

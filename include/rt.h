@@ -298,7 +298,9 @@ int rt_range_select_async(const rt_tree *t, const float *d_queries, uint64_t nq,
  * stage, enqueued later with the same tree, queries, d_offsets and d_work
  * (whose first rt_select_workspace_bytes(nq, 0) bytes must be unchanged),
  * writes the ids and d_status as rt_range_select_device does.  A count stage
- * may be followed by no fill stage.  Both only enqueue on `stream`.
+ * may be followed by no fill stage, and each fill stage needs a count stage
+ * of its own (it consumes the work counters the count stage resets).  Both
+ * only enqueue on `stream`.
  * work_bytes: at least rt_select_workspace_bytes(nq, 0) for the count stage
  * and rt_select_workspace_bytes(nq, ids_capacity) for the fill stage. */
 int rt_range_select_device_count(const rt_tree *t, const float *d_queries, uint64_t nq, uint64_t *d_offsets,
@@ -364,6 +366,17 @@ int rt_tree_set_split(rt_tree *t, uint32_t kmin);
  * loads each node when it is popped.  Other values -> RT_EINVAL.  Not to be
  * called while selects on the tree run. */
 int rt_tree_set_lookahead(rt_tree *t, uint32_t on);
+
+/* Where the fill pass of later selects on this tree copies contained runs
+ * (section 3, the whole-subtree copy of a node fully inside the window; never
+ * changes a result).  RT_BULK_AUTO (default): runs of at least 2048 ids are
+ * appended as descriptors and copied by a streaming kernel after the pass on
+ * trees of at least 2^25 objects, whose leaf-id array does not stay cached;
+ * smaller trees copy every run in the pass.  RT_BULK_ON / RT_BULK_OFF force
+ * the one or the other.  Other values -> RT_EINVAL.  Not to be called while
+ * selects on the tree run. */
+enum { RT_BULK_AUTO = 0, RT_BULK_ON = 1, RT_BULK_OFF = 2 };
+int rt_tree_set_bulk_copy(rt_tree *t, uint32_t mode);
 
 /* Copy the tree to host arrays in a neutral node/entry form: per node
  * (root = node 0) level (0 = leaf), entry count and index of its first entry;

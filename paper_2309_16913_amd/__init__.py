@@ -93,6 +93,7 @@ _sig = {
     "rt_tree_stats": ([_vp, C.POINTER(TreeInfo)], C.c_int),
     "rt_tree_set_split": ([_vp, _u32], C.c_int),
     "rt_tree_set_lookahead": ([_vp, _u32], C.c_int),
+    "rt_tree_set_bulk_copy": ([_vp, _u32], C.c_int),
     "rt_tree_export": ([_vp] + [_vp] * 8, C.c_int),
     "rt_select_visit_stats": ([_vp, _fp, _u64, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)], C.c_int),
     "rt_last_error": ([], C.c_char_p),
@@ -157,6 +158,12 @@ class Tree:
         """Load the next node ahead after a leaf in later selects (never
         changes results)."""
         _check(_L.rt_tree_set_lookahead(self.h, 1 if on else 0))
+
+    def set_bulk_copy(self, mode: str):
+        """Where the fill pass copies long contained runs (never changes
+        results): "auto" (a streaming kernel after the pass on trees of at
+        least 2^25 objects), "on" (always) or "off" (in the pass)."""
+        _check(_L.rt_tree_set_bulk_copy(self.h, {"auto": 0, "on": 1, "off": 2}[mode]))
 
     def free(self):
         if self.h is not None and self.h.value:

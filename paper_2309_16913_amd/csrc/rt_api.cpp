@@ -144,6 +144,9 @@ static uint64_t split_budget(uint64_t nq) { return split_hcap(nq) * kXcds; }
 //   Ctrl | counts[nq] | scan tmp | sort lists | query order | slots per query
 //   | slot offsets per query | slot counts | slot offsets | split items
 //   | slot scan tmp | sort scratch (cap ids, then class-L descriptors)
+//   | bulk-copy descriptors (bulk_capacity(cap))
+// Everything before the sort scratch depends on nq only, so a workspace for
+// (nq, 0) is a prefix of one for (nq, cap).
 struct SelWs {
     Ctrl *ctrl;
     uint32_t *counts;
@@ -165,7 +168,13 @@ static uint64_t sel_ws_bytes(uint64_t nq, uint64_t cap) {
     return align256(sizeof(Ctrl)) + align256(4 * nq) + align256(8 * scan_tmp_elems(nq)) +
            align256(4 * segsort_ws_elems(nq)) + align256(order_ws_bytes(nq)) + align256(4 * nq) +
            align256(8 * (nq + 1)) + align256(4 * S) + align256(8 * (S + 1)) + align256(16 * split_budget(nq)) +
-           align256(8 * scan_tmp_elems(S)) + align256(4 * segsort_scratch_elems(cap));
+           align256(8 * scan_tmp_elems(S)) + align256(4 * segsort_scratch_elems(cap)) +
+           align256(16 * bulk_capacity(cap));
+}
+
+// The bulk-copy descriptors of a workspace for (nq, cap).
+static uint4 *sel_bulk(uint32_t *scratch, uint64_t cap) {
+    return reinterpret_cast<uint4 *>(reinterpret_cast<uint8_t *>(scratch) + align256(4 * segsort_scratch_elems(cap)));
 }
 
 static SelWs sel_ws(void *w, uint64_t nq) {
@@ -233,6 +242,13 @@ extern "C" int rt_tree_set_lookahead(rt_tree *t, uint32_t on) {
     if (!t) return fail(RT_EINVAL, "tree is NULL");
     if (on > 1) return fail(RT_EINVAL, "lookahead %u is not 0 or 1", on);
     t->lookahead = on;
+    return RT_OK;
+}
+
+extern "C" int rt_tree_set_bulk_copy(rt_tree *t, uint32_t mode) {
+    if (!t) return fail(RT_EINVAL, "tree is NULL");
+    if (mode > RT_BULK_OFF) return fail(RT_EINVAL, "bulk-copy mode %u is not 0, 1 or 2", mode);
+    t->bulk_copy = mode;
     return RT_OK;
 }
 
@@ -400,7 +416,16 @@ int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, u
         if (nq >= kOrderMinQueries) plan.order = query_order_result(w.order, nq);
         const uint64_t *fo = sc.on ? w.slot_off : d_off;
         const uint32_t no = sc.on ? (uint32_t)w.nslot_max : (uint32_t)nq;
+        // on large trees long contained runs go to the bulk copy after the pass
+        if (t->bulk_copy == RT_BULK_ON || (t->bulk_copy == RT_BULK_AUTO && t->n_objects >= kBulkMinObjects)) {
+            const uint64_t bcap = bulk_capacity(cap);
+            plan.bulk = sel_bulk(w.scratch, cap);
+            plan.bulk_cap = (uint32_t)(bcap < 0xFFFFFFFFull ? bcap : 0xFFFFFFFFull);
+        }
         e = launch_select_pass(v, dq, (uint32_t)nq, SEL_FILL, nullptr, fo, d_ids, cap, w.ctrl, 1, plan, no, s);
+        if (e == hipSuccess && plan.bulk)
+            e = launch_bulk_copy(static_cast<const uint32_t *>(t->d_leaf_ids), plan.bulk, plan.bulk_cap, d_ids, w.ctrl,
+                                 s);
         if (e == hipSuccess) e = mark(3);
         if (e == hipSuccess)
             e = launch_segsort(d_off, nq, d_ids, w.scratch, cap, w.lists, t->n_objects, nullptr, s);

@@ -16,6 +16,7 @@ struct rt_tree {
     uint32_t level_start[33] = {0};   // first node index of each level (0 = leaves)
     uint32_t sorted_lx = 0;           // 1: every node's entries ascend in low x
     uint32_t lookahead = 0;           // 1: select loads the next node ahead after a leaf
+    uint32_t bulk_copy = 0;           // RT_BULK_AUTO / ON / OFF: deferral of long contained runs
     uint32_t split_kmin = 0;          // mapping: split queries reaching >= this many
                                       // parents-of-leaves (0 = one group per query)
     void *d_nodes = nullptr;   // n_nodes * node_bytes

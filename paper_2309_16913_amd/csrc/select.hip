@@ -172,6 +172,9 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
 // them without waiting for a fresh load.  After an internal node the next
 // node is one of its children, decided only by the comparison, so nothing is
 // loaded ahead there.
+// BULK = 1 (fill pass only): contained runs of at least kBulkMin ids are
+// appended to the plan's descriptor list for the bulk copy instead of being
+// copied in the pass.
 constexpr uint32_t kCountChunk = 2;
 // Contained runs of at most this many leaves are copied from the leaves' own
 // ptr arrays (layouts D1, D2: a leaf's ids are 4F contiguous bytes of its
@@ -182,7 +185,7 @@ constexpr uint32_t kCountChunk = 2;
 // nodes 5.29 vs 4.85 ms).
 constexpr uint32_t kNodeCopyLeaves = 4;
 
-template <int G, int LAYOUT, int MODE, int LA>
+template <int G, int LAYOUT, int MODE, int LA, int BULK>
 __global__ void __launch_bounds__(256)
 select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *__restrict__ counts,
               const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint64_t cap,
@@ -396,6 +399,13 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                             const uint32_t len = ~sh ? (uint32_t)__builtin_ctzll(~sh) : 64u - j0;
                             todo = (j0 + len >= 64) ? 0ull : (todo & (~0ull << (j0 + len)));
                             const uint32_t l0 = t.range[first + j0].x, l1 = t.range[first + j0 + len - 1].y;
+                            if constexpr (BULK != 0) {
+                                if (subtree_objects(t, make_uint2(l0, l1)) >= kBulkMin) {
+                                    pos += defer_leaf_run(t, l0, l1, ids, pos, end, e, G, gbase, plan.bulk,
+                                                          plan.bulk_cap, ctrl, &bad);
+                                    continue;
+                                }
+                            }
                             if (LAYOUT != LAYOUT_AOS && (G == 64 || l1 - l0 <= kNodeCopyLeaves)) {
                                 // lane e copies entry e of U leaves at a time
                                 const bool hasp = t.partial_leaf >= l0 && t.partial_leaf < l1;
@@ -426,7 +436,7 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                                 }
                                 pos += subtree_objects(t, make_uint2(l0, l1));
                             } else
-                                pos += copy_leaf_run<4>(t, l0, l1, ids, pos, end, e, G, &bad);
+                                pos += copy_leaf_run<BULK != 0 ? 2 : 4>(t, l0, l1, ids, pos, end, e, G, &bad);
                         }
                         if (bad && e == 0) atomicOr(&ctrl->err, kErrBounds);
                     } else {
@@ -575,6 +585,55 @@ split_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t sp
     }
 }
 
+// Bulk copy of deferred contained runs: one block per descriptor at a time;
+// stores start at a 64-byte boundary of the destination (the first ids up
+// to it are written by the first lanes), so every store instruction writes
+// whole granules.
+__global__ void __launch_bounds__(256)
+bulk_copy_kernel(const uint32_t *__restrict__ leaf_ids, const uint4 *__restrict__ bulk, uint32_t bulk_cap,
+                 uint32_t *__restrict__ ids, Ctrl *__restrict__ ctrl) {
+    __shared__ uint32_t item;
+    const uint32_t nitems = min(ctrl->bulk_n, bulk_cap);
+    const uint32_t t = threadIdx.x;
+    while (true) {
+        if (t == 0) item = atomicAdd(&ctrl->bulk_taken, 1u);
+        __syncthreads();
+        const uint32_t it = item;
+        __syncthreads();
+        if (it >= nitems) break;
+        const uint4 d = bulk[it];
+        const uint32_t *__restrict__ src = leaf_ids + d.x;
+        uint32_t *__restrict__ dst = ids + (((uint64_t)d.z << 32) | d.y);
+        const uint32_t len = d.w;
+        const uint32_t head = min((16u - (uint32_t)((reinterpret_cast<uintptr_t>(dst) >> 2) & 15u)) & 15u, len);
+        constexpr uint32_t U = 8;
+        const uint32_t hv = t < head ? src[t] : 0u;   // loaded with the first round
+        uint32_t k = head;
+        do {
+            uint32_t v[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t i = k + u * 256 + t;
+                v[u] = i < len ? src[i] : 0u;
+            }
+            if (k == head && t < head) put_id(dst + t, hv);
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t i = k + u * 256 + t;
+                if (i < len) put_id(dst + i, v[u]);
+            }
+            k += 256 * U;
+        } while (k < len);
+    }
+}
+
+hipError_t launch_bulk_copy(const uint32_t *leaf_ids, const uint4 *bulk, uint32_t bulk_cap, uint32_t *ids, Ctrl *ctrl,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(bulk_copy_kernel, dim3((uint32_t)num_cus() * 8), dim3(256), 0, s, leaf_ids, bulk, bulk_cap,
+                       ids, ctrl);
+    return hipGetLastError();
+}
+
 int num_cus() {
     static int cus = 0;
     if (!cus) {
@@ -599,11 +658,21 @@ static hipError_t launch_g(const TreeView &t, const float4 *q, uint32_t nq, uint
     uint32_t blocks = (uint32_t)(want < persistent ? want : persistent);
     if (plan.heavy) blocks = (uint32_t)persistent;   // split items add work beyond nq
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // every XCD gets blocks
-    if (MODE != SEL_STATS && t.lookahead)
-        hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 1>), dim3(blocks), dim3(256), smem, s, t, q, nq,
+    // the fill pass with deferred contained runs is an instance of its own:
+    // the deferral branch costs the in-pass copies registers and time
+    const bool la = MODE != SEL_STATS && t.lookahead;
+    if (MODE == SEL_FILL && plan.bulk) {
+        if (la)
+            hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 1, MODE == SEL_FILL>), dim3(blocks), dim3(256), smem, s,
+                               t, q, nq, counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
+        else
+            hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 0, MODE == SEL_FILL>), dim3(blocks), dim3(256), smem, s,
+                               t, q, nq, counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
+    } else if (la)
+        hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 1, 0>), dim3(blocks), dim3(256), smem, s, t, q, nq,
                            counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
     else
-        hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 0>), dim3(blocks), dim3(256), smem, s, t, q, nq,
+        hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 0, 0>), dim3(blocks), dim3(256), smem, s, t, q, nq,
                            counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
     return hipGetLastError();
 }

@@ -135,6 +135,49 @@ def test_lookahead_parity(rt, ora):
         rt._check(rt._L.rt_tree_set_lookahead(t.h, 2))
 
 
+def test_bulk_copy_parity(rt, ora):
+    """Long contained runs (>= 2048 ids) deferred to the streaming copy after
+    the fill pass, forced on a small tree, and kept in the pass: results
+    equal the oracle's with windows of up to 0.3 of the space (contained runs
+    of up to ~10^5 ids), for every layout, the split mapping and lookahead,
+    through the host and the device entry points."""
+    import torch
+    r = rtgen.c2_rects(400_000)
+    q = rtgen.windows_loguniform(1500, 1e-5, 0.3, 91)
+    want = ora.select(ora.build_str(r, 32), q)
+    say(f"case bulk copy: {want[1].size} ids")
+    for fanout, layout, kmin, la, mode in [(16, "soa", 0, False, "on"), (32, "aos", 0, True, "on"),
+                                           (64, "d2", 16, False, "on"), (64, "soa", 0, False, "on"),
+                                           (64, "soa", 0, False, "off"), (32, "soa", 2, True, "auto")]:
+        say(f"case bulk copy F={fanout} {layout} kmin={kmin} lookahead={la} mode={mode}")
+        t = rt.build_str(r, fanout, layout)
+        t.set_split(kmin)
+        t.set_lookahead(la)
+        t.set_bulk_copy(mode)
+        assert_csr_equal(rt.range_select(t, q), want, f"bulk copy F={fanout} {layout} kmin={kmin} {mode}")
+        # device entry point, resident queries, twice on one workspace
+        nq, cap = q.shape[0], int(want[1].size)
+        dq = torch.from_numpy(q).cuda()
+        off = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+        ids = torch.empty(cap, dtype=torch.int32, device="cuda")
+        wb = rt.select_workspace_bytes(nq, cap)
+        w = torch.empty(wb, dtype=torch.uint8, device="cuda")
+        st = torch.zeros(2, dtype=torch.int64, device="cuda")
+        s = torch.cuda.current_stream().cuda_stream
+        for _ in range(2):
+            ids.fill_(-1)
+            rt.range_select_device(t, dq.data_ptr(), nq, off.data_ptr(), ids.data_ptr(), cap, w.data_ptr(), wb,
+                                   st.data_ptr(), s)
+            torch.cuda.synchronize()
+            assert st.cpu().tolist() == [cap, 0]
+            assert np.array_equal(off.cpu().numpy(), want[0].astype(np.int64))
+            assert np.array_equal(ids.cpu().numpy().view(np.uint32), want[1])
+        t.free()
+    t = rt.build_str(r[:1000], 16, "soa")
+    with pytest.raises(rt.RTError):
+        rt._check(rt._L.rt_tree_set_bulk_copy(t.h, 3))
+
+
 def test_select_all_windows(rt):
     """64 windows covering all 2M rectangles: 2M-id segments, whose
     sub-buckets hold 8192 ids each, sorted by the wide (1024 x 32) group

@@ -1,6 +1,8 @@
 """Full-size range select in the launch configuration the benchmark times:
 10M rectangles (half uniform, half clustered), 1M windows with selectivity
-log-uniform in [1e-6, 1e-3], fanout 32 SoA, device-pointer entry point.
+log-uniform in [1e-6, 1e-3], device-pointer entry point, for fanout 32 SoA,
+fanout 64 SoA and AoS (the configurations the benchmark's tuner picks among)
+and fanout 16 in the third layout.
 
 The oracle computes a random sample of queries one by one (exact equality);
 for every query the output is checked for properties that hold at any size:
@@ -23,15 +25,22 @@ def say(*a):
     sys.stdout.flush()
 
 
-def test_fullsize_select_bench_config():
+@pytest.fixture(scope="module")
+def c2_data():
+    say("case fullsize: generating 10M rectangles, 1M windows")
+    return rtgen.c2_rects(), rtgen.c2_queries()
+
+
+@pytest.mark.parametrize("fanout,layout,nsample", [(32, "soa", 2000), (64, "soa", 1000), (64, "aos", 1000),
+                                                   (16, "d2", 500)])
+def test_fullsize_select_bench_config(c2_data, fanout, layout, nsample):
     import torch
     assert torch.cuda.is_available()
     import paper_2309_16913_amd as rt
-    say("case fullsize: generating 10M rectangles, 1M windows")
-    rects = rtgen.c2_rects()
-    queries = rtgen.c2_queries()
+    rects, queries = c2_data
     nq = queries.shape[0]
-    tree = rt.build_str(rects, 32, "soa")
+    say(f"case fullsize: F{fanout} {layout}")
+    tree = rt.build_str(rects, fanout, layout)
     dq = torch.from_numpy(queries).cuda()
     counts = torch.empty(nq, dtype=torch.int32, device="cuda")
     s = torch.cuda.current_stream()
@@ -79,9 +88,9 @@ def test_fullsize_select_bench_config():
     # exact equality with the oracle on a sample of queries
     say("case fullsize: oracle sample")
     o = oracle.get()
-    ot = o.build_str(rects, 32)
-    g = np.random.Generator(np.random.PCG64(77))
-    sample = np.sort(g.choice(nq, size=2000, replace=False))
+    ot = o.build_str(rects, fanout)
+    g = np.random.Generator(np.random.PCG64(77 + fanout))
+    sample = np.sort(g.choice(nq, size=nsample, replace=False))
     woff, wids = o.select(ot, queries[sample])
     hoff = off.cpu().numpy()
     for k, qi in enumerate(sample):
@@ -89,3 +98,4 @@ def test_fullsize_select_bench_config():
         got = ids[a0:a1].cpu().numpy().view(np.uint32)
         want = wids[int(woff[k]):int(woff[k + 1])]
         assert np.array_equal(got, want), f"query {qi}: {got.size} vs {want.size} ids"
+    tree.free()
