@@ -98,7 +98,7 @@ def source_hash(*names):
 
 def kernel_phase(name: str):
     """Which phase of a select step a kernel belongs to (None: not timed)."""
-    m = re.search(r"select_kernel<\d+, \d+, (\d), \d>", name)
+    m = re.search(r"select_kernel<\d+, \d+, (\d), \d(?:, \d)?>", name)
     if m:
         return {"0": "count", "1": "fill"}.get(m.group(1))
     if "bulk_copy_kernel" in name:   # the fill pass's deferred contained runs
@@ -351,7 +351,8 @@ def select_leg(rt, torch, ev, args, rects, queries, kmin=0):
     cap = int(counts.to(torch.int64).sum().item())
     del work0, counts
     ids = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
-    wb = rt.select_workspace_bytes(nq, cap)
+    # room for the count pass's records: the fill replays them
+    wb = (rt.select_replay_workspace_bytes if args.replay else rt.select_workspace_bytes)(nq, cap)
     work = torch.empty(wb, dtype=torch.uint8, device="cuda")
     status = torch.zeros(2, dtype=torch.int64, device="cuda")
     events = [ev.create(5) for _ in range(args.steps)]
@@ -370,6 +371,9 @@ def select_leg(rt, torch, ev, args, rects, queries, kmin=0):
     wall = time.perf_counter() - t0
     st = status.cpu().numpy()
     assert st[1] == 0 and st[0] == cap, f"select status {st} (cap {cap})"
+    rec_chunks, rec_over = rt.select_replay_info(work.data_ptr())
+    replay = {"workspace_bytes": wb, "record_chunks": rec_chunks, "overflowed": rec_over,
+              "replayed": bool(args.replay and rec_chunks and not rec_over)}
     lookahead = None
     if args.lookahead:
         # the lookahead variant (loads one node ahead after each leaf), timed
@@ -400,8 +404,17 @@ def select_leg(rt, torch, ev, args, rects, queries, kmin=0):
     comp = {"count": 16 * nq + tree_bytes + 4 * nq,
             "fill": 16 * nq + tree_bytes + 8 * (nq + 1) + 4 * cap,
             "sort": 8 * cap + 8 * (nq + 1)}
+    if replay["replayed"]:
+        # the count pass also writes its records (16 B each, at most 256 per
+        # chunk taken); the fill reads them and each hit id once, and writes
+        # the ids, without visiting nodes
+        rb = 16 * 256 * rec_chunks
+        visit["count"] += rb
+        comp["count"] += rb
+        visit["fill"] = rb + 8 * (nq + 1) + 8 * cap
+        comp["fill"] = rb + 8 * (nq + 1) + 4 * cap + min(tree_bytes, 4 * cap)
     return dict(tree=tree, info=info, build_s=build_s, cap=cap, wall=wall, avg=avg, vn=vn, ve=ve, vc=vc,
-                visit=visit, comp=comp, off=off, ids=ids, lookahead=lookahead)
+                visit=visit, comp=comp, off=off, ids=ids, lookahead=lookahead, replay=replay)
 
 
 def cpu_info():
@@ -753,7 +766,7 @@ def serve_device_leg(rt, torch, ev, args, tb):
     cap = int(off[nq].item())
     del w0
     ids = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
-    wb = rt.select_workspace_bytes(nq, cap)
+    wb = (rt.select_replay_workspace_bytes if args.replay else rt.select_workspace_bytes)(nq, cap)
     work = torch.empty(wb, dtype=torch.uint8, device="cuda")
     st = torch.zeros(2, dtype=torch.int64, device="cuda")
     evs = [ev.create(5) for _ in range(args.serve_device_reps)]
@@ -764,6 +777,7 @@ def serve_device_leg(rt, torch, ev, args, tb):
                                      wb, st.data_ptr(), s.cuda_stream, e)
     torch.cuda.synchronize()
     assert st.cpu().tolist() == [cap, 0]
+    rec_chunks, rec_over = rt.select_replay_info(work.data_ptr())
     ph = {k: float(np.mean([ev.ms(e[a], e[b]) for e in evs]))
           for k, (a, b) in {"count": (0, 1), "scan": (1, 2), "fill": (2, 3), "sort": (3, 4)}.items()}
     step = float(np.mean([ev.ms(e[0], e[4]) for e in evs]))
@@ -771,9 +785,15 @@ def serve_device_leg(rt, torch, ev, args, tb):
     info = tb.info()
     visit_fill = 16 * nq + 20 * ve + 8 * vn + 4 * cap + 4 * vc + 8 * (nq + 1)
     comp_fill = 16 * nq + int(info.device_bytes) + 8 * (nq + 1) + 4 * cap
+    if args.replay and rec_chunks and not rec_over:   # the fill replays the count pass's records
+        rb = 16 * 256 * rec_chunks
+        visit_fill = rb + 8 * (nq + 1) + 8 * cap
+        comp_fill = rb + 8 * (nq + 1) + 4 * cap + min(int(info.device_bytes), 4 * cap)
     tr = read_traffic(f"select_serve50m_w{nq}")
     out = {"workload": f"select_clustered{info.n_objects}_f{info.fanout}_soa_windows{nq}_device",
            "windows": nq, "ids": cap, "ms_per_select": step, "phases_ms": ph,
+           "replay": {"record_chunks": rec_chunks, "overflowed": rec_over,
+                      "replayed": bool(args.replay and rec_chunks and not rec_over)},
            "queries_per_s": nq / (step / 1e3), "ids_per_s": cap / (step / 1e3),
            "visited": {"nodes": vn, "entries": ve, "ids_from_contained_subtrees": vc},
            "roofline_fill": roofline_entry("select_kernel (fill pass)", ph["fill"], comp_fill, visit_fill,
@@ -803,6 +823,8 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="time --fanout/--layout directly instead of the autotuner's choice")
     ap.add_argument("--no-lookahead", dest="lookahead", action="store_false")
+    ap.add_argument("--no-replay", dest="replay", action="store_false",
+                    help="workspace without room for the count pass's records (the fill walks the tree again)")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--join-n", type=int, default=2_000_000)
     ap.add_argument("--join-reps", type=int, default=5)
@@ -884,7 +906,7 @@ def main():
             from paper_2309_16913_amd.autotune import Autotuner
             log("[bench] autotuning fanout x layout x mapping on the full workload")
             tuner = Autotuner(cache_path=None, fanouts=(16, 32, 64), layouts=("aos", "soa", "d2"), kmins=(0, 16),
-                              sample=args.nq, reps=2)
+                              sample=args.nq, reps=2, replay=args.replay)
             tune = tuner.tune(rects, queries, "mixed")
             args.fanout, args.layout, kmin = tune["fanout"], tune["layout"], tune["kmin"]
         log(f"[bench] select leg (fanout {args.fanout}, {args.layout}, split kmin {kmin})")
@@ -905,6 +927,7 @@ def main():
                              for ph in ("count", "fill", "sort")},
             traffic_profile=tr.get("file"),
             lookahead_ms=s["lookahead"],
+            replay=s["replay"],
             tree={"height": s["info"].height, "nodes": s["info"].n_nodes, "device_bytes": s["info"].device_bytes,
                   "build_s": s["build_s"]},
             visited={"nodes": s["vn"], "entries": s["ve"], "ids_from_contained_subtrees": s["vc"]})

@@ -221,6 +221,29 @@ void rt_free(void *obj);
  * output capacity of ids_capacity ids. */
 uint64_t rt_select_workspace_bytes(uint64_t nq, uint64_t ids_capacity);
 
+/* Workspace bytes with which rt_range_select_device (and _timed) also keeps
+ * the count pass's output in compact records (per leaf with hits: its hit
+ * mask; per contained subtree: its leaf range) and the fill writes the ids
+ * by replaying them instead of walking the tree a second time (section 3's
+ * two traversals, the second replaced by a streaming pass; results are
+ * identical).  Any size from rt_select_workspace_bytes up is accepted: the
+ * bytes past it hold the records, and when they do not suffice (or the tree
+ * has 2^30 nodes or more, or replay is off for the tree) the fill walks the
+ * tree.  The two-stage calls never replay. */
+uint64_t rt_select_replay_workspace_bytes(uint64_t nq, uint64_t ids_capacity);
+
+/* Whether one-call selects on this tree may replay the count pass's records
+ * (see rt_select_replay_workspace_bytes; on = 1, the default) or always walk
+ * the tree twice (on = 0).  Never changes a result.  Other values ->
+ * RT_EINVAL.  Not to be called while selects on the tree run. */
+int rt_tree_set_replay(rt_tree *t, uint32_t on);
+
+/* After a one-call select on the workspace d_work has finished (the caller
+ * synchronizes its stream): *chunks = record chunks of 256 records its count
+ * pass took (0 if it did not record), *overflowed = 1 if the records did not
+ * fit and the fill walked the tree.  Blocking copy of 64 bytes. */
+int rt_select_replay_info(const void *d_work, uint32_t *chunks, uint32_t *overflowed);
+
 /*
  * Enqueue a complete range select on `stream` and return without waiting.
  *   d_queries   device, nq*4 floats (not validated: the caller guarantees

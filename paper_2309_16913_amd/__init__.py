@@ -75,6 +75,7 @@ _sig = {
     "rt_join_visit_stats": ([_vp, _vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)], C.c_int),
     "rt_free": ([_vp], None),
     "rt_select_workspace_bytes": ([_u64, _u64], _u64),
+    "rt_select_replay_workspace_bytes": ([_u64, _u64], _u64),
     "rt_range_select_device": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _u64, _vp, _vp], C.c_int),
     "rt_range_select_device_timed": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp], C.c_int),
     "rt_range_count_device": ([_vp, _vp, _u64, _vp, _vp, _u64, _vp], C.c_int),
@@ -94,6 +95,8 @@ _sig = {
     "rt_tree_set_split": ([_vp, _u32], C.c_int),
     "rt_tree_set_lookahead": ([_vp, _u32], C.c_int),
     "rt_tree_set_bulk_copy": ([_vp, _u32], C.c_int),
+    "rt_tree_set_replay": ([_vp, _u32], C.c_int),
+    "rt_select_replay_info": ([_vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)], C.c_int),
     "rt_tree_export": ([_vp] + [_vp] * 8, C.c_int),
     "rt_select_visit_stats": ([_vp, _fp, _u64, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64)], C.c_int),
     "rt_last_error": ([], C.c_char_p),
@@ -164,6 +167,12 @@ class Tree:
         results): "auto" (a streaming kernel after the pass on trees of at
         least 2^25 objects), "on" (always) or "off" (in the pass)."""
         _check(_L.rt_tree_set_bulk_copy(self.h, {"auto": 0, "on": 1, "off": 2}[mode]))
+
+    def set_replay(self, on: bool):
+        """Let one-call selects replay the count pass's records in the fill
+        (given a workspace of select_replay_workspace_bytes) instead of
+        walking the tree again (never changes results)."""
+        _check(_L.rt_tree_set_replay(self.h, 1 if on else 0))
 
     def free(self):
         if self.h is not None and self.h.value:
@@ -267,6 +276,20 @@ def visit_stats(tree: Tree, queries):
 
 def select_workspace_bytes(nq: int, ids_capacity: int) -> int:
     return int(_L.rt_select_workspace_bytes(int(nq), int(ids_capacity)))
+
+
+def select_replay_info(d_work: int):
+    """(record chunks taken, overflowed) of the last one-call select on the
+    workspace d_work (after its stream has been synchronized)."""
+    c, o = C.c_uint32(0), C.c_uint32(0)
+    _check(_L.rt_select_replay_info(_vp(d_work), C.byref(c), C.byref(o)))
+    return int(c.value), bool(o.value)
+
+
+def select_replay_workspace_bytes(nq: int, ids_capacity: int) -> int:
+    """Workspace with room for the count pass's records (the fill replays
+    them instead of walking the tree again)."""
+    return int(_L.rt_select_replay_workspace_bytes(int(nq), int(ids_capacity)))
 
 
 def range_select_device(tree: Tree, d_queries: int, nq: int, d_offsets: int, d_ids: int, ids_capacity: int,

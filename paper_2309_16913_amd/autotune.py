@@ -40,20 +40,21 @@ def selectivity_decade(rects: np.ndarray, queries: np.ndarray) -> int:
 
 class Autotuner:
     def __init__(self, cache_path: str | None = DEFAULT_CACHE, fanouts=(16, 32, 64), layouts=("aos", "soa"),
-                 kmins=(0, 16), sample: int = 16384, reps: int = 3):
+                 kmins=(0, 16), sample: int = 16384, reps: int = 3, replay: bool = True):
         import paper_2309_16913_amd as rt
         import torch
         self.rt, self.torch = rt, torch
         self.cache_path = cache_path
         self.fanouts, self.layouts, self.kmins = tuple(fanouts), tuple(layouts), tuple(kmins)
-        self.sample, self.reps = sample, reps
+        self.sample, self.reps, self.replay = sample, reps, replay
         self.cache = {}
         if cache_path and os.path.exists(cache_path):
             with open(cache_path) as f:
                 self.cache = json.load(f)
 
     def key(self, n: int, tag: str, rects, queries) -> str:
-        cand = f"F{'-'.join(map(str, self.fanouts))}_L{'-'.join(self.layouts)}_K{'-'.join(map(str, self.kmins))}"
+        cand = (f"F{'-'.join(map(str, self.fanouts))}_L{'-'.join(self.layouts)}_K{'-'.join(map(str, self.kmins))}"
+                + ("_R" if self.replay else ""))
         return f"n2^{int(math.log2(max(n, 1)))}_{tag}_sel1e{selectivity_decade(rects, queries)}_{cand}"
 
     def _time_select(self, tree, dq, nq):
@@ -69,7 +70,9 @@ class Autotuner:
         cap = int(counts[:nq].to(torch.int64).sum().item())
         off = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
         ids = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
-        wb = rt.select_workspace_bytes(nq, cap)
+        # with room for the count pass's records, as a one-call select would
+        # normally be given
+        wb = rt.select_replay_workspace_bytes(nq, cap) if self.replay else rt.select_workspace_bytes(nq, cap)
         w = torch.empty(wb, dtype=torch.uint8, device="cuda")
         st = torch.zeros(2, dtype=torch.int64, device="cuda")
         times = []

@@ -172,6 +172,32 @@ static uint64_t sel_ws_bytes(uint64_t nq, uint64_t cap) {
            align256(16 * bulk_capacity(cap));
 }
 
+// Record arena past the select's own layout: chunks of kRecChunk 16-byte
+// records, then one count per chunk.  Sized for cap / 16 + 16 nq records
+// (leaf visits with hits and contained subtrees: about cap / 64 at 10M
+// rectangles / 1M windows, fanout 64), a third more for chunks closed early
+// (a node's records never straddle two chunks), and one chunk per lane group
+// that can hold a partly used one at the end of the pass; a count pass that
+// needs more sets the overflow flag and the fill walks the tree instead.
+static uint64_t rec_arena_bytes(uint64_t nq, uint64_t cap) {
+    const uint64_t recs = (cap / 16 + 16 * nq) * 4 / 3;
+    const uint64_t groups = (uint64_t)num_cus() * 8 * 16;
+    const uint64_t chunks = (recs + kRecChunk - 1) / kRecChunk + (nq < groups ? nq : groups);
+    return align256(16 * kRecChunk * chunks) + align256(4 * chunks) + 512;
+}
+
+// Chunks of an arena of `bytes` bytes.
+static uint32_t rec_chunks_in(uint64_t bytes) {
+    const uint64_t per = 16 * kRecChunk + 4;
+    const uint64_t c = bytes > 512 ? (bytes - 512) / per : 0;
+    return (uint32_t)(c < 0xFFFFFFF0ull ? c : 0xFFFFFFF0ull);
+}
+
+uint64_t rtk::select_ws_bytes(uint64_t nq, uint64_t cap) { return sel_ws_bytes(nq, cap); }
+uint64_t rtk::select_replay_ws_bytes(uint64_t nq, uint64_t cap) {
+    return sel_ws_bytes(nq, cap) + rec_arena_bytes(nq, cap);
+}
+
 // The bulk-copy descriptors of a workspace for (nq, cap).
 static uint4 *sel_bulk(uint32_t *scratch, uint64_t cap) {
     return reinterpret_cast<uint4 *>(reinterpret_cast<uint8_t *>(scratch) + align256(4 * segsort_scratch_elems(cap)));
@@ -252,6 +278,23 @@ extern "C" int rt_tree_set_bulk_copy(rt_tree *t, uint32_t mode) {
     return RT_OK;
 }
 
+extern "C" int rt_select_replay_info(const void *d_work, uint32_t *chunks, uint32_t *overflowed) {
+    if (!d_work || !chunks || !overflowed) return fail(RT_EINVAL, "NULL argument");
+    Ctrl hc;
+    const hipError_t e = hipMemcpy(&hc, d_work, sizeof(Ctrl), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "reading the select's control words");
+    *chunks = hc.rec_chunks;
+    *overflowed = hc.rec_overflow;
+    return RT_OK;
+}
+
+extern "C" int rt_tree_set_replay(rt_tree *t, uint32_t on) {
+    if (!t) return fail(RT_EINVAL, "tree is NULL");
+    if (on > 1) return fail(RT_EINVAL, "replay %u is not 0 or 1", on);
+    t->replay = on;
+    return RT_OK;
+}
+
 extern "C" int rt_tree_set_split(rt_tree *t, uint32_t kmin) {
     if (!t) return fail(RT_EINVAL, "tree is NULL");
     t->split_kmin = kmin;
@@ -322,6 +365,9 @@ extern "C" int rt_tree_export(const rt_tree *t, uint32_t *level, uint32_t *count
 // range select
 // ---------------------------------------------------------------------------
 extern "C" uint64_t rt_select_workspace_bytes(uint64_t nq, uint64_t cap) { return sel_ws_bytes(nq, cap); }
+extern "C" uint64_t rt_select_replay_workspace_bytes(uint64_t nq, uint64_t cap) {
+    return select_replay_ws_bytes(nq, cap);
+}
 
 static int check_nq(uint64_t nq) {
     if (nq > 0xFFF00000ull) return fail(RT_EINVAL, "nq = %llu too large", (unsigned long long)nq);
@@ -354,7 +400,7 @@ static SplitCfg split_cfg(const rt_tree *t, uint64_t nq) {
 
 int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
                               uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, int stage,
-                              uint32_t *d_counts_out, void *const *events) {
+                              uint32_t *d_counts_out, void *const *events, uint64_t rec_bytes) {
     SelWs w = sel_ws(work, nq);
     if (nq == 0) {   // no launch of an empty grid: offsets = {0}, status = {0, 0}
         hipError_t e = hipSuccess;
@@ -376,6 +422,16 @@ int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, u
         plan.slot_first = w.slot_first;
         plan.heavy = w.heavy;
         plan.hcap = sc.budget;
+    }
+    // records of the count pass, replayed by the fill stage of the same call
+    // (node and leaf indices must leave the two flag bits free)
+    const uint32_t rec_nchunks = rec_chunks_in(rec_bytes);
+    const bool rec = stage == 3 && !d_counts_out && t->replay && rec_nchunks > 0 && t->n_nodes < (1u << 30);
+    if (rec) {
+        uint8_t *base = static_cast<uint8_t *>(work) + sel_ws_bytes(nq, cap);
+        plan.rec = reinterpret_cast<uint4 *>(base);
+        plan.rec_count = reinterpret_cast<uint32_t *>(base + align256(16ull * kRecChunk * rec_nchunks));
+        plan.rec_nchunks = rec_nchunks;
     }
     if (stage & 1) {   // count stage: ctrl, order, split, count pass, offsets
         uint32_t *counts = d_counts_out ? d_counts_out : (sc.on ? w.slot_counts : w.counts);
@@ -422,7 +478,12 @@ int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, u
             plan.bulk = sel_bulk(w.scratch, cap);
             plan.bulk_cap = (uint32_t)(bcap < 0xFFFFFFFFull ? bcap : 0xFFFFFFFFull);
         }
-        e = launch_select_pass(v, dq, (uint32_t)nq, SEL_FILL, nullptr, fo, d_ids, cap, w.ctrl, 1, plan, no, s);
+        if (rec) {   // replay the records; the walk runs only if they overflowed
+            e = launch_replay(v, plan, fo, no, d_ids, cap, w.ctrl, s);
+            plan.fill_guard = 1;
+        }
+        if (e == hipSuccess)
+            e = launch_select_pass(v, dq, (uint32_t)nq, SEL_FILL, nullptr, fo, d_ids, cap, w.ctrl, 1, plan, no, s);
         if (e == hipSuccess && plan.bulk)
             e = launch_bulk_copy(static_cast<const uint32_t *>(t->d_leaf_ids), plan.bulk, plan.bulk_cap, d_ids, w.ctrl,
                                  s);
@@ -438,9 +499,9 @@ int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, u
 
 int rtk::enqueue_select(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
                         uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, bool count_only,
-                        uint32_t *d_counts_out, void *const *events) {
+                        uint32_t *d_counts_out, void *const *events, uint64_t rec_bytes) {
     return enqueue_select_stage(t, dq, nq, d_off, d_ids, cap, work, d_status, s, count_only ? 1 : 3,
-                                count_only ? d_counts_out : nullptr, events);
+                                count_only ? d_counts_out : nullptr, events, count_only ? 0 : rec_bytes);
 }
 
 extern "C" int rt_range_select_device_timed(const rt_tree *t, const float *d_queries, uint64_t nq,
@@ -454,7 +515,8 @@ extern "C" int rt_range_select_device_timed(const rt_tree *t, const float *d_que
     if ((reinterpret_cast<uintptr_t>(d_queries) & 15) != 0) return fail(RT_EINVAL, "queries not 16-byte aligned");
     DevSet ds(t->device);
     return enqueue_select(t, reinterpret_cast<const float4 *>(d_queries), nq, d_offsets, d_ids, cap, d_work,
-                          d_status, static_cast<hipStream_t>(stream), false, nullptr, events);
+                          d_status, static_cast<hipStream_t>(stream), false, nullptr, events,
+                          work_bytes - sel_ws_bytes(nq, cap));
 }
 
 extern "C" int rt_range_select_device(const rt_tree *t, const float *d_queries, uint64_t nq, uint64_t *d_offsets,

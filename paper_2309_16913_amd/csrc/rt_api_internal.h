@@ -17,6 +17,7 @@ struct rt_tree {
     uint32_t sorted_lx = 0;           // 1: every node's entries ascend in low x
     uint32_t lookahead = 0;           // 1: select loads the next node ahead after a leaf
     uint32_t bulk_copy = 0;           // RT_BULK_AUTO / ON / OFF: deferral of long contained runs
+    uint32_t replay = 1;              // 1: one-call selects replay the count pass's records
     uint32_t split_kmin = 0;          // mapping: split queries reaching >= this many
                                       // parents-of-leaves (0 = one group per query)
     void *d_nodes = nullptr;   // n_nodes * node_bytes
@@ -57,12 +58,18 @@ int build_tuned(const float4 *d_rects, uint64_t n, uint32_t fanout, uint32_t lay
 int make_ids(uint64_t nq, uint64_t total, rt_ids **out);
 // stage bit 1: count stage (order, split, count pass, offsets); bit 2: fill
 // stage (fill pass, sort, status).  d_counts_out: count-only mode.
+// rec_bytes: workspace bytes past the select's own layout for (nq, cap) that
+// may hold the count pass's records (both stages in one call only; 0: none).
 int enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
                          uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, int stage,
-                         uint32_t *d_counts_out, void *const *events);
+                         uint32_t *d_counts_out, void *const *events, uint64_t rec_bytes = 0);
 int enqueue_select(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_off, uint32_t *d_ids,
                    uint64_t cap, void *work, uint64_t *d_status, hipStream_t s, bool count_only,
-                   uint32_t *d_counts_out, void *const *events = nullptr);
+                   uint32_t *d_counts_out, void *const *events = nullptr, uint64_t rec_bytes = 0);
+// Workspace bytes of a select for (nq, cap) without and with room for the
+// records of the count pass.
+uint64_t select_ws_bytes(uint64_t nq, uint64_t cap);
+uint64_t select_replay_ws_bytes(uint64_t nq, uint64_t cap);
 
 // Owning device buffer.
 struct DevBuf {

@@ -59,6 +59,18 @@ __device__ __forceinline__ uint64_t leaf_start(const TreeView &t, uint32_t l) {
 // it leaves L2 and the Infinity Cache to the tree nodes.
 __device__ __forceinline__ void put_id(uint32_t *p, uint32_t v) { __builtin_nontemporal_store(v, p); }
 
+// Records of the count pass are written once and read once by the fill
+// stage: both bypass the caches, which keep the tree nodes.
+typedef uint32_t rec_vec __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void put_rec(uint4 *p, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    rec_vec v = {a, b, c, d};
+    __builtin_nontemporal_store(v, reinterpret_cast<rec_vec *>(p));
+}
+__device__ __forceinline__ uint4 get_rec(const uint4 *p) {
+    const rec_vec v = __builtin_nontemporal_load(reinterpret_cast<const rec_vec *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Copy the ids of a run of contained leaves [l0, l1) -- one contiguous run
 // of TreeView::leaf_ids -- to out[pos, pos + n) with the G lanes of a group
 // (e = lane in the group).  Loads and stores are both aligned to G-id
@@ -113,7 +125,9 @@ struct Ctrl {
     uint32_t err;            // internal error flags
     uint32_t bulk_n;         // long contained runs deferred to the bulk copy (descriptors appended)
     uint32_t bulk_taken;     // descriptors taken by the bulk copy
-    uint32_t pad[5];
+    uint32_t rec_chunks;     // record chunks taken by the count pass
+    uint32_t rec_overflow;   // 1: the record arena filled up (the fill walks the tree)
+    uint32_t pad[3];
     uint64_t stats[4];       // visit statistics
     // per-pass, per-XCD query counters, one 128-byte cache line each
     uint32_t xwork[3][kXcds][32];
@@ -204,7 +218,25 @@ struct SelectPlan {
     // follows the pass (NULL: every run is copied in place)
     uint4 *bulk = nullptr;
     uint32_t bulk_cap = 0;
+    // count pass: every leaf with hits and every contained subtree is also
+    // recorded in chunks of kRecChunk records {output slot, position in the
+    // slot, leaf node (| kRecHi: entries 32..63) or kRecRun | first leaf,
+    // hit mask or end leaf}; rec_count[c] = records in chunk c.  The fill
+    // stage replays them instead of walking the tree (NULL: no records).
+    uint4 *rec = nullptr;
+    uint32_t *rec_count = nullptr;
+    uint32_t rec_nchunks = 0;
+    // fill pass: run only if the count pass's record arena overflowed
+    uint32_t fill_guard = 0;
 };
+
+constexpr uint32_t kRecChunk = 256;          // records per chunk a lane group takes
+// records a lane group collects in LDS before storing them (128 measured no
+// faster for groups of 64 lanes)
+constexpr uint32_t kRecBuf = 64;
+constexpr uint32_t kRecRun = 0x80000000u;    // record of a contained leaf range
+constexpr uint32_t kRecHi = 0x40000000u;     // leaf record of entries 32..63
+constexpr uint32_t kRecDead = 0xFFFFFFFEu;   // the group's chunk state after an overflow
 
 
 
@@ -237,6 +269,12 @@ constexpr uint32_t kOrderMinQueries = 8192;   // smaller batches keep input orde
 // Bulk copy of the long contained runs a fill pass deferred (descriptors in
 // bulk[0 .. min(ctrl->bulk_n, bulk_cap))) into ids: persistent grid, one block
 // per descriptor at a time.  Enqueue right after that fill pass.
+// Replay of the count pass's records (plan.rec): writes every recorded hit
+// and contained leaf range at offsets[slot] + position; does nothing if the
+// arena overflowed or the result does not fit.
+hipError_t launch_replay(const TreeView &t, const SelectPlan &plan, const uint64_t *offsets, uint32_t noffsets,
+                         uint32_t *ids, uint64_t ids_capacity, Ctrl *ctrl, hipStream_t s);
+
 hipError_t launch_bulk_copy(const uint32_t *leaf_ids, const uint4 *bulk, uint32_t bulk_cap, uint32_t *ids,
                             Ctrl *ctrl, hipStream_t s);
 

@@ -172,9 +172,11 @@ __device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
 // them without waiting for a fresh load.  After an internal node the next
 // node is one of its children, decided only by the comparison, so nothing is
 // loaded ahead there.
-// BULK = 1 (fill pass only): contained runs of at least kBulkMin ids are
-// appended to the plan's descriptor list for the bulk copy instead of being
-// copied in the pass.
+// EXT = 1, fill pass: contained runs of at least kBulkMin ids are appended
+// to the plan's descriptor list for the bulk copy instead of being copied in
+// the pass.  EXT = 1, count pass: every leaf with hits and every contained
+// subtree is also written to the plan's record arena, which the fill stage
+// replays instead of walking the tree again.
 constexpr uint32_t kCountChunk = 2;
 // Contained runs of at most this many leaves are copied from the leaves' own
 // ptr arrays (layouts D1, D2: a leaf's ids are 4F contiguous bytes of its
@@ -185,7 +187,7 @@ constexpr uint32_t kCountChunk = 2;
 // nodes 5.29 vs 4.85 ms).
 constexpr uint32_t kNodeCopyLeaves = 4;
 
-template <int G, int LAYOUT, int MODE, int LA, int BULK>
+template <int G, int LAYOUT, int MODE, int LA, int EXT>
 __global__ void __launch_bounds__(256)
 select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *__restrict__ counts,
               const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint64_t cap,
@@ -193,6 +195,7 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
     extern __shared__ uint32_t smem[];
     if constexpr (MODE == SEL_FILL) {
         if (offsets[noffsets] > cap) return;   // result does not fit: leave ids untouched
+        if (plan.fill_guard && ctrl->rec_overflow == 0) return;   // the replay wrote everything
     }
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t e = lane & (G - 1);
@@ -221,6 +224,39 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
     // lookahead registers: the node loaded ahead and this lane's entry of it
     uint32_t pf_node = kNoNode, pf_ref = 0;
     float pf_lx = 0.f, pf_ly = 0.f, pf_hx = 0.f, pf_hy = 0.f;
+    // recording count pass: records collect in the group's LDS buffer (after
+    // the stacks) and go out kRecBuf at a time to the group's current chunk
+    // of the arena (rchunk, rcnt records used).  Stores and loads share one
+    // completion counter, so a store issued before a node load delays the
+    // wait for that load: batching the stores keeps such waits rare.
+    uint32_t rchunk = kNoNode, rcnt = 0, nbuf = 0;
+    uint4 *rbuf = reinterpret_cast<uint4 *>(smem + ((256 / G) * stack_cap + 3u) / 4u * 4u) + (threadIdx.x / G) * kRecBuf;
+    auto rec_flush = [&]() {   // group-uniform
+        if (nbuf == 0) return;
+        __builtin_amdgcn_wave_barrier();
+        if (rchunk != kRecDead && (rchunk == kNoNode || rcnt + nbuf > kRecChunk)) {
+            if (rchunk != kNoNode && e == 0) plan.rec_count[rchunk] = rcnt;
+            uint32_t c = 0;
+            if (e == 0) c = atomicAdd(&ctrl->rec_chunks, 1u);
+            c = (uint32_t)__shfl((int)c, (int)gbase);
+            if (c < plan.rec_nchunks) {
+                rchunk = c;
+                rcnt = 0;
+            } else {
+                if (e == 0) atomicOr(&ctrl->rec_overflow, 1u);
+                rchunk = kRecDead;
+            }
+        }
+        if (rchunk < kRecDead) {
+            for (uint32_t i = e; i < nbuf; i += G) {
+                const uint4 v = rbuf[i];
+                put_rec(plan.rec + (size_t)rchunk * kRecChunk + rcnt + i, v.x, v.y, v.z, v.w);
+            }
+            rcnt += nbuf;
+        }
+        nbuf = 0;
+        __builtin_amdgcn_wave_barrier();
+    };
 
     while (true) {
         if (!done && sp == 0) {
@@ -381,6 +417,18 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                             atomicOr(&ctrl->err, kErrBounds);
                     }
                 }
+                if constexpr (MODE == SEL_COUNT && EXT != 0) {
+                    if (n) {   // one record per 32 entries with hits
+                        const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+                        const uint32_t k = (lo ? 1u : 0u) + (hi ? 1u : 0u);
+                        if (nbuf + k > kRecBuf) rec_flush();
+                        if (e == 0 && lo) rbuf[nbuf] = make_uint4(oslot, (uint32_t)pos, node, lo);
+                        if (G == 64 && e == 32 && hi)
+                            rbuf[nbuf + (lo ? 1u : 0u)] =
+                                make_uint4(oslot, (uint32_t)pos + (uint32_t)__popc(lo), node | kRecHi, hi);
+                        nbuf += k;
+                    }
+                }
                 pos += n;
             } else {
                 // children of a node are contiguous: entry e points at first + e
@@ -399,7 +447,7 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                             const uint32_t len = ~sh ? (uint32_t)__builtin_ctzll(~sh) : 64u - j0;
                             todo = (j0 + len >= 64) ? 0ull : (todo & (~0ull << (j0 + len)));
                             const uint32_t l0 = t.range[first + j0].x, l1 = t.range[first + j0 + len - 1].y;
-                            if constexpr (BULK != 0) {
+                            if constexpr (EXT != 0) {
                                 if (subtree_objects(t, make_uint2(l0, l1)) >= kBulkMin) {
                                     pos += defer_leaf_run(t, l0, l1, ids, pos, end, e, G, gbase, plan.bulk,
                                                           plan.bulk_cap, ctrl, &bad);
@@ -436,9 +484,27 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
                                 }
                                 pos += subtree_objects(t, make_uint2(l0, l1));
                             } else
-                                pos += copy_leaf_run<BULK != 0 ? 2 : 4>(t, l0, l1, ids, pos, end, e, G, &bad);
+                                pos += copy_leaf_run<EXT != 0 ? 2 : 4>(t, l0, l1, ids, pos, end, e, G, &bad);
                         }
                         if (bad && e == 0) atomicOr(&ctrl->err, kErrBounds);
+                    } else if constexpr (MODE == SEL_COUNT && EXT != 0) {
+                        // one record per contained child: its leaf range, at
+                        // the position after the contained children before it
+                        const uint2 rg = cont ? t.range[first + e] : make_uint2(0u, 0u);
+                        const uint32_t sc = cont ? subtree_objects(t, rg) : 0u;
+                        uint32_t inc = sc;
+                        for (uint32_t d = 1; d < G; d <<= 1) {
+                            const uint32_t x = (uint32_t)__shfl_up((int)inc, d, G);
+                            if (e >= d) inc += x;
+                        }
+                        const uint32_t tot = (uint32_t)__shfl((int)inc, (int)(gbase + G - 1));
+                        const uint32_t k = (uint32_t)__popcll(cm);
+                        if (nbuf + k > kRecBuf) rec_flush();
+                        if (cont)
+                            rbuf[nbuf + (uint32_t)__popcll(cm & below)] =
+                                make_uint4(oslot, (uint32_t)pos + inc - sc, kRecRun | rg.x, rg.y);
+                        nbuf += k;
+                        pos += tot;
                     } else {
                         uint32_t sc = cont ? subtree_objects(t, t.range[first + e]) : 0u;
                         for (uint32_t d = 1; d < G; d <<= 1) sc += (uint32_t)__shfl_xor((int)sc, (int)d);
@@ -457,6 +523,10 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
             }
         }
         __builtin_amdgcn_wave_barrier();
+    }
+    if constexpr (MODE == SEL_COUNT && EXT != 0) {
+        rec_flush();
+        if (e == 0 && rchunk < kRecDead) plan.rec_count[rchunk] = rcnt;
     }
     if constexpr (MODE == SEL_STATS) {
         if (e == 0 && (vnodes | ventries)) {
@@ -627,6 +697,114 @@ bulk_copy_kernel(const uint32_t *__restrict__ leaf_ids, const uint4 *__restrict_
     }
 }
 
+// Replay of the recording count pass: persistent blocks take record chunks;
+// a chunk's records are staged in LDS with their absolute output positions
+// (one offsets lookup per record, all loaded at once), then every half-wave
+// takes records 8 apart, RU at a time: a leaf record writes the ids of its
+// hit entries (lane l: entry l of the record's 32, at its rank in the hit
+// mask), a range record copies the leaves' ids from the leaf-id array
+// (measured faster than from the leaves' own ptr arrays: fill 2.81 against
+// 4.13 ms at 10M rectangles / 1M windows, fanout 64 SoA).
+template <int LAYOUT>
+__global__ void __launch_bounds__(256)
+replay_kernel(TreeView t, const uint4 *__restrict__ rec, const uint32_t *__restrict__ rec_count, uint32_t nchunks,
+              const uint64_t *__restrict__ offsets, uint32_t noffsets, uint32_t *__restrict__ ids, uint64_t cap,
+              Ctrl *__restrict__ ctrl) {
+    __shared__ uint64_t sbase[kRecChunk], send[kRecChunk];
+    __shared__ uint2 sref[kRecChunk];
+    if (ctrl->rec_overflow || offsets[noffsets] > cap) return;
+    const uint32_t nch = min(ctrl->rec_chunks, nchunks);
+    const uint32_t th = threadIdx.x, hw = th >> 5, l = th & 31u;
+    const uint32_t F = t.fanout;
+    // records in flight per half-wave (4: fill 2.89 ms, 8: 2.81 at 10M rectangles / 1M windows, fanout 64
+    // SoA; on the 50M-rectangle tree 5.70 against 4.05 ms); half-waves per block
+    constexpr uint32_t U = 8, HW = 8;
+    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const uint32_t cnt = min(rec_count[c], kRecChunk);
+        __syncthreads();   // the previous chunk's records are consumed
+        if (th < cnt) {
+            const uint4 d = get_rec(rec + (size_t)c * kRecChunk + th);
+            sbase[th] = offsets[d.x] + d.y;
+            send[th] = offsets[d.x + 1];
+            sref[th] = make_uint2(d.z, d.w);
+        }
+        __syncthreads();
+        for (uint32_t r0 = hw; r0 < cnt; r0 += HW * U) {
+            uint32_t v[U];
+            uint64_t o[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t r = r0 + u * HW;
+                o[u] = ~0ull;
+                v[u] = 0;
+                if (r < cnt) {
+                    const uint2 d = sref[r];
+                    if (!(d.x & kRecRun) && ((d.y >> l) & 1u)) {
+                        const uint32_t node = d.x & ~kRecHi;
+                        const uint32_t ent = ((d.x & kRecHi) ? 32u : 0u) + l;
+                        v[u] = load_ptr<LAYOUT>(t.nodes + (size_t)node * t.node_bytes, F, ent);
+                        o[u] = sbase[r] + (uint32_t)__popc(d.y & ((1u << l) - 1u));
+                        if (o[u] >= send[r]) {
+                            atomicOr(&ctrl->err, kErrBounds);
+                            o[u] = ~0ull;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (o[u] != ~0ull) put_id(ids + o[u], v[u]);
+#pragma unroll 1
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t r = r0 + u * HW;
+                if (r >= cnt) break;
+                const uint2 d = sref[r];
+                if (!(d.x & kRecRun)) continue;
+                const uint32_t l0 = d.x & ~kRecRun, l1 = d.y;
+                const uint64_t s0 = leaf_start(t, l0);
+                const uint64_t n = leaf_start(t, l1) - s0;
+                const uint64_t b = sbase[r];
+                if (b + n > send[r]) {
+                    if (l == 0) atomicOr(&ctrl->err, kErrBounds);
+                    continue;
+                }
+                {
+                    const uint32_t *__restrict__ src = t.leaf_ids + s0;
+                    constexpr uint32_t RU = 8;   // 16: more registers, fill 4.2 ms
+                    for (uint64_t i0 = l; i0 < n; i0 += 32 * RU) {
+                        uint32_t w[RU];
+#pragma unroll
+                        for (uint32_t k = 0; k < RU; ++k) {
+                            const uint64_t i = i0 + 32 * k;
+                            w[k] = i < n ? src[i] : 0u;
+                        }
+#pragma unroll
+                        for (uint32_t k = 0; k < RU; ++k) {
+                            const uint64_t i = i0 + 32 * k;
+                            if (i < n) put_id(ids + b + i, w[k]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_replay(const TreeView &t, const SelectPlan &plan, const uint64_t *offsets, uint32_t noffsets,
+                         uint32_t *ids, uint64_t cap, Ctrl *ctrl, hipStream_t s) {
+    const dim3 grid((uint32_t)num_cus() * 8), block(256);
+    if (t.layout == LAYOUT_AOS)
+        hipLaunchKernelGGL(replay_kernel<LAYOUT_AOS>, grid, block, 0, s, t, plan.rec, plan.rec_count,
+                           plan.rec_nchunks, offsets, noffsets, ids, cap, ctrl);
+    else if (t.layout == LAYOUT_SOA)
+        hipLaunchKernelGGL(replay_kernel<LAYOUT_SOA>, grid, block, 0, s, t, plan.rec, plan.rec_count,
+                           plan.rec_nchunks, offsets, noffsets, ids, cap, ctrl);
+    else
+        hipLaunchKernelGGL(replay_kernel<LAYOUT_D2>, grid, block, 0, s, t, plan.rec, plan.rec_count,
+                           plan.rec_nchunks, offsets, noffsets, ids, cap, ctrl);
+    return hipGetLastError();
+}
+
 hipError_t launch_bulk_copy(const uint32_t *leaf_ids, const uint4 *bulk, uint32_t bulk_cap, uint32_t *ids, Ctrl *ctrl,
                             hipStream_t s) {
     hipLaunchKernelGGL(bulk_copy_kernel, dim3((uint32_t)num_cus() * 8), dim3(256), 0, s, leaf_ids, bulk, bulk_cap,
@@ -652,7 +830,9 @@ static hipError_t launch_g(const TreeView &t, const float4 *q, uint32_t nq, uint
                            uint32_t slot, const SelectPlan &plan, uint32_t noffsets, hipStream_t s) {
     const uint32_t stack_cap = stack_bound(t.height, t.fanout);
     const uint32_t groups_per_block = 256 / G;
-    const size_t smem = (size_t)groups_per_block * stack_cap * sizeof(uint32_t);
+    size_t smem = (size_t)groups_per_block * stack_cap * sizeof(uint32_t);
+    if (MODE == SEL_COUNT && plan.rec)   // the groups' record buffers follow the stacks, 16-byte aligned
+        smem = (smem + 15) / 16 * 16 + (size_t)groups_per_block * kRecBuf * 16;
     uint64_t want = ((uint64_t)nq + groups_per_block - 1) / groups_per_block;
     uint64_t persistent = (uint64_t)num_cus() * 8;
     uint32_t blocks = (uint32_t)(want < persistent ? want : persistent);
@@ -660,13 +840,15 @@ static hipError_t launch_g(const TreeView &t, const float4 *q, uint32_t nq, uint
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // every XCD gets blocks
     // the fill pass with deferred contained runs is an instance of its own:
     // the deferral branch costs the in-pass copies registers and time
+    // (and the recording count pass likewise)
     const bool la = MODE != SEL_STATS && t.lookahead;
-    if (MODE == SEL_FILL && plan.bulk) {
+    constexpr int EXT = MODE == SEL_STATS ? 0 : 1;
+    if ((MODE == SEL_FILL && plan.bulk) || (MODE == SEL_COUNT && plan.rec)) {
         if (la)
-            hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 1, MODE == SEL_FILL>), dim3(blocks), dim3(256), smem, s,
+            hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 1, EXT>), dim3(blocks), dim3(256), smem, s,
                                t, q, nq, counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
         else
-            hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 0, MODE == SEL_FILL>), dim3(blocks), dim3(256), smem, s,
+            hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 0, EXT>), dim3(blocks), dim3(256), smem, s,
                                t, q, nq, counts, offsets, ids, cap, ctrl, slot, stack_cap, plan, noffsets);
     } else if (la)
         hipLaunchKernelGGL((select_kernel<G, LAYOUT, MODE, 1, 0>), dim3(blocks), dim3(256), smem, s, t, q, nq,

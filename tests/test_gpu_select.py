@@ -178,6 +178,71 @@ def test_bulk_copy_parity(rt, ora):
         rt._check(rt._L.rt_tree_set_bulk_copy(t.h, 3))
 
 
+def _device_select(rt, t, q, cap, wb):
+    """One-call device select on a fresh workspace of wb bytes; returns
+    (offsets, ids, replay info), run twice on the same buffers."""
+    import torch
+    nq = q.shape[0]
+    dq = torch.from_numpy(q).cuda()
+    off = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    ids = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    w = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(2, dtype=torch.int64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    out = []
+    for _ in range(2):
+        ids.fill_(-1)
+        rt.range_select_device(t, dq.data_ptr(), nq, off.data_ptr(), ids.data_ptr(), cap, w.data_ptr(), wb,
+                               st.data_ptr(), s)
+        torch.cuda.synchronize()
+        assert st.cpu().tolist() == [cap, 0]
+        out.append((off.cpu().numpy().copy(), ids[:cap].cpu().numpy().view(np.uint32).copy(),
+                    rt.select_replay_info(w.data_ptr())))
+    return out
+
+
+def test_replay_parity(rt, ora):
+    """The fill replaying the count pass's records (leaf hit masks, contained
+    leaf ranges) instead of walking the tree: results equal the oracle's for
+    every layout, fanouts 7 to 64 (64: two records per leaf), the split
+    mapping, lookahead and long deferred runs; an arena too small for the
+    records falls back to the walk; replay switched off records nothing."""
+    r = rtgen.c2_rects(300_000)
+    q = np.concatenate([rtgen.c2_queries(20_000), rtgen.windows_loguniform(500, 1e-5, 0.1, 93)])
+    want = ora.select(ora.build_str(r, 32), q)
+    cap = int(want[1].size)
+    wo = want[0].astype(np.int64)
+    say(f"case replay: {q.shape[0]} windows, {cap} ids")
+    nq = q.shape[0]
+    full = rt.select_replay_workspace_bytes(nq, cap)
+    base = rt.select_workspace_bytes(nq, cap)
+    assert full > base
+    for fanout, layout, kmin, la, bulk in [(16, "soa", 0, False, "auto"), (32, "aos", 0, True, "auto"),
+                                           (64, "d2", 16, False, "auto"), (64, "soa", 0, False, "on"),
+                                           (7, "aos", 0, False, "auto"), (64, "aos", 2, True, "auto"),
+                                           (33, "soa", 0, False, "on")]:
+        say(f"case replay F={fanout} {layout} kmin={kmin} lookahead={la} bulk={bulk}")
+        t = rt.build_str(r, fanout, layout)
+        t.set_split(kmin)
+        t.set_lookahead(la)
+        t.set_bulk_copy(bulk)
+        for go, gi, (chunks, over) in _device_select(rt, t, q, cap, full):
+            assert chunks > 0 and not over, f"F={fanout} {layout}: replay did not run ({chunks}, {over})"
+            assert np.array_equal(go, wo) and np.array_equal(gi, want[1]), f"replay F={fanout} {layout} kmin={kmin}"
+        # an arena of a few chunks overflows: the fill walks the tree
+        for go, gi, (chunks, over) in _device_select(rt, t, q, cap, base + 64 * 4096):
+            assert over, f"F={fanout} {layout}: a 64-chunk arena did not overflow"
+            assert np.array_equal(go, wo) and np.array_equal(gi, want[1]), f"fallback F={fanout} {layout}"
+        t.set_replay(False)
+        for go, gi, (chunks, over) in _device_select(rt, t, q, cap, full):
+            assert chunks == 0 and not over
+            assert np.array_equal(go, wo) and np.array_equal(gi, want[1]), f"replay off F={fanout} {layout}"
+        t.free()
+    t = rt.build_str(r[:1000], 16, "soa")
+    with pytest.raises(rt.RTError):
+        rt._check(rt._L.rt_tree_set_replay(t.h, 2))
+
+
 def test_select_all_windows(rt):
     """64 windows covering all 2M rectangles: 2M-id segments, whose
     sub-buckets hold 8192 ids each, sorted by the wide (1024 x 32) group

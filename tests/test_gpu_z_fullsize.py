@@ -1,8 +1,9 @@
 """Full-size range select in the launch configuration the benchmark times:
 10M rectangles (half uniform, half clustered), 1M windows with selectivity
-log-uniform in [1e-6, 1e-3], device-pointer entry point, for fanout 32 SoA,
-fanout 64 SoA and AoS (the configurations the benchmark's tuner picks among)
-and fanout 16 in the third layout.
+log-uniform in [1e-6, 1e-3], device-pointer entry point, for fanout 32 SoA
+(fill walking the tree), fanout 64 SoA and AoS (the configurations the
+benchmark's tuner picks among) and fanout 16 in the third layout (fill
+replaying the count pass's records, as the benchmark runs it).
 
 The oracle computes a random sample of queries one by one (exact equality);
 for every query the output is checked for properties that hold at any size:
@@ -31,9 +32,9 @@ def c2_data():
     return rtgen.c2_rects(), rtgen.c2_queries()
 
 
-@pytest.mark.parametrize("fanout,layout,nsample", [(32, "soa", 2000), (64, "soa", 1000), (64, "aos", 1000),
-                                                   (16, "d2", 500)])
-def test_fullsize_select_bench_config(c2_data, fanout, layout, nsample):
+@pytest.mark.parametrize("fanout,layout,nsample,replay", [(32, "soa", 2000, False), (64, "soa", 1000, True),
+                                                          (64, "aos", 1000, True), (16, "d2", 500, True)])
+def test_fullsize_select_bench_config(c2_data, fanout, layout, nsample, replay):
     import torch
     assert torch.cuda.is_available()
     import paper_2309_16913_amd as rt
@@ -53,12 +54,17 @@ def test_fullsize_select_bench_config(c2_data, fanout, layout, nsample):
     say(f"case fullsize: {cap} ids")
     off = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
     ids = torch.empty(cap, dtype=torch.int32, device="cuda")
-    wb = rt.select_workspace_bytes(nq, cap)
+    # the benchmark's workspace: with room for the count pass's records, the
+    # fill replays them
+    wb = (rt.select_replay_workspace_bytes if replay else rt.select_workspace_bytes)(nq, cap)
     work = torch.empty(wb, dtype=torch.uint8, device="cuda")
     st = torch.zeros(2, dtype=torch.int64, device="cuda")
     rt.range_select_device(tree, dq.data_ptr(), nq, off.data_ptr(), ids.data_ptr(), cap, work.data_ptr(), wb,
                            st.data_ptr(), s.cuda_stream)
     torch.cuda.synchronize()
+    chunks, over = rt.select_replay_info(work.data_ptr())
+    assert (chunks > 0 and not over) if replay else chunks == 0
+    say(f"case fullsize: replay {replay}, {chunks} record chunks")
     del work
     stat = st.cpu().numpy()
     assert stat[0] == cap and stat[1] == 0

@@ -158,6 +158,21 @@ def test_fullsize_serving_tree_c5():
     hids = ids.cpu().numpy().view(np.uint32)
     say(f"case fullsize serving tree: {total} ids")
     _check_csr_properties(big, q, hoff, hids, "50M tree")
+    # the one-call select with the record replay (the closed loop's path)
+    # gives the same bytes
+    wb = rt.select_replay_workspace_bytes(nq, total)
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    st = torch.zeros(2, dtype=torch.int64, device="cuda")
+    off2 = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    ids2 = torch.empty(total, dtype=torch.int32, device="cuda")
+    rt.range_select_device(t, dq.data_ptr(), nq, off2.data_ptr(), ids2.data_ptr(), total, work.data_ptr(), wb,
+                           st.data_ptr(), s)
+    torch.cuda.synchronize()
+    chunks, over = rt.select_replay_info(work.data_ptr())
+    say(f"case fullsize serving tree: replay {chunks} record chunks, overflow {over}")
+    assert chunks > 0 and not over and st.cpu().tolist() == [total, 0]
+    assert torch.equal(off2, off) and torch.equal(ids2, ids)
+    del work, off2, ids2
     g = np.random.Generator(np.random.PCG64(5055))
     pick = np.sort(g.choice(nq, size=400, replace=False))
     woff, wids = o.select(o.build_str(big, 32), q[pick])
