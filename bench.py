@@ -101,7 +101,7 @@ def kernel_phase(name: str):
     m = re.search(r"select_kernel<\d+, \d+, (\d), \d(?:, \d)?>", name)
     if m:
         return {"0": "count", "1": "fill"}.get(m.group(1))
-    if "bulk_copy_kernel" in name:   # the fill pass's deferred contained runs
+    if "bulk_copy_kernel" in name or "replay_kernel" in name:   # the fill stage's other kernels
         return "fill"
     if "segsort" in name or "seg_classify" in name:
         return "sort"

@@ -593,7 +593,7 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
         for (uint32_t i = t; i < W * kLongDigits; i += T) whist[i] = 0;
         if (t == 0) big = 0;
         __syncthreads();
-        constexpr uint32_t U = 8;   // loads in flight per thread
+        constexpr uint32_t U = 16;   // loads in flight per thread
         for (uint32_t i0 = t; i0 < c; i0 += T * U) {
             uint32_t kk[U];
 #pragma unroll
@@ -655,7 +655,14 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
         }
         __syncthreads();
         if (t < ngroups) (wide ? sub_lists_wide : sub_lists)[subbase[0] + t] = (li << 8) | t;
-        // chunks, digit-sorted in LDS, written out as runs
+        // chunks, digit-sorted in LDS, written out as runs; the next chunk's
+        // ids are loaded while this one is sorted and written
+        uint32_t nkey[R];
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            const uint32_t i = r * T + t;
+            nkey[r] = i < c ? seg[i] : 0u;
+        }
         for (uint32_t base = 0; base < c; base += kLongChunk) {
             const uint32_t len = (c - base) < kLongChunk ? (c - base) : kLongChunk;
             if (t < kLongDigits) lh[t] = 0;
@@ -663,9 +670,14 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
             uint32_t key[R];
 #pragma unroll
             for (uint32_t r = 0; r < R; ++r) {
+                key[r] = nkey[r];
+                if (r * T + t < len) atomicAdd(&lh[(key[r] >> sh) & dmask], 1u);
+            }
+            const uint32_t nb = base + kLongChunk;
+#pragma unroll
+            for (uint32_t r = 0; r < R; ++r) {
                 const uint32_t i = r * T + t;
-                key[r] = i < len ? seg[base + i] : 0u;
-                if (i < len) atomicAdd(&lh[(key[r] >> sh) & dmask], 1u);
+                nkey[r] = nb + i < c ? seg[nb + i] : 0u;
             }
             __syncthreads();
             if (w == 0) {
