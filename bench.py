@@ -101,11 +101,13 @@ def kernel_phase(name: str):
     m = re.search(r"select_kernel<\d+, \d+, (\d), \d(?:, \d)?>", name)
     if m:
         return {"0": "count", "1": "fill"}.get(m.group(1))
+    if "batch_replay_kernel" in name:   # the batch graph's replayed fill
+        return "batch"
     if "bulk_copy_kernel" in name or "replay_kernel" in name:   # the fill stage's other kernels
         return "fill"
     if "segsort" in name or "seg_classify" in name:
         return "sort"
-    m = re.search(r"batch_kernel<(\d)>", name)
+    m = re.search(r"batch_kernel<(\d)(?:, \d)?>", name)
     if m:
         return "batch_count" if m.group(1) == "0" else "batch"
     return None
@@ -641,6 +643,15 @@ def batch_leg(rt, torch, args):
             continue
         ms, tot = timed(b, fn, args.batch_reps)
         out[name] = dict(ms=ms * 1e3, queries_per_s=nq / ms, ids=tot)
+        if name == "batched_graph":
+            chunks, over = b.replay_info()
+            out[name]["replay"] = {"record_chunks": chunks, "overflowed": over, "replayed": bool(chunks and not over)}
+    if not args.batch_tuned_only:
+        # the same graph with the walking fill (second traversal), for reference
+        b.set_replay(False)
+        ms, tot = timed(b, b.run, args.batch_reps)
+        out["batched_graph_walking_fill"] = dict(ms=ms * 1e3, queries_per_s=nq / ms, ids=tot)
+        b.set_replay(True)
     if args.batch_tuned_only:
         b.free()
         for t in trees:
@@ -658,6 +669,11 @@ def batch_leg(rt, torch, args):
     ids = out["batched_graph"]["ids"]
     visit_fill = 16 * nq + 20 * ve + 8 * vn + 4 * ids + 4 * vc + 8 * (nq + 1)
     comp_fill = 16 * nq + tree_bytes + 8 * (nq + 1) + 4 * ids
+    rep = out["batched_graph"].get("replay", {})
+    if rep.get("replayed"):   # the graph's fill replays the count pass's records
+        rb = 16 * 256 * rep["record_chunks"]
+        visit_fill = rb + 8 * (nq + 1) + 8 * ids
+        comp_fill = rb + 8 * (nq + 1) + 4 * ids + min(tree_bytes, 4 * ids)
     b.free()
     # the library's own per-tree choice (fanout 0, RT_LAYOUT_AUTO: probe
     # windows drawn from each tree's data, not the batch's windows)

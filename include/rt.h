@@ -355,7 +355,10 @@ typedef struct rt_batch rt_batch;   /* opaque prepared batch (device-resident) *
 /* Prepare a device-resident batch: copies the queries to the device, builds
  * the work queue and captures the count -> scan -> fill -> sort launches
  * into a HIP graph whose output pool holds ids_capacity ids.
- * ids_capacity = 0 sizes the pool by running the count pass once. */
+ * ids_capacity = 0 sizes the pool by running the count pass once.  The
+ * graph's count pass records its leaves and contained subtrees and the fill
+ * replays them (see rt_select_replay_workspace_bytes; the walking fill runs
+ * instead if the records outgrow their arena). */
 int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees,
                     const float *const *queries, const uint64_t *nq,
                     uint64_t ids_capacity, rt_batch **out);
@@ -368,6 +371,14 @@ int rt_batch_run_plain(rt_batch *b, void *stream);
 int rt_batch_status(rt_batch *b, uint64_t *total, uint64_t *flags);
 /* Copy tree i's CSR to the host. */
 int rt_batch_result(rt_batch *b, uint32_t i, rt_ids **out);
+/* Recapture the batch's graph with the replayed fill (on = 1, the default)
+ * or the walking fill (on = 0); results are identical.  Other values ->
+ * RT_EINVAL.  Not to be called while a run of the batch is in flight. */
+int rt_batch_set_replay(rt_batch *b, uint32_t on);
+/* After a graph run has finished: record chunks its count pass took and
+ * whether they overflowed (both 0 after rt_batch_run_plain).  Synchronizes
+ * the device. */
+int rt_batch_replay_info(rt_batch *b, uint32_t *chunks, uint32_t *overflowed);
 
 /* ------------------------------------------------------------------------ */
 /* Introspection                                                             */

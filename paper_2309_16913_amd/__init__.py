@@ -90,6 +90,8 @@ _sig = {
     "rt_batch_run": ([_vp, _vp], C.c_int),
     "rt_batch_run_plain": ([_vp, _vp], C.c_int),
     "rt_batch_status": ([_vp, C.POINTER(_u64), C.POINTER(_u64)], C.c_int),
+    "rt_batch_set_replay": ([_vp, _u32], C.c_int),
+    "rt_batch_replay_info": ([_vp, C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)], C.c_int),
     "rt_batch_result": ([_vp, _u32, C.POINTER(C.POINTER(_Ids))], C.c_int),
     "rt_tree_stats": ([_vp, C.POINTER(TreeInfo)], C.c_int),
     "rt_tree_set_split": ([_vp, _u32], C.c_int),
@@ -374,6 +376,16 @@ class Batch:
 
     def run_plain(self, stream: int = 0):
         _check(_L.rt_batch_run_plain(self.h, _vp(stream)))
+
+    def set_replay(self, on: bool):
+        """Recapture the graph with the replayed (True) or walking fill."""
+        _check(_L.rt_batch_set_replay(self.h, 1 if on else 0))
+
+    def replay_info(self):
+        """(record chunks taken, overflowed) of the last graph run."""
+        c, o = C.c_uint32(0), C.c_uint32(0)
+        _check(_L.rt_batch_replay_info(self.h, C.byref(c), C.byref(o)))
+        return int(c.value), bool(o.value)
 
     def status(self):
         t, f = _u64(), _u64()

@@ -36,6 +36,10 @@ struct rt_batch {
     void *d_qrange = nullptr;   // per query: its tree's object count (the bound of its ids)
     void *d_qorder = nullptr;   // per position of a tree's processing order: the local query index
     void *d_list_begin = nullptr;   // kXcds + 1 item list bounds
+    void *d_qtree = nullptr;        // per query: its tree's index
+    void *d_rec = nullptr;          // record arena of the recording count pass
+    uint32_t rec_nchunks = 0;
+    bool replay = true;             // the graph's fill replays the count pass's records
     uint64_t id_range = 0;   // largest object count of the batch's trees
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -48,7 +52,7 @@ void rtk::batch_release(rt_batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     void *bufs[] = {b->d_trees, b->d_items, b->d_q,    b->d_counts, b->d_off,       b->d_ids,
                     b->d_scratch, b->d_ctrl, b->d_scan, b->d_status, b->d_plain_off, b->d_lists,
-                    b->d_qrange, b->d_qorder, b->d_list_begin};
+                    b->d_qrange, b->d_qorder, b->d_list_begin, b->d_qtree, b->d_rec};
     for (void *p : bufs)
         if (p) (void)hipFree(p);
     b->~rt_batch();
@@ -56,8 +60,21 @@ void rtk::batch_release(rt_batch *b) {
 
 static hipError_t dmalloc(void **p, size_t bytes) { return hipMalloc(p, bytes ? bytes : 16); }
 
-// Persistent count pass + scan over all instances' queries.
-static hipError_t enqueue_count_scan(rt_batch *b, hipStream_t s) {
+// The record arena as the kernels take it (rec = NULL: no records).
+static BatchRec batch_rec(const rt_batch *b) {
+    BatchRec r;
+    if (!b->replay || !b->d_rec || !b->rec_nchunks) return r;
+    for (const rt_tree *t : b->trees)
+        if (t->n_nodes >= (1u << 30)) return r;   // node indices must leave the flag bits free
+    r.rec = static_cast<uint4 *>(b->d_rec);
+    r.rec_count = reinterpret_cast<uint32_t *>(static_cast<uint8_t *>(b->d_rec) +
+                                               ((16ull * kRecChunk * b->rec_nchunks + 255) & ~255ull));
+    r.rec_nchunks = b->rec_nchunks;
+    return r;
+}
+
+// Persistent count pass (recording with rp.rec) + scan over all instances' queries.
+static hipError_t enqueue_count_scan(rt_batch *b, hipStream_t s, const BatchRec &rp = BatchRec()) {
     Ctrl *ctrl = static_cast<Ctrl *>(b->d_ctrl);
     hipError_t e = launch_zero(ctrl, sizeof(Ctrl), s);
     if (e == hipSuccess)
@@ -65,7 +82,7 @@ static hipError_t enqueue_count_scan(rt_batch *b, hipStream_t s) {
                               static_cast<const uint32_t *>(b->d_list_begin), b->nitems,
                               static_cast<const uint32_t *>(b->d_qorder), static_cast<float4 *>(b->d_q), SEL_COUNT,
                               static_cast<uint32_t *>(b->d_counts), nullptr, nullptr, 0, b->total_q, ctrl, 0,
-                              b->wave_words, s);
+                              b->wave_words, rp, s);
     if (e == hipSuccess)
         e = launch_scan_u32(static_cast<uint32_t *>(b->d_counts), b->total_q, static_cast<uint64_t *>(b->d_off),
                             static_cast<uint64_t *>(b->d_scan), s);
@@ -73,14 +90,21 @@ static hipError_t enqueue_count_scan(rt_batch *b, hipStream_t s) {
 }
 
 static hipError_t enqueue_all(rt_batch *b, hipStream_t s) {
-    hipError_t e = enqueue_count_scan(b, s);
+    BatchRec rp = batch_rec(b);
+    hipError_t e = enqueue_count_scan(b, s, rp);
     Ctrl *ctrl = static_cast<Ctrl *>(b->d_ctrl);
+    if (e == hipSuccess && rp.rec) {   // replay the records; the walk runs only if they overflowed
+        e = launch_batch_replay(static_cast<BatchTree *>(b->d_trees), static_cast<const uint32_t *>(b->d_qtree), rp,
+                                static_cast<uint64_t *>(b->d_off), b->total_q, static_cast<uint32_t *>(b->d_ids),
+                                b->cap, ctrl, s);
+        rp.fill_guard = 1;
+    }
     if (e == hipSuccess)
         e = launch_batch_pass(static_cast<BatchTree *>(b->d_trees), static_cast<BatchItem *>(b->d_items),
                               static_cast<const uint32_t *>(b->d_list_begin), b->nitems,
                               static_cast<const uint32_t *>(b->d_qorder), static_cast<float4 *>(b->d_q), SEL_FILL,
                               static_cast<uint32_t *>(b->d_counts), static_cast<uint64_t *>(b->d_off),
-                              static_cast<uint32_t *>(b->d_ids), b->cap, b->total_q, ctrl, 1, b->wave_words, s);
+                              static_cast<uint32_t *>(b->d_ids), b->cap, b->total_q, ctrl, 1, b->wave_words, rp, s);
     if (e == hipSuccess)
         e = launch_segsort(static_cast<uint64_t *>(b->d_off), b->total_q, static_cast<uint32_t *>(b->d_ids),
                            static_cast<uint32_t *>(b->d_scratch), b->cap, static_cast<uint32_t *>(b->d_lists),
@@ -88,6 +112,25 @@ static hipError_t enqueue_all(rt_batch *b, hipStream_t s) {
     if (e == hipSuccess)
         e = launch_finalize(static_cast<uint64_t *>(b->d_off), b->total_q, b->cap, ctrl,
                             static_cast<uint64_t *>(b->d_status), s);
+    return e;
+}
+
+// (Re)capture the whole select into the batch's graph.
+static hipError_t capture(rt_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = enqueue_all(b, cs);
+        e = hipStreamEndCapture(cs, &b->graph);
+        if (e2 != hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (cs) (void)hipStreamDestroy(cs);
     return e;
 }
 
@@ -129,7 +172,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         std::vector<std::vector<Cand>> per_tree(ntrees);
         std::vector<double> tree_cost(ntrees, 0.0);
         std::vector<float> hq((size_t)total * 4);
-        std::vector<uint32_t> hrange((size_t)total), horder((size_t)total);
+        std::vector<uint32_t> hrange((size_t)total), horder((size_t)total), htree((size_t)total);
         std::vector<uint64_t> code;
         uint64_t qb = 0;
         for (uint32_t i = 0; i < ntrees; ++i) {
@@ -145,6 +188,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
             if (nq[i]) std::memcpy(hq.data() + 4 * qb, queries[i], nq[i] * 16);
             std::fill(hrange.begin() + qb, hrange.begin() + qb + nq[i],
                       (uint32_t)std::min<uint64_t>(t->n_objects, 0xFFFFFFFFull));
+            std::fill(htree.begin() + qb, htree.begin() + qb + nq[i], i);
             // processing order: Morton code of the window centres on a
             // 65536 x 65536 grid over the tree's MBR (only the order of the
             // work depends on it)
@@ -235,6 +279,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         if (e == hipSuccess) e = dmalloc(&b->d_qrange, std::max<uint64_t>(total, 1) * 4);
         if (e == hipSuccess) e = dmalloc(&b->d_qorder, std::max<uint64_t>(total, 1) * 4);
         if (e == hipSuccess) e = dmalloc(&b->d_list_begin, (kXcds + 1) * 4);
+        if (e == hipSuccess) e = dmalloc(&b->d_qtree, std::max<uint64_t>(total, 1) * 4);
         uint64_t plain_total = 0;
         b->plain_begin.resize(ntrees);
         for (uint32_t i = 0; i < ntrees; ++i) {
@@ -250,6 +295,7 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
             e = hipMemcpy(b->d_qrange, hrange.data(), total * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess && total)
             e = hipMemcpy(b->d_qorder, horder.data(), total * 4, hipMemcpyHostToDevice);
+        if (e == hipSuccess && total) e = hipMemcpy(b->d_qtree, htree.data(), total * 4, hipMemcpyHostToDevice);
         if (e == hipSuccess)
             e = hipMemcpy(b->d_list_begin, list_begin.data(), (kXcds + 1) * 4, hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(hip_fail(e, "batch setup"));
@@ -268,19 +314,14 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
         b->cap = ids_capacity ? ids_capacity : off[total];
         e = dmalloc(&b->d_ids, b->cap * 4);
         if (e == hipSuccess) e = dmalloc(&b->d_scratch, segsort_scratch_elems(b->cap) * 4);
+        // the record arena for the count pass inside the graph
+        const uint64_t rb = rec_arena_bytes(total, b->cap);
+        if (e == hipSuccess) e = dmalloc(&b->d_rec, rb);
+        b->rec_nchunks = rec_chunks_in(rb);
         if (e != hipSuccess) return bail(hip_fail(e, "batch output pool"));
 
         // capture the whole select into a graph
-        hipStream_t cs = nullptr;
-        e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipError_t e2 = enqueue_all(b, cs);
-            e = hipStreamEndCapture(cs, &b->graph);
-            if (e2 != hipSuccess) e = e2;
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-        if (cs) (void)hipStreamDestroy(cs);
+        e = capture(b);
         if (e != hipSuccess) return bail(hip_fail(e, "batch graph capture"));
         *out = b;
         return RT_OK;
@@ -289,6 +330,27 @@ extern "C" int rt_batch_create(const rt_tree *const *trees, uint32_t ntrees, con
     } catch (...) {
         return fail(RT_EDEVICE, "unexpected failure");
     }
+}
+
+extern "C" int rt_batch_set_replay(rt_batch *b, uint32_t on) {
+    if (!b) return fail(RT_EINVAL, "batch is NULL");
+    if (on > 1) return fail(RT_EINVAL, "replay %u is not 0 or 1", on);
+    DevSet ds(b->device);
+    b->replay = on != 0;
+    const hipError_t e = capture(b);
+    return e == hipSuccess ? RT_OK : hip_fail(e, "batch graph capture");
+}
+
+extern "C" int rt_batch_replay_info(rt_batch *b, uint32_t *chunks, uint32_t *overflowed) {
+    if (!b || !chunks || !overflowed) return fail(RT_EINVAL, "NULL argument");
+    DevSet ds(b->device);
+    Ctrl hc;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(&hc, b->d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "batch replay info");
+    *chunks = b->last_plain ? 0u : hc.rec_chunks;
+    *overflowed = b->last_plain ? 0u : hc.rec_overflow;
+    return RT_OK;
 }
 
 extern "C" int rt_batch_run(rt_batch *b, void *stream) {

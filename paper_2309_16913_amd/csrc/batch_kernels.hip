@@ -71,12 +71,12 @@ __device__ __forceinline__ uint32_t grab_item(Ctrl *ctrl, uint32_t slot, const u
 
 // One work item: the queries [item.q0, item.q1) of one tree's processing
 // order, run by the wave's groups of G lanes on a tree of node layout LAYOUT.
-template <int MODE, int G, int LAYOUT>
+template <int MODE, int G, int LAYOUT, int REC>
 __device__ __forceinline__ void batch_item(const BatchTree &bt, const BatchItem &item, const uint32_t *__restrict__ qorder,
                                            const float4 *__restrict__ qs, uint32_t *__restrict__ counts,
                                            const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids,
                                            Ctrl *__restrict__ ctrl, uint32_t *wstk, uint32_t lane,
-                                           uint64_t lanes_below) {
+                                           uint64_t lanes_below, const BatchRec &rp, uint4 *wrec) {
     const TreeView &t = bt.t;
     const uint32_t F = t.fanout;
     const uint32_t e = lane & (G - 1);
@@ -90,6 +90,37 @@ __device__ __forceinline__ void batch_item(const BatchTree &bt, const BatchItem 
     uint32_t sp = 0;
     float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
     uint64_t pos = 0, end = 0;
+    // recording count pass: as in the single-tree kernel, records collect in
+    // the group's LDS buffer and go out kRecBuf at a time to the group's
+    // chunk of the arena; the output slot of a record is the global query
+    uint32_t rchunk = kNoNode, rcnt = 0, nbuf = 0;
+    uint4 *rbuf = wrec + (lane / G) * kRecBuf;
+    auto rec_flush = [&]() {   // group-uniform
+        if (nbuf == 0) return;
+        __builtin_amdgcn_wave_barrier();
+        if (rchunk != kRecDead && (rchunk == kNoNode || rcnt + nbuf > kRecChunk)) {
+            if (rchunk != kNoNode && e == 0) rp.rec_count[rchunk] = rcnt;
+            uint32_t c = 0;
+            if (e == 0) c = atomicAdd(&ctrl->rec_chunks, 1u);
+            c = (uint32_t)__shfl((int)c, (int)gbase);
+            if (c < rp.rec_nchunks) {
+                rchunk = c;
+                rcnt = 0;
+            } else {
+                if (e == 0) atomicOr(&ctrl->rec_overflow, 1u);
+                rchunk = kRecDead;
+            }
+        }
+        if (rchunk < kRecDead) {
+            for (uint32_t i = e; i < nbuf; i += G) {
+                const uint4 v = rbuf[i];
+                put_rec(rp.rec + (size_t)rchunk * kRecChunk + rcnt + i, v.x, v.y, v.z, v.w);
+            }
+            rcnt += nbuf;
+        }
+        nbuf = 0;
+        __builtin_amdgcn_wave_barrier();
+    };
 
     while (true) {
         const bool need = !done && sp == 0;
@@ -160,6 +191,18 @@ __device__ __forceinline__ void batch_item(const BatchTree &bt, const BatchItem 
                             atomicOr(&ctrl->err, kErrBounds);
                     }
                 }
+                if constexpr (MODE == SEL_COUNT && REC != 0) {
+                    if (n) {   // one record per 32 entries with hits
+                        const uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+                        const uint32_t k = (lo ? 1u : 0u) + (hi ? 1u : 0u);
+                        if (nbuf + k > kRecBuf) rec_flush();
+                        if (e == 0 && lo) rbuf[nbuf] = make_uint4((uint32_t)gq, (uint32_t)pos, node, lo);
+                        if (G == 64 && e == 32 && hi)
+                            rbuf[nbuf + (lo ? 1u : 0u)] =
+                                make_uint4((uint32_t)gq, (uint32_t)pos + (uint32_t)__popc(lo), node | kRecHi, hi);
+                        nbuf += k;
+                    }
+                }
                 pos += n;
             } else {
                 const uint32_t first = __shfl(ref, (int)gbase);
@@ -178,6 +221,23 @@ __device__ __forceinline__ void batch_item(const BatchTree &bt, const BatchItem 
                             pos += copy_leaf_run<4>(t, l0, l1, ids, pos, end, e, G, &bad);
                         }
                         if (bad && e == 0) atomicOr(&ctrl->err, kErrBounds);
+                    } else if constexpr (REC != 0) {
+                        // one record per contained child: its leaf range
+                        const uint2 rg = cont ? t.range[first + e] : make_uint2(0u, 0u);
+                        const uint32_t sc = cont ? subtree_objects(t, rg) : 0u;
+                        uint32_t inc = sc;
+                        for (uint32_t d = 1; d < G; d <<= 1) {
+                            const uint32_t x = (uint32_t)__shfl_up((int)inc, d, G);
+                            if (e >= d) inc += x;
+                        }
+                        const uint32_t tot = (uint32_t)__shfl((int)inc, (int)(gbase + G - 1));
+                        const uint32_t k = (uint32_t)__popcll(cm);
+                        if (nbuf + k > kRecBuf) rec_flush();
+                        if (cont)
+                            rbuf[nbuf + (uint32_t)__popcll(cm & below)] =
+                                make_uint4((uint32_t)gq, (uint32_t)pos + inc - sc, kRecRun | rg.x, rg.y);
+                        nbuf += k;
+                        pos += tot;
                     } else {
                         uint32_t sc = cont ? subtree_objects(t, t.range[first + e]) : 0u;
                         for (uint32_t d = 1; d < G; d <<= 1) sc += (uint32_t)__shfl_xor((int)sc, (int)d);
@@ -196,21 +256,29 @@ __device__ __forceinline__ void batch_item(const BatchTree &bt, const BatchItem 
         }
         __builtin_amdgcn_wave_barrier();
     }
+    if constexpr (MODE == SEL_COUNT && REC != 0) {
+        rec_flush();
+        if (e == 0 && rchunk < kRecDead) rp.rec_count[rchunk] = rcnt;
+    }
 }
 
-template <int MODE>
+template <int MODE, int REC>
 __global__ void __launch_bounds__(256)
 batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ items,
              const uint32_t *__restrict__ list_begin, uint32_t nitems, const uint32_t *__restrict__ qorder,
              const float4 *__restrict__ qs, uint32_t *__restrict__ counts, const uint64_t *__restrict__ offsets,
              uint32_t *__restrict__ ids, uint64_t cap, uint64_t total_q, Ctrl *__restrict__ ctrl, uint32_t slot,
-             uint32_t wave_words) {
+             uint32_t wave_words, BatchRec rp) {
     extern __shared__ uint32_t smem[];
     if constexpr (MODE == SEL_FILL) {
         if (offsets[total_q] > cap) return;
+        if (rp.fill_guard && ctrl->rec_overflow == 0) return;   // the replay wrote everything
     }
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t *wstk = smem + (threadIdx.x >> 6) * wave_words;
+    // record buffers (recording count pass): after the four waves' stacks,
+    // 16-byte aligned, 64 / 16 groups of kRecBuf records per wave
+    uint4 *wrec = reinterpret_cast<uint4 *>(smem + (4 * wave_words + 3u) / 4u * 4u) + (threadIdx.x >> 6) * 4 * kRecBuf;
     const uint64_t lanes_below = lane ? (~0ull >> (64 - lane)) : 0ull;
     const uint32_t home = blockIdx.x % kXcds;
     uint32_t visited = 0;
@@ -225,7 +293,7 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
         const BatchTree bt = trees[item.tree];
         const uint32_t G = bt.t.fanout <= 16 ? 16u : (bt.t.fanout <= 32 ? 32u : 64u);
 #define RT_ITEM(G_, L_) \
-    batch_item<MODE, G_, L_>(bt, item, qorder, qs, counts, offsets, ids, ctrl, wstk, lane, lanes_below)
+    batch_item<MODE, G_, L_, REC>(bt, item, qorder, qs, counts, offsets, ids, ctrl, wstk, lane, lanes_below, rp, wrec)
         if (bt.t.layout == LAYOUT_SOA) {
             if (G == 16) RT_ITEM(16, LAYOUT_SOA);
             else if (G == 32) RT_ITEM(32, LAYOUT_SOA);
@@ -246,19 +314,134 @@ batch_kernel(const BatchTree *__restrict__ trees, const BatchItem *__restrict__ 
 hipError_t launch_batch_pass(const BatchTree *trees, const BatchItem *items, const uint32_t *list_begin,
                              uint32_t nitems, const uint32_t *qorder, const float4 *q, int mode, uint32_t *counts,
                              const uint64_t *offsets, uint32_t *ids, uint64_t cap, uint64_t total_q, Ctrl *ctrl,
-                             uint32_t slot, uint32_t wave_words, hipStream_t s) {
+                             uint32_t slot, uint32_t wave_words, const BatchRec &rp, hipStream_t s) {
     // wave_words: largest (64 / G) * stack_cap over the trees (one region per wave)
-    const size_t smem = (size_t)4 * wave_words * sizeof(uint32_t);
+    size_t smem = (size_t)4 * wave_words * sizeof(uint32_t);
+    const bool rec = mode == SEL_COUNT && rp.rec;
+    if (rec) smem = (smem + 15) / 16 * 16 + (size_t)4 * 4 * kRecBuf * 16;
     uint32_t blocks = (uint32_t)num_cus() * 8;
     const uint32_t want = (nitems + 3) / 4;
     if (want < blocks) blocks = want ? want : 1;
     blocks = (blocks + kXcds - 1) / kXcds * kXcds;   // every XCD gets blocks
-    if (mode == SEL_COUNT)
-        hipLaunchKernelGGL(batch_kernel<SEL_COUNT>, dim3(blocks), dim3(256), smem, s, trees, items, list_begin, nitems,
-                           qorder, q, counts, offsets, ids, cap, total_q, ctrl, slot, wave_words);
+    if (rec)
+        hipLaunchKernelGGL((batch_kernel<SEL_COUNT, 1>), dim3(blocks), dim3(256), smem, s, trees, items, list_begin,
+                           nitems, qorder, q, counts, offsets, ids, cap, total_q, ctrl, slot, wave_words, rp);
+    else if (mode == SEL_COUNT)
+        hipLaunchKernelGGL((batch_kernel<SEL_COUNT, 0>), dim3(blocks), dim3(256), smem, s, trees, items, list_begin,
+                           nitems, qorder, q, counts, offsets, ids, cap, total_q, ctrl, slot, wave_words, rp);
     else
-        hipLaunchKernelGGL(batch_kernel<SEL_FILL>, dim3(blocks), dim3(256), smem, s, trees, items, list_begin, nitems,
-                           qorder, q, counts, offsets, ids, cap, total_q, ctrl, slot, wave_words);
+        hipLaunchKernelGGL((batch_kernel<SEL_FILL, 0>), dim3(blocks), dim3(256), smem, s, trees, items, list_begin,
+                           nitems, qorder, q, counts, offsets, ids, cap, total_q, ctrl, slot, wave_words, rp);
+    return hipGetLastError();
+}
+
+// Replay of the recording batch count pass (records' slots are global query
+// indices; qtree gives a query's tree).  As the single-tree replay, with the
+// source of each record resolved in the staging step: a leaf record's ptr
+// array (address of its first entry and the stride between entries: 20
+// bytes in AoS, 4 otherwise), a range record's run of its tree's leaf-id
+// array.
+__global__ void __launch_bounds__(256)
+batch_replay_kernel(const BatchTree *__restrict__ trees, const uint32_t *__restrict__ qtree,
+                    const uint4 *__restrict__ rec, const uint32_t *__restrict__ rec_count, uint32_t nchunks,
+                    const uint64_t *__restrict__ offsets, uint64_t total_q, uint32_t *__restrict__ ids, uint64_t cap,
+                    Ctrl *__restrict__ ctrl) {
+    constexpr uint32_t U = 8, HW = 8;
+    __shared__ uint64_t ssrc[kRecChunk], sbase[kRecChunk];
+    __shared__ uint32_t sinfo[kRecChunk];   // leaf: stride; range: id count
+    __shared__ uint32_t smask[kRecChunk];   // leaf: hit mask; range: 0 (and sinfo's top bit set)
+    constexpr uint32_t kRange = 0x80000000u;
+    if (ctrl->rec_overflow || offsets[total_q] > cap) return;
+    const uint32_t nch = min(ctrl->rec_chunks, nchunks);
+    const uint32_t th = threadIdx.x, hw = th >> 5, l = th & 31u;
+    for (uint32_t c = blockIdx.x; c < nch; c += gridDim.x) {
+        const uint32_t cnt = min(rec_count[c], kRecChunk);
+        __syncthreads();
+        if (th < cnt) {
+            const uint4 d = get_rec(rec + (size_t)c * kRecChunk + th);
+            const uint64_t b = offsets[d.x] + d.y, en = offsets[d.x + 1];
+            const TreeView &t = trees[qtree[d.x]].t;
+            uint64_t src = 0;
+            uint32_t info = 0, mask = 0;
+            if (d.z & kRecRun) {
+                const uint64_t s0 = leaf_start(t, d.z & ~kRecRun);
+                const uint64_t n = leaf_start(t, d.w) - s0;
+                src = reinterpret_cast<uint64_t>(t.leaf_ids + s0);
+                info = kRange | (uint32_t)n;
+                if (b + n > en || n >= kRange) {
+                    atomicOr(&ctrl->err, kErrBounds);
+                    info = kRange;
+                }
+            } else {
+                const uint32_t node = d.z & ~kRecHi, half = (d.z & kRecHi) ? 32u : 0u;
+                const uint8_t *nb = t.nodes + (size_t)node * t.node_bytes;
+                const bool aos = t.layout == LAYOUT_AOS;
+                src = reinterpret_cast<uint64_t>(nb + (aos ? 16u + 20u * half : 16u * t.fanout + 4u * half));
+                info = aos ? 20u : 4u;
+                mask = d.w;
+                if (b + (uint32_t)__popc(mask) > en) {
+                    atomicOr(&ctrl->err, kErrBounds);
+                    mask = 0;
+                }
+            }
+            ssrc[th] = src;
+            sbase[th] = b;
+            sinfo[th] = info;
+            smask[th] = mask;
+        }
+        __syncthreads();
+        for (uint32_t r0 = hw; r0 < cnt; r0 += HW * U) {
+            uint32_t v[U];
+            uint64_t o[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t r = r0 + u * HW;
+                o[u] = ~0ull;
+                v[u] = 0;
+                if (r < cnt) {
+                    const uint32_t mask = smask[r];
+                    if ((mask >> l) & 1u) {
+                        const uint8_t *p = reinterpret_cast<const uint8_t *>(ssrc[r]) + (size_t)sinfo[r] * l;
+                        v[u] = *reinterpret_cast<const uint32_t *>(p);
+                        o[u] = sbase[r] + (uint32_t)__popc(mask & ((1u << l) - 1u));
+                    }
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (o[u] != ~0ull) put_id(ids + o[u], v[u]);
+#pragma unroll 1
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t r = r0 + u * HW;
+                if (r >= cnt) break;
+                const uint32_t info = sinfo[r];
+                if (!(info & kRange)) continue;
+                const uint32_t n = info & ~kRange;
+                const uint32_t *__restrict__ src = reinterpret_cast<const uint32_t *>(ssrc[r]);
+                const uint64_t b = sbase[r];
+                for (uint32_t i0 = l; i0 < n; i0 += 32 * U) {
+                    uint32_t w[U];
+#pragma unroll
+                    for (uint32_t k = 0; k < U; ++k) {
+                        const uint32_t i = i0 + 32 * k;
+                        w[k] = i < n ? src[i] : 0u;
+                    }
+#pragma unroll
+                    for (uint32_t k = 0; k < U; ++k) {
+                        const uint32_t i = i0 + 32 * k;
+                        if (i < n) put_id(ids + b + i, w[k]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_batch_replay(const BatchTree *trees, const uint32_t *qtree, const BatchRec &rp,
+                               const uint64_t *offsets, uint64_t total_q, uint32_t *ids, uint64_t cap, Ctrl *ctrl,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(batch_replay_kernel, dim3((uint32_t)num_cus() * 8), dim3(256), 0, s, trees, qtree, rp.rec,
+                       rp.rec_count, rp.rec_nchunks, offsets, total_q, ids, cap, ctrl);
     return hipGetLastError();
 }
 

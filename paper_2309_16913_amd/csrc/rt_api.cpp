@@ -179,7 +179,7 @@ static uint64_t sel_ws_bytes(uint64_t nq, uint64_t cap) {
 // (a node's records never straddle two chunks), and one chunk per lane group
 // that can hold a partly used one at the end of the pass; a count pass that
 // needs more sets the overflow flag and the fill walks the tree instead.
-static uint64_t rec_arena_bytes(uint64_t nq, uint64_t cap) {
+uint64_t rtk::rec_arena_bytes(uint64_t nq, uint64_t cap) {
     const uint64_t recs = (cap / 16 + 16 * nq) * 4 / 3;
     const uint64_t groups = (uint64_t)num_cus() * 8 * 16;
     const uint64_t chunks = (recs + kRecChunk - 1) / kRecChunk + (nq < groups ? nq : groups);
@@ -187,7 +187,7 @@ static uint64_t rec_arena_bytes(uint64_t nq, uint64_t cap) {
 }
 
 // Chunks of an arena of `bytes` bytes.
-static uint32_t rec_chunks_in(uint64_t bytes) {
+uint32_t rtk::rec_chunks_in(uint64_t bytes) {
     const uint64_t per = 16 * kRecChunk + 4;
     const uint64_t c = bytes > 512 ? (bytes - 512) / per : 0;
     return (uint32_t)(c < 0xFFFFFFF0ull ? c : 0xFFFFFFF0ull);

@@ -70,6 +70,10 @@ int enqueue_select(const rt_tree *t, const float4 *dq, uint64_t nq, uint64_t *d_
 // records of the count pass.
 uint64_t select_ws_bytes(uint64_t nq, uint64_t cap);
 uint64_t select_replay_ws_bytes(uint64_t nq, uint64_t cap);
+// Record arena for nq queries and cap ids (records, then one count per
+// chunk), and the chunks an arena of `bytes` holds.
+uint64_t rec_arena_bytes(uint64_t nq, uint64_t cap);
+uint32_t rec_chunks_in(uint64_t bytes);
 
 // Owning device buffer.
 struct DevBuf {

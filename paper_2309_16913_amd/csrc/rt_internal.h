@@ -362,10 +362,23 @@ struct BatchItem {           // a chunk of one tree's queries
 // Work items in kXcds lists (list x = items[list_begin[x] .. list_begin[x+1])),
 // drained first by the blocks of XCD x; qorder[q_begin + position] = local
 // query index (each tree's queries in the Morton order of their centres).
+// rec (count pass): record arena as SelectPlan::rec / rec_count / rec_nchunks,
+// with global query indices as output slots (NULL: no records).  fill_guard
+// (fill pass): run only if the count pass's records overflowed.
+struct BatchRec {
+    uint4 *rec = nullptr;
+    uint32_t *rec_count = nullptr;
+    uint32_t rec_nchunks = 0;
+    uint32_t fill_guard = 0;
+};
 hipError_t launch_batch_pass(const BatchTree *trees, const BatchItem *items, const uint32_t *list_begin,
                              uint32_t nitems, const uint32_t *qorder, const float4 *q, int mode, uint32_t *counts,
                              const uint64_t *offsets, uint32_t *ids, uint64_t capacity, uint64_t total_q, Ctrl *ctrl,
-                             uint32_t work_slot, uint32_t wave_words, hipStream_t s);
+                             uint32_t work_slot, uint32_t wave_words, const BatchRec &rec, hipStream_t s);
+// Replay of a recording batch count pass; qtree[global query] = its tree.
+hipError_t launch_batch_replay(const BatchTree *trees, const uint32_t *qtree, const BatchRec &rec,
+                               const uint64_t *offsets, uint64_t total_q, uint32_t *ids, uint64_t capacity,
+                               Ctrl *ctrl, hipStream_t s);
 
 int num_cus();
 

@@ -75,7 +75,8 @@ def _small_batch(scale=0.02, ntrees=24):
 
 def test_batch_matches_oracle_and_plain(rt, ora):
     """Many uneven trees (mixed fanout and layout) in one persistent, graph-
-    replayed launch: each instance's CSR equals the oracle's; the plain
+    replayed launch: each instance's CSR equals the oracle's, with the fill
+    replaying the count pass's records and with the walking fill; the plain
     per-tree launch sequence gives the same results."""
     inst = _small_batch()
     trees, qs, wants = [], [], []
@@ -92,9 +93,24 @@ def test_batch_matches_oracle_and_plain(rt, ora):
         tot, flags = b.status()
         assert flags == 0, flags
         assert tot == sum(int(w[0][-1]) for w in wants)
+        chunks, over = b.replay_info()
+        assert chunks > 0 and not over, "the graph's fill did not replay the count pass's records"
         for i, w in enumerate(wants):
             got = b.result(i)
             assert np.array_equal(got[0], w[0]) and np.array_equal(got[1], w[1]), (rep, i)
+    # the walking fill in the graph gives the same results
+    b.set_replay(False)
+    for rep in range(2):
+        b.run()
+        assert b.status() == (tot, 0) and b.replay_info() == (0, False)
+        for i, w in enumerate(wants):
+            got = b.result(i)
+            assert np.array_equal(got[0], w[0]) and np.array_equal(got[1], w[1]), ("walk", rep, i)
+    b.set_replay(True)
+    b.run()
+    assert b.status() == (tot, 0) and b.replay_info()[0] > 0
+    with pytest.raises(rt.RTError):
+        rt._check(rt._L.rt_batch_set_replay(b.h, 2))
     b.run_plain()
     tot, flags = b.status()
     assert flags == 0

@@ -107,6 +107,8 @@ def test_fullsize_batch_c4():
     torch.cuda.synchronize()
     total, flags = b.status()
     assert flags == 0
+    chunks, over = b.replay_info()
+    assert chunks > 0 and not over, "the graph's fill did not replay the count pass's records"
     g = np.random.Generator(np.random.PCG64(4242))
     digests = []
     seen = 0
