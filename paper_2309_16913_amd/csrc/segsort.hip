@@ -232,16 +232,73 @@ seg_classify(const uint64_t *__restrict__ offsets, uint64_t nq, uint64_t cap, ui
 // ---------------------------------------------------------------------------
 // class S: one wave per segment
 // ---------------------------------------------------------------------------
+// Sort the s <= 256 keys a wave holds (v[r] = key r*64 + lane, pad beyond
+// s) into dst[0..s).
+__device__ __forceinline__ void wave_sort_regs4(uint32_t (&v)[4], uint32_t *dst, uint32_t s) {
+    const uint32_t lane = threadIdx.x & 63u;
+    if (s < 2) {
+        if (s == 1 && lane == 0) dst[0] = v[0];
+        return;
+    }
+    if (s <= 16) {   // ranks by broadcasting each key
+        uint32_t rk = 0;
+        for (uint32_t j = 0; j < s; ++j) {
+            const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)v[0], (int)j);
+            rk += (x < v[0] || (x == v[0] && j < lane)) ? 1u : 0u;
+        }
+        if (lane < s) dst[rk] = v[0];
+        return;
+    }
+    if (s <= 64) {
+        uint32_t a[1] = {v[0]};
+        wave_bitonic<1>(a);
+        if (lane < s) dst[lane] = a[0];
+    } else if (s <= 128) {
+        uint32_t a[2] = {v[0], v[1]};
+        wave_bitonic<2>(a);
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+            if ((uint32_t)r * 64 + lane < s) dst[r * 64 + lane] = a[r];
+    } else {
+        wave_bitonic<4>(v);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if ((uint32_t)r * 64 + lane < s) dst[r * 64 + lane] = v[r];
+    }
+}
+
+// One wave per segment; the wave's next segment is loaded into registers
+// before the current one is sorted, so its load overlaps the sort.
 __global__ void __launch_bounds__(256)
 segsort_small(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, const uint32_t *__restrict__ list,
               const uint32_t *__restrict__ list_count) {
     const uint32_t m = *list_count;
     const uint32_t wpb = blockDim.x / 64;
-    for (uint32_t i = blockIdx.x * wpb + (threadIdx.x >> 6); i < m; i += gridDim.x * wpb) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t step = gridDim.x * wpb;
+    uint32_t nv[4];
+    uint64_t no = 0;
+    uint32_t nc = 0;
+    auto load = [&](uint32_t i) {
         const uint32_t q = list[i];
-        const uint64_t o = offsets[q];
-        const uint32_t c = (uint32_t)(offsets[q + 1] - o);
-        wave_sort_any(ids + o, ids + o, c);
+        no = offsets[q];
+        nc = (uint32_t)(offsets[q + 1] - no);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t k = (uint32_t)r * 64 + lane;
+            nv[r] = k < nc ? ids[no + k] : kKeyPad;
+        }
+    };
+    uint32_t i = blockIdx.x * wpb + (threadIdx.x >> 6);
+    if (i < m) load(i);
+    for (; i < m; i += step) {
+        uint32_t v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = nv[r];
+        const uint64_t o = no;
+        const uint32_t c = nc;
+        if (i + step < m) load(i + step);   // segments are disjoint: never the ids written below
+        wave_sort_regs4(v, ids + o, c);
     }
 }
 
