@@ -139,12 +139,14 @@ typedef struct rt_tree_info {
  * (fanouts 16, 32, 64 and/or layouts D0, D1, D2) is built on the device and
  * a probe set of windows drawn from the data (centred on seeded objects,
  * area log-uniform in [1e-6, 1e-3] of the data's bounding box) is selected on
- * it; the fastest is kept, together with the faster split mapping
+ * it (one-call device selects whose workspace holds the count pass's
+ * records); the fastest is kept, together with the faster split mapping
  * (rt_tree_set_split 0 or 16).  The choice is cached per (device
  * architecture, log2 n, candidate sets, RT_BUILD_SORT_LX) in memory and
  * appended to the text file $RT_TUNE_CACHE (empty: memory only; unset:
- * $HOME/.cache/rt_mi355x_tune.txt), so later builds with the same key do
- * no timing.  rt_tree_stats reports the choice.
+ * $HOME/.cache/rt_mi355x_tune.txt; lines "rt-tune-v2 key fanout layout
+ * kmin", lines of other formats ignored), so later builds with the same key
+ * do no timing.  rt_tree_stats reports the choice.
  */
 int rt_build_str(const float *rects, uint64_t n, uint32_t fanout, uint32_t layout,
                  rt_tree **out);

@@ -86,10 +86,13 @@ void load_cache_locked() {
     if (path.empty()) return;
     FILE *f = std::fopen(path.c_str(), "r");
     if (!f) return;
-    char key[256];
+    // one choice per line; lines of other formats (an earlier version's
+    // timings of another select form) are skipped
+    char line[512], key[256];
     unsigned F, L, K;
-    while (std::fscanf(f, "rt-tune-v1 %255s %u %u %u\n", key, &F, &L, &K) == 4) {
-        if (F >= 2 && F <= 64 && (L == RT_LAYOUT_AOS || L == RT_LAYOUT_SOA || L == RT_LAYOUT_D2))
+    while (std::fgets(line, sizeof line, f)) {
+        if (std::sscanf(line, "rt-tune-v2 %255s %u %u %u", key, &F, &L, &K) == 4 && F >= 2 && F <= 64 &&
+            (L == RT_LAYOUT_AOS || L == RT_LAYOUT_SOA || L == RT_LAYOUT_D2))
             g_cache[key] = Choice{F, L, K};
     }
     std::fclose(f);
@@ -103,7 +106,7 @@ void store_locked(const std::string &key, const Choice &c) {
     if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
     FILE *f = std::fopen(path.c_str(), "a");
     if (!f) return;   // not writable: the in-memory cache still holds it
-    std::fprintf(f, "rt-tune-v1 %s %u %u %u\n", key.c_str(), c.fanout, c.layout, c.kmin);
+    std::fprintf(f, "rt-tune-v2 %s %u %u %u\n", key.c_str(), c.fanout, c.layout, c.kmin);
     std::fclose(f);
 }
 
@@ -160,7 +163,9 @@ struct Prober {
         if (rc) return rc;
         e = hipMemcpyAsync(&total, static_cast<uint64_t *>(off.p) + np, 8, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        wb = rt_select_workspace_bytes(np, total);
+        // timed as one-call selects with room for the count pass's records
+        // (the fill replays them), the form the device select is given
+        wb = select_replay_ws_bytes(np, total);
         if (e == hipSuccess) e = ids.alloc(total * 4);
         if (e == hipSuccess) e = work.alloc(wb);
         return e == hipSuccess ? RT_OK : hip_fail(e, "tuner setup");
@@ -173,7 +178,8 @@ struct Prober {
             if (hipEventRecord(ev[0], s) != hipSuccess) return -1.f;
             if (enqueue_select_stage(t, static_cast<const float4 *>(dq.p), np, static_cast<uint64_t *>(off.p),
                                      static_cast<uint32_t *>(ids.p), total, work.p,
-                                     static_cast<uint64_t *>(status.p), s, 3, nullptr, nullptr) != RT_OK)
+                                     static_cast<uint64_t *>(status.p), s, 3, nullptr, nullptr,
+                                     wb - select_ws_bytes(np, total)) != RT_OK)
                 return -1.f;
             if (hipEventRecord(ev[1], s) != hipSuccess || hipEventSynchronize(ev[1]) != hipSuccess) return -1.f;
             float ms = 0.f;

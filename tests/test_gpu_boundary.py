@@ -157,7 +157,7 @@ def test_library_chosen_fanout_and_layout(rt, ora, tmp_path):
         go, gi = rt.range_select(t, q)
         _csr_equal(go, gi, want[0], want[1], "tuned F and layout")
         lines = cache.read_text().splitlines()
-        assert len(lines) == 1 and lines[0].startswith("rt-tune-v1 ")
+        assert len(lines) == 1 and lines[0].startswith("rt-tune-v2 ")
         assert lines[0].split()[2:4] == [str(i.fanout), str(i.layout)]
         # same key: the cached choice, no new timing line
         t2 = rt.build_str(r, 0, "auto")
