@@ -241,6 +241,19 @@ def test_replay_parity(rt, ora):
     t = rt.build_str(r[:1000], 16, "soa")
     with pytest.raises(rt.RTError):
         rt._check(rt._L.rt_tree_set_replay(t.h, 2))
+    # windows over the whole space: every root child is one range record of
+    # tens of thousands of ids, every segment holds all 300k ids
+    qa = np.array([[-1.0, -1.0, 2.0, 2.0]] * 8 + [[0.0, 0.0, 0.5, 1.0]] * 4, np.float32)
+    wa = ora.select(ora.build_str(r, 32), qa)
+    capa = int(wa[1].size)
+    for fanout, layout in [(64, "soa"), (16, "d2")]:
+        say(f"case replay whole-space windows F={fanout} {layout}: {capa} ids")
+        t = rt.build_str(r, fanout, layout)
+        for go, gi, (chunks, over) in _device_select(rt, t, qa, capa,
+                                                     rt.select_replay_workspace_bytes(qa.shape[0], capa)):
+            assert chunks > 0 and not over
+            assert np.array_equal(go, wa[0].astype(np.int64)) and np.array_equal(gi, wa[1]), f"F={fanout} {layout}"
+        t.free()
 
 
 def test_select_all_windows(rt):

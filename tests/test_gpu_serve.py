@@ -46,7 +46,10 @@ def test_served_results_equal_oracle_and_alone():
     def sink(r, off, ids):
         got[r.rid] = (off.copy(), ids.copy())
     srv = Server(tb, tj, nslots=3, max_windows=2048, pool_ids=pool)
-    out = srv.run(reqs, sink=sink)
+    # every request has arrived at the start (arrival times scaled to ~0): the
+    # first batch is a full, unsized one of max_windows windows, whatever the
+    # box's launch latencies, so it exceeds the pool and is re-queued
+    out = srv.run(reqs, sink=sink, time_scale=1e-9)
     say(f"case serve: {out}")
     assert len(got) == len(reqs)
     assert out["requeued_batches"] > 0, "the first batches were meant to exceed the pool"
