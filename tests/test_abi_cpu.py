@@ -76,6 +76,21 @@ def test_null_arguments_rejected():
     lib.rt_free(None)   # no-op
     assert lib.rt_tree_stats(None, None) == rt.RT_EINVAL
     assert lib.rt_select_workspace_bytes(1000, 0) > 1000 * 4
+    # the replay workspace: the plain layout plus room for 256-record chunks
+    # (cap/16 + 16 nq records and more), growing with both arguments
+    for nq, cap in [(1, 0), (1000, 0), (1000, 10**6), (10**6, 1_416_539_337)]:
+        plain = lib.rt_select_workspace_bytes(nq, cap)
+        full = lib.rt_select_replay_workspace_bytes(nq, cap)
+        assert full - plain >= 16 * (cap // 16 + 16 * nq), (nq, cap)
+    assert lib.rt_select_replay_workspace_bytes(1000, 2 * 10**6) > lib.rt_select_replay_workspace_bytes(1000, 10**6)
+    assert lib.rt_select_replay_workspace_bytes(2000, 10**6) > lib.rt_select_replay_workspace_bytes(1000, 10**6)
+    # the knobs reject a NULL tree
+    assert lib.rt_tree_set_replay(None, 1) == rt.RT_EINVAL
+    assert lib.rt_tree_set_bulk_copy(None, 0) == rt.RT_EINVAL
+    c, o = C.c_uint32(0), C.c_uint32(0)
+    assert lib.rt_select_replay_info(None, C.byref(c), C.byref(o)) == rt.RT_EINVAL
+    assert lib.rt_batch_set_replay(None, 1) == rt.RT_EINVAL
+    assert lib.rt_batch_replay_info(None, C.byref(c), C.byref(o)) == rt.RT_EINVAL
 
 
 def test_stack_bound_formula():
