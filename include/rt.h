@@ -231,7 +231,8 @@ uint64_t rt_select_workspace_bytes(uint64_t nq, uint64_t ids_capacity);
  * identical).  Any size from rt_select_workspace_bytes up is accepted: the
  * bytes past it hold the records, and when they do not suffice (or the tree
  * has 2^30 nodes or more, or replay is off for the tree) the fill walks the
- * tree.  The two-stage calls never replay. */
+ * tree.  The two-stage calls replay when the count stage's workspace has room
+ * past its own layout. */
 uint64_t rt_select_replay_workspace_bytes(uint64_t nq, uint64_t ids_capacity);
 
 /* Whether one-call selects on this tree may replay the count pass's records
@@ -327,7 +328,12 @@ int rt_range_select_async(const rt_tree *t, const float *d_queries, uint64_t nq,
  * of its own (it consumes the work counters the count stage resets).  Both
  * only enqueue on `stream`.
  * work_bytes: at least rt_select_workspace_bytes(nq, 0) for the count stage
- * and rt_select_workspace_bytes(nq, ids_capacity) for the fill stage. */
+ * and rt_select_workspace_bytes(nq, ids_capacity) for the fill stage.  The
+ * count stage uses any bytes of d_work past rt_select_workspace_bytes(nq, 0)
+ * for its records (see rt_select_replay_workspace_bytes): the fill stage
+ * then replays them instead of walking the tree, and those bytes must also
+ * stay unchanged until it runs.  With exactly rt_select_workspace_bytes(nq,
+ * 0) bytes for the count stage the fill stage walks the tree. */
 int rt_range_select_device_count(const rt_tree *t, const float *d_queries, uint64_t nq, uint64_t *d_offsets,
                                  void *d_work, uint64_t work_bytes, void *stream);
 int rt_range_select_device_fill(const rt_tree *t, const float *d_queries, uint64_t nq, uint64_t *d_offsets,

@@ -423,12 +423,14 @@ int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, u
         plan.heavy = w.heavy;
         plan.hcap = sc.budget;
     }
-    // records of the count pass, replayed by the fill stage of the same call
-    // (node and leaf indices must leave the two flag bits free)
+    // records of the count pass (node and leaf indices must leave the two
+    // flag bits free), in the rec_bytes after the layout for (nq, cap) in one
+    // call, or for (nq, 0) in a separate count stage; the count stage names
+    // the arena in the control words, where the fill stage's replay finds it
     const uint32_t rec_nchunks = rec_chunks_in(rec_bytes);
-    const bool rec = stage == 3 && !d_counts_out && t->replay && rec_nchunks > 0 && t->n_nodes < (1u << 30);
+    const bool rec = (stage & 1) && !d_counts_out && t->replay && rec_nchunks > 0 && t->n_nodes < (1u << 30);
     if (rec) {
-        uint8_t *base = static_cast<uint8_t *>(work) + sel_ws_bytes(nq, cap);
+        uint8_t *base = static_cast<uint8_t *>(work) + sel_ws_bytes(nq, stage == 1 ? 0 : cap);
         plan.rec = reinterpret_cast<uint4 *>(base);
         plan.rec_count = reinterpret_cast<uint32_t *>(base + align256(16ull * kRecChunk * rec_nchunks));
         plan.rec_nchunks = rec_nchunks;
@@ -436,6 +438,7 @@ int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, u
     if (stage & 1) {   // count stage: ctrl, order, split, count pass, offsets
         uint32_t *counts = d_counts_out ? d_counts_out : (sc.on ? w.slot_counts : w.counts);
         e = launch_zero(w.ctrl, sizeof(Ctrl), s);
+        if (e == hipSuccess && rec) e = launch_set_rec(w.ctrl, plan, s);
         if (e == hipSuccess) e = mark(0);
         const uint64_t *order = nullptr;
         if (e == hipSuccess && nq >= kOrderMinQueries)
@@ -478,8 +481,11 @@ int rtk::enqueue_select_stage(const rt_tree *t, const float4 *dq, uint64_t nq, u
             plan.bulk = sel_bulk(w.scratch, cap);
             plan.bulk_cap = (uint32_t)(bcap < 0xFFFFFFFFull ? bcap : 0xFFFFFFFFull);
         }
-        if (rec) {   // replay the records; the walk runs only if they overflowed
-            e = launch_replay(v, plan, fo, no, d_ids, cap, w.ctrl, s);
+        // replay the count pass's records (a separate fill stage cannot know
+        // whether its count stage made any: the replay checks); the walk then
+        // runs only if there were none or they overflowed
+        if (rec || stage == 2) {
+            e = launch_replay(v, fo, no, d_ids, cap, w.ctrl, s);
             plan.fill_guard = 1;
         }
         if (e == hipSuccess)
@@ -541,8 +547,10 @@ extern "C" int rt_range_select_device_count(const rt_tree *t, const float *d_que
     if (int rc = check_stage_args(t, d_queries, nq, d_offsets, d_work)) return rc;
     if (work_bytes < sel_ws_bytes(nq, 0)) return fail(RT_EINVAL, "workspace too small");
     DevSet ds(t->device);
+    // the workspace past the count stage's own layout holds its records
     return enqueue_select_stage(t, reinterpret_cast<const float4 *>(d_queries), nq, d_offsets, nullptr, 0, d_work,
-                                nullptr, static_cast<hipStream_t>(stream), 1, nullptr, nullptr);
+                                nullptr, static_cast<hipStream_t>(stream), 1, nullptr, nullptr,
+                                work_bytes - sel_ws_bytes(nq, 0));
 }
 
 extern "C" int rt_range_select_device_fill(const rt_tree *t, const float *d_queries, uint64_t nq,

@@ -127,7 +127,10 @@ struct Ctrl {
     uint32_t bulk_taken;     // descriptors taken by the bulk copy
     uint32_t rec_chunks;     // record chunks taken by the count pass
     uint32_t rec_overflow;   // 1: the record arena filled up (the fill walks the tree)
-    uint32_t pad[3];
+    uint32_t rec_nchunks;    // the count pass's record arena (0: it recorded nothing); set by the
+    uint32_t pad[2];         // count stage, read by the fill stage's replay, which may be a
+    uint4 *rec_base;         // separate call
+    uint32_t *rec_count;
     uint64_t stats[4];       // visit statistics
     // per-pass, per-XCD query counters, one 128-byte cache line each
     uint32_t xwork[3][kXcds][32];
@@ -226,7 +229,8 @@ struct SelectPlan {
     uint4 *rec = nullptr;
     uint32_t *rec_count = nullptr;
     uint32_t rec_nchunks = 0;
-    // fill pass: run only if the count pass's record arena overflowed
+    // fill pass: run only if the count pass made no records or they
+    // overflowed (the replay wrote everything otherwise)
     uint32_t fill_guard = 0;
 };
 
@@ -269,11 +273,14 @@ constexpr uint32_t kOrderMinQueries = 8192;   // smaller batches keep input orde
 // Bulk copy of the long contained runs a fill pass deferred (descriptors in
 // bulk[0 .. min(ctrl->bulk_n, bulk_cap))) into ids: persistent grid, one block
 // per descriptor at a time.  Enqueue right after that fill pass.
-// Replay of the count pass's records (plan.rec): writes every recorded hit
-// and contained leaf range at offsets[slot] + position; does nothing if the
-// arena overflowed or the result does not fit.
-hipError_t launch_replay(const TreeView &t, const SelectPlan &plan, const uint64_t *offsets, uint32_t noffsets,
-                         uint32_t *ids, uint64_t ids_capacity, Ctrl *ctrl, hipStream_t s);
+// Store the plan's record arena in the control words (after they are zeroed).
+hipError_t launch_set_rec(Ctrl *ctrl, const SelectPlan &plan, hipStream_t s);
+// Replay of the count pass's records (arena named in the control words):
+// writes every recorded hit and contained leaf range at offsets[slot] +
+// position; does nothing if the count pass made no records, they overflowed,
+// or the result does not fit.
+hipError_t launch_replay(const TreeView &t, const uint64_t *offsets, uint32_t noffsets, uint32_t *ids,
+                         uint64_t ids_capacity, Ctrl *ctrl, hipStream_t s);
 
 hipError_t launch_bulk_copy(const uint32_t *leaf_ids, const uint4 *bulk, uint32_t bulk_cap, uint32_t *ids,
                             Ctrl *ctrl, hipStream_t s);

@@ -195,7 +195,7 @@ select_kernel(TreeView t, const float4 *__restrict__ qs, uint32_t nq, uint32_t *
     extern __shared__ uint32_t smem[];
     if constexpr (MODE == SEL_FILL) {
         if (offsets[noffsets] > cap) return;   // result does not fit: leave ids untouched
-        if (plan.fill_guard && ctrl->rec_overflow == 0) return;   // the replay wrote everything
+        if (plan.fill_guard && ctrl->rec_nchunks && !ctrl->rec_overflow) return;   // the replay wrote everything
     }
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t e = lane & (G - 1);
@@ -707,12 +707,14 @@ bulk_copy_kernel(const uint32_t *__restrict__ leaf_ids, const uint4 *__restrict_
 // 4.13 ms at 10M rectangles / 1M windows, fanout 64 SoA).
 template <int LAYOUT>
 __global__ void __launch_bounds__(256)
-replay_kernel(TreeView t, const uint4 *__restrict__ rec, const uint32_t *__restrict__ rec_count, uint32_t nchunks,
-              const uint64_t *__restrict__ offsets, uint32_t noffsets, uint32_t *__restrict__ ids, uint64_t cap,
-              Ctrl *__restrict__ ctrl) {
+replay_kernel(TreeView t, const uint64_t *__restrict__ offsets, uint32_t noffsets, uint32_t *__restrict__ ids,
+              uint64_t cap, Ctrl *__restrict__ ctrl) {
     __shared__ uint64_t sbase[kRecChunk], send[kRecChunk];
     __shared__ uint2 sref[kRecChunk];
-    if (ctrl->rec_overflow || offsets[noffsets] > cap) return;
+    const uint32_t nchunks = ctrl->rec_nchunks;
+    if (!nchunks || ctrl->rec_overflow || offsets[noffsets] > cap) return;
+    const uint4 *__restrict__ rec = ctrl->rec_base;
+    const uint32_t *__restrict__ rec_count = ctrl->rec_count;
     const uint32_t nch = min(ctrl->rec_chunks, nchunks);
     const uint32_t th = threadIdx.x, hw = th >> 5, l = th & 31u;
     const uint32_t F = t.fanout;
@@ -790,18 +792,26 @@ replay_kernel(TreeView t, const uint4 *__restrict__ rec, const uint32_t *__restr
     }
 }
 
-hipError_t launch_replay(const TreeView &t, const SelectPlan &plan, const uint64_t *offsets, uint32_t noffsets,
-                         uint32_t *ids, uint64_t cap, Ctrl *ctrl, hipStream_t s) {
+__global__ void set_rec_kernel(Ctrl *ctrl, uint4 *rec, uint32_t *rec_count, uint32_t nchunks) {
+    ctrl->rec_base = rec;
+    ctrl->rec_count = rec_count;
+    ctrl->rec_nchunks = nchunks;
+}
+
+hipError_t launch_set_rec(Ctrl *ctrl, const SelectPlan &plan, hipStream_t s) {
+    hipLaunchKernelGGL(set_rec_kernel, dim3(1), dim3(1), 0, s, ctrl, plan.rec, plan.rec_count, plan.rec_nchunks);
+    return hipGetLastError();
+}
+
+hipError_t launch_replay(const TreeView &t, const uint64_t *offsets, uint32_t noffsets, uint32_t *ids,
+                         uint64_t cap, Ctrl *ctrl, hipStream_t s) {
     const dim3 grid((uint32_t)num_cus() * 8), block(256);
     if (t.layout == LAYOUT_AOS)
-        hipLaunchKernelGGL(replay_kernel<LAYOUT_AOS>, grid, block, 0, s, t, plan.rec, plan.rec_count,
-                           plan.rec_nchunks, offsets, noffsets, ids, cap, ctrl);
+        hipLaunchKernelGGL(replay_kernel<LAYOUT_AOS>, grid, block, 0, s, t, offsets, noffsets, ids, cap, ctrl);
     else if (t.layout == LAYOUT_SOA)
-        hipLaunchKernelGGL(replay_kernel<LAYOUT_SOA>, grid, block, 0, s, t, plan.rec, plan.rec_count,
-                           plan.rec_nchunks, offsets, noffsets, ids, cap, ctrl);
+        hipLaunchKernelGGL(replay_kernel<LAYOUT_SOA>, grid, block, 0, s, t, offsets, noffsets, ids, cap, ctrl);
     else
-        hipLaunchKernelGGL(replay_kernel<LAYOUT_D2>, grid, block, 0, s, t, plan.rec, plan.rec_count,
-                           plan.rec_nchunks, offsets, noffsets, ids, cap, ctrl);
+        hipLaunchKernelGGL(replay_kernel<LAYOUT_D2>, grid, block, 0, s, t, offsets, noffsets, ids, cap, ctrl);
     return hipGetLastError();
 }
 

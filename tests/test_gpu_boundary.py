@@ -136,7 +136,21 @@ def test_two_stage_select(rt, ora, kmin):
                                 st.data_ptr(), s)
     torch.cuda.synchronize()
     assert st.cpu().tolist() == [total, 0]
+    assert rt.select_replay_info(work.data_ptr()) == (0, False)   # no room to record: the fill walked
     _csr_equal(off.cpu().numpy(), ids.cpu().numpy(), wo, wi, f"two-stage kmin={kmin}")
+    # the count stage given room past its layout records, the fill replays
+    wr = rt.select_replay_workspace_bytes(nq, total)
+    workr = torch.empty(wr, dtype=torch.uint8, device="cuda")
+    for rep in range(2):
+        ids.fill_(-1)
+        rt.range_select_device_count(t, dq.data_ptr(), nq, off.data_ptr(), workr.data_ptr(), wr, s)
+        rt.range_select_device_fill(t, dq.data_ptr(), nq, off.data_ptr(), ids.data_ptr(), total, workr.data_ptr(),
+                                    wr, st.data_ptr(), s)
+        torch.cuda.synchronize()
+        assert st.cpu().tolist() == [total, 0]
+        chunks, over = rt.select_replay_info(workr.data_ptr())
+        assert chunks > 0 and not over, f"two-stage kmin={kmin}: the fill did not replay"
+        _csr_equal(off.cpu().numpy(), ids.cpu().numpy(), wo, wi, f"two-stage replay kmin={kmin} rep {rep}")
 
 
 def test_library_chosen_fanout_and_layout(rt, ora, tmp_path):
