@@ -153,6 +153,37 @@ def test_two_stage_select(rt, ora, kmin):
         _csr_equal(off.cpu().numpy(), ids.cpu().numpy(), wo, wi, f"two-stage replay kmin={kmin} rep {rep}")
 
 
+def test_two_stage_replay_overflow(rt, ora):
+    """Two-stage select whose count stage has room for only a few record
+    chunks (tiny windows: about one record per id): the records overflow,
+    the fill stage walks the tree, the results equal the oracle's."""
+    import torch
+    r = rtgen.c2_rects(200_000)
+    q = rtgen.windows_loguniform(20_000, 1e-8, 1e-6, 541)
+    t = rt.build_str(r, 16, "soa")
+    nq = q.shape[0]
+    wo, wi = ora.select(ora.build_str(r, 16), q)
+    total = int(wo[-1])
+    say(f"case two-stage replay overflow: {total} ids")
+    dq = torch.from_numpy(q).cuda()
+    off = torch.empty(nq + 1, dtype=torch.int64, device="cuda")
+    ids = torch.empty(max(total, 1), dtype=torch.int32, device="cuda")
+    st = torch.zeros(2, dtype=torch.int64, device="cuda")
+    # room for eight 256-record chunks past the count stage's layout; every
+    # lane group that finds anything takes a chunk of its own
+    wb = rt.select_workspace_bytes(nq, total) + 8 * (256 * 16 + 4) + 512
+    work = torch.empty(wb, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    rt.range_select_device_count(t, dq.data_ptr(), nq, off.data_ptr(), work.data_ptr(), wb, s)
+    rt.range_select_device_fill(t, dq.data_ptr(), nq, off.data_ptr(), ids.data_ptr(), total, work.data_ptr(), wb,
+                                st.data_ptr(), s)
+    torch.cuda.synchronize()
+    assert st.cpu().tolist() == [total, 0]
+    chunks, over = rt.select_replay_info(work.data_ptr())
+    assert chunks > 0 and over, f"{chunks} chunks, overflow {over}: the case was meant to overflow"
+    _csr_equal(off.cpu().numpy(), ids[:total].cpu().numpy(), wo, wi, "two-stage replay overflow")
+
+
 def test_library_chosen_fanout_and_layout(rt, ora, tmp_path):
     """fanout 0 / RT_LAYOUT_AUTO: the library times its candidates, keeps the
     fastest, caches the choice in the file named by RT_TUNE_CACHE, and the
