@@ -605,20 +605,25 @@ segsort_mid(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, co
 // thread), a scan, then chunks of 8192
 // ids are counting-sorted by that digit in LDS and written out as contiguous
 // runs, one run per digit and chunk; the 257 sub-bucket starts go to the
-// segment's descriptor.  Then groups of G consecutive sub-buckets (G chosen
-// so that a group holds at most 4096 ids) are sorted from scratch back into
-// place by the whole grid, one block per group (segsort_sub).  A segment with
-// a sub-bucket over 4096 ids (ids far from uniform, or more than about a
-// million ids) is left as it is and goes to the fallback list.
+// segment's descriptor.  Then groups of G consecutive sub-buckets are sorted
+// from scratch back into place by the whole grid, one block per group
+// (segsort_sub): G is chosen so that a group holds at most 4096 ids, or at
+// most 32768 (a 1024-thread block) when a sub-bucket holds more than 4096
+// (segments of about a million ids).  A segment with a sub-bucket over 32768
+// ids (ids far from uniform) is left as it is and goes to the fallback list.
 constexpr uint32_t kLongDigits = 256;
-constexpr uint32_t kLongChunk = 8192;   // ids per chunk: 512 threads x 16
+constexpr uint32_t kLongChunk = 8192;   // ids per chunk: 1024 threads x 8
 constexpr uint32_t kSubMax = 4096;      // longest group sorted by a 256-thread block
 constexpr uint32_t kSubBigMax = 32768;  // longest group sorted by a 1024-thread block
 constexpr uint32_t kDesc = kLongDigits + 2;   // 257 sub-bucket starts, group width
 constexpr uint32_t kSubCounts = 8;      // counters of the two group work lists (in the class counter block)
 
+// 1024 threads held to 64 registers (two blocks, 32 waves per CU; one 4-byte
+// spill, reloaded once per segment): the pass waits on LDS and memory, and
+// at 16 waves per CU (512 threads, 122 registers) the 50M-rectangle loop's
+// sort took 16.1 instead of 15.5 ms.
 template <int T>
-__global__ void __launch_bounds__(T)
+__global__ void __launch_bounds__(T, 8)
 segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, uint32_t *__restrict__ scratch,
              uint32_t *__restrict__ desc, uint32_t *__restrict__ sub_lists, uint32_t *__restrict__ sub_lists_wide,
              uint32_t *__restrict__ sub_counts,
@@ -650,7 +655,7 @@ segsort_long(const uint64_t *__restrict__ offsets, uint32_t *__restrict__ ids, u
         for (uint32_t i = t; i < W * kLongDigits; i += T) whist[i] = 0;
         if (t == 0) big = 0;
         __syncthreads();
-        constexpr uint32_t U = 16;   // loads in flight per thread
+        constexpr uint32_t U = 8192 / T;   // loads in flight per thread
         for (uint32_t i0 = t; i0 < c; i0 += T * U) {
             uint32_t kk[U];
 #pragma unroll
@@ -1009,7 +1014,7 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
     static const uint32_t g_m2 = resident_per_cu(segsort_mid<256, 16, false, true, 4>, 256);
     static const uint32_t g_m3 = resident_per_cu(segsort_mid<512, 32, false, true, 8>, 512);
     static const uint32_t g_m4 = resident_per_cu(segsort_mid<1024, 32, false, false, 8>, 1024);
-    static const uint32_t g_long = resident_per_cu(segsort_long<512>, 512);
+    static const uint32_t g_long = resident_per_cu(segsort_long<1024>, 1024);
     static const uint32_t g_sub = resident_per_cu(segsort_sub<256, 16, 4, true>, 256);
     static const uint32_t g_subw = resident_per_cu(segsort_sub<1024, 32, 8, false>, 1024);
     hipError_t e = launch_zero(counts, 64 * 4, s);
@@ -1037,7 +1042,7 @@ hipError_t launch_segsort(const uint64_t *offsets, uint64_t nq, uint32_t *ids, u
                        lists + 3 * nq, counts + 3, range, seg_range);
     hipLaunchKernelGGL((segsort_mid<1024, 32, false, false, 8>), dim3(cus * g_m4), dim3(1024), 0, s, offsets, ids,
                        lists + 4 * nq, counts + 4, range, seg_range);
-    hipLaunchKernelGGL(segsort_long<512>, dim3(cus * g_long), dim3(512), 0, s, offsets, ids, scratch, desc, sub_list,
+    hipLaunchKernelGGL(segsort_long<1024>, dim3(cus * g_long), dim3(1024), 0, s, offsets, ids, scratch, desc, sub_list,
                        sub_list_wide, counts + kSubCounts, lists + kLong * nq, counts + kLong, lists + kFallback * nq,
                        counts + kFallback, range, seg_range);
     hipLaunchKernelGGL((segsort_sub<256, 16, 4, true>), dim3(cus * g_sub), dim3(256), 0, s, offsets, ids, scratch,
