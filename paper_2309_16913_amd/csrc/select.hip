@@ -753,9 +753,15 @@ replay_kernel(TreeView t, const uint64_t *__restrict__ offsets, uint32_t noffset
                     }
                 }
             }
+            // a leaf record's ids are a short run next to the runs of the
+            // records beside it in the chunk (the same block, the same L2):
+            // cached stores let L2 merge their partly written lines, where
+            // stores that bypass it write each part to memory on its own
+            // (fill 2.83 -> 2.67 ms at 10M rectangles / 1M windows).  Range
+            // copies write whole lines and keep the bypassing stores.
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u)
-                if (o[u] != ~0ull) put_id(ids + o[u], v[u]);
+                if (o[u] != ~0ull) ids[o[u]] = v[u];
 #pragma unroll 1
             for (uint32_t u = 0; u < U; ++u) {
                 const uint32_t r = r0 + u * HW;
