@@ -55,6 +55,19 @@ __device__ __forceinline__ uint32_t ceil_log2(uint32_t v) {
     return b;
 }
 
+// The key of lane (lane ^ j), for the constant distances of a bitonic
+// network: a DPP quad permutation for 1 and 2 (an ordinary vector move), the
+// bit-mask swizzle for 4, 8 and 16 (within each 32-lane half, no address
+// register), a lane permute for 32.
+__device__ __forceinline__ uint32_t xor_lane(uint32_t v, uint32_t j) {
+    if (j == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);   // quad [1,0,3,2]
+    if (j == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);   // quad [2,3,0,1]
+    if (j == 4) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (4 << 10));
+    if (j == 8) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (8 << 10));
+    if (j == 16) return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1F | (16 << 10));
+    return (uint32_t)__shfl_xor((int)v, (int)j);
+}
+
 // Bitonic sort of the 64*R keys v[r] (element index r*64 + lane) ascending.
 template <int R>
 __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[R]) {
@@ -78,7 +91,7 @@ __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[R]) {
             } else {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const uint32_t o = __shfl_xor(v[r], (int)j);
+                    const uint32_t o = xor_lane(v[r], j);
                     const bool up = (((uint32_t)r * 64 + lane) & k) == 0;
                     const bool lower = (lane & j) == 0;
                     v[r] = (lower == up) ? min(v[r], o) : max(v[r], o);
