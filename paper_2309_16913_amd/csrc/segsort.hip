@@ -58,7 +58,8 @@ __device__ __forceinline__ uint32_t ceil_log2(uint32_t v) {
 // The key of lane (lane ^ j), for the constant distances of a bitonic
 // network: a DPP quad permutation for 1 and 2 (an ordinary vector move), the
 // bit-mask swizzle for 4, 8 and 16 (within each 32-lane half, no address
-// register), a lane permute for 32.
+// register), a lane permute for 32.  All 64 lanes must be active: DPP and
+// swizzle reads of a lane outside the execution mask do not return its key.
 __device__ __forceinline__ uint32_t xor_lane(uint32_t v, uint32_t j) {
     if (j == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, true);   // quad [1,0,3,2]
     if (j == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, true);   // quad [2,3,0,1]
@@ -99,77 +100,6 @@ __device__ __forceinline__ void wave_bitonic(uint32_t (&v)[R]) {
             }
         }
     }
-}
-
-// Sort s (<= 64*R) keys at src[0..s) into dst[0..s) with one wave.
-template <int R>
-__device__ __forceinline__ void wave_sort_n(const uint32_t *src, uint32_t *dst, uint32_t s) {
-    const uint32_t lane = threadIdx.x & 63u;
-    uint32_t v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t i = (uint32_t)r * 64 + lane;
-        v[r] = i < s ? src[i] : kKeyPad;
-    }
-    wave_bitonic<R>(v);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t i = (uint32_t)r * 64 + lane;
-        if (i < s) dst[i] = v[r];
-    }
-}
-
-// Rank sort of s <= 64*R keys by one wave: every lane holds R keys, and the
-// rank of a key is the number of keys that precede it (smaller, or equal and
-// earlier), counted by broadcasting each key with readlane -- plain VALU work
-// without cross-lane latency chains.  Each key is then stored at its rank.
-template <int R>
-__device__ __forceinline__ void wave_rank_sort(const uint32_t *src, uint32_t *dst, uint32_t s) {
-    const uint32_t lane = threadIdx.x & 63u;
-    uint32_t v[R], rk[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t i = (uint32_t)r * 64 + lane;
-        v[r] = i < s ? src[i] : kKeyPad;
-        rk[r] = 0;
-    }
-#pragma unroll
-    for (int rs = 0; rs < R; ++rs) {
-        const uint32_t j1 = s > (uint32_t)rs * 64 ? min(s - (uint32_t)rs * 64, 64u) : 0u;
-        for (uint32_t j = 0; j < j1; ++j) {
-            const uint32_t x = (uint32_t)__builtin_amdgcn_readlane((int)v[rs], (int)j);
-            const uint32_t xi = (uint32_t)rs * 64 + j;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint32_t i = (uint32_t)r * 64 + lane;
-                rk[r] += (x < v[r] || (x == v[r] && xi < i)) ? 1u : 0u;
-            }
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const uint32_t i = (uint32_t)r * 64 + lane;
-        if (i < s) dst[rk[r]] = v[r];
-    }
-}
-
-// One wave sorts s <= 512 keys (src and dst may alias: all reads precede writes).
-__device__ __forceinline__ void wave_sort_any(const uint32_t *src, uint32_t *dst, uint32_t s) {
-    if (s < 2) {
-        if (s == 1 && src != dst && (threadIdx.x & 63u) == 0) dst[0] = src[0];
-        return;
-    }
-    if (s <= 16)
-        wave_rank_sort<1>(src, dst, s);
-    else if (s <= 64)
-        wave_sort_n<1>(src, dst, s);
-    else if (s <= 128)
-        wave_sort_n<2>(src, dst, s);
-    else if (s <= 256)
-        wave_sort_n<4>(src, dst, s);
-    else
-        wave_sort_n<8>(src, dst, s);
 }
 
 // Block bitonic sort of the first P (power of two) keys of an LDS array.
