@@ -429,7 +429,7 @@ def cpu_info():
     except OSError:
         pass
     nproc = os.cpu_count() or 1
-    # the host share of one GPU on a shared box (OMP_NUM_THREADS is set to it)
+    # the host share of one GPU on a shared machine (OMP_NUM_THREADS is set to it)
     share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
     threads = min(nproc, share) if share > 0 else nproc
     return model, nproc, threads

@@ -48,7 +48,7 @@ def test_served_results_equal_oracle_and_alone():
     srv = Server(tb, tj, nslots=3, max_windows=2048, pool_ids=pool)
     # every request has arrived at the start (arrival times scaled to ~0): the
     # first batch is a full, unsized one of max_windows windows, whatever the
-    # box's launch latencies, so it exceeds the pool and is re-queued
+    # machine's launch latencies, so it exceeds the pool and is re-queued
     out = srv.run(reqs, sink=sink, time_scale=1e-9)
     say(f"case serve: {out}")
     assert len(got) == len(reqs)
